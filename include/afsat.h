@@ -1,0 +1,234 @@
+/*
+ * afsat.h -- C ABI of the MI355X Accelerated Fourier SAT hot path.
+ *
+ * The library evaluates, for a batch of B real points x in [-1,1]^n ("restarts"),
+ * the Walsh-Fourier expansion FE of every symmetric constraint of an instance
+ * (Sec. 2.1, Eq. 1), the objective F = sum_c w_c FE_c (Sec. 2.1.1, Eq. 2) and its
+ * gradient, takes the projected gradient step of Algorithm 1, rounds the points to
+ * Boolean assignments and counts unsatisfied constraints exactly (Algorithm 1's
+ * unsat_count).  FE is computed the way Sec. 2.1.2 describes: a product, per root
+ * of unity of order k+1, of one factor per literal, contracted against a per
+ * constraint coefficient vector (an inverse DFT of the constraint's truth table).
+ *
+ * Conventions shared by every call:
+ *   - Truth values: True -> -1, False -> +1 (Sec. 2.1).  A constraint's FE is -1
+ *     when it is satisfied and +1 when it is violated at a Boolean corner.
+ *   - Points: x is a device float32 array of shape [n][B] (restart index
+ *     contiguous, row stride B).  grad has the same shape.  Literal i of a
+ *     constraint has value y_i = x[v] for a positive DIMACS literal v+1 and
+ *     y_i = -x[v] for a negative one.
+ *   - Rounding: variable v of restart b is True iff x[v][b] < 0 (so +0.0, -0.0
+ *     and NaN are False).  A literal is true iff its variable's truth differs from
+ *     the literal's negation.
+ *   - Ownership: an instance owns its device tables (allocated at create, freed
+ *     at destroy).  Every per-call buffer and the workspace are owned by the
+ *     caller and passed as raw device pointers.  Nothing a call receives is
+ *     retained after it returns.
+ *   - Execution: device calls enqueue work on `stream` (a hipStream_t; NULL is
+ *     the default stream) and return without synchronising.  afs_eval, afs_fe_grad,
+ *     afs_scatter, afs_step, afs_round_verify and afs_pgd_step allocate nothing
+ *     and copy nothing between host and device.
+ *   - Errors: invalid arguments return AFS_EINVAL before anything is launched; a
+ *     launch failure returns AFS_EDEVICE.  afs_last_error() gives a message for
+ *     the last non-OK status of the calling thread.
+ *   - Thread safety: an instance is immutable after creation; concurrent calls
+ *     on different streams with distinct workspaces and outputs are safe.
+ *   - A restart is satisfied iff its unsat count is 0.  Finding no satisfied
+ *     restart means "unknown", never "unsatisfiable" (the method is incomplete).
+ */
+#ifndef AFSAT_H
+#define AFSAT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    AFS_OK = 0,
+    AFS_EINVAL = -1,   /* invalid argument or instance */
+    AFS_EUNSAT = -2,   /* reserved: conflicting unit literals at ingestion */
+    AFS_ENOMEM = -3,   /* host or device allocation failed */
+    AFS_EDEVICE = -4,  /* HIP runtime or kernel launch error */
+    AFS_ESTATE = -5    /* call not valid for this instance (e.g. host-only) */
+} afs_status;
+
+/* Symmetric constraint types (Table 1; Table 2 and the CARD normalisation of
+ * Appendix A).  t = number of true literals out of k. */
+typedef enum {
+    AFS_OR = 0,       /* t >= 1                                    */
+    AFS_XOR = 1,      /* t = param (mod 2); param 1 = odd parity   */
+    AFS_NAE = 2,      /* 0 < t < k                                 */
+    AFS_CARD_GE = 3,  /* t >= param                                */
+    AFS_CARD_LT = 4,  /* t <  param                                */
+    AFS_AMO = 5,      /* t <= 1                                    */
+    AFS_EO = 6,       /* t == 1                                    */
+    AFS_EK = 7        /* t == param                                */
+} afs_ctype;
+
+typedef struct afs_instance afs_instance;
+
+typedef struct {
+    int32_t n_vars;
+    int32_t n_cons;
+    int64_t n_lits;      /* L = total literal occurrences */
+    int32_t n_buckets;   /* length buckets (one kernel launch each) */
+    int32_t n_tables;    /* distinct (type, k, param) coefficient tables */
+    int32_t max_k;
+    int32_t device;      /* HIP device ordinal, or -1 for a host-only instance */
+} afs_info;
+
+/* One length bucket: constraints of lengths [k_lo, k_hi] evaluated by one kernel
+ * variant.  lanes_per_restart = 1 means one lane per restart holding the whole
+ * constraint; otherwise that many lanes split the literals of one restart into
+ * segments of lits_per_lane. */
+typedef struct {
+    int32_t k_lo, k_hi;
+    int32_t n_cons;
+    int64_t n_lits;
+    int32_t lanes_per_restart;
+    int32_t lits_per_lane;
+    int64_t slot0;       /* first literal slot of the bucket */
+} afs_bucket_info;
+
+/* ---- instance -------------------------------------------------------------- */
+
+/* Build an instance from a constraint list in CSR form (Sec. 2.1.1: a formula is a
+ * list of symmetric constraints C_1..C_m over n variables).
+ *   n_vars   : number of variables, >= 1
+ *   n_cons   : number of constraints, >= 0
+ *   con_off  : host int64 [n_cons+1], con_off[0] = 0, non-decreasing; constraint
+ *              c owns lits[con_off[c] .. con_off[c+1]) and has length k >= 1
+ *   lits     : host int32 [L] DIMACS literals, +-(1..n_vars)
+ *   types    : host int32 [n_cons] afs_ctype
+ *   params   : host int32 [n_cons] XOR parity (0/1), or K for CARD_GE/CARD_LT/EK
+ *              (any integer; K outside 0..k+1 makes the constraint constant);
+ *              ignored for other types.  May be NULL if no type needs it.
+ *   weights  : host float [n_cons] constraint weights w_c, or NULL for all 1
+ *   device   : HIP device ordinal, or -1 to build host tables only (for
+ *              inspection; device calls on it return AFS_ESTATE)
+ *   out      : receives the instance
+ * Computes the truth table g_c(t) of every constraint, its coefficient vector
+ * (an FP64 DFT with exactly mirrored roots, Sec. 3.5.1), length buckets and the
+ * variable -> literal-slot transpose, then uploads them.  Host arrays are copied;
+ * the caller keeps ownership. */
+afs_status afs_instance_create(int32_t n_vars, int32_t n_cons, const int64_t *con_off,
+                               const int32_t *lits, const int32_t *types,
+                               const int32_t *params, const float *weights,
+                               int32_t device, afs_instance **out);
+
+/* Free the instance and its device tables.  NULL is accepted.  The caller must
+ * make sure no enqueued work still uses it. */
+void afs_instance_destroy(afs_instance *inst);
+
+afs_status afs_instance_info(const afs_instance *inst, afs_info *out);
+
+/* Describe bucket `b` (0 <= b < n_buckets). */
+afs_status afs_bucket_info_get(const afs_instance *inst, int32_t b, afs_bucket_info *out);
+
+/* Host copy of the literal slot order: slot_to_lit[s] = index into the input
+ * `lits` array of the literal occurrence stored in slot s (int64 [L]). */
+afs_status afs_instance_slot_map(const afs_instance *inst, int64_t *slot_to_lit);
+
+/* Host copy of the variable -> slot transpose: voff int64 [n_vars+1] and
+ * vslot int64 [L]; the slots of variable v are vslot[voff[v] .. voff[v+1]),
+ * ascending. */
+afs_status afs_instance_transpose(const afs_instance *inst, int64_t *voff, int64_t *vslot);
+
+/* FP64 coefficient vector of one constraint (Sec. 2.1.2): with N = k+1 and
+ * omega = exp(2*pi*i/N), d_m = (1/N) * sum_{t=0..k} g(t) * omega^(-m*t) for
+ * m = 0..k, where g(t) = -1 if t true literals satisfy the constraint, else +1.
+ * re, im: host double [k+1].  Needs no instance. */
+afs_status afs_coefficients(int32_t type, int32_t k, int32_t param, double *re, double *im);
+
+/* Bytes of device workspace that afs_eval / afs_fe_grad / afs_pgd_step need for
+ * B restarts.  The workspace is caller-owned, at least 256-byte aligned, and may
+ * be reused across calls on the same stream. */
+afs_status afs_workspace_bytes(const afs_instance *inst, int32_t B, size_t *bytes);
+
+/* ---- evaluation (Sec. 2.1.2; Sec. 2.1.1 Eq. 2) ------------------------------- */
+
+/* FE, objective and gradient at B points.
+ *   x    : device f32 [n][B], values in [-1,1]
+ *   ws   : device workspace of afs_workspace_bytes(inst, B) bytes
+ *   obj  : device f32 [B]      sum_c w_c FE_c                   (NULL: skip)
+ *   grad : device f32 [n][B]   dF/dx                            (NULL: skip)
+ *   fe   : device f32 [C][B]   FE_c per constraint, input order (NULL: skip)
+ *   adj  : device f32 [L][B]   w_c * dFE_c/dx_v per literal occurrence, in the
+ *                              input literal order              (NULL: skip) */
+afs_status afs_eval(afs_instance *inst, int32_t B, const float *x, void *ws, size_t ws_bytes,
+                    float *obj, float *grad, float *fe, float *adj, void *stream);
+
+/* Lower-level pieces of afs_eval, in the order they must run on one stream:
+ * afs_fe_grad evaluates buckets [bucket_lo, bucket_hi) into the workspace (per
+ * literal adjoints and per-tile objective partials); afs_scatter sums the
+ * adjoints of each variable in ascending slot order into grad and reduces the
+ * objective partials into obj (either may be NULL). */
+afs_status afs_fe_grad(afs_instance *inst, int32_t B, const float *x, void *ws, size_t ws_bytes,
+                       int32_t bucket_lo, int32_t bucket_hi, float *fe, void *stream);
+afs_status afs_scatter(afs_instance *inst, int32_t B, void *ws, size_t ws_bytes,
+                       float *obj, float *grad, void *stream);
+
+/* ---- Algorithm 1 --------------------------------------------------------------- */
+
+/* Projected gradient step with constant step length (Algorithm 1,
+ * projectToBounds onto [-1,1]^n):  x <- min(1, max(-1, x - lr * grad)) in FP32,
+ * skipped for variables with fixed[v] != 0 (partial assignment, Sec. 3.4) and
+ * restarts with done[b] != 0 (finished candidates do no-ops, Sec. 3.3).
+ *   x: device f32 [n][B] updated in place; grad: device f32 [n][B];
+ *   fixed: device u8 [n] or NULL; done: device u8 [B] or NULL. */
+afs_status afs_step(afs_instance *inst, int32_t B, float *x, const float *grad, float lr,
+                    const uint8_t *fixed, const uint8_t *done, void *stream);
+
+/* Round and count unsatisfied constraints exactly (Algorithm 1's unsat_count).
+ *   x    : device f32 [n][B]
+ *   bits : device u32 [n][ceil(B/32)]: bit (b % 32) of word b/32 = (x[v][b] < 0)
+ *          (NULL: not returned; a workspace copy is used)
+ *   ws   : workspace as for afs_eval
+ *   unsat: device i32 [B] (required)
+ *   done : device u8 [B] or NULL; set to 1 where unsat == 0 (never cleared) */
+afs_status afs_round_verify(afs_instance *inst, int32_t B, const float *x, uint32_t *bits,
+                            void *ws, size_t ws_bytes, int32_t *unsat, uint8_t *done,
+                            void *stream);
+
+/* Device state of a batched run of Algorithm 1 (all caller-owned device arrays). */
+typedef struct {
+    int32_t *unsat;      /* [B] unsat count at the current point                    */
+    uint8_t *done;       /* [B] 1 once the restart has verified (then frozen)       */
+    int32_t *first_sat;  /* [B] iteration at which it verified, -1 if not yet       */
+    int32_t *counter;    /* [2] {iteration t, number of restarts done}; t counts
+                            completed iterations                                     */
+} afs_pgd_state;
+
+/* Reset the state and check the initial point X_(0): unsat, done and first_sat = 0
+ * where X_(0) already verifies, t = 0. */
+afs_status afs_pgd_init(afs_instance *inst, int32_t B, const float *x, void *ws, size_t ws_bytes,
+                        const afs_pgd_state *st, void *stream);
+
+/* One iteration of Algorithm 1 with constant step length lr: the gradient at
+ * X_(t-1), the projected step to X_(t) (frozen for done restarts and fixed
+ * variables), rounding and the exact unsat count of X_(t); restarts that verify
+ * become done with first_sat = t.  Same launches every call (the iteration
+ * number lives in st->counter), so a sequence of calls may be captured in a
+ * HIP graph and replayed. */
+afs_status afs_pgd_step(afs_instance *inst, int32_t B, float *x, float lr, const uint8_t *fixed,
+                        void *ws, size_t ws_bytes, const afs_pgd_state *st, void *stream);
+
+/* The part of afs_pgd_step that follows the FE kernels: with the per-literal
+ * adjoints of X_(t-1) already in the workspace (afs_fe_grad over every bucket),
+ * sum them per variable, take the projected step, round, count unsatisfied
+ * constraints and update the state.  afs_fe_grad(all buckets) followed by
+ * afs_pgd_update is exactly afs_pgd_step. */
+afs_status afs_pgd_update(afs_instance *inst, int32_t B, float *x, float lr, const uint8_t *fixed,
+                          void *ws, size_t ws_bytes, const afs_pgd_state *st, void *stream);
+
+/* Thread-local message describing the last non-OK status. */
+const char *afs_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AFSAT_H */

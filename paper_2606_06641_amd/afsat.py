@@ -1,0 +1,324 @@
+"""Python binding of ``libafsat`` (the C ABI in ``include/afsat.h``).
+
+Argument marshalling only: every step of the path runs in the library's HIP
+kernels.  Torch provides device memory and streams; tensors are passed as raw
+device pointers together with torch's current HIP stream.  If the library is
+not built this module raises on import instead of falling back to anything.
+"""
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libafsat.so")
+
+OR, XOR, NAE, CARD_GE, CARD_LT, AMO, EO, EK = range(8)
+
+AFS_OK, AFS_EINVAL, AFS_EUNSAT, AFS_ENOMEM, AFS_EDEVICE, AFS_ESTATE = 0, -1, -2, -3, -4, -5
+
+_vp = ctypes.c_void_p
+_i32 = ctypes.c_int32
+_i64p = ctypes.POINTER(ctypes.c_int64)
+_i32p = ctypes.POINTER(ctypes.c_int32)
+_f32p = ctypes.POINTER(ctypes.c_float)
+_f64p = ctypes.POINTER(ctypes.c_double)
+
+
+class AfsError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("afsat status %d: %s" % (status, msg))
+        self.status = status
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("n_vars", ctypes.c_int32), ("n_cons", ctypes.c_int32), ("n_lits", ctypes.c_int64),
+                ("n_buckets", ctypes.c_int32), ("n_tables", ctypes.c_int32),
+                ("max_k", ctypes.c_int32), ("device", ctypes.c_int32)]
+
+
+class _BucketInfo(ctypes.Structure):
+    _fields_ = [("k_lo", ctypes.c_int32), ("k_hi", ctypes.c_int32), ("n_cons", ctypes.c_int32),
+                ("n_lits", ctypes.c_int64), ("lanes_per_restart", ctypes.c_int32),
+                ("lits_per_lane", ctypes.c_int32), ("slot0", ctypes.c_int64)]
+
+
+class _PgdState(ctypes.Structure):
+    _fields_ = [("unsat", _vp), ("done", _vp), ("first_sat", _vp), ("counter", _vp)]
+
+
+# (name, restype, argtypes) of every exported function; the CPU tests check that
+# the library exports exactly these.
+SIGNATURES = [
+    ("afs_last_error", ctypes.c_char_p, []),
+    ("afs_coefficients", ctypes.c_int, [_i32, _i32, _i32, _f64p, _f64p]),
+    ("afs_instance_create", ctypes.c_int, [_i32, _i32, _i64p, _i32p, _i32p, _i32p, _f32p, _i32,
+                                           ctypes.POINTER(_vp)]),
+    ("afs_instance_destroy", None, [_vp]),
+    ("afs_instance_info", ctypes.c_int, [_vp, ctypes.POINTER(_Info)]),
+    ("afs_bucket_info_get", ctypes.c_int, [_vp, _i32, ctypes.POINTER(_BucketInfo)]),
+    ("afs_instance_slot_map", ctypes.c_int, [_vp, _i64p]),
+    ("afs_instance_transpose", ctypes.c_int, [_vp, _i64p, _i64p]),
+    ("afs_workspace_bytes", ctypes.c_int, [_vp, _i32, ctypes.POINTER(ctypes.c_size_t)]),
+    ("afs_eval", ctypes.c_int, [_vp, _i32, _vp, _vp, ctypes.c_size_t, _vp, _vp, _vp, _vp, _vp]),
+    ("afs_fe_grad", ctypes.c_int, [_vp, _i32, _vp, _vp, ctypes.c_size_t, _i32, _i32, _vp, _vp]),
+    ("afs_scatter", ctypes.c_int, [_vp, _i32, _vp, ctypes.c_size_t, _vp, _vp, _vp]),
+    ("afs_step", ctypes.c_int, [_vp, _i32, _vp, _vp, ctypes.c_float, _vp, _vp, _vp]),
+    ("afs_round_verify", ctypes.c_int, [_vp, _i32, _vp, _vp, _vp, ctypes.c_size_t, _vp, _vp, _vp]),
+    ("afs_pgd_init", ctypes.c_int, [_vp, _i32, _vp, _vp, ctypes.c_size_t, ctypes.POINTER(_PgdState), _vp]),
+    ("afs_pgd_step", ctypes.c_int, [_vp, _i32, _vp, ctypes.c_float, _vp, _vp, ctypes.c_size_t,
+                                    ctypes.POINTER(_PgdState), _vp]),
+    ("afs_pgd_update", ctypes.c_int, [_vp, _i32, _vp, ctypes.c_float, _vp, _vp, ctypes.c_size_t,
+                                      ctypes.POINTER(_PgdState), _vp]),
+]
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libafsat.so is not built (run: python -m paper_2606_06641_amd.build)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, res, args in SIGNATURES:
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != AFS_OK:
+        raise AfsError(rc, lib().afs_last_error().decode())
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _np_ptr(a, ctype):
+    return None if a is None else a.ctypes.data_as(ctype)
+
+
+def coefficients(ctype: int, k: int, param: int = 0):
+    """FP64 coefficient vector d_m, m = 0..k (inverse DFT of the truth table)."""
+    re = np.zeros(k + 1)
+    im = np.zeros(k + 1)
+    _check(lib().afs_coefficients(int(ctype), int(k), int(param), _np_ptr(re, _f64p), _np_ptr(im, _f64p)))
+    return re + 1j * im
+
+
+def _stream(device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+@dataclass
+class BucketInfo:
+    k_lo: int
+    k_hi: int
+    n_cons: int
+    n_lits: int
+    lanes_per_restart: int
+    lits_per_lane: int
+    slot0: int
+
+
+class Instance:
+    """A packed instance: n variables, symmetric constraints in CSR form.
+
+    ``device`` is a CUDA/HIP device ordinal, or -1 for a host-only instance
+    (tables and layout can be inspected; device calls raise)."""
+
+    def __init__(self, n, con_off, lits, types, params=None, weights=None, device=0):
+        con_off = np.ascontiguousarray(con_off, dtype=np.int64)
+        lits = np.ascontiguousarray(lits, dtype=np.int32)
+        types = np.ascontiguousarray(types, dtype=np.int32)
+        params = None if params is None else np.ascontiguousarray(params, dtype=np.int32)
+        weights = None if weights is None else np.ascontiguousarray(weights, dtype=np.float32)
+        h = ctypes.c_void_p()
+        _check(lib().afs_instance_create(int(n), len(types), _np_ptr(con_off, _i64p), _np_ptr(lits, _i32p),
+                                         _np_ptr(types, _i32p), _np_ptr(params, _i32p),
+                                         _np_ptr(weights, _f32p), int(device), ctypes.byref(h)))
+        self._h = h
+        info = _Info()
+        _check(lib().afs_instance_info(h, ctypes.byref(info)))
+        self.n = info.n_vars
+        self.n_cons = info.n_cons
+        self.n_lits = info.n_lits
+        self.n_buckets = info.n_buckets
+        self.n_tables = info.n_tables
+        self.max_k = info.max_k
+        self.device = info.device
+        self._ws = {}
+
+    @classmethod
+    def from_arrays(cls, inst, device=0):
+        """From any object with ``n, con_off, lits, types, params, weights``."""
+        return cls(inst.n, inst.con_off, inst.lits, inst.types, getattr(inst, "params", None),
+                   getattr(inst, "weights", None), device=device)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().afs_instance_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- layout --------------------------------------------------------------------
+    def buckets(self):
+        out = []
+        for b in range(self.n_buckets):
+            bi = _BucketInfo()
+            _check(lib().afs_bucket_info_get(self._h, b, ctypes.byref(bi)))
+            out.append(BucketInfo(bi.k_lo, bi.k_hi, bi.n_cons, bi.n_lits, bi.lanes_per_restart,
+                                  bi.lits_per_lane, bi.slot0))
+        return out
+
+    def slot_map(self):
+        a = np.zeros(self.n_lits, dtype=np.int64)
+        _check(lib().afs_instance_slot_map(self._h, _np_ptr(a, _i64p)))
+        return a
+
+    def transpose(self):
+        voff = np.zeros(self.n + 1, dtype=np.int64)
+        vslot = np.zeros(self.n_lits, dtype=np.int64)
+        _check(lib().afs_instance_transpose(self._h, _np_ptr(voff, _i64p), _np_ptr(vslot, _i64p)))
+        return voff, vslot
+
+    def workspace_bytes(self, B):
+        nb = ctypes.c_size_t()
+        _check(lib().afs_workspace_bytes(self._h, int(B), ctypes.byref(nb)))
+        return nb.value
+
+    def workspace(self, B):
+        ws = self._ws.get(B)
+        if ws is None:
+            nbytes = self.workspace_bytes(B)
+            ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self._dev())
+            self._ws = {B: ws}          # keep one workspace at a time
+        return ws
+
+    def _dev(self):
+        if self.device < 0:
+            raise AfsError(AFS_ESTATE, "host-only instance")
+        return torch.device("cuda", self.device)
+
+    def _check_x(self, x, name="x"):
+        if not (isinstance(x, torch.Tensor) and x.dtype == torch.float32 and x.is_cuda
+                and x.dim() == 2 and x.shape[0] == self.n and x.is_contiguous()):
+            raise ValueError("%s must be a contiguous float32 CUDA tensor of shape (n, B)" % name)
+        if x.device.index != self.device:
+            raise ValueError("%s is on device %s, instance on %d" % (name, x.device, self.device))
+        return x.shape[1]
+
+    # -- evaluation ------------------------------------------------------------------
+    def eval(self, x, obj=True, grad=True, fe=False, adj=False, ws=None):
+        """FE / objective / gradient at the columns of x (n, B)."""
+        B = self._check_x(x)
+        dev = self._dev()
+        ws = self.workspace(B) if ws is None else ws
+        out = {}
+        if obj:
+            out["obj"] = torch.empty(B, dtype=torch.float32, device=dev)
+        if grad:
+            out["grad"] = torch.empty((self.n, B), dtype=torch.float32, device=dev)
+        if fe:
+            out["fe"] = torch.empty((self.n_cons, B), dtype=torch.float32, device=dev)
+        if adj:
+            out["adj"] = torch.empty((self.n_lits, B), dtype=torch.float32, device=dev)
+        _check(lib().afs_eval(self._h, B, _ptr(x), _ptr(ws), ws.numel(), _ptr(out.get("obj")),
+                              _ptr(out.get("grad")), _ptr(out.get("fe")), _ptr(out.get("adj")),
+                              _stream(dev)))
+        return out
+
+    def fe_grad(self, x, ws, bucket_lo=0, bucket_hi=None, fe=None):
+        B = self._check_x(x)
+        hi = self.n_buckets if bucket_hi is None else bucket_hi
+        _check(lib().afs_fe_grad(self._h, B, _ptr(x), _ptr(ws), ws.numel(), int(bucket_lo), int(hi),
+                                 _ptr(fe), _stream(self._dev())))
+
+    def scatter(self, B, ws, obj=None, grad=None):
+        _check(lib().afs_scatter(self._h, int(B), _ptr(ws), ws.numel(), _ptr(obj), _ptr(grad),
+                                 _stream(self._dev())))
+
+    # -- Algorithm 1 -------------------------------------------------------------------
+    def step(self, x, grad, lr, fixed=None, done=None):
+        """x <- clip(x - lr*grad, -1, 1) in place, except fixed variables / done restarts."""
+        B = self._check_x(x)
+        self._check_x(grad, "grad")
+        _check(lib().afs_step(self._h, B, _ptr(x), _ptr(grad), float(lr), _ptr(fixed), _ptr(done),
+                              _stream(self._dev())))
+        return x
+
+    def round_verify(self, x, want_bits=False, done=None):
+        """Exact unsat count per restart (int32 [B]); optionally the packed bits."""
+        B = self._check_x(x)
+        dev = self._dev()
+        unsat = torch.empty(B, dtype=torch.int32, device=dev)
+        bits = torch.empty((self.n, (B + 31) // 32), dtype=torch.int32, device=dev) if want_bits else None
+        ws = self.workspace(B)
+        _check(lib().afs_round_verify(self._h, B, _ptr(x), _ptr(bits), _ptr(ws), ws.numel(), _ptr(unsat),
+                                      _ptr(done), _stream(dev)))
+        return (unsat, bits) if want_bits else unsat
+
+    def pgd_state(self, B):
+        dev = self._dev()
+        return {"unsat": torch.zeros(B, dtype=torch.int32, device=dev),
+                "done": torch.zeros(B, dtype=torch.uint8, device=dev),
+                "first_sat": torch.full((B,), -1, dtype=torch.int32, device=dev),
+                "counter": torch.zeros(2, dtype=torch.int32, device=dev)}
+
+    @staticmethod
+    def _state_struct(st):
+        return _PgdState(st["unsat"].data_ptr(), st["done"].data_ptr(), st["first_sat"].data_ptr(),
+                         st["counter"].data_ptr())
+
+    def pgd_init(self, x, st, ws=None):
+        B = self._check_x(x)
+        ws = self.workspace(B) if ws is None else ws
+        s = self._state_struct(st)
+        _check(lib().afs_pgd_init(self._h, B, _ptr(x), _ptr(ws), ws.numel(), ctypes.byref(s),
+                                  _stream(self._dev())))
+
+    def pgd_step(self, x, st, lr, fixed=None, ws=None):
+        B = self._check_x(x)
+        ws = self.workspace(B) if ws is None else ws
+        s = self._state_struct(st)
+        _check(lib().afs_pgd_step(self._h, B, _ptr(x), float(lr), _ptr(fixed), _ptr(ws), ws.numel(),
+                                  ctypes.byref(s), _stream(self._dev())))
+
+    def pgd_update(self, x, st, lr, fixed=None, ws=None):
+        B = self._check_x(x)
+        ws = self.workspace(B) if ws is None else ws
+        s = self._state_struct(st)
+        _check(lib().afs_pgd_update(self._h, B, _ptr(x), float(lr), _ptr(fixed), _ptr(ws), ws.numel(),
+                                    ctypes.byref(s), _stream(self._dev())))
+
+    def pgd(self, x, lr, steps, fixed=None, poll=10, stop_on_sat=True):
+        """Algorithm 1 with constant step length on the columns of x (updated in place).
+
+        Stops after ``steps`` iterations, or (``stop_on_sat``) once any restart
+        verifies; the host reads the 'done' counter every ``poll`` iterations."""
+        B = self._check_x(x)
+        st = self.pgd_state(B)
+        ws = self.workspace(B)
+        self.pgd_init(x, st, ws)
+        t = 0
+        while t < steps:
+            if stop_on_sat and int(st["counter"][1].item()) > 0:
+                break
+            for _ in range(min(poll, steps - t)):
+                self.pgd_step(x, st, lr, fixed, ws)
+                t += 1
+        st["x"] = x
+        st["iters"] = int(st["counter"][0].item())
+        return st

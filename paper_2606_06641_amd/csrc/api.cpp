@@ -1,0 +1,422 @@
+// api.cpp -- the C ABI declared in include/afsat.h.
+#include "afsat.h"
+
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "host.hpp"
+#include "kernels.hpp"
+
+struct afs_instance {
+    afs::HostInstance H;
+    afs::DevInstance D;
+    int device = -1;
+    std::vector<void *> allocs;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+afs_status fail(afs_status s, const std::string &msg)
+{
+    g_err = msg;
+    return s;
+}
+
+afs_status dev_fail(hipError_t e, const char *what)
+{
+    return fail(AFS_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+class DeviceGuard {
+public:
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev_) != hipSuccess) { err_ = hipErrorNoDevice; return; }
+        if (prev_ != dev) err_ = hipSetDevice(dev);
+        dev_ = dev;
+    }
+    ~DeviceGuard()
+    {
+        if (err_ == hipSuccess && prev_ >= 0 && prev_ != dev_) (void)hipSetDevice(prev_);
+    }
+    hipError_t error() const { return err_; }
+
+private:
+    int prev_ = -1, dev_ = -1;
+    hipError_t err_ = hipSuccess;
+};
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+struct WsLayout {
+    int Bp = 0, W = 0;
+    size_t adj = 0, part = 0, part2 = 0, bits = 0, total = 0;
+};
+
+WsLayout ws_layout(const afs::HostInstance &H, int B)
+{
+    WsLayout l;
+    l.Bp = (B + 63) / 64 * 64;
+    l.W = (B + 31) / 32;
+    size_t off = 0;
+    l.adj = off;
+    off = align256(off + (size_t)H.L * l.Bp * sizeof(float));
+    l.part = off;
+    off = align256(off + (size_t)H.total_tiles * l.Bp * sizeof(float));
+    l.part2 = off;
+    off = align256(off + (size_t)((H.total_tiles + 31) / 32) * l.Bp * sizeof(float));
+    l.bits = off;
+    off = align256(off + (size_t)H.n * l.W * sizeof(uint32_t));
+    l.total = off;
+    return l;
+}
+
+template <class T>
+afs_status upload(afs_instance *I, const std::vector<T> &v, const T **out)
+{
+    void *p = nullptr;
+    const size_t bytes = std::max<size_t>(v.size() * sizeof(T), 16);
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) return fail(AFS_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    I->allocs.push_back(p);
+    if (!v.empty()) {
+        e = hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
+        if (e != hipSuccess) return dev_fail(e, "hipMemcpy");
+    }
+    *out = static_cast<const T *>(p);
+    return AFS_OK;
+}
+
+void release(afs_instance *I)
+{
+    if (!I) return;
+    if (I->device >= 0) {
+        DeviceGuard g(I->device);
+        for (void *p : I->allocs) (void)hipFree(p);
+    }
+    delete I;
+}
+
+afs_status check_call(const afs_instance *I, int32_t B)
+{
+    if (!I) return fail(AFS_EINVAL, "instance is NULL");
+    if (I->device < 0) return fail(AFS_ESTATE, "instance was created host-only (device -1)");
+    if (B < 0) return fail(AFS_EINVAL, "B must be >= 0");
+    if ((int64_t)B * I->H.n >= ((int64_t)1 << 40)) return fail(AFS_EINVAL, "n*B too large");
+    return AFS_OK;
+}
+
+afs_status check_ws(const afs_instance *I, int32_t B, const void *ws, size_t ws_bytes, WsLayout &l)
+{
+    l = ws_layout(I->H, B);
+    if (!ws) return fail(AFS_EINVAL, "workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(AFS_EINVAL, "workspace is not 256-byte aligned");
+    if (ws_bytes < l.total)
+        return fail(AFS_EINVAL, "workspace too small: need " + std::to_string(l.total) + " bytes");
+    return AFS_OK;
+}
+
+template <class T>
+T *at(void *ws, size_t off) { return reinterpret_cast<T *>(static_cast<char *>(ws) + off); }
+
+afs_status fe_grad_range(afs_instance *I, int B, const float *x, void *ws, const WsLayout &l,
+                         int lo, int hi, bool want_part, float *fe, hipStream_t s)
+{
+    for (int bi = lo; bi < hi; ++bi) {
+        const afs::Bucket &b = I->H.buckets[bi];
+        afs::BucketLaunch bl{b.J, b.S, b.c0, b.nc, b.tile, b.ntiles, b.tile0};
+        hipError_t e = afs::launch_fe_grad(I->D, bl, B, l.Bp, x, at<float>(ws, l.adj),
+                                           want_part ? at<float>(ws, l.part) : nullptr, fe, s);
+        if (e != hipSuccess) return dev_fail(e, "fe_grad launch");
+    }
+    return AFS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *afs_last_error(void) { return g_err.c_str(); }
+
+afs_status afs_coefficients(int32_t type, int32_t k, int32_t param, double *re, double *im)
+{
+    if (!re || !im) return fail(AFS_EINVAL, "output is NULL");
+    if (k < 1 || k > afs::kMaxLen) return fail(AFS_EINVAL, "k out of range");
+    if (type < 0 || type > 7) return fail(AFS_EINVAL, "unknown type");
+    afs::coefficients(type, k, param, re, im);
+    return AFS_OK;
+}
+
+afs_status afs_instance_create(int32_t n_vars, int32_t n_cons, const int64_t *con_off,
+                               const int32_t *lits, const int32_t *types, const int32_t *params,
+                               const float *weights, int32_t device, afs_instance **out)
+{
+    if (!out) return fail(AFS_EINVAL, "out is NULL");
+    *out = nullptr;
+    afs_instance *I = new (std::nothrow) afs_instance();
+    if (!I) return fail(AFS_ENOMEM, "host allocation failed");
+    std::string err;
+    try {
+        err = afs::build_instance(n_vars, n_cons, con_off, lits, types, params, weights, I->H);
+    } catch (const std::bad_alloc &) {
+        delete I;
+        return fail(AFS_ENOMEM, "host allocation failed");
+    }
+    if (!err.empty()) {
+        delete I;
+        return fail(AFS_EINVAL, err);
+    }
+    if (device < 0) {
+        I->device = -1;
+        *out = I;
+        return AFS_OK;
+    }
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || device >= count) {
+        delete I;
+        return fail(AFS_EINVAL, "no HIP device " + std::to_string(device));
+    }
+    I->device = device;
+    DeviceGuard g(device);
+    if (g.error() != hipSuccess) {
+        I->device = -1;
+        delete I;
+        return dev_fail(g.error(), "hipSetDevice");
+    }
+    const afs::HostInstance &H = I->H;
+    afs::DevInstance &D = I->D;
+    D.n = H.n; D.C = H.C; D.L = H.L;
+    std::vector<int32_t> con_off32(H.C + 1);
+    for (int32_t c = 0; c <= H.C; ++c) con_off32[c] = (int32_t)H.con_off[c];
+    std::vector<float4> tab(H.tab.size());
+    for (size_t i = 0; i < H.tab.size(); ++i) tab[i] = make_float4(H.tab[i].x, H.tab[i].y, H.tab[i].z, H.tab[i].w);
+    afs_status st = AFS_OK;
+    if (st == AFS_OK) st = upload(I, H.bc_slot0, &D.bc_slot0);
+    if (st == AFS_OK) st = upload(I, H.bc_k, &D.bc_k);
+    if (st == AFS_OK) st = upload(I, H.bc_tab, &D.bc_tab);
+    if (st == AFS_OK) st = upload(I, H.bc_orig, &D.bc_orig);
+    if (st == AFS_OK) st = upload(I, H.bc_w, &D.bc_w);
+    if (st == AFS_OK) st = upload(I, H.slot_lit, &D.slot_lit);
+    if (st == AFS_OK) st = upload(I, H.slot_to_lit, &D.slot_to_lit);
+    if (st == AFS_OK) st = upload(I, tab, &D.tab);
+    if (st == AFS_OK) st = upload(I, H.voff, &D.voff);
+    if (st == AFS_OK) st = upload(I, H.vslot, &D.vslot);
+    if (st == AFS_OK) st = upload(I, con_off32, &D.con_off);
+    if (st == AFS_OK) st = upload(I, H.lits, &D.lits);
+    if (st == AFS_OK) st = upload(I, H.types, &D.types);
+    if (st == AFS_OK) st = upload(I, H.params, &D.params);
+    if (st != AFS_OK) {
+        const std::string msg = g_err;
+        release(I);
+        g_err = msg;
+        return st;
+    }
+    *out = I;
+    return AFS_OK;
+}
+
+void afs_instance_destroy(afs_instance *inst) { release(inst); }
+
+afs_status afs_instance_info(const afs_instance *I, afs_info *out)
+{
+    if (!I || !out) return fail(AFS_EINVAL, "NULL argument");
+    out->n_vars = I->H.n;
+    out->n_cons = I->H.C;
+    out->n_lits = I->H.L;
+    out->n_buckets = (int32_t)I->H.buckets.size();
+    out->n_tables = I->H.n_tables;
+    out->max_k = I->H.max_k;
+    out->device = I->device;
+    return AFS_OK;
+}
+
+afs_status afs_bucket_info_get(const afs_instance *I, int32_t b, afs_bucket_info *out)
+{
+    if (!I || !out) return fail(AFS_EINVAL, "NULL argument");
+    if (b < 0 || b >= (int32_t)I->H.buckets.size()) return fail(AFS_EINVAL, "bucket index out of range");
+    const afs::Bucket &k = I->H.buckets[b];
+    out->k_lo = k.k_lo;
+    out->k_hi = k.k_hi;
+    out->n_cons = k.nc;
+    out->n_lits = k.nslots;
+    out->lanes_per_restart = k.J;
+    out->lits_per_lane = k.S;
+    out->slot0 = k.slot0;
+    return AFS_OK;
+}
+
+afs_status afs_instance_slot_map(const afs_instance *I, int64_t *slot_to_lit)
+{
+    if (!I || (!slot_to_lit && I->H.L > 0)) return fail(AFS_EINVAL, "NULL argument");
+    for (int64_t s = 0; s < I->H.L; ++s) slot_to_lit[s] = I->H.slot_to_lit[s];
+    return AFS_OK;
+}
+
+afs_status afs_instance_transpose(const afs_instance *I, int64_t *voff, int64_t *vslot)
+{
+    if (!I || !voff || (!vslot && I->H.L > 0)) return fail(AFS_EINVAL, "NULL argument");
+    for (int32_t v = 0; v <= I->H.n; ++v) voff[v] = I->H.voff[v];
+    for (int64_t s = 0; s < I->H.L; ++s) vslot[s] = I->H.vslot[s];
+    return AFS_OK;
+}
+
+afs_status afs_workspace_bytes(const afs_instance *I, int32_t B, size_t *bytes)
+{
+    if (!I || !bytes) return fail(AFS_EINVAL, "NULL argument");
+    if (B < 0) return fail(AFS_EINVAL, "B must be >= 0");
+    *bytes = ws_layout(I->H, B).total;
+    return AFS_OK;
+}
+
+afs_status afs_fe_grad(afs_instance *I, int32_t B, const float *x, void *ws, size_t ws_bytes,
+                       int32_t bucket_lo, int32_t bucket_hi, float *fe, void *stream)
+{
+    afs_status st = check_call(I, B);
+    if (st != AFS_OK) return st;
+    WsLayout l;
+    if ((st = check_ws(I, B, ws, ws_bytes, l)) != AFS_OK) return st;
+    const int nb = (int)I->H.buckets.size();
+    if (bucket_lo < 0 || bucket_hi > nb || bucket_lo > bucket_hi) return fail(AFS_EINVAL, "bucket range out of range");
+    if (!x && B > 0) return fail(AFS_EINVAL, "x is NULL");
+    DeviceGuard g(I->device);
+    if (g.error() != hipSuccess) return dev_fail(g.error(), "hipSetDevice");
+    return fe_grad_range(I, B, x, ws, l, bucket_lo, bucket_hi, true, fe, (hipStream_t)stream);
+}
+
+afs_status afs_scatter(afs_instance *I, int32_t B, void *ws, size_t ws_bytes, float *obj,
+                       float *grad, void *stream)
+{
+    afs_status st = check_call(I, B);
+    if (st != AFS_OK) return st;
+    WsLayout l;
+    if ((st = check_ws(I, B, ws, ws_bytes, l)) != AFS_OK) return st;
+    DeviceGuard g(I->device);
+    if (g.error() != hipSuccess) return dev_fail(g.error(), "hipSetDevice");
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e;
+    if (grad && (e = afs::launch_scatter(I->D, B, l.Bp, at<float>(ws, l.adj), grad, s)) != hipSuccess)
+        return dev_fail(e, "scatter launch");
+    if (obj && (e = afs::launch_obj_reduce(I->H.total_tiles, B, l.Bp, at<float>(ws, l.part),
+                                           at<float>(ws, l.part2), obj, s)) != hipSuccess)
+        return dev_fail(e, "objective reduction launch");
+    return AFS_OK;
+}
+
+afs_status afs_eval(afs_instance *I, int32_t B, const float *x, void *ws, size_t ws_bytes,
+                    float *obj, float *grad, float *fe, float *adj, void *stream)
+{
+    afs_status st = check_call(I, B);
+    if (st != AFS_OK) return st;
+    WsLayout l;
+    if ((st = check_ws(I, B, ws, ws_bytes, l)) != AFS_OK) return st;
+    if (!x && B > 0) return fail(AFS_EINVAL, "x is NULL");
+    DeviceGuard g(I->device);
+    if (g.error() != hipSuccess) return dev_fail(g.error(), "hipSetDevice");
+    hipStream_t s = (hipStream_t)stream;
+    st = fe_grad_range(I, B, x, ws, l, 0, (int)I->H.buckets.size(), obj != nullptr, fe, s);
+    if (st != AFS_OK) return st;
+    hipError_t e;
+    if (grad && (e = afs::launch_scatter(I->D, B, l.Bp, at<float>(ws, l.adj), grad, s)) != hipSuccess)
+        return dev_fail(e, "scatter launch");
+    if (obj && (e = afs::launch_obj_reduce(I->H.total_tiles, B, l.Bp, at<float>(ws, l.part),
+                                           at<float>(ws, l.part2), obj, s)) != hipSuccess)
+        return dev_fail(e, "objective reduction launch");
+    if (adj && (e = afs::launch_permute_adj(I->D, B, l.Bp, at<float>(ws, l.adj), adj, s)) != hipSuccess)
+        return dev_fail(e, "adjoint permute launch");
+    return AFS_OK;
+}
+
+afs_status afs_step(afs_instance *I, int32_t B, float *x, const float *grad, float lr,
+                    const uint8_t *fixed, const uint8_t *done, void *stream)
+{
+    afs_status st = check_call(I, B);
+    if (st != AFS_OK) return st;
+    if (B > 0 && (!x || !grad)) return fail(AFS_EINVAL, "x or grad is NULL");
+    DeviceGuard g(I->device);
+    if (g.error() != hipSuccess) return dev_fail(g.error(), "hipSetDevice");
+    hipError_t e = afs::launch_step(I->H.n, B, x, grad, lr, fixed, done, (hipStream_t)stream);
+    return e == hipSuccess ? AFS_OK : dev_fail(e, "step launch");
+}
+
+afs_status afs_round_verify(afs_instance *I, int32_t B, const float *x, uint32_t *bits, void *ws,
+                            size_t ws_bytes, int32_t *unsat, uint8_t *done, void *stream)
+{
+    afs_status st = check_call(I, B);
+    if (st != AFS_OK) return st;
+    if (B > 0 && (!x || !unsat)) return fail(AFS_EINVAL, "x or unsat is NULL");
+    if (!bits) {
+        WsLayout l;
+        if ((st = check_ws(I, B, ws, ws_bytes, l)) != AFS_OK) return st;
+        bits = at<uint32_t>(ws, l.bits);
+    }
+    DeviceGuard g(I->device);
+    if (g.error() != hipSuccess) return dev_fail(g.error(), "hipSetDevice");
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = afs::launch_round(I->H.n, B, x, bits, unsat, s);
+    if (e == hipSuccess) e = afs::launch_verify(I->D, B, bits, unsat, s);
+    if (e == hipSuccess && done) e = afs::launch_finalize(B, unsat, done, nullptr, nullptr, afs::FIN_VERIFY, s);
+    return e == hipSuccess ? AFS_OK : dev_fail(e, "round/verify launch");
+}
+
+afs_status afs_pgd_init(afs_instance *I, int32_t B, const float *x, void *ws, size_t ws_bytes,
+                        const afs_pgd_state *P, void *stream)
+{
+    afs_status st = check_call(I, B);
+    if (st != AFS_OK) return st;
+    WsLayout l;
+    if ((st = check_ws(I, B, ws, ws_bytes, l)) != AFS_OK) return st;
+    if (!P || !P->unsat || !P->done || !P->first_sat || !P->counter) return fail(AFS_EINVAL, "incomplete PGD state");
+    if (B > 0 && !x) return fail(AFS_EINVAL, "x is NULL");
+    DeviceGuard g(I->device);
+    if (g.error() != hipSuccess) return dev_fail(g.error(), "hipSetDevice");
+    hipStream_t s = (hipStream_t)stream;
+    uint32_t *bits = at<uint32_t>(ws, l.bits);
+    hipError_t e = afs::launch_round(I->H.n, B, x, bits, P->unsat, s);
+    if (e == hipSuccess) e = afs::launch_verify(I->D, B, bits, P->unsat, s);
+    if (e == hipSuccess) e = afs::launch_finalize(B, P->unsat, P->done, P->first_sat, P->counter, afs::FIN_INIT, s);
+    return e == hipSuccess ? AFS_OK : dev_fail(e, "PGD init launch");
+}
+
+static afs_status pgd_call(afs_instance *I, int32_t B, float *x, float lr, const uint8_t *fixed, void *ws,
+                           size_t ws_bytes, const afs_pgd_state *P, void *stream, bool with_fe)
+{
+    afs_status st = check_call(I, B);
+    if (st != AFS_OK) return st;
+    WsLayout l;
+    if ((st = check_ws(I, B, ws, ws_bytes, l)) != AFS_OK) return st;
+    if (!P || !P->unsat || !P->done || !P->first_sat || !P->counter) return fail(AFS_EINVAL, "incomplete PGD state");
+    if (B > 0 && !x) return fail(AFS_EINVAL, "x is NULL");
+    DeviceGuard g(I->device);
+    if (g.error() != hipSuccess) return dev_fail(g.error(), "hipSetDevice");
+    hipStream_t s = (hipStream_t)stream;
+    if (with_fe) {
+        st = fe_grad_range(I, B, x, ws, l, 0, (int)I->H.buckets.size(), false, nullptr, s);
+        if (st != AFS_OK) return st;
+    }
+    uint32_t *bits = at<uint32_t>(ws, l.bits);
+    hipError_t e = afs::launch_scatter_step(I->D, B, l.Bp, at<float>(ws, l.adj), x, lr, fixed, P->done,
+                                            bits, P->unsat, s);
+    if (e == hipSuccess) e = afs::launch_verify(I->D, B, bits, P->unsat, s);
+    if (e == hipSuccess) e = afs::launch_finalize(B, P->unsat, P->done, P->first_sat, P->counter, afs::FIN_STEP, s);
+    return e == hipSuccess ? AFS_OK : dev_fail(e, "PGD step launch");
+}
+
+afs_status afs_pgd_step(afs_instance *I, int32_t B, float *x, float lr, const uint8_t *fixed, void *ws,
+                        size_t ws_bytes, const afs_pgd_state *P, void *stream)
+{
+    return pgd_call(I, B, x, lr, fixed, ws, ws_bytes, P, stream, true);
+}
+
+afs_status afs_pgd_update(afs_instance *I, int32_t B, float *x, float lr, const uint8_t *fixed, void *ws,
+                          size_t ws_bytes, const afs_pgd_state *P, void *stream)
+{
+    return pgd_call(I, B, x, lr, fixed, ws, ws_bytes, P, stream, false);
+}
+
+}  // extern "C"

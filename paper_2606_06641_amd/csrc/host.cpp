@@ -1,0 +1,235 @@
+// host.cpp -- host-side instance packing (see host.hpp).
+#include "host.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <map>
+#include <numeric>
+#include <tuple>
+
+namespace afs {
+
+int satisfied(int type, int k, int param, int t)
+{
+    switch (type) {
+    case 0: return t >= 1;                       // OR
+    case 1: return (t & 1) == (param & 1);       // XOR, param = parity
+    case 2: return t > 0 && t < k;               // NAE
+    case 3: return t >= param;                   // CARD >= K
+    case 4: return t < param;                    // CARD < K
+    case 5: return t <= 1;                       // AMO
+    case 6: return t == 1;                       // EO
+    case 7: return t == param;                   // EK
+    default: return -1;
+    }
+}
+
+static bool uses_param(int type) { return type == 1 || type == 3 || type == 4 || type == 7; }
+
+// Parameter reduced to a canonical value with the same truth table, so equal
+// tables are shared.
+static int canonical_param(int type, int k, int param)
+{
+    switch (type) {
+    case 1: return param & 1;
+    case 3:
+    case 4: return std::min(std::max(param, 0), k + 1);
+    case 7: return (param < 0 || param > k) ? k + 1 : param;
+    default: return 0;
+    }
+}
+
+// Roots of unity of order N for j = 0..N-1, computed for j <= N/2 and mirrored
+// (conj) above, with exact values at the axis crossings.
+static void roots(int N, std::vector<long double> &c, std::vector<long double> &s)
+{
+    c.assign(N, 0.0L);
+    s.assign(N, 0.0L);
+    const long double two_pi = 6.283185307179586476925286766559005768L;
+    for (int j = 0; 2 * j <= N; ++j) {
+        long double cj, sj;
+        if (j == 0) { cj = 1.0L; sj = 0.0L; }
+        else if (2 * j == N) { cj = -1.0L; sj = 0.0L; }
+        else if (4 * j == N) { cj = 0.0L; sj = 1.0L; }
+        else {
+            const long double th = two_pi * (long double)j / (long double)N;
+            cj = cosl(th);
+            sj = sinl(th);
+        }
+        c[j] = cj;
+        s[j] = sj;
+        if (j > 0 && 2 * j != N) { c[N - j] = cj; s[N - j] = -sj; }
+    }
+}
+
+void coefficients(int type, int k, int param, double *re, double *im)
+{
+    const int N = k + 1;
+    std::vector<long double> c, s;
+    roots(N, c, s);
+    for (int m = 0; m <= k; ++m) {
+        long double ar = 0.0L, ai = 0.0L;
+        for (int t = 0; t <= k; ++t) {
+            const long double g = satisfied(type, k, param, t) == 1 ? -1.0L : 1.0L;
+            const int r = (int)(((int64_t)m * t) % N);
+            ar += g * c[r];
+            ai -= g * s[r];        // omega^(-r) = cos - i sin
+        }
+        re[m] = (double)(ar / N);
+        im[m] = (double)(ai / N);
+    }
+}
+
+void bucket_shape(int k, int &J, int &S)
+{
+    if (k <= kShortMax) { J = 1; S = k; return; }
+    // smallest capacity J*S >= k with S in {12, 16} and J a power of two
+    for (J = 2; J <= 64; J *= 2) {
+        if (J * 12 >= k) { S = 12; return; }
+        if (J * 16 >= k) { S = 16; return; }
+    }
+    J = 64; S = 16;
+}
+
+static int tile_for(int J) { return J == 1 ? 16 : std::max(1, 16 / J); }
+
+std::string build_instance(int32_t n, int32_t C, const int64_t *con_off, const int32_t *lits,
+                           const int32_t *types, const int32_t *params, const float *weights,
+                           HostInstance &H)
+{
+    if (n < 1) return "n_vars must be >= 1";
+    if (C < 0) return "n_cons must be >= 0";
+    if (!con_off) return "con_off is NULL";
+    if (con_off[0] != 0) return "con_off[0] must be 0";
+    if (C > 0 && !types) return "types is NULL";
+    int max_k = 0;
+    for (int32_t c = 0; c < C; ++c) {
+        const int64_t k = con_off[c + 1] - con_off[c];
+        if (k < 1) return "constraint " + std::to_string(c) + " has length < 1";
+        if (k > kMaxLen)
+            return "constraint " + std::to_string(c) + " is longer than " + std::to_string(kMaxLen);
+        max_k = std::max(max_k, (int)k);
+        if (types[c] < 0 || types[c] > 7) return "constraint " + std::to_string(c) + " has an unknown type";
+        if (uses_param(types[c]) && !params) return "params is NULL but a constraint needs a parameter";
+        if (weights && !std::isfinite(weights[c])) return "weight of constraint " + std::to_string(c) + " is not finite";
+    }
+    const int64_t L = C > 0 ? con_off[C] : 0;
+    if (L >= ((int64_t)1 << 31)) return "more than 2^31-1 literals";
+    if (L > 0 && !lits) return "lits is NULL";
+    for (int64_t i = 0; i < L; ++i) {
+        const int32_t l = lits[i];
+        if (l == 0 || l > n || l < -n) return "literal " + std::to_string(i) + " is out of range";
+    }
+
+    H = HostInstance();
+    H.n = n; H.C = C; H.L = L; H.max_k = max_k;
+    H.con_off.assign(con_off, con_off + C + 1);
+    H.lits.assign(lits, lits + L);
+    H.types.assign(types, types + C);
+    H.params.assign(C, 0);
+    H.weights.assign(C, 1.0f);
+    for (int32_t c = 0; c < C; ++c) {
+        if (params) H.params[c] = params[c];
+        if (weights) H.weights[c] = weights[c];
+    }
+
+    // ---- coefficient tables, one per distinct (type, k, canonical param) ----
+    std::map<std::tuple<int, int, int>, int32_t> table_of;
+    std::vector<int32_t> con_tab(C);
+    std::vector<double> re, im;
+    for (int32_t c = 0; c < C; ++c) {
+        const int k = (int)(con_off[c + 1] - con_off[c]);
+        const int p = canonical_param(types[c], k, H.params[c]);
+        auto key = std::make_tuple(types[c], k, p);
+        auto it = table_of.find(key);
+        if (it != table_of.end()) { con_tab[c] = it->second; continue; }
+        const int32_t off = (int32_t)H.tab.size();
+        table_of.emplace(key, off);
+        con_tab[c] = off;
+        re.assign(k + 1, 0.0);
+        im.assign(k + 1, 0.0);
+        coefficients(types[c], k, p, re.data(), im.data());
+        const int N = k + 1;
+        const int M = k / 2;
+        const double dhalf = (N % 2 == 0) ? re[N / 2] : 0.0;
+        H.tab.push_back({(float)re[0], (float)dhalf, 0.0f, 0.0f});
+        const long double pi = 3.141592653589793238462643383279502884L;
+        for (int m = 1; m <= M; ++m) {
+            const long double half = pi * (long double)m / (long double)N;
+            const long double sh = sinl(half);
+            const long double cm1 = -2.0L * sh * sh;                    // cos(theta) - 1
+            const long double sn = 2.0L * sh * cosl(half);              // sin(theta)
+            H.tab.push_back({(float)re[m], (float)im[m], (float)cm1, (float)sn});
+        }
+        ++H.n_tables;
+    }
+
+    // ---- buckets ----
+    std::vector<int32_t> order(C);
+    std::iota(order.begin(), order.end(), 0);
+    auto klen = [&](int32_t c) { return (int)(con_off[c + 1] - con_off[c]); };
+    auto shape_key = [&](int32_t c) {
+        int J, S;
+        bucket_shape(klen(c), J, S);
+        return std::make_pair(J, J == 1 ? klen(c) : J * S);
+    };
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+        const auto ka = shape_key(a), kb = shape_key(b);
+        if (ka != kb) return ka.second != kb.second ? ka.second < kb.second : ka.first < kb.first;
+        if (klen(a) != klen(b)) return klen(a) < klen(b);
+        return con_tab[a] < con_tab[b];
+    });
+
+    H.bc_slot0.resize(C); H.bc_k.resize(C); H.bc_tab.resize(C); H.bc_orig.resize(C); H.bc_w.resize(C);
+    H.slot_lit.resize(L); H.slot_to_lit.resize(L);
+    int64_t slot = 0;
+    int32_t tiles = 0;
+    for (int32_t i = 0; i < C;) {
+        const auto key = shape_key(order[i]);
+        Bucket bk;
+        bucket_shape(klen(order[i]), bk.J, bk.S);
+        bk.c0 = i;
+        bk.slot0 = slot;
+        bk.k_lo = klen(order[i]);
+        int32_t j = i;
+        while (j < C && shape_key(order[j]) == key) {
+            const int32_t c = order[j];
+            const int k = klen(c);
+            H.bc_slot0[j] = (int32_t)slot;
+            H.bc_k[j] = k;
+            H.bc_tab[j] = con_tab[c];
+            H.bc_orig[j] = c;
+            H.bc_w[j] = H.weights[c];
+            for (int q = 0; q < k; ++q) {
+                H.slot_lit[slot + q] = lits[con_off[c] + q];
+                H.slot_to_lit[slot + q] = (int32_t)(con_off[c] + q);
+            }
+            slot += k;
+            bk.k_hi = k;
+            ++j;
+        }
+        bk.nc = j - i;
+        bk.nslots = slot - bk.slot0;
+        bk.tile = tile_for(bk.J);
+        bk.ntiles = (bk.nc + bk.tile - 1) / bk.tile;
+        bk.tile0 = tiles;
+        tiles += bk.ntiles;
+        H.buckets.push_back(bk);
+        i = j;
+    }
+    H.total_tiles = tiles;
+
+    // ---- variable -> slot transpose, ascending slots ----
+    H.voff.assign(n + 1, 0);
+    for (int64_t s = 0; s < L; ++s) H.voff[std::abs(H.slot_lit[s])]++;   // count into v+1
+    for (int32_t v = 0; v < n; ++v) H.voff[v + 1] += H.voff[v];
+    H.vslot.assign(L, 0);
+    std::vector<int32_t> fill(H.voff.begin(), H.voff.end() - 1);
+    for (int64_t s = 0; s < L; ++s) {
+        const int v = std::abs(H.slot_lit[s]) - 1;
+        H.vslot[fill[v]++] = (int32_t)s;
+    }
+    return std::string();
+}
+
+}  // namespace afs

@@ -1,0 +1,84 @@
+// host.hpp -- host-side instance packing for the Accelerated Fourier SAT hot path.
+//
+// Pure C++17 (no HIP): validation, per-constraint truth tables, FP64 coefficient
+// tables, length buckets and the variable -> literal-slot transpose.  The device
+// layer uploads what is built here.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace afs {
+
+// Largest constraint length the kernels handle (64 lanes x 16 literals).
+constexpr int kMaxLen = 1024;
+// Lengths up to this use one lane per restart with the whole constraint in registers.
+constexpr int kShortMax = 16;
+
+// One row of a coefficient table, consumed by the kernels as a float4.
+//   row 0      : {d_0, d_half, 0, 0}   (d_half = d_{N/2} when N = k+1 is even, else 0)
+//   row m >= 1 : {Re d_m, Im d_m, cos(theta_m) - 1, sin(theta_m)}, theta_m = 2 pi m / N,
+//                for m = 1 .. floor((N-1)/2)   (the complex roots of one conjugate pair)
+struct TabRow {
+    float x, y, z, w;
+};
+
+struct Bucket {
+    int k_lo = 0, k_hi = 0;
+    int J = 1;            // lanes per restart
+    int S = 1;            // literals per lane (J == 1: S == k exactly)
+    int32_t c0 = 0;       // first bucket-ordered constraint
+    int32_t nc = 0;       // number of constraints
+    int64_t slot0 = 0;    // first literal slot
+    int64_t nslots = 0;
+    int32_t tile = 1;     // constraints per work tile
+    int32_t ntiles = 0;
+    int32_t tile0 = 0;    // first global tile index (objective partial rows)
+};
+
+struct HostInstance {
+    int32_t n = 0, C = 0;
+    int64_t L = 0;
+    int32_t max_k = 0;
+    // input (original order)
+    std::vector<int64_t> con_off;
+    std::vector<int32_t> lits, types, params;
+    std::vector<float> weights;
+    // coefficient tables
+    std::vector<TabRow> tab;
+    int32_t n_tables = 0;
+    // buckets and bucket-ordered constraints
+    std::vector<Bucket> buckets;
+    int32_t total_tiles = 0;
+    std::vector<int32_t> bc_slot0, bc_k, bc_tab, bc_orig;
+    std::vector<float> bc_w;
+    // literal slots (bucket order)
+    std::vector<int32_t> slot_lit;      // DIMACS literal stored in the slot
+    std::vector<int32_t> slot_to_lit;   // input literal index of the slot
+    // variable -> slot transpose (ascending slots per variable)
+    std::vector<int32_t> voff;          // [n+1]
+    std::vector<int32_t> vslot;         // [L]
+};
+
+// Truth predicate of a constraint with t true literals out of k (Table 1 and
+// Table 2; CARD normalised to ">= K" or "< K" as in Appendix A).
+// Returns 1 satisfied, 0 violated, -1 unknown type.
+int satisfied(int type, int k, int param, int t);
+
+// FP64 coefficient vector d_m, m = 0..k, of a constraint of length k (N = k+1):
+// d_m = (1/N) sum_t g(t) omega^(-m t), g = -1 satisfied / +1 violated,
+// omega = exp(2 pi i / N); angles use the index m*t mod N and roots j > N/2 are
+// mirrored conjugates of N - j, so conjugate symmetry is exact.
+void coefficients(int type, int k, int param, double *re, double *im);
+
+// Build the packed instance.  Returns an empty string on success, else a message.
+std::string build_instance(int32_t n, int32_t C, const int64_t *con_off, const int32_t *lits,
+                           const int32_t *types, const int32_t *params, const float *weights,
+                           HostInstance &out);
+
+// Bucket shape (J lanes per restart, S literals per lane) for a length k.
+void bucket_shape(int k, int &J, int &S);
+
+}  // namespace afs

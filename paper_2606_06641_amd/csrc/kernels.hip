@@ -1,0 +1,747 @@
+// kernels.hip -- HIP kernels for gfx950 (CDNA4, wave64).
+//
+// Evaluation of a symmetric constraint of length k at a real point (Sec. 2.1.2).
+// With p_i = (1 - y_i)/2 the probability that literal i is true, the generating
+// function of the number of true literals is prod_i ((1-p_i) + p_i z); its values
+// at the N = k+1 roots of unity z = omega^m are
+//     G_m = prod_i a_{i,m},   a_{i,m} = 1 + p_i (cos th_m - 1) + i p_i sin th_m,
+// and FE = sum_m d_m G_m with d = inverse DFT of the truth table.  Every |a| <= 1,
+// so no product can overflow at any length.  Because d and G are conjugate
+// symmetric and G_0 = 1,
+//     FE = d_0 + 2 sum_{m=1..M} Re(d_m G_m) + [k odd] d_{N/2} prod_i y_i,  M = floor(k/2).
+// The gradient is taken by prefix and suffix products (no division):
+//     dFE/dy_i = 2 sum_m Re(d_m beta_m prod_{l != i} a_{l,m}) + [k odd] d_{N/2} prod_{l != i} y_l
+// with beta_m = (1 - omega^m)/2 = da/dy.  The kernels run the prefix chain
+// U = d_m prod_{l<i} a_l and the suffix chain S = w (1 - omega^m) prod_{l>i} a_l,
+// so adj_i = sign_i * sum_m Re(U_i S_i) needs two FMAs per root and literal.
+//
+// Layouts: x [n][B] f32 (restart contiguous); adj [L][Bp] f32 in slot order with
+// Bp = B rounded up to 64; constraint and literal metadata are wave-uniform and
+// are read through the scalar cache.
+
+#include "kernels.hpp"
+
+namespace afs {
+
+namespace {
+
+constexpr int kWave = 64;
+constexpr int kBlock = 256;
+constexpr int kWavesPerBlock = kBlock / kWave;
+constexpr int kXcds = 8;
+
+// Workgroups are handed to the 8 XCDs round-robin.  Renumber them so that each
+// XCD receives one contiguous range of logical blocks (and with it a contiguous
+// range of restart columns, whose x rows then stay in that XCD's L2).
+__device__ __forceinline__ int64_t xcd_block()
+{
+    const int64_t nb = gridDim.x;
+    const int64_t i = blockIdx.x;
+    const int64_t xcd = i % kXcds, idx = i / kXcds;
+    const int64_t base = nb / kXcds, extra = nb % kXcds;
+    return xcd * base + (xcd < extra ? xcd : extra) + idx;
+}
+
+__device__ __forceinline__ int wave_id()
+{
+    return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+}
+
+__device__ __forceinline__ void cmul(float &ar, float &ai, float br, float bi)
+{
+    const float r = ar * br - ai * bi;
+    ai = ar * bi + ai * br;
+    ar = r;
+}
+
+struct FeArgs {
+    const float *x;
+    float *adj, *part, *fe;
+    const int32_t *bc_slot0, *bc_k, *bc_tab, *bc_orig;
+    const float *bc_w;
+    const int32_t *slot_lit;
+    const float4 *tab;
+    int B, Bp;
+    int32_t c0, nc, tile, ntiles, tile0;
+    int64_t items;
+};
+
+// ---------------------------------------------------------------------------
+// Short constraints (k <= 16): one lane per restart, k known at compile time, the
+// whole constraint in registers.  A wave takes 64 restarts and a tile of
+// constraints of the bucket.
+// ---------------------------------------------------------------------------
+template <int K, bool PART, bool FE>
+__global__ __launch_bounds__(kBlock) void fe_grad_short(FeArgs A)
+{
+    const int64_t item = xcd_block() * kWavesPerBlock + wave_id();
+    if (item >= A.items) return;
+    const int lane = threadIdx.x & 63;
+    const int group = (int)(item / A.ntiles);
+    const int tile = (int)(item % A.ntiles);
+    const int b = group * kWave + lane;
+    const bool valid = b < A.B;
+    const int bl = valid ? b : A.B - 1;
+    const int cbeg = A.c0 + tile * A.tile;
+    const int cend = min(cbeg + A.tile, A.c0 + A.nc);
+    float objacc = 0.f;
+    for (int c = cbeg; c < cend; ++c) {
+        const int slot0 = A.bc_slot0[c];
+        const int tab = A.bc_tab[c];
+        const float w = A.bc_w[c];
+        int lit[K];
+        float y[K], p[K], adj[K];
+#pragma unroll
+        for (int i = 0; i < K; ++i) {
+            lit[i] = A.slot_lit[slot0 + i];
+            const int v = (lit[i] > 0 ? lit[i] : -lit[i]) - 1;
+            const float xv = A.x[(int64_t)v * A.B + bl];
+            y[i] = lit[i] > 0 ? xv : -xv;
+        }
+#pragma unroll
+        for (int i = 0; i < K; ++i) {
+            p[i] = fmaf(-0.5f, y[i], 0.5f);
+            adj[i] = 0.f;
+        }
+        const float4 r0 = A.tab[tab];
+        float fe = r0.x;
+        // Roots one at a time (unrolling them multiplies register use by K/2).
+#pragma unroll 1
+        for (int m = 1; m <= K / 2; ++m) {
+            const float4 r = A.tab[tab + m];
+            float ar[K], ai[K], pr[K], pi[K];
+#pragma unroll
+            for (int i = 0; i < K; ++i) {
+                ar[i] = fmaf(p[i], r.z, 1.0f);
+                ai[i] = p[i] * r.w;
+            }
+            float ur = r.x, ui = r.y;
+#pragma unroll
+            for (int i = 0; i < K; ++i) {
+                pr[i] = ur;
+                pi[i] = ui;
+                cmul(ur, ui, ar[i], ai[i]);
+            }
+            fe = fmaf(2.0f, ur, fe);
+            float sr = -w * r.z, si = -w * r.w;
+#pragma unroll
+            for (int i = K - 1; i >= 0; --i) {
+                adj[i] = fmaf(pr[i], sr, adj[i]);
+                adj[i] = fmaf(-pi[i], si, adj[i]);
+                if (i > 0) cmul(sr, si, ar[i], ai[i]);
+            }
+        }
+        if (K & 1) {                       // real root omega^(N/2) = -1: factor y_i
+            const float dh = r0.y;
+            float hp[K], h = 1.0f;
+#pragma unroll
+            for (int i = 0; i < K; ++i) {
+                hp[i] = h;
+                h *= y[i];
+            }
+            fe = fmaf(dh, h, fe);
+            float hs = w * dh;
+#pragma unroll
+            for (int i = K - 1; i >= 0; --i) {
+                adj[i] = fmaf(hp[i], hs, adj[i]);
+                hs *= y[i];
+            }
+        }
+        if (valid) {
+#pragma unroll
+            for (int i = 0; i < K; ++i)
+                A.adj[(int64_t)(slot0 + i) * A.Bp + b] = lit[i] > 0 ? adj[i] : -adj[i];
+            if (FE) A.fe[(int64_t)A.bc_orig[c] * A.B + b] = fe;
+        }
+        objacc = fmaf(w, fe, objacc);
+    }
+    if (PART) A.part[(int64_t)(A.tile0 + tile) * A.Bp + b] = objacc;
+}
+
+// ---------------------------------------------------------------------------
+// Long constraints: J lanes per restart (64/J restarts per wave), lane j holding
+// literals [j*S, j*S + S).  Per root, each lane forms the product of its
+// segment; an exclusive prefix scan and an exclusive suffix scan across the J
+// lanes give the products of everything left and right of the segment, from
+// which the lane runs its own prefix and suffix chains.  Each literal's adjoint
+// is owned by exactly one lane: no cross-lane reduction, deterministic order.
+// Slots past the end of the constraint hold y = 1 (factor exactly 1).
+// ---------------------------------------------------------------------------
+template <int J>
+__device__ __forceinline__ void scan_prefix(float &r, float &i, int j)
+{
+#pragma unroll
+    for (int d = 1; d < J; d <<= 1) {
+        const float tr = __shfl_up(r, d, J), ti = __shfl_up(i, d, J);
+        if (j >= d) cmul(r, i, tr, ti);
+    }
+}
+
+template <int J>
+__device__ __forceinline__ void scan_suffix(float &r, float &i, int j)
+{
+#pragma unroll
+    for (int d = 1; d < J; d <<= 1) {
+        const float tr = __shfl_down(r, d, J), ti = __shfl_down(i, d, J);
+        if (j + d < J) cmul(r, i, tr, ti);
+    }
+}
+
+template <int J>
+__device__ __forceinline__ void scan_prefix_real(float &r, int j)
+{
+#pragma unroll
+    for (int d = 1; d < J; d <<= 1) {
+        const float t = __shfl_up(r, d, J);
+        if (j >= d) r *= t;
+    }
+}
+
+template <int J>
+__device__ __forceinline__ void scan_suffix_real(float &r, int j)
+{
+#pragma unroll
+    for (int d = 1; d < J; d <<= 1) {
+        const float t = __shfl_down(r, d, J);
+        if (j + d < J) r *= t;
+    }
+}
+
+template <int J, int S, bool PART, bool FE>
+__global__ __launch_bounds__(kBlock) void fe_grad_seg(FeArgs A)
+{
+    constexpr int R = kWave / J;
+    const int64_t item = xcd_block() * kWavesPerBlock + wave_id();
+    if (item >= A.items) return;
+    const int lane = threadIdx.x & 63;
+    const int group = (int)(item / A.ntiles);
+    const int tile = (int)(item % A.ntiles);
+    const int r = lane / J, j = lane % J;
+    const int b = group * R + r;
+    const bool valid = b < A.B;
+    const int bl = valid ? b : A.B - 1;
+    const int cbeg = A.c0 + tile * A.tile;
+    const int cend = min(cbeg + A.tile, A.c0 + A.nc);
+    const int base = j * S;
+    float objacc = 0.f;
+    for (int c = cbeg; c < cend; ++c) {
+        const int slot0 = A.bc_slot0[c];
+        const int k = A.bc_k[c];
+        const int tab = A.bc_tab[c];
+        const float w = A.bc_w[c];
+        unsigned neg = 0;            // bit s: literal s of this lane is negated
+        float y[S], p[S], adj[S];
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            const int i = base + s;
+            y[s] = 1.0f;
+            if (i < k) {
+                const int lit = A.slot_lit[slot0 + i];
+                const int v = (lit > 0 ? lit : -lit) - 1;
+                const float xv = A.x[(int64_t)v * A.B + bl];
+                y[s] = lit > 0 ? xv : -xv;
+                neg |= (lit < 0 ? 1u : 0u) << s;
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            p[s] = fmaf(-0.5f, y[s], 0.5f);
+            adj[s] = 0.f;
+        }
+        const float4 r0 = A.tab[tab];
+        float fe = r0.x;
+        const int M = k >> 1;
+        for (int m = 1; m <= M; ++m) {
+            const float4 rw = A.tab[tab + m];
+            float ar[S], ai[S], pr[S], pi[S];
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                ar[s] = fmaf(p[s], rw.z, 1.0f);
+                ai[s] = p[s] * rw.w;
+            }
+            float qr = ar[0], qi = ai[0];
+#pragma unroll
+            for (int s = 1; s < S; ++s) cmul(qr, qi, ar[s], ai[s]);
+            float er = qr, ei = qi;
+            scan_prefix<J>(er, ei, j);
+            float fr = qr, fi = qi;
+            scan_suffix<J>(fr, fi, j);
+            {   // inclusive -> exclusive
+                const float er1 = __shfl_up(er, 1, J), ei1 = __shfl_up(ei, 1, J);
+                const float fr1 = __shfl_down(fr, 1, J), fi1 = __shfl_down(fi, 1, J);
+                er = j == 0 ? 1.0f : er1;
+                ei = j == 0 ? 0.0f : ei1;
+                fr = j == J - 1 ? 1.0f : fr1;
+                fi = j == J - 1 ? 0.0f : fi1;
+            }
+            float ur = rw.x, ui = rw.y;
+            cmul(ur, ui, er, ei);
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                pr[s] = ur;
+                pi[s] = ui;
+                cmul(ur, ui, ar[s], ai[s]);
+            }
+            fe = fmaf(2.0f, ur, fe);
+            float sr = -w * rw.z, si = -w * rw.w;
+            cmul(sr, si, fr, fi);
+#pragma unroll
+            for (int s = S - 1; s >= 0; --s) {
+                adj[s] = fmaf(pr[s], sr, adj[s]);
+                adj[s] = fmaf(-pi[s], si, adj[s]);
+                if (s > 0) cmul(sr, si, ar[s], ai[s]);
+            }
+        }
+        if (k & 1) {
+            const float dh = r0.y;
+            float q = y[0];
+#pragma unroll
+            for (int s = 1; s < S; ++s) q *= y[s];
+            float e = q, f = q;
+            scan_prefix_real<J>(e, j);
+            scan_suffix_real<J>(f, j);
+            const float e1 = __shfl_up(e, 1, J), f1 = __shfl_down(f, 1, J);
+            e = j == 0 ? 1.0f : e1;
+            f = j == J - 1 ? 1.0f : f1;
+            float hp[S], h = e;
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                hp[s] = h;
+                h *= y[s];
+            }
+            fe = fmaf(dh, h, fe);
+            float hs = w * dh * f;
+#pragma unroll
+            for (int s = S - 1; s >= 0; --s) {
+                adj[s] = fmaf(hp[s], hs, adj[s]);
+                hs *= y[s];
+            }
+        }
+        if (valid) {
+#pragma unroll
+            for (int s = 0; s < S; ++s)
+                if (base + s < k)
+                    A.adj[(int64_t)(slot0 + base + s) * A.Bp + b] = ((neg >> s) & 1u) ? -adj[s] : adj[s];
+            if (FE && j == J - 1) A.fe[(int64_t)A.bc_orig[c] * A.B + b] = fe;
+        }
+        objacc = fmaf(w, fe, objacc);
+    }
+    if (PART && j == J - 1) A.part[(int64_t)(A.tile0 + tile) * A.Bp + b] = objacc;
+}
+
+template <bool PART, bool FE>
+hipError_t dispatch_short(int K, dim3 g, hipStream_t s, const FeArgs &a)
+{
+#define AFS_SHORT(KK) case KK: hipLaunchKernelGGL((fe_grad_short<KK, PART, FE>), g, dim3(kBlock), 0, s, a); break;
+    switch (K) {
+        AFS_SHORT(1) AFS_SHORT(2) AFS_SHORT(3) AFS_SHORT(4) AFS_SHORT(5) AFS_SHORT(6)
+        AFS_SHORT(7) AFS_SHORT(8) AFS_SHORT(9) AFS_SHORT(10) AFS_SHORT(11) AFS_SHORT(12)
+        AFS_SHORT(13) AFS_SHORT(14) AFS_SHORT(15) AFS_SHORT(16)
+    default: return hipErrorInvalidValue;
+    }
+#undef AFS_SHORT
+    return hipGetLastError();
+}
+
+template <bool PART, bool FE>
+hipError_t dispatch_seg(int J, int S, dim3 g, hipStream_t s, const FeArgs &a)
+{
+#define AFS_SEG(JJ, SS) if (J == JJ && S == SS) { hipLaunchKernelGGL((fe_grad_seg<JJ, SS, PART, FE>), g, dim3(kBlock), 0, s, a); return hipGetLastError(); }
+    AFS_SEG(2, 12) AFS_SEG(2, 16) AFS_SEG(4, 12) AFS_SEG(4, 16) AFS_SEG(8, 12) AFS_SEG(8, 16)
+    AFS_SEG(16, 12) AFS_SEG(16, 16) AFS_SEG(32, 12) AFS_SEG(32, 16) AFS_SEG(64, 12) AFS_SEG(64, 16)
+#undef AFS_SEG
+    return hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------------------
+// Gradient: segmented sum of the per-literal adjoints through the variable ->
+// slot transpose.  One wave per (variable, 64 restarts); the slot list is
+// wave-uniform and every adjoint row read is a coalesced 256-byte row.
+// ---------------------------------------------------------------------------
+struct ScatterArgs {
+    const float *adj;
+    float *grad, *x;
+    const int32_t *voff, *vslot;
+    const uint8_t *fixed, *done;
+    uint32_t *bits;
+    int32_t *unsat;
+    float lr;
+    int B, Bp, W, nchunks;
+    int64_t items;
+};
+
+__device__ __forceinline__ float gather_sum(const ScatterArgs &A, int v, int b)
+{
+    const int o0 = A.voff[v], o1 = A.voff[v + 1];
+    float g = 0.f;
+    int o = o0;
+    for (; o + 4 <= o1; o += 4) {
+        const float a0 = A.adj[(int64_t)A.vslot[o] * A.Bp + b];
+        const float a1 = A.adj[(int64_t)A.vslot[o + 1] * A.Bp + b];
+        const float a2 = A.adj[(int64_t)A.vslot[o + 2] * A.Bp + b];
+        const float a3 = A.adj[(int64_t)A.vslot[o + 3] * A.Bp + b];
+        g += a0;
+        g += a1;
+        g += a2;
+        g += a3;
+    }
+    for (; o < o1; ++o) g += A.adj[(int64_t)A.vslot[o] * A.Bp + b];
+    return g;
+}
+
+// Projected step of Algorithm 1: x - lr*g clipped to [-1, 1] (NaN stays NaN).
+__device__ __forceinline__ float project_step(float xv, float g, float lr)
+{
+    float t = xv - lr * g;
+    t = t > 1.0f ? 1.0f : t;
+    t = t < -1.0f ? -1.0f : t;
+    return t;
+}
+
+__device__ __forceinline__ void store_bits(uint32_t *bits, int v, int W, int chunk, bool neg)
+{
+    const unsigned long long m = __ballot(neg);
+    if ((threadIdx.x & 63) == 0) {
+        const int w0 = chunk * 2;
+        if (w0 < W) bits[(int64_t)v * W + w0] = (uint32_t)m;
+        if (w0 + 1 < W) bits[(int64_t)v * W + w0 + 1] = (uint32_t)(m >> 32);
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void scatter_grad_kernel(ScatterArgs A)
+{
+    const int64_t item = (int64_t)blockIdx.x * kWavesPerBlock + wave_id();
+    if (item >= A.items) return;
+    const int v = (int)(item / A.nchunks), chunk = (int)(item % A.nchunks);
+    const int b = chunk * kWave + (threadIdx.x & 63);
+    const float g = gather_sum(A, v, b);
+    if (b < A.B) A.grad[(int64_t)v * A.B + b] = g;
+}
+
+__global__ __launch_bounds__(kBlock) void scatter_step_kernel(ScatterArgs A)
+{
+    const int64_t item = (int64_t)blockIdx.x * kWavesPerBlock + wave_id();
+    if (item >= A.items) return;
+    const int v = (int)(item / A.nchunks), chunk = (int)(item % A.nchunks);
+    const int b = chunk * kWave + (threadIdx.x & 63);
+    const bool valid = b < A.B;
+    const float g = gather_sum(A, v, b);
+    float xv = 0.f;
+    if (valid) {
+        const int64_t at = (int64_t)v * A.B + b;
+        xv = A.x[at];
+        const bool frozen = (A.fixed && A.fixed[v]) || (A.done && A.done[b]);
+        if (!frozen) {
+            xv = project_step(xv, g, A.lr);
+            A.x[at] = xv;
+        }
+        if (v == 0) A.unsat[b] = 0;
+    }
+    store_bits(A.bits, v, A.W, chunk, valid && xv < 0.0f);
+}
+
+// ---------------------------------------------------------------------------
+// Elementwise step, rounding.
+// ---------------------------------------------------------------------------
+struct EltArgs {
+    float *x;
+    const float *xin, *grad;
+    const uint8_t *fixed, *done;
+    uint32_t *bits;
+    int32_t *unsat;
+    float lr;
+    int B, W, nchunks;
+    int64_t items;
+};
+
+__global__ __launch_bounds__(kBlock) void step_kernel(EltArgs A)
+{
+    const int64_t item = (int64_t)blockIdx.x * kWavesPerBlock + wave_id();
+    if (item >= A.items) return;
+    const int v = (int)(item / A.nchunks), chunk = (int)(item % A.nchunks);
+    const int b = chunk * kWave + (threadIdx.x & 63);
+    if (b >= A.B) return;
+    if ((A.fixed && A.fixed[v]) || (A.done && A.done[b])) return;
+    const int64_t at = (int64_t)v * A.B + b;
+    A.x[at] = project_step(A.x[at], A.grad[at], A.lr);
+}
+
+__global__ __launch_bounds__(kBlock) void round_kernel(EltArgs A)
+{
+    const int64_t item = (int64_t)blockIdx.x * kWavesPerBlock + wave_id();
+    if (item >= A.items) return;
+    const int v = (int)(item / A.nchunks), chunk = (int)(item % A.nchunks);
+    const int b = chunk * kWave + (threadIdx.x & 63);
+    const bool valid = b < A.B;
+    const float xv = valid ? A.xin[(int64_t)v * A.B + b] : 0.f;
+    if (valid && v == 0) A.unsat[b] = 0;
+    store_bits(A.bits, v, A.W, chunk, valid && xv < 0.0f);
+}
+
+// ---------------------------------------------------------------------------
+// Exact verification: per constraint and restart, t = number of true literals
+// (variable bit XOR negation), then the integer predicate of its type.
+// ---------------------------------------------------------------------------
+struct VerifyArgs {
+    const uint32_t *bits;
+    int32_t *unsat;
+    const int32_t *con_off, *lits, *types, *params;
+    int B, W, C, tile, ntiles;
+    int64_t items;
+};
+
+__device__ __forceinline__ bool sat_pred(int type, int k, int param, int t)
+{
+    switch (type) {
+    case 0: return t >= 1;
+    case 1: return (t & 1) == (param & 1);
+    case 2: return t > 0 && t < k;
+    case 3: return t >= param;
+    case 4: return t < param;
+    case 5: return t <= 1;
+    case 6: return t == 1;
+    default: return t == param;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void verify_kernel(VerifyArgs A)
+{
+    const int64_t item = xcd_block() * kWavesPerBlock + wave_id();
+    if (item >= A.items) return;
+    const int group = (int)(item / A.ntiles), tile = (int)(item % A.ntiles);
+    const int b = group * kWave + (threadIdx.x & 63);
+    const bool valid = b < A.B;
+    const int wi = (valid ? b : A.B - 1) >> 5;
+    const int sh = b & 31;
+    const int cbeg = tile * A.tile, cend = min(cbeg + A.tile, A.C);
+    int cnt = 0;
+    for (int c = cbeg; c < cend; ++c) {
+        const int o0 = A.con_off[c], o1 = A.con_off[c + 1];
+        int t = 0;
+#pragma unroll 4
+        for (int o = o0; o < o1; ++o) {
+            const int l = A.lits[o];
+            const int v = (l > 0 ? l : -l) - 1;
+            const uint32_t word = A.bits[(int64_t)v * A.W + wi];
+            t += (int)((word >> sh) & 1u) ^ (l < 0 ? 1 : 0);
+        }
+        cnt += sat_pred(A.types[c], o1 - o0, A.params[c], t) ? 0 : 1;
+    }
+    if (valid && cnt) atomicAdd(&A.unsat[b], cnt);
+}
+
+// One block: done / first_sat bookkeeping and the {t, number done} counter.
+__global__ __launch_bounds__(1024) void finalize_kernel(int B, const int32_t *unsat, uint8_t *done,
+                                                        int32_t *first_sat, int32_t *counter, int mode)
+{
+    __shared__ int red[1024 / kWave];
+    const int t = (mode == FIN_STEP) ? counter[0] + 1 : 0;
+    __syncthreads();
+    int cnt = 0;
+    for (int b = threadIdx.x; b < B; b += blockDim.x) {
+        const bool ok = unsat[b] == 0;
+        if (mode == FIN_INIT) {
+            done[b] = ok ? 1 : 0;
+            first_sat[b] = ok ? 0 : -1;
+            cnt += ok;
+        } else if (mode == FIN_STEP) {
+            uint8_t d = done[b];
+            if (!d && ok) {
+                done[b] = d = 1;
+                first_sat[b] = t;
+            }
+            cnt += d;
+        } else {
+            if (ok) done[b] = 1;
+        }
+    }
+    if (mode == FIN_VERIFY) return;
+    for (int off = 32; off > 0; off >>= 1) cnt += __shfl_down(cnt, off);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = cnt;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int total = 0;
+        for (int i = 0; i < (int)(blockDim.x / kWave); ++i) total += red[i];
+        counter[0] = t;
+        counter[1] = total;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Objective: fixed-order two-pass sum of the per-tile partials.
+// ---------------------------------------------------------------------------
+constexpr int kRedGroup = 32;
+
+__global__ __launch_bounds__(kWave) void obj_reduce1(int tiles, int Bp, const float *part, float *part2)
+{
+    const int chunk = blockIdx.x, g = blockIdx.y;
+    const int b = chunk * kWave + threadIdx.x;
+    const int t0 = g * kRedGroup, t1 = min(t0 + kRedGroup, tiles);
+    float s = 0.f;
+    for (int t = t0; t < t1; ++t) s += part[(int64_t)t * Bp + b];
+    part2[(int64_t)g * Bp + b] = s;
+}
+
+__global__ __launch_bounds__(kBlock) void obj_reduce2(int groups, int B, int Bp, const float *part2, float *obj)
+{
+    const int b = blockIdx.x * kBlock + threadIdx.x;
+    if (b >= B) return;
+    float s = 0.f;
+    for (int g = 0; g < groups; ++g) s += part2[(int64_t)g * Bp + b];
+    obj[b] = s;
+}
+
+__global__ __launch_bounds__(kBlock) void permute_adj_kernel(const float *adj, float *out,
+                                                             const int32_t *slot_to_lit, int B, int Bp,
+                                                             int nchunks, int64_t items)
+{
+    const int64_t item = (int64_t)blockIdx.x * kWavesPerBlock + wave_id();
+    if (item >= items) return;
+    const int64_t s = item / nchunks;
+    const int chunk = (int)(item % nchunks);
+    const int b = chunk * kWave + (threadIdx.x & 63);
+    if (b < B) out[(int64_t)slot_to_lit[s] * B + b] = adj[s * Bp + b];
+}
+
+inline dim3 grid_for_waves(int64_t items)
+{
+    return dim3((unsigned)((items + kWavesPerBlock - 1) / kWavesPerBlock));
+}
+
+}  // namespace
+
+hipError_t launch_fe_grad(const DevInstance &I, const BucketLaunch &bk, int B, int Bp,
+                          const float *x, float *adj, float *part, float *fe, hipStream_t s)
+{
+    if (bk.nc == 0 || B == 0) return hipSuccess;
+    FeArgs a;
+    a.x = x; a.adj = adj; a.part = part; a.fe = fe;
+    a.bc_slot0 = I.bc_slot0; a.bc_k = I.bc_k; a.bc_tab = I.bc_tab; a.bc_orig = I.bc_orig;
+    a.bc_w = I.bc_w; a.slot_lit = I.slot_lit; a.tab = I.tab;
+    a.B = B; a.Bp = Bp;
+    a.c0 = bk.c0; a.nc = bk.nc; a.tile = bk.tile; a.ntiles = bk.ntiles; a.tile0 = bk.tile0;
+    const int R = kWave / bk.J;
+    const int64_t groups = (B + R - 1) / R;
+    a.items = groups * bk.ntiles;
+    const dim3 g = grid_for_waves(a.items);
+    const bool P = part != nullptr, F = fe != nullptr;
+    if (bk.J == 1) {
+        if (P && F) return dispatch_short<true, true>(bk.S, g, s, a);
+        if (P) return dispatch_short<true, false>(bk.S, g, s, a);
+        if (F) return dispatch_short<false, true>(bk.S, g, s, a);
+        return dispatch_short<false, false>(bk.S, g, s, a);
+    }
+    if (P && F) return dispatch_seg<true, true>(bk.J, bk.S, g, s, a);
+    if (P) return dispatch_seg<true, false>(bk.J, bk.S, g, s, a);
+    if (F) return dispatch_seg<false, true>(bk.J, bk.S, g, s, a);
+    return dispatch_seg<false, false>(bk.J, bk.S, g, s, a);
+}
+
+static ScatterArgs scatter_args(const DevInstance &I, int B, int Bp, const float *adj)
+{
+    ScatterArgs a{};
+    a.adj = adj;
+    a.voff = I.voff; a.vslot = I.vslot;
+    a.B = B; a.Bp = Bp; a.W = (B + 31) / 32;
+    a.nchunks = Bp / kWave;
+    a.items = (int64_t)I.n * a.nchunks;
+    return a;
+}
+
+hipError_t launch_scatter(const DevInstance &I, int B, int Bp, const float *adj, float *grad,
+                          hipStream_t s)
+{
+    if (B == 0) return hipSuccess;
+    ScatterArgs a = scatter_args(I, B, Bp, adj);
+    a.grad = grad;
+    hipLaunchKernelGGL(scatter_grad_kernel, grid_for_waves(a.items), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter_step(const DevInstance &I, int B, int Bp, const float *adj, float *x,
+                               float lr, const uint8_t *fixed, const uint8_t *done,
+                               uint32_t *bits, int32_t *unsat, hipStream_t s)
+{
+    if (B == 0) return hipSuccess;
+    ScatterArgs a = scatter_args(I, B, Bp, adj);
+    a.x = x; a.lr = lr; a.fixed = fixed; a.done = done; a.bits = bits; a.unsat = unsat;
+    hipLaunchKernelGGL(scatter_step_kernel, grid_for_waves(a.items), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_obj_reduce(int tiles, int B, int Bp, const float *part, float *part2,
+                             float *obj, hipStream_t s)
+{
+    if (B == 0) return hipSuccess;
+    const int groups = (tiles + kRedGroup - 1) / kRedGroup;
+    if (groups > 0)
+        hipLaunchKernelGGL(obj_reduce1, dim3(Bp / kWave, groups), dim3(kWave), 0, s, tiles, Bp, part, part2);
+    hipLaunchKernelGGL(obj_reduce2, dim3((B + kBlock - 1) / kBlock), dim3(kBlock), 0, s, groups, B, Bp,
+                       part2, obj);
+    return hipGetLastError();
+}
+
+static EltArgs elt_args(int n, int B)
+{
+    EltArgs a{};
+    a.B = B;
+    a.W = (B + 31) / 32;
+    a.nchunks = (B + kWave - 1) / kWave;
+    a.items = (int64_t)n * a.nchunks;
+    return a;
+}
+
+hipError_t launch_step(int n, int B, float *x, const float *grad, float lr, const uint8_t *fixed,
+                       const uint8_t *done, hipStream_t s)
+{
+    if (B == 0) return hipSuccess;
+    EltArgs a = elt_args(n, B);
+    a.x = x; a.grad = grad; a.lr = lr; a.fixed = fixed; a.done = done;
+    hipLaunchKernelGGL(step_kernel, grid_for_waves(a.items), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_round(int n, int B, const float *x, uint32_t *bits, int32_t *unsat, hipStream_t s)
+{
+    if (B == 0) return hipSuccess;
+    EltArgs a = elt_args(n, B);
+    a.xin = x; a.bits = bits; a.unsat = unsat;
+    hipLaunchKernelGGL(round_kernel, grid_for_waves(a.items), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_verify(const DevInstance &I, int B, const uint32_t *bits, int32_t *unsat,
+                         hipStream_t s)
+{
+    if (B == 0 || I.C == 0) return hipSuccess;
+    VerifyArgs a{};
+    a.bits = bits; a.unsat = unsat;
+    a.con_off = I.con_off; a.lits = I.lits; a.types = I.types; a.params = I.params;
+    a.B = B; a.W = (B + 31) / 32; a.C = I.C;
+    a.tile = 32;
+    a.ntiles = (I.C + a.tile - 1) / a.tile;
+    a.items = (int64_t)((B + kWave - 1) / kWave) * a.ntiles;
+    hipLaunchKernelGGL(verify_kernel, grid_for_waves(a.items), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize(int B, const int32_t *unsat, uint8_t *done, int32_t *first_sat,
+                           int32_t *counter, int mode, hipStream_t s)
+{
+    if (B == 0) return hipSuccess;
+    hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(1024), 0, s, B, unsat, done, first_sat, counter, mode);
+    return hipGetLastError();
+}
+
+hipError_t launch_permute_adj(const DevInstance &I, int B, int Bp, const float *adj,
+                              float *adj_out, hipStream_t s)
+{
+    if (B == 0 || I.L == 0) return hipSuccess;
+    const int nchunks = Bp / kWave;
+    const int64_t items = I.L * nchunks;
+    hipLaunchKernelGGL(permute_adj_kernel, grid_for_waves(items), dim3(kBlock), 0, s, adj, adj_out,
+                       I.slot_to_lit, B, Bp, nchunks, items);
+    return hipGetLastError();
+}
+
+}  // namespace afs

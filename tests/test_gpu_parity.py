@@ -1,0 +1,272 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Every comparison feeds both sides the same FP32 points (the oracle widens them
+exactly to FP64).  Tolerances are per length bucket (see parity.py); rounding,
+verification and step bookkeeping are compared bit for bit.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import parity
+from paper_2606_06641_amd import afsat
+from paper_2606_06641_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    afsat.lib()          # raises if the HIP library is missing
+
+
+def log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def check(inst, x32, label):
+    log("case:", label, "n=%d C=%d L=%d B=%d" % (inst.n, inst.n_cons, inst.n_lits, x32.shape[1]))
+    d = afsat.Instance.from_arrays(inst)
+    gpu = parity.gpu_eval(d, x32)
+    orc = oracle.eval(inst, x32, fe=True, adj=True, grad=True)
+    rows = parity.compare(inst, d, gpu, orc, label)
+    log(parity.format_rows(rows))
+    return d, gpu, orc
+
+
+def adversarial_points(n, rng):
+    cols = [np.ones(n), -np.ones(n), np.zeros(n),
+            (1 - 1e-3) * np.ones(n), -(1 - 1e-3) * np.ones(n),
+            rng.choice([-1.0, 1.0], size=n),
+            rng.choice([-1.0, 1.0], size=n) * (1 - 1e-3),
+            rng.choice([-1.0, 1.0], size=n) * (1 - rng.uniform(0, 1e-2, size=n))]
+    c = rng.choice([-1.0, 1.0], size=n)
+    c[rng.choice(n, size=max(1, n // 10), replace=False)] = rng.uniform(-1e-3, 1e-3, size=max(1, n // 10))
+    cols.append(c)
+    return np.stack(cols, axis=1).astype(np.float32)
+
+
+def test_short_all_types_ragged_batch():
+    rng = np.random.default_rng(10)
+    inst = W.random_instance(rng, n=300, count=500, k_lo=1, k_hi=16)
+    inst.weights = rng.uniform(0.5, 2.0, size=inst.n_cons).astype(np.float32)
+    x = rng.uniform(-1, 1, size=(inst.n, 37)).astype(np.float32)
+    check(inst, x, "short k1-16 B=37 weighted")
+
+
+def test_long_every_bucket_shape():
+    rng = np.random.default_rng(11)
+    ks = [17, 24, 25, 32, 33, 48, 49, 64, 65, 96, 97, 128, 129, 192, 193, 256, 257, 384, 385, 512,
+          513, 768, 769, 1000, 1024]
+    parts = []
+    for k in ks:
+        parts.append(W.random_instance(rng, n=1500, count=3, k_lo=k, k_hi=k))
+    inst = concat(parts, n=1500)
+    x = rng.uniform(-1, 1, size=(inst.n, 70)).astype(np.float32)
+    check(inst, x, "long k17-1024 B=70")
+
+
+def test_adversarial_points():
+    rng = np.random.default_rng(12)
+    parts = [W.random_instance(rng, n=1200, count=60, k_lo=1, k_hi=16),
+             W.random_instance(rng, n=1200, count=30, k_lo=17, k_hi=300),
+             W.random_instance(rng, n=1200, count=6, k_lo=700, k_hi=1024)]
+    inst = concat(parts, n=1200)
+    x = adversarial_points(inst.n, rng)
+    check(inst, x, "adversarial")
+
+
+def test_single_restart_and_k1():
+    rng = np.random.default_rng(13)
+    inst = W.random_instance(rng, n=50, count=80, k_lo=1, k_hi=3)
+    x = rng.uniform(-1, 1, size=(inst.n, 1)).astype(np.float32)
+    check(inst, x, "B=1")
+    x = rng.uniform(-1, 1, size=(inst.n, 65)).astype(np.float32)
+    check(inst, x, "B=65")
+
+
+def test_empty_instance():
+    inst = W.Instance(n=7, con_off=np.zeros(1, np.int64), lits=np.zeros(0, np.int32),
+                      types=np.zeros(0, np.int32), params=np.zeros(0, np.int32))
+    d = afsat.Instance.from_arrays(inst)
+    x = parity.to_dev(np.random.default_rng(0).uniform(-1, 1, size=(7, 5)))
+    out = d.eval(x, obj=True, grad=True)
+    assert torch.all(out["obj"] == 0) and torch.all(out["grad"] == 0)
+    assert torch.all(d.round_verify(x) == 0)
+    out = d.eval(x[:, :0].contiguous(), obj=True, grad=True)       # B = 0
+    assert out["obj"].numel() == 0
+
+
+def test_config1_planted_3sat_parity():
+    inst = W.planted_3sat(instance=0)
+    x = W.uniform_x0(inst.n, 32, workload=1)
+    check(inst, x, "planted 3-SAT n=100 m=426 B=32")
+
+
+def test_config2_mixed_full_size():
+    inst = W.mixed_10k()
+    x = W.uniform_x0(inst.n, 1024, workload=2)
+    check(inst, x, "mixed n=10k B=1024 (all restarts)")
+
+
+def test_config4_long_card_sampled():
+    """n=50k, 200k clauses, 1k CARD k 256-1024, B=512 on the GPU; the oracle checks
+    16 sampled restart columns (columns are independent)."""
+    inst = W.long_card_50k()
+    B = 512
+    x = W.uniform_x0(inst.n, B, workload=4)
+    log("case: long-card n=50k B=512 sampled")
+    d = afsat.Instance.from_arrays(inst)
+    gpu = parity.gpu_eval(d, x)
+    cols = np.random.default_rng(4).choice(B, size=16, replace=False)
+    orc = oracle.eval(inst, x[:, cols], fe=True, adj=True, grad=True)
+    sub = {k: (v[..., cols] if v.ndim == 2 else v[cols]) for k, v in gpu.items()}
+    rows = parity.compare(inst, d, sub, orc, "cfg4 sampled")
+    log(parity.format_rows(rows))
+
+
+def test_verify_bit_exact():
+    rng = np.random.default_rng(14)
+    inst = W.random_instance(rng, n=200, count=900, k_lo=1, k_hi=40)
+    x = rng.uniform(-1, 1, size=(inst.n, 77)).astype(np.float32)
+    x[rng.random(x.shape) < 0.1] = 0.0
+    x[rng.random(x.shape) < 0.05] = -0.0
+    x[rng.random(x.shape) < 0.05] = 1.0
+    x[rng.random(x.shape) < 0.05] = -1.0
+    d = afsat.Instance.from_arrays(inst)
+    unsat, bits = d.round_verify(parity.to_dev(x), want_bits=True)
+    want_u, want_bits = oracle.verify(inst, x, want_bits=True)
+    assert np.array_equal(unsat.cpu().numpy(), want_u)
+    assert np.array_equal(bits.cpu().numpy().view(np.uint32), want_bits)
+
+
+def test_verify_planted_witness():
+    for inst in [W.planted_3sat(instance=3), W.mixed_10k()]:
+        H = np.where(inst.hidden, -1.0, 1.0).astype(np.float32)
+        x = np.stack([H, 0.3 * H, -H], axis=1)
+        d = afsat.Instance.from_arrays(inst)
+        u = d.round_verify(parity.to_dev(x)).cpu().numpy()
+        assert u[0] == 0 and u[1] == 0 and u[2] > 0
+        assert np.array_equal(u, oracle.verify(inst, x))
+
+
+def test_step_matches_oracle():
+    rng = np.random.default_rng(15)
+    n, B = 300, 90
+    x = rng.uniform(-1, 1, size=(n, B)).astype(np.float32)
+    g = rng.normal(0, 5, size=(n, B)).astype(np.float32)
+    fixed = (rng.random(n) < 0.2).astype(np.uint8)
+    done = (rng.random(B) < 0.3).astype(np.uint8)
+    inst = W.random_instance(rng, n=n, count=10, k_lo=2, k_hi=3)
+    d = afsat.Instance.from_arrays(inst)
+    xd = parity.to_dev(x)
+    d.step(xd, parity.to_dev(g), 0.1, fixed=torch.from_numpy(fixed).cuda(), done=torch.from_numpy(done).cuda())
+    want = oracle.step(x, g, 0.1, fixed=fixed, done=done)
+    got = xd.cpu().numpy()
+    assert np.max(np.abs(got - want)) <= 1e-6
+    frozen = fixed[:, None].astype(bool) | done[None, :].astype(bool)
+    assert np.array_equal(got[frozen], x[frozen])
+    assert got.min() >= -1 and got.max() <= 1
+
+
+def test_pgd_step_is_eval_step_verify_and_deterministic():
+    rng = np.random.default_rng(16)
+    inst = concat([W.random_instance(rng, n=400, count=700, k_lo=1, k_hi=12),
+                   W.random_instance(rng, n=400, count=20, k_lo=20, k_hi=200)], n=400)
+    d = afsat.Instance.from_arrays(inst)
+    B = 100
+    x0 = parity.to_dev(rng.uniform(-1, 1, size=(inst.n, B)))
+    # reference composition
+    xa = x0.clone()
+    g = d.eval(xa, obj=False, grad=True)["grad"]
+    d.step(xa, g, 0.1)
+    ua = d.round_verify(xa)
+    # fused PGD step
+    xb = x0.clone()
+    st = d.pgd_state(B)
+    d.pgd_init(xb, st)
+    u0 = st["unsat"].clone()
+    d.pgd_step(xb, st, 0.1)
+    torch.cuda.synchronize()
+    assert torch.equal(u0, d.round_verify(x0))
+    assert torch.equal(xa, xb)
+    assert torch.equal(ua, st["unsat"])
+    assert int(st["counter"][0]) == 1
+    # deterministic: same again bit for bit
+    xc = x0.clone()
+    st2 = d.pgd_state(B)
+    d.pgd_init(xc, st2)
+    d.pgd_step(xc, st2, 0.1)
+    torch.cuda.synchronize()
+    assert torch.equal(xb, xc)
+    e1 = d.eval(x0, obj=True, grad=True)
+    e2 = d.eval(x0, obj=True, grad=True)
+    assert torch.equal(e1["grad"], e2["grad"]) and torch.equal(e1["obj"], e2["obj"])
+
+
+def test_pgd_done_bookkeeping():
+    inst = W.planted_3sat(instance=1)
+    d = afsat.Instance.from_arrays(inst)
+    H = np.where(inst.hidden, -1.0, 1.0).astype(np.float32)
+    rng = np.random.default_rng(17)
+    x = rng.uniform(-1, 1, size=(inst.n, 40)).astype(np.float32)
+    x[:, 0] = H                                          # restart 0 starts satisfied
+    xd = parity.to_dev(x)
+    st = d.pgd_state(40)
+    d.pgd_init(xd, st)
+    assert int(st["done"][0]) == 1 and int(st["first_sat"][0]) == 0
+    for t in range(1, 31):
+        d.pgd_step(xd, st, 0.1)
+    torch.cuda.synchronize()
+    xs = xd.cpu().numpy()
+    assert np.array_equal(xs[:, 0], H)                    # frozen
+    done = st["done"].cpu().numpy().astype(bool)
+    fs = st["first_sat"].cpu().numpy()
+    u = st["unsat"].cpu().numpy()
+    assert np.all(fs[done] >= 0) and np.all(fs[~done] == -1)
+    assert np.all(u[done] == 0)
+    assert np.array_equal(u, oracle.verify(inst, xs))
+    assert int(st["counter"][0]) == 30 and int(st["counter"][1]) == done.sum()
+
+
+def test_config1_end_to_end_solves():
+    """Algorithm 1 on planted 3-SAT (n=100, m=426, the 4.26 threshold ratio), 32
+    restarts, lr 0.1, 200 steps.  Trajectories are chaotic, so success is compared
+    per instance with the oracle's own FP64 PGD run, not restart by restart; every
+    restart the GPU reports as done must verify on the CPU."""
+    solved_gpu = solved_orc = 0
+    for i in range(8):
+        inst = W.planted_3sat(instance=i)
+        x0 = W.uniform_x0(inst.n, 32, workload=1, instance=i)
+        d = afsat.Instance.from_arrays(inst)
+        xd = parity.to_dev(x0)
+        res = d.pgd(xd, lr=0.1, steps=200, stop_on_sat=False)
+        done = res["done"].cpu().numpy().astype(bool)
+        xs = xd.cpu().numpy()
+        if done.any():
+            solved_gpu += 1
+            assert np.all(oracle.verify(inst, xs[:, done]) == 0)
+        ro = oracle.pgd(inst, x0, lr=0.1, steps=200)
+        solved_orc += int((ro["first_sat"] >= 0).any())
+        log("instance", i, "gpu restarts solved", int(done.sum()), "oracle", int((ro["first_sat"] >= 0).sum()))
+    assert solved_gpu >= 1 and solved_gpu >= solved_orc - 2
+
+
+def concat(parts, n):
+    offs = [np.zeros(1, np.int64)]
+    lits, types, params = [], [], []
+    base = 0
+    for p in parts:
+        offs.append(p.con_off[1:] + base)
+        base += p.n_lits
+        lits.append(p.lits)
+        types.append(p.types)
+        params.append(p.params)
+    return W.Instance(n=n, con_off=np.concatenate(offs), lits=np.concatenate(lits),
+                      types=np.concatenate(types), params=np.concatenate(params))

@@ -1,0 +1,185 @@
+"""Host logic of the C-ABI library (CPU only, no device calls).
+
+* the library loads and exports every function ``include/afsat.h`` declares;
+* coefficient tables: an independent numpy inverse FFT of the truth table,
+  Parseval, exact conjugate symmetry, and FE = sum_m d_m G_m evaluated in
+  numpy/FP64 at points against the oracle (the DFT route of Sec. 2.1.2 checked
+  against the direct count-basis recursion);
+* packing: buckets cover every constraint once, the slot order is a
+  permutation, the variable -> slot transpose lists each slot once in ascending
+  order;
+* validation: malformed instances are rejected with AFS_EINVAL.
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2606_06641_amd import afsat
+from paper_2606_06641_amd import workloads as W
+import oracle
+import exact
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "afsat.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(afs_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_function():
+    L = afsat.lib()
+    names = declared_functions()
+    assert len(names) >= 15
+    for name in names:
+        assert hasattr(L, name), name
+    # and the binding's signature list is exactly the header's
+    assert sorted(n for n, _, _ in afsat.SIGNATURES) == names
+
+
+def g_table(ctype, k, param):
+    return np.array([exact.g(ctype, k, param, t) for t in range(k + 1)], dtype=np.float64)
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 7, 16, 17, 64, 255, 1024])
+def test_coefficients_are_inverse_dft_of_truth_table(k):
+    for ctype in range(8):
+        for param in sorted({0, 1, k // 3, k // 2, k, k + 1}):
+            d = afsat.coefficients(ctype, k, param)
+            g = g_table(ctype, k, param)
+            want = np.fft.ifft(g)                 # (1/N) sum_t g(t) e^{+2 pi i m t/N}
+            want = np.conj(want)                  # d_m uses omega^(-m t): conj for real g
+            assert np.max(np.abs(d - want)) <= 1e-13, (ctype, k, param)
+            # inverse relation: g(t) = sum_m d_m omega^(m t)
+            N = k + 1
+            back = np.fft.fft(np.conj(d)).real    # sum_m conj(d_m) e^{-2pi i m t/N} = conj(sum d w^{mt})
+            assert np.max(np.abs(back - g)) <= 1e-12
+            # Parseval: sum_m |d_m|^2 = (1/N) sum_t g(t)^2 = 1
+            assert abs(np.sum(np.abs(d) ** 2) - 1.0) <= 1e-12
+            # exact conjugate symmetry d_{N-m} = conj(d_m)
+            for m in range(1, N):
+                assert d[N - m] == np.conj(d[m])
+
+
+@pytest.mark.parametrize("k", [3, 10, 33, 200])
+def test_dft_route_equals_oracle_recursion(k):
+    """FE via the product over roots (Sec. 2.1.2, count basis) in FP64 numpy vs the oracle."""
+    rng = np.random.default_rng(k)
+    y = rng.uniform(-1, 1, size=(k, 4))
+    N = k + 1
+    w = np.exp(2j * np.pi * np.arange(N) / N)
+    p = (1 - y) / 2
+    for ctype, param in [(W.OR, 0), (W.CARD_GE, k // 2), (W.XOR, 1), (W.NAE, 0), (W.EK, k // 3)]:
+        d = afsat.coefficients(ctype, k, param)
+        G = np.prod((1 - p)[:, None, :] + p[:, None, :] * w[None, :, None], axis=0)   # (N, B)
+        fe = np.real(np.sum(d[:, None] * G, axis=0))
+        inst = W.Instance(n=k, con_off=np.array([0, k]), lits=np.arange(1, k + 1, dtype=np.int32),
+                          types=np.array([ctype], np.int32), params=np.array([param], np.int32))
+        want = oracle.eval(inst, y, fe=True, grad=False)["fe"][0]
+        assert np.max(np.abs(fe - want)) <= 1e-10, (ctype, param)
+
+
+def host_instance(inst):
+    return afsat.Instance.from_arrays(inst, device=-1)
+
+
+def test_packing_layout():
+    rng = np.random.default_rng(0)
+    inst = W.random_instance(rng, n=400, count=600, k_lo=1, k_hi=300)
+    H = host_instance(inst)
+    assert H.n == 400 and H.n_cons == 600 and H.n_lits == inst.n_lits
+    bks = H.buckets()
+    assert sum(b.n_cons for b in bks) == 600
+    assert sum(b.n_lits for b in bks) == inst.n_lits
+    lens = inst.lengths()
+    slot = 0
+    for b in bks:
+        assert b.slot0 == slot
+        slot += b.n_lits
+        if b.lanes_per_restart == 1:
+            assert b.k_lo == b.k_hi == b.lits_per_lane <= 16
+        else:
+            assert b.k_hi <= b.lanes_per_restart * b.lits_per_lane
+            assert b.k_lo > 16
+    # every constraint length lands in exactly one bucket's range
+    for k in np.unique(lens):
+        n_in = sum(1 for b in bks if b.k_lo <= k <= b.k_hi)
+        assert n_in == 1
+    smap = H.slot_map()
+    assert np.array_equal(np.sort(smap), np.arange(inst.n_lits))
+    # slots of one constraint are contiguous and in its literal order
+    lit_of_slot = inst.lits[smap]
+    voff, vslot = H.transpose()
+    assert voff[0] == 0 and voff[-1] == inst.n_lits
+    assert np.array_equal(np.sort(vslot), np.arange(inst.n_lits))
+    for v in range(inst.n):
+        s = vslot[voff[v]:voff[v + 1]]
+        assert np.all(np.diff(s) > 0)
+        assert np.all(np.abs(lit_of_slot[s]) == v + 1)
+    assert np.array_equal(np.diff(voff), np.bincount(np.abs(inst.lits) - 1, minlength=inst.n))
+
+
+def test_bucket_shapes_cover_lengths():
+    # long constraints: J lanes x S literals, S in {12, 16}, J a power of two, tightest fit
+    rng = np.random.default_rng(1)
+    for k in [17, 24, 25, 32, 33, 100, 129, 256, 257, 512, 1000, 1024]:
+        inst = W.random_instance(rng, n=2000, count=1, k_lo=k, k_hi=k)
+        (b,) = host_instance(inst).buckets()
+        J, S = b.lanes_per_restart, b.lits_per_lane
+        assert J & (J - 1) == 0 and 2 <= J <= 64 and S in (12, 16)
+        assert J * S >= k
+        caps = sorted(j * s for j in (2, 4, 8, 16, 32, 64) for s in (12, 16))
+        assert J * S == min(c for c in caps if c >= k)
+
+
+def _create(n, con_off, lits, types, params=None):
+    return afsat.Instance(n, con_off, lits, types, params, device=-1)
+
+
+@pytest.mark.parametrize("case", [
+    dict(n=3, con_off=[0, 2], lits=[1, 0], types=[0]),            # literal 0
+    dict(n=3, con_off=[0, 2], lits=[1, 4], types=[0]),            # |lit| > n
+    dict(n=3, con_off=[0, 2], lits=[1, -4], types=[0]),
+    dict(n=3, con_off=[0, 0], lits=[], types=[0]),                # empty constraint
+    dict(n=3, con_off=[0, 2], lits=[1, 2], types=[9]),            # unknown type
+    dict(n=0, con_off=[0], lits=[], types=[]),                    # no variables
+    dict(n=3, con_off=[1, 2], lits=[1, 2], types=[0]),            # con_off[0] != 0
+])
+def test_invalid_instances_rejected(case):
+    with pytest.raises(afsat.AfsError) as e:
+        _create(**case)
+    assert e.value.status == afsat.AFS_EINVAL
+
+
+def test_too_long_constraint_rejected():
+    k = 1025
+    with pytest.raises(afsat.AfsError) as e:
+        _create(2000, [0, k], np.arange(1, k + 1), [W.CARD_GE], [3])
+    assert e.value.status == afsat.AFS_EINVAL
+    assert "longer than 1024" in str(e.value)
+
+
+def test_host_only_instance_refuses_device_calls():
+    H = _create(3, [0, 2], [1, -2], [W.OR])
+    with pytest.raises(afsat.AfsError) as e:
+        H._dev()
+    assert e.value.status == afsat.AFS_ESTATE
+
+
+def test_empty_instance_and_workspace():
+    H = _create(5, [0], [], [])
+    assert H.n_cons == 0 and H.n_buckets == 0
+    assert H.workspace_bytes(0) >= 0
+    assert H.workspace_bytes(100) >= 5 * 4 * 4
+
+
+def test_tables_shared_between_equal_truth_tables():
+    # CARD>=0 and CARD>=-5 are the same (always true); XOR parity 3 == parity 1
+    H = _create(6, [0, 3, 6, 9, 12], [1, 2, 3, 4, 5, 6, 1, 2, 3, 4, 5, 6],
+                [W.CARD_GE, W.CARD_GE, W.XOR, W.XOR], [0, -5, 1, 3])
+    assert H.n_tables == 2

@@ -119,6 +119,29 @@ afs_status afs_instance_create(int32_t n_vars, int32_t n_cons, const int64_t *co
                                const int32_t *params, const float *weights,
                                int32_t device, afs_instance **out);
 
+/* Optional packing choices (every field 0 / NULL: the built-in defaults).
+ *   n_shapes, shape_k_hi, shape_lanes, shape_seg: kernel shape per length range for
+ *       constraints longer than 16: a constraint of length k uses the first entry
+ *       with k <= shape_k_hi[e] (ascending), evaluated by shape_lanes[e] lanes per
+ *       restart (2, 4, 8, 16, 32 or 64) holding shape_seg[e] literals each (8, 16,
+ *       24 or 32), with lanes * seg >= shape_k_hi[e].  Lengths past the last entry
+ *       use the default shape model.  (These are what the autotuner picks.)
+ *   tile_short / tile_long: constraints per work tile for lengths <= 16 / > 16. */
+typedef struct {
+    int32_t n_shapes;
+    const int32_t *shape_k_hi;
+    const int32_t *shape_lanes;
+    const int32_t *shape_seg;
+    int32_t tile_short;
+    int32_t tile_long;
+} afs_options;
+
+/* afs_instance_create with packing options (opts may be NULL). */
+afs_status afs_instance_create_ex(int32_t n_vars, int32_t n_cons, const int64_t *con_off,
+                                  const int32_t *lits, const int32_t *types,
+                                  const int32_t *params, const float *weights,
+                                  const afs_options *opts, int32_t device, afs_instance **out);
+
 /* Free the instance and its device tables.  NULL is accepted.  The caller must
  * make sure no enqueued work still uses it. */
 void afs_instance_destroy(afs_instance *inst);
@@ -163,11 +186,14 @@ afs_status afs_eval(afs_instance *inst, int32_t B, const float *x, void *ws, siz
 
 /* Lower-level pieces of afs_eval, in the order they must run on one stream:
  * afs_fe_grad evaluates buckets [bucket_lo, bucket_hi) into the workspace (per
- * literal adjoints and per-tile objective partials); afs_scatter sums the
- * adjoints of each variable in ascending slot order into grad and reduces the
- * objective partials into obj (either may be NULL). */
+ * literal adjoints, and per-tile objective partials when want_obj != 0; fe as in
+ * afs_eval, for the constraints of those buckets); afs_scatter sums the adjoints
+ * of each variable in ascending slot order into grad and reduces the objective
+ * partials into obj (either may be NULL; obj needs every bucket evaluated with
+ * want_obj != 0). */
 afs_status afs_fe_grad(afs_instance *inst, int32_t B, const float *x, void *ws, size_t ws_bytes,
-                       int32_t bucket_lo, int32_t bucket_hi, float *fe, void *stream);
+                       int32_t bucket_lo, int32_t bucket_hi, int32_t want_obj, float *fe,
+                       void *stream);
 afs_status afs_scatter(afs_instance *inst, int32_t B, void *ws, size_t ws_bytes,
                        float *obj, float *grad, void *stream);
 

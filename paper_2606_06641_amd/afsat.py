@@ -46,6 +46,11 @@ class _BucketInfo(ctypes.Structure):
                 ("lits_per_lane", ctypes.c_int32), ("slot0", ctypes.c_int64)]
 
 
+class _Options(ctypes.Structure):
+    _fields_ = [("n_shapes", ctypes.c_int32), ("shape_k_hi", _i32p), ("shape_lanes", _i32p),
+                ("shape_seg", _i32p), ("tile_short", ctypes.c_int32), ("tile_long", ctypes.c_int32)]
+
+
 class _PgdState(ctypes.Structure):
     _fields_ = [("unsat", _vp), ("done", _vp), ("first_sat", _vp), ("counter", _vp)]
 
@@ -57,6 +62,8 @@ SIGNATURES = [
     ("afs_coefficients", ctypes.c_int, [_i32, _i32, _i32, _f64p, _f64p]),
     ("afs_instance_create", ctypes.c_int, [_i32, _i32, _i64p, _i32p, _i32p, _i32p, _f32p, _i32,
                                            ctypes.POINTER(_vp)]),
+    ("afs_instance_create_ex", ctypes.c_int, [_i32, _i32, _i64p, _i32p, _i32p, _i32p, _f32p,
+                                              ctypes.POINTER(_Options), _i32, ctypes.POINTER(_vp)]),
     ("afs_instance_destroy", None, [_vp]),
     ("afs_instance_info", ctypes.c_int, [_vp, ctypes.POINTER(_Info)]),
     ("afs_bucket_info_get", ctypes.c_int, [_vp, _i32, ctypes.POINTER(_BucketInfo)]),
@@ -64,7 +71,7 @@ SIGNATURES = [
     ("afs_instance_transpose", ctypes.c_int, [_vp, _i64p, _i64p]),
     ("afs_workspace_bytes", ctypes.c_int, [_vp, _i32, ctypes.POINTER(ctypes.c_size_t)]),
     ("afs_eval", ctypes.c_int, [_vp, _i32, _vp, _vp, ctypes.c_size_t, _vp, _vp, _vp, _vp, _vp]),
-    ("afs_fe_grad", ctypes.c_int, [_vp, _i32, _vp, _vp, ctypes.c_size_t, _i32, _i32, _vp, _vp]),
+    ("afs_fe_grad", ctypes.c_int, [_vp, _i32, _vp, _vp, ctypes.c_size_t, _i32, _i32, _i32, _vp, _vp]),
     ("afs_scatter", ctypes.c_int, [_vp, _i32, _vp, ctypes.c_size_t, _vp, _vp, _vp]),
     ("afs_step", ctypes.c_int, [_vp, _i32, _vp, _vp, ctypes.c_float, _vp, _vp, _vp]),
     ("afs_round_verify", ctypes.c_int, [_vp, _i32, _vp, _vp, _vp, ctypes.c_size_t, _vp, _vp, _vp]),
@@ -134,16 +141,27 @@ class Instance:
     ``device`` is a CUDA/HIP device ordinal, or -1 for a host-only instance
     (tables and layout can be inspected; device calls raise)."""
 
-    def __init__(self, n, con_off, lits, types, params=None, weights=None, device=0):
+    def __init__(self, n, con_off, lits, types, params=None, weights=None, device=0,
+                 shapes=None, tile_short=0, tile_long=0):
+        """``shapes``: optional [(k_hi, lanes, seg), ...] kernel shapes for lengths > 16
+        (ascending k_hi), as chosen by the autotuner."""
         con_off = np.ascontiguousarray(con_off, dtype=np.int64)
         lits = np.ascontiguousarray(lits, dtype=np.int32)
         types = np.ascontiguousarray(types, dtype=np.int32)
         params = None if params is None else np.ascontiguousarray(params, dtype=np.int32)
         weights = None if weights is None else np.ascontiguousarray(weights, dtype=np.float32)
+        shapes = list(shapes or [])
+        kh = np.array([s[0] for s in shapes], dtype=np.int32)
+        ln = np.array([s[1] for s in shapes], dtype=np.int32)
+        sg = np.array([s[2] for s in shapes], dtype=np.int32)
+        opts = _Options(len(shapes), _np_ptr(kh, _i32p), _np_ptr(ln, _i32p), _np_ptr(sg, _i32p),
+                        int(tile_short), int(tile_long))
         h = ctypes.c_void_p()
-        _check(lib().afs_instance_create(int(n), len(types), _np_ptr(con_off, _i64p), _np_ptr(lits, _i32p),
-                                         _np_ptr(types, _i32p), _np_ptr(params, _i32p),
-                                         _np_ptr(weights, _f32p), int(device), ctypes.byref(h)))
+        _check(lib().afs_instance_create_ex(int(n), len(types), _np_ptr(con_off, _i64p), _np_ptr(lits, _i32p),
+                                            _np_ptr(types, _i32p), _np_ptr(params, _i32p),
+                                            _np_ptr(weights, _f32p), ctypes.byref(opts), int(device),
+                                            ctypes.byref(h)))
+        self.shapes = shapes
         self._h = h
         info = _Info()
         _check(lib().afs_instance_info(h, ctypes.byref(info)))
@@ -157,10 +175,10 @@ class Instance:
         self._ws = {}
 
     @classmethod
-    def from_arrays(cls, inst, device=0):
+    def from_arrays(cls, inst, device=0, **kw):
         """From any object with ``n, con_off, lits, types, params, weights``."""
         return cls(inst.n, inst.con_off, inst.lits, inst.types, getattr(inst, "params", None),
-                   getattr(inst, "weights", None), device=device)
+                   getattr(inst, "weights", None), device=device, **kw)
 
     def close(self):
         if getattr(self, "_h", None):
@@ -240,11 +258,11 @@ class Instance:
                               _stream(dev)))
         return out
 
-    def fe_grad(self, x, ws, bucket_lo=0, bucket_hi=None, fe=None):
+    def fe_grad(self, x, ws, bucket_lo=0, bucket_hi=None, want_obj=False, fe=None):
         B = self._check_x(x)
         hi = self.n_buckets if bucket_hi is None else bucket_hi
         _check(lib().afs_fe_grad(self._h, B, _ptr(x), _ptr(ws), ws.numel(), int(bucket_lo), int(hi),
-                                 _ptr(fe), _stream(self._dev())))
+                                 int(bool(want_obj)), _ptr(fe), _stream(self._dev())))
 
     def scatter(self, B, ws, obj=None, grad=None):
         _check(lib().afs_scatter(self._h, int(B), _ptr(ws), ws.numel(), _ptr(obj), _ptr(grad),

@@ -157,13 +157,34 @@ afs_status afs_instance_create(int32_t n_vars, int32_t n_cons, const int64_t *co
                                const int32_t *lits, const int32_t *types, const int32_t *params,
                                const float *weights, int32_t device, afs_instance **out)
 {
+    return afs_instance_create_ex(n_vars, n_cons, con_off, lits, types, params, weights, nullptr,
+                                  device, out);
+}
+
+afs_status afs_instance_create_ex(int32_t n_vars, int32_t n_cons, const int64_t *con_off,
+                                  const int32_t *lits, const int32_t *types, const int32_t *params,
+                                  const float *weights, const afs_options *opts, int32_t device,
+                                  afs_instance **out)
+{
     if (!out) return fail(AFS_EINVAL, "out is NULL");
     *out = nullptr;
+    afs::PackOptions po;
+    if (opts) {
+        if (opts->n_shapes < 0 || (opts->n_shapes > 0 && (!opts->shape_k_hi || !opts->shape_lanes || !opts->shape_seg)))
+            return fail(AFS_EINVAL, "invalid shape arrays");
+        for (int32_t e = 0; e < opts->n_shapes; ++e) {
+            po.k_hi.push_back(opts->shape_k_hi[e]);
+            po.lanes.push_back(opts->shape_lanes[e]);
+            po.seg.push_back(opts->shape_seg[e]);
+        }
+        po.tile_short = opts->tile_short;
+        po.tile_long = opts->tile_long;
+    }
     afs_instance *I = new (std::nothrow) afs_instance();
     if (!I) return fail(AFS_ENOMEM, "host allocation failed");
     std::string err;
     try {
-        err = afs::build_instance(n_vars, n_cons, con_off, lits, types, params, weights, I->H);
+        err = afs::build_instance(n_vars, n_cons, con_off, lits, types, params, weights, po, I->H);
     } catch (const std::bad_alloc &) {
         delete I;
         return fail(AFS_ENOMEM, "host allocation failed");
@@ -275,7 +296,8 @@ afs_status afs_workspace_bytes(const afs_instance *I, int32_t B, size_t *bytes)
 }
 
 afs_status afs_fe_grad(afs_instance *I, int32_t B, const float *x, void *ws, size_t ws_bytes,
-                       int32_t bucket_lo, int32_t bucket_hi, float *fe, void *stream)
+                       int32_t bucket_lo, int32_t bucket_hi, int32_t want_obj, float *fe,
+                       void *stream)
 {
     afs_status st = check_call(I, B);
     if (st != AFS_OK) return st;
@@ -286,7 +308,7 @@ afs_status afs_fe_grad(afs_instance *I, int32_t B, const float *x, void *ws, siz
     if (!x && B > 0) return fail(AFS_EINVAL, "x is NULL");
     DeviceGuard g(I->device);
     if (g.error() != hipSuccess) return dev_fail(g.error(), "hipSetDevice");
-    return fe_grad_range(I, B, x, ws, l, bucket_lo, bucket_hi, true, fe, (hipStream_t)stream);
+    return fe_grad_range(I, B, x, ws, l, bucket_lo, bucket_hi, want_obj != 0, fe, (hipStream_t)stream);
 }
 
 afs_status afs_scatter(afs_instance *I, int32_t B, void *ws, size_t ws_bytes, float *obj,

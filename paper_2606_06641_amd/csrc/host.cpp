@@ -83,20 +83,112 @@ void coefficients(int type, int k, int param, double *re, double *im)
 void bucket_shape(int k, int &J, int &S)
 {
     if (k <= kShortMax) { J = 1; S = k; return; }
-    // smallest capacity J*S >= k with S in {12, 16} and J a power of two
-    for (J = 2; J <= 64; J *= 2) {
-        if (J * 12 >= k) { S = 12; return; }
-        if (J * 16 >= k) { S = 16; return; }
-    }
+    // Cheapest (J, S) with J*S >= k by a simple instruction model: per lane and root,
+    // 8 VALU instructions per literal slot plus the two cross-lane scans; per useful
+    // literal that is J * (8 S + scan(J)) / k.
+    double best = 1e30;
     J = 64; S = 16;
+    for (int j = 2; j <= 64; j *= 2) {
+        int lg = 0;
+        while ((1 << lg) < j) ++lg;
+        const double scan = 14.0 * lg + 30.0 + (j > 16 ? 40.0 : 0.0);
+        for (int s = 8; s <= kMaxSeg; s += 8) {
+            if (j * s < k) continue;
+            const double cost = j * (8.0 * s + scan) / k;
+            if (cost < best - 1e-9) { best = cost; J = j; S = s; }
+        }
+    }
 }
 
-static int tile_for(int J) { return J == 1 ? 16 : std::max(1, 16 / J); }
+// Rows m = 1..floor(k/2) of a coefficient table (two float4 rows per root).
+// With alpha_m = (1 + omega^m)/2 = c e^{i h} (h = pi m / N, c = cos h) every factor is
+// a = alpha_m (1 + i z), z = -tan(h) y.  Kernels multiply the unit-real-part
+// factors (1 + i z) and restore the alpha powers with a rescale by alpha^8 after
+// every 8 literals, so the stored prefix at literal s lacks alpha^(s mod 8) and
+// the stored suffix alpha^(C - s mod 8); their product lacks alpha^C for every s,
+// and the constant
+//     Kc = 2 d_m beta_m alpha^C,  beta_m = (1 - omega^m)/2,
+// turns prefix * suffix into the adjoint term.  The FE term uses dF = d_m alpha^F
+// where F is the number of unscaled factors left in the final product.
+//   row A: {Re dF, Im dF, Re Kc, Im Kc}     row B: {Re alpha^8, Im alpha^8, -tan h, 0}
+// Short kernels (one lane per restart, k <= 16): C = k-1-8[k>8], F = k-8[k>8].
+// Segment kernels (S a multiple of 8): C = 7, F = 0 (they rescale the segment
+// product by alpha^8 themselves).
+void append_root_rows(int k, const double *re, const double *im, std::vector<TabRow> &tab)
+{
+    const int N = k + 1;
+    const int M = k / 2;
+    const bool shrt = k <= kShortMax;
+    const int Cpow = shrt ? k - 1 - (k > 8 ? 8 : 0) : 7;
+    const int Fpow = shrt ? k - (k > 8 ? 8 : 0) : 0;
+    const long double pi = 3.141592653589793238462643383279502884L;
+    // alpha^n = c^n e^{i n h}; the angle n*h = pi (m n mod 2N) / N is reduced exactly.
+    auto alpha_pow = [&](int m, int n, long double &ar, long double &ai) {
+        const long double c = cosl(pi * (long double)m / (long double)N);
+        const long double mag = powl(c, (long double)n);
+        const long double ang = pi * (long double)(((int64_t)m * n) % (2 * N)) / (long double)N;
+        ar = mag * cosl(ang);
+        ai = mag * sinl(ang);
+    };
+    for (int m = 1; m <= M; ++m) {
+        const long double h = pi * (long double)m / (long double)N;
+        const long double sh = sinl(h), ch = cosl(h);
+        // beta = (1 - omega)/2 = -i sin(h) e^{i h} = (sin^2 h, -sin h cos h)
+        const long double br = sh * sh, bi = -sh * ch;
+        long double cr, ci, fr, fi, a8r, a8i;
+        alpha_pow(m, Cpow, cr, ci);
+        alpha_pow(m, Fpow, fr, fi);
+        alpha_pow(m, 8, a8r, a8i);
+        const long double dr = re[m], di = im[m];
+        // Kc = 2 d beta alpha^C
+        const long double tr = dr * br - di * bi, ti = dr * bi + di * br;
+        const long double kr = 2.0L * (tr * cr - ti * ci), ki = 2.0L * (tr * ci + ti * cr);
+        const long double dfr = dr * fr - di * fi, dfi = dr * fi + di * fr;
+        tab.push_back({(float)dfr, (float)dfi, (float)kr, (float)ki});
+        tab.push_back({(float)a8r, (float)a8i, (float)(-sh / ch), 0.0f});
+    }
+}
+
+void bucket_shape(int k, const PackOptions &o, int &J, int &S)
+{
+    if (k > kShortMax) {
+        for (size_t e = 0; e < o.k_hi.size(); ++e)
+            if (k <= o.k_hi[e]) { J = o.lanes[e]; S = o.seg[e]; return; }
+    }
+    bucket_shape(k, J, S);
+}
+
+std::string check_options(const PackOptions &o)
+{
+    if (o.k_hi.size() != o.lanes.size() || o.k_hi.size() != o.seg.size()) return "shape arrays differ in length";
+    int prev = kShortMax;
+    for (size_t e = 0; e < o.k_hi.size(); ++e) {
+        const int J = o.lanes[e], S = o.seg[e], kh = o.k_hi[e];
+        if (kh <= prev) return "shape_k_hi must be ascending and > 16";
+        if (kh > kMaxLen) return "shape_k_hi exceeds the maximum length";
+        if (J < 2 || J > 64 || (J & (J - 1))) return "shape_lanes must be 2, 4, 8, 16, 32 or 64";
+        if (S < 8 || S > kMaxSeg || S % 8) return "shape_seg must be 8, 16, 24 or 32";
+        if (J * S < kh) return "shape_lanes * shape_seg is smaller than shape_k_hi";
+        prev = kh;
+    }
+    if (o.tile_short < 0 || o.tile_long < 0 || o.tile_short > 4096 || o.tile_long > 4096) return "tile out of range";
+    return std::string();
+}
+
+static int tile_for(int J, const PackOptions &o)
+{
+    if (J == 1) return o.tile_short > 0 ? o.tile_short : 16;
+    return o.tile_long > 0 ? o.tile_long : std::max(1, 16 / J);
+}
 
 std::string build_instance(int32_t n, int32_t C, const int64_t *con_off, const int32_t *lits,
                            const int32_t *types, const int32_t *params, const float *weights,
-                           HostInstance &H)
+                           const PackOptions &opts, HostInstance &H)
 {
+    {
+        const std::string e = check_options(opts);
+        if (!e.empty()) return e;
+    }
     if (n < 1) return "n_vars must be >= 1";
     if (C < 0) return "n_cons must be >= 0";
     if (!con_off) return "con_off is NULL";
@@ -150,17 +242,9 @@ std::string build_instance(int32_t n, int32_t C, const int64_t *con_off, const i
         im.assign(k + 1, 0.0);
         coefficients(types[c], k, p, re.data(), im.data());
         const int N = k + 1;
-        const int M = k / 2;
         const double dhalf = (N % 2 == 0) ? re[N / 2] : 0.0;
         H.tab.push_back({(float)re[0], (float)dhalf, 0.0f, 0.0f});
-        const long double pi = 3.141592653589793238462643383279502884L;
-        for (int m = 1; m <= M; ++m) {
-            const long double half = pi * (long double)m / (long double)N;
-            const long double sh = sinl(half);
-            const long double cm1 = -2.0L * sh * sh;                    // cos(theta) - 1
-            const long double sn = 2.0L * sh * cosl(half);              // sin(theta)
-            H.tab.push_back({(float)re[m], (float)im[m], (float)cm1, (float)sn});
-        }
+        append_root_rows(k, re.data(), im.data(), H.tab);
         ++H.n_tables;
     }
 
@@ -170,12 +254,16 @@ std::string build_instance(int32_t n, int32_t C, const int64_t *con_off, const i
     auto klen = [&](int32_t c) { return (int)(con_off[c + 1] - con_off[c]); };
     auto shape_key = [&](int32_t c) {
         int J, S;
-        bucket_shape(klen(c), J, S);
-        return std::make_pair(J, J == 1 ? klen(c) : J * S);
+        bucket_shape(klen(c), opts, J, S);
+        return std::make_pair(J, J == 1 ? klen(c) : S);
     };
     std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
         const auto ka = shape_key(a), kb = shape_key(b);
-        if (ka != kb) return ka.second != kb.second ? ka.second < kb.second : ka.first < kb.first;
+        if (ka != kb) {
+            const int ca = ka.first == 1 ? ka.second : ka.first * ka.second + 1000;
+            const int cb = kb.first == 1 ? kb.second : kb.first * kb.second + 1000;
+            return ca != cb ? ca < cb : ka.first < kb.first;
+        }
         if (klen(a) != klen(b)) return klen(a) < klen(b);
         return con_tab[a] < con_tab[b];
     });
@@ -187,7 +275,7 @@ std::string build_instance(int32_t n, int32_t C, const int64_t *con_off, const i
     for (int32_t i = 0; i < C;) {
         const auto key = shape_key(order[i]);
         Bucket bk;
-        bucket_shape(klen(order[i]), bk.J, bk.S);
+        bucket_shape(klen(order[i]), opts, bk.J, bk.S);
         bk.c0 = i;
         bk.slot0 = slot;
         bk.k_lo = klen(order[i]);
@@ -210,7 +298,7 @@ std::string build_instance(int32_t n, int32_t C, const int64_t *con_off, const i
         }
         bk.nc = j - i;
         bk.nslots = slot - bk.slot0;
-        bk.tile = tile_for(bk.J);
+        bk.tile = tile_for(bk.J, opts);
         bk.ntiles = (bk.nc + bk.tile - 1) / bk.tile;
         bk.tile0 = tiles;
         tiles += bk.ntiles;

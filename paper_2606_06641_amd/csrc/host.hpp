@@ -12,18 +12,23 @@
 
 namespace afs {
 
-// Largest constraint length the kernels handle (64 lanes x 16 literals).
+// Largest constraint length the kernels handle.
 constexpr int kMaxLen = 1024;
 // Lengths up to this use one lane per restart with the whole constraint in registers.
 constexpr int kShortMax = 16;
+// Largest number of literals one lane holds in the segment kernels.
+constexpr int kMaxSeg = 32;
 
 // One row of a coefficient table, consumed by the kernels as a float4.
-//   row 0      : {d_0, d_half, 0, 0}   (d_half = d_{N/2} when N = k+1 is even, else 0)
-//   row m >= 1 : {Re d_m, Im d_m, cos(theta_m) - 1, sin(theta_m)}, theta_m = 2 pi m / N,
-//                for m = 1 .. floor((N-1)/2)   (the complex roots of one conjugate pair)
+//   row 0                : {d_0, d_half, 0, 0}  (d_half = d_{N/2} when N = k+1 is even, else 0)
+//   rows 2m-1, 2m (m>=1) : the complex root omega^m, see append_root_rows
 struct TabRow {
     float x, y, z, w;
 };
+
+// Append the two rows of each complex root m = 1..floor(k/2) of a table whose
+// coefficient vector is (re, im) (length k+1).
+void append_root_rows(int k, const double *re, const double *im, std::vector<TabRow> &tab);
 
 struct Bucket {
     int k_lo = 0, k_hi = 0;
@@ -73,12 +78,24 @@ int satisfied(int type, int k, int param, int t);
 // mirrored conjugates of N - j, so conjugate symmetry is exact.
 void coefficients(int type, int k, int param, double *re, double *im);
 
+// Packing choices (see afs_options in afsat.h).
+struct PackOptions {
+    std::vector<int> k_hi, lanes, seg;   // shape overrides for k > kShortMax, ascending k_hi
+    int tile_short = 0, tile_long = 0;   // 0: defaults
+};
+
+// Validate options; returns an empty string or a message.
+std::string check_options(const PackOptions &o);
+
 // Build the packed instance.  Returns an empty string on success, else a message.
 std::string build_instance(int32_t n, int32_t C, const int64_t *con_off, const int32_t *lits,
                            const int32_t *types, const int32_t *params, const float *weights,
-                           HostInstance &out);
+                           const PackOptions &opts, HostInstance &out);
 
-// Bucket shape (J lanes per restart, S literals per lane) for a length k.
+// Default bucket shape (J lanes per restart, S literals per lane) for a length k.
 void bucket_shape(int k, int &J, int &S);
+
+// Shape for a length k under the options (overrides, else the default).
+void bucket_shape(int k, const PackOptions &o, int &J, int &S);
 
 }  // namespace afs

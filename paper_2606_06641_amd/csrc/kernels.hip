@@ -3,17 +3,15 @@
 // Evaluation of a symmetric constraint of length k at a real point (Sec. 2.1.2).
 // With p_i = (1 - y_i)/2 the probability that literal i is true, the generating
 // function of the number of true literals is prod_i ((1-p_i) + p_i z); its values
-// at the N = k+1 roots of unity z = omega^m are
-//     G_m = prod_i a_{i,m},   a_{i,m} = 1 + p_i (cos th_m - 1) + i p_i sin th_m,
-// and FE = sum_m d_m G_m with d = inverse DFT of the truth table.  Every |a| <= 1,
-// so no product can overflow at any length.  Because d and G are conjugate
-// symmetric and G_0 = 1,
+// at the N = k+1 roots of unity z = omega^m are G_m = prod_i a_{i,m}, and
+// FE = sum_m d_m G_m with d = inverse DFT of the truth table.  Because d and G are
+// conjugate symmetric and G_0 = 1,
 //     FE = d_0 + 2 sum_{m=1..M} Re(d_m G_m) + [k odd] d_{N/2} prod_i y_i,  M = floor(k/2).
 // The gradient is taken by prefix and suffix products (no division):
 //     dFE/dy_i = 2 sum_m Re(d_m beta_m prod_{l != i} a_{l,m}) + [k odd] d_{N/2} prod_{l != i} y_l
-// with beta_m = (1 - omega^m)/2 = da/dy.  The kernels run the prefix chain
-// U = d_m prod_{l<i} a_l and the suffix chain S = w (1 - omega^m) prod_{l>i} a_l,
-// so adj_i = sign_i * sum_m Re(U_i S_i) needs two FMAs per root and literal.
+// with beta_m = (1 - omega^m)/2 = da/dy.  Every true factor has |a| <= 1, so the
+// true products cannot overflow at any length; the kernels carry them in the
+// rotated form described above mul_unit.
 //
 // Layouts: x [n][B] f32 (restart contiguous); adj [L][Bp] f32 in slot order with
 // Bp = B rounded up to 64; constraint and literal metadata are wave-uniform and
@@ -67,11 +65,28 @@ struct FeArgs {
 };
 
 // ---------------------------------------------------------------------------
+// Factor form shared by the FE kernels.  With h = pi m / N, c = cos h and
+// alpha = (1 + omega^m)/2 = c e^{i h}, the factor of a literal with value y is
+//     a = (1-p) + p omega^m = alpha (1 + i z),   z = -tan(h) y,
+// so one step of a product chain multiplies by (1 + i z): two FMAs.  Since
+// |1 + i z| <= 1/c, the running products are multiplied by alpha^8 after every
+// 8 literals, and the remaining constant alpha powers are folded into the table
+// (host.cpp, append_root_rows).  Padding literals hold y = +1, whose factor
+// alpha (1 - i tan h) is exactly 1.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void mul_unit(float &r, float &i, float z)
+{
+    const float nr = fmaf(-i, z, r);
+    i = fmaf(r, z, i);
+    r = nr;
+}
+
+// ---------------------------------------------------------------------------
 // Short constraints (k <= 16): one lane per restart, k known at compile time, the
 // whole constraint in registers.  A wave takes 64 restarts and a tile of
 // constraints of the bucket.
 // ---------------------------------------------------------------------------
-template <int K, bool PART, bool FE>
+template <int K>
 __global__ __launch_bounds__(kBlock) void fe_grad_short(FeArgs A)
 {
     const int64_t item = xcd_block() * kWavesPerBlock + wave_id();
@@ -90,17 +105,13 @@ __global__ __launch_bounds__(kBlock) void fe_grad_short(FeArgs A)
         const int tab = A.bc_tab[c];
         const float w = A.bc_w[c];
         int lit[K];
-        float y[K], p[K], adj[K];
+        float y[K], adj[K];
 #pragma unroll
         for (int i = 0; i < K; ++i) {
             lit[i] = A.slot_lit[slot0 + i];
             const int v = (lit[i] > 0 ? lit[i] : -lit[i]) - 1;
             const float xv = A.x[(int64_t)v * A.B + bl];
             y[i] = lit[i] > 0 ? xv : -xv;
-        }
-#pragma unroll
-        for (int i = 0; i < K; ++i) {
-            p[i] = fmaf(-0.5f, y[i], 0.5f);
             adj[i] = 0.f;
         }
         const float4 r0 = A.tab[tab];
@@ -108,27 +119,29 @@ __global__ __launch_bounds__(kBlock) void fe_grad_short(FeArgs A)
         // Roots one at a time (unrolling them multiplies register use by K/2).
 #pragma unroll 1
         for (int m = 1; m <= K / 2; ++m) {
-            const float4 r = A.tab[tab + m];
-            float ar[K], ai[K], pr[K], pi[K];
+            const float4 ra = A.tab[tab + 2 * m - 1];   // {dF, Kc}
+            const float4 rb = A.tab[tab + 2 * m];       // {alpha^8, -tan h}
+            float z[K], pr[K], pi[K];
+#pragma unroll
+            for (int i = 0; i < K; ++i) z[i] = rb.z * y[i];
+            float ur = 1.0f, ui = 0.0f;
 #pragma unroll
             for (int i = 0; i < K; ++i) {
-                ar[i] = fmaf(p[i], r.z, 1.0f);
-                ai[i] = p[i] * r.w;
-            }
-            float ur = r.x, ui = r.y;
-#pragma unroll
-            for (int i = 0; i < K; ++i) {
+                if (i > 0 && i % 8 == 0) cmul(ur, ui, rb.x, rb.y);
                 pr[i] = ur;
                 pi[i] = ui;
-                cmul(ur, ui, ar[i], ai[i]);
+                mul_unit(ur, ui, z[i]);
             }
-            fe = fmaf(2.0f, ur, fe);
-            float sr = -w * r.z, si = -w * r.w;
+            fe = fmaf(2.0f, ra.x * ur - ra.y * ui, fe);
+            float sr = w * ra.z, si = w * ra.w;
 #pragma unroll
             for (int i = K - 1; i >= 0; --i) {
                 adj[i] = fmaf(pr[i], sr, adj[i]);
                 adj[i] = fmaf(-pi[i], si, adj[i]);
-                if (i > 0) cmul(sr, si, ar[i], ai[i]);
+                if (i > 0) {
+                    mul_unit(sr, si, z[i]);
+                    if (i % 8 == 0) cmul(sr, si, rb.x, rb.y);
+                }
             }
         }
         if (K & 1) {                       // real root omega^(N/2) = -1: factor y_i
@@ -151,65 +164,178 @@ __global__ __launch_bounds__(kBlock) void fe_grad_short(FeArgs A)
 #pragma unroll
             for (int i = 0; i < K; ++i)
                 A.adj[(int64_t)(slot0 + i) * A.Bp + b] = lit[i] > 0 ? adj[i] : -adj[i];
-            if (FE) A.fe[(int64_t)A.bc_orig[c] * A.B + b] = fe;
+            if (A.fe) A.fe[(int64_t)A.bc_orig[c] * A.B + b] = fe;
         }
         objacc = fmaf(w, fe, objacc);
     }
-    if (PART) A.part[(int64_t)(A.tile0 + tile) * A.Bp + b] = objacc;
+    if (A.part) A.part[(int64_t)(A.tile0 + tile) * A.Bp + b] = objacc;
+}
+
+// ---------------------------------------------------------------------------
+// Cross-lane products over the J lanes that share one restart.
+// Inside a 16-lane row the shifts are DPP row shifts whose out-of-row lanes read
+// the identity; groups of 32 or 64 lanes then take the neighbouring rows' totals.
+// ---------------------------------------------------------------------------
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float old, float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
+constexpr int kRowShr = 0x110;   // row_shr:n = 0x110 + n
+constexpr int kRowShl = 0x100;   // row_shl:n = 0x100 + n
+
+// value of lane j-D of the group (identity below j = D), complex or real
+template <int J, int D>
+__device__ __forceinline__ float from_below(float v, float ident, int j)
+{
+    float t = dpp_mov<kRowShr + D>(ident, v);
+    if constexpr (J < 16) t = (j >= D) ? t : ident;
+    return t;
+}
+
+template <int J, int D>
+__device__ __forceinline__ float from_above(float v, float ident, int j)
+{
+    float t = dpp_mov<kRowShl + D>(ident, v);
+    if constexpr (J < 16) t = (j + D < J) ? t : ident;
+    return t;
+}
+
+template <int J, int D = 1>
+__device__ __forceinline__ void scan_up_rows(float &r, float &i, int j)
+{
+    if constexpr (D < J && D < 16) {
+        const float tr = from_below<J, D>(r, 1.0f, j), ti = from_below<J, D>(i, 0.0f, j);
+        cmul(r, i, tr, ti);
+        scan_up_rows<J, 2 * D>(r, i, j);
+    }
+}
+
+template <int J, int D = 1>
+__device__ __forceinline__ void scan_down_rows(float &r, float &i, int j)
+{
+    if constexpr (D < J && D < 16) {
+        const float tr = from_above<J, D>(r, 1.0f, j), ti = from_above<J, D>(i, 0.0f, j);
+        cmul(r, i, tr, ti);
+        scan_down_rows<J, 2 * D>(r, i, j);
+    }
+}
+
+// inclusive prefix product: afterwards lane j holds prod_{l <= j}
+template <int J>
+__device__ __forceinline__ void scan_prefix(float &r, float &i, int lane, int j)
+{
+    scan_up_rows<J>(r, i, j);
+    if constexpr (J >= 32) {                 // odd rows take the total of the row below
+        const int src = ((lane | 15) - 16) & 63;
+        float tr = __shfl(r, src), ti = __shfl(i, src);
+        if (!(lane & 16)) { tr = 1.0f; ti = 0.0f; }
+        cmul(r, i, tr, ti);
+    }
+    if constexpr (J == 64) {                 // rows 2-3 take the total of rows 0-1
+        float tr = __shfl(r, 31), ti = __shfl(i, 31);
+        if (!(lane & 32)) { tr = 1.0f; ti = 0.0f; }
+        cmul(r, i, tr, ti);
+    }
+}
+
+// inclusive suffix product: afterwards lane j holds prod_{l >= j}
+template <int J>
+__device__ __forceinline__ void scan_suffix(float &r, float &i, int lane, int j)
+{
+    scan_down_rows<J>(r, i, j);
+    if constexpr (J >= 32) {                 // even rows take the total of the row above
+        const int src = ((lane & ~15) + 16) & 63;
+        float tr = __shfl(r, src), ti = __shfl(i, src);
+        if (lane & 16) { tr = 1.0f; ti = 0.0f; }
+        cmul(r, i, tr, ti);
+    }
+    if constexpr (J == 64) {                 // rows 0-1 take the total of rows 2-3
+        float tr = __shfl(r, 32), ti = __shfl(i, 32);
+        if (lane & 32) { tr = 1.0f; ti = 0.0f; }
+        cmul(r, i, tr, ti);
+    }
+}
+
+// inclusive -> exclusive (value of lane j-1, identity at j = 0)
+template <int J>
+__device__ __forceinline__ float prev_lane(float v, float ident, int j)
+{
+    float t;
+    if constexpr (J <= 16) t = dpp_mov<kRowShr + 1>(ident, v);
+    else t = __shfl_up(v, 1, J);
+    return j == 0 ? ident : t;
+}
+
+template <int J>
+__device__ __forceinline__ float next_lane(float v, float ident, int j)
+{
+    float t;
+    if constexpr (J <= 16) t = dpp_mov<kRowShl + 1>(ident, v);
+    else t = __shfl_down(v, 1, J);
+    return j == J - 1 ? ident : t;
+}
+
+// Real-valued versions for the root omega^(N/2) = -1 (factor y).
+template <int J, int D = 1>
+__device__ __forceinline__ void scan_up_rows_real(float &r, int j)
+{
+    if constexpr (D < J && D < 16) {
+        r *= from_below<J, D>(r, 1.0f, j);
+        scan_up_rows_real<J, 2 * D>(r, j);
+    }
+}
+
+template <int J, int D = 1>
+__device__ __forceinline__ void scan_down_rows_real(float &r, int j)
+{
+    if constexpr (D < J && D < 16) {
+        r *= from_above<J, D>(r, 1.0f, j);
+        scan_down_rows_real<J, 2 * D>(r, j);
+    }
+}
+
+template <int J>
+__device__ __forceinline__ void scan_prefix_real(float &r, int lane, int j)
+{
+    scan_up_rows_real<J>(r, j);
+    if constexpr (J >= 32) {
+        const float t = __shfl(r, ((lane | 15) - 16) & 63);
+        if (lane & 16) r *= t;
+    }
+    if constexpr (J == 64) {
+        const float t = __shfl(r, 31);
+        if (lane & 32) r *= t;
+    }
+}
+
+template <int J>
+__device__ __forceinline__ void scan_suffix_real(float &r, int lane, int j)
+{
+    scan_down_rows_real<J>(r, j);
+    if constexpr (J >= 32) {
+        const float t = __shfl(r, ((lane & ~15) + 16) & 63);
+        if (!(lane & 16)) r *= t;
+    }
+    if constexpr (J == 64) {
+        const float t = __shfl(r, 32);
+        if (!(lane & 32)) r *= t;
+    }
 }
 
 // ---------------------------------------------------------------------------
 // Long constraints: J lanes per restart (64/J restarts per wave), lane j holding
-// literals [j*S, j*S + S).  Per root, each lane forms the product of its
-// segment; an exclusive prefix scan and an exclusive suffix scan across the J
-// lanes give the products of everything left and right of the segment, from
-// which the lane runs its own prefix and suffix chains.  Each literal's adjoint
-// is owned by exactly one lane: no cross-lane reduction, deterministic order.
-// Slots past the end of the constraint hold y = 1 (factor exactly 1).
+// literals [j*S, j*S + S), S a multiple of 8.  Per root, each lane runs its
+// local prefix chain (storing the prefixes) and forms its segment's product;
+// exclusive prefix and suffix products across the J lanes then seed the lane's
+// suffix chain, which accumulates the adjoint of each literal the lane owns:
+// no cross-lane reduction, deterministic order.
 // ---------------------------------------------------------------------------
-template <int J>
-__device__ __forceinline__ void scan_prefix(float &r, float &i, int j)
-{
-#pragma unroll
-    for (int d = 1; d < J; d <<= 1) {
-        const float tr = __shfl_up(r, d, J), ti = __shfl_up(i, d, J);
-        if (j >= d) cmul(r, i, tr, ti);
-    }
-}
-
-template <int J>
-__device__ __forceinline__ void scan_suffix(float &r, float &i, int j)
-{
-#pragma unroll
-    for (int d = 1; d < J; d <<= 1) {
-        const float tr = __shfl_down(r, d, J), ti = __shfl_down(i, d, J);
-        if (j + d < J) cmul(r, i, tr, ti);
-    }
-}
-
-template <int J>
-__device__ __forceinline__ void scan_prefix_real(float &r, int j)
-{
-#pragma unroll
-    for (int d = 1; d < J; d <<= 1) {
-        const float t = __shfl_up(r, d, J);
-        if (j >= d) r *= t;
-    }
-}
-
-template <int J>
-__device__ __forceinline__ void scan_suffix_real(float &r, int j)
-{
-#pragma unroll
-    for (int d = 1; d < J; d <<= 1) {
-        const float t = __shfl_down(r, d, J);
-        if (j + d < J) r *= t;
-    }
-}
-
-template <int J, int S, bool PART, bool FE>
+template <int J, int S>
 __global__ __launch_bounds__(kBlock) void fe_grad_seg(FeArgs A)
 {
+    static_assert(S % 8 == 0 && S <= 32, "segment length must be 8, 16, 24 or 32");
     constexpr int R = kWave / J;
     const int64_t item = xcd_block() * kWavesPerBlock + wave_id();
     if (item >= A.items) return;
@@ -230,11 +356,12 @@ __global__ __launch_bounds__(kBlock) void fe_grad_seg(FeArgs A)
         const int tab = A.bc_tab[c];
         const float w = A.bc_w[c];
         unsigned neg = 0;            // bit s: literal s of this lane is negated
-        float y[S], p[S], adj[S];
+        float y[S], adj[S];
 #pragma unroll
         for (int s = 0; s < S; ++s) {
             const int i = base + s;
             y[s] = 1.0f;
+            adj[s] = 0.f;
             if (i < k) {
                 const int lit = A.slot_lit[slot0 + i];
                 const int v = (lit > 0 ? lit : -lit) - 1;
@@ -243,53 +370,42 @@ __global__ __launch_bounds__(kBlock) void fe_grad_seg(FeArgs A)
                 neg |= (lit < 0 ? 1u : 0u) << s;
             }
         }
-#pragma unroll
-        for (int s = 0; s < S; ++s) {
-            p[s] = fmaf(-0.5f, y[s], 0.5f);
-            adj[s] = 0.f;
-        }
         const float4 r0 = A.tab[tab];
         float fe = r0.x;
         const int M = k >> 1;
         for (int m = 1; m <= M; ++m) {
-            const float4 rw = A.tab[tab + m];
-            float ar[S], ai[S], pr[S], pi[S];
+            const float4 ra = A.tab[tab + 2 * m - 1];   // {d, Kc}
+            const float4 rb = A.tab[tab + 2 * m];       // {alpha^8, -tan h}
+            float z[S], pr[S], pi[S];
+#pragma unroll
+            for (int s = 0; s < S; ++s) z[s] = rb.z * y[s];
+            float ur = 1.0f, ui = 0.0f;
 #pragma unroll
             for (int s = 0; s < S; ++s) {
-                ar[s] = fmaf(p[s], rw.z, 1.0f);
-                ai[s] = p[s] * rw.w;
-            }
-            float qr = ar[0], qi = ai[0];
-#pragma unroll
-            for (int s = 1; s < S; ++s) cmul(qr, qi, ar[s], ai[s]);
-            float er = qr, ei = qi;
-            scan_prefix<J>(er, ei, j);
-            float fr = qr, fi = qi;
-            scan_suffix<J>(fr, fi, j);
-            {   // inclusive -> exclusive
-                const float er1 = __shfl_up(er, 1, J), ei1 = __shfl_up(ei, 1, J);
-                const float fr1 = __shfl_down(fr, 1, J), fi1 = __shfl_down(fi, 1, J);
-                er = j == 0 ? 1.0f : er1;
-                ei = j == 0 ? 0.0f : ei1;
-                fr = j == J - 1 ? 1.0f : fr1;
-                fi = j == J - 1 ? 0.0f : fi1;
-            }
-            float ur = rw.x, ui = rw.y;
-            cmul(ur, ui, er, ei);
-#pragma unroll
-            for (int s = 0; s < S; ++s) {
+                if (s > 0 && s % 8 == 0) cmul(ur, ui, rb.x, rb.y);
                 pr[s] = ur;
                 pi[s] = ui;
-                cmul(ur, ui, ar[s], ai[s]);
+                mul_unit(ur, ui, z[s]);
             }
-            fe = fmaf(2.0f, ur, fe);
-            float sr = -w * rw.z, si = -w * rw.w;
-            cmul(sr, si, fr, fi);
+            cmul(ur, ui, rb.x, rb.y);                   // the segment's product
+            float er = ur, ei = ui;
+            scan_prefix<J>(er, ei, lane, j);
+            float fr = ur, fi = ui;
+            scan_suffix<J>(fr, fi, lane, j);
+            fe = fmaf(2.0f, ra.x * er - ra.y * ei, fe);  // lane J-1: d G
+            const float exr = prev_lane<J>(er, 1.0f, j), exi = prev_lane<J>(ei, 0.0f, j);
+            const float fxr = next_lane<J>(fr, 1.0f, j), fxi = next_lane<J>(fi, 0.0f, j);
+            float sr = w * ra.z, si = w * ra.w;
+            cmul(sr, si, exr, exi);
+            cmul(sr, si, fxr, fxi);
 #pragma unroll
             for (int s = S - 1; s >= 0; --s) {
                 adj[s] = fmaf(pr[s], sr, adj[s]);
                 adj[s] = fmaf(-pi[s], si, adj[s]);
-                if (s > 0) cmul(sr, si, ar[s], ai[s]);
+                if (s > 0) {
+                    mul_unit(sr, si, z[s]);
+                    if (s % 8 == 0) cmul(sr, si, rb.x, rb.y);
+                }
             }
         }
         if (k & 1) {
@@ -298,18 +414,17 @@ __global__ __launch_bounds__(kBlock) void fe_grad_seg(FeArgs A)
 #pragma unroll
             for (int s = 1; s < S; ++s) q *= y[s];
             float e = q, f = q;
-            scan_prefix_real<J>(e, j);
-            scan_suffix_real<J>(f, j);
-            const float e1 = __shfl_up(e, 1, J), f1 = __shfl_down(f, 1, J);
-            e = j == 0 ? 1.0f : e1;
-            f = j == J - 1 ? 1.0f : f1;
+            scan_prefix_real<J>(e, lane, j);
+            scan_suffix_real<J>(f, lane, j);
+            fe = fmaf(dh, e, fe);                       // lane J-1: product of all y
+            e = prev_lane<J>(e, 1.0f, j);
+            f = next_lane<J>(f, 1.0f, j);
             float hp[S], h = e;
 #pragma unroll
             for (int s = 0; s < S; ++s) {
                 hp[s] = h;
                 h *= y[s];
             }
-            fe = fmaf(dh, h, fe);
             float hs = w * dh * f;
 #pragma unroll
             for (int s = S - 1; s >= 0; --s) {
@@ -322,17 +437,16 @@ __global__ __launch_bounds__(kBlock) void fe_grad_seg(FeArgs A)
             for (int s = 0; s < S; ++s)
                 if (base + s < k)
                     A.adj[(int64_t)(slot0 + base + s) * A.Bp + b] = ((neg >> s) & 1u) ? -adj[s] : adj[s];
-            if (FE && j == J - 1) A.fe[(int64_t)A.bc_orig[c] * A.B + b] = fe;
+            if (A.fe && j == J - 1) A.fe[(int64_t)A.bc_orig[c] * A.B + b] = fe;
         }
         objacc = fmaf(w, fe, objacc);
     }
-    if (PART && j == J - 1) A.part[(int64_t)(A.tile0 + tile) * A.Bp + b] = objacc;
+    if (A.part && j == J - 1) A.part[(int64_t)(A.tile0 + tile) * A.Bp + b] = objacc;
 }
 
-template <bool PART, bool FE>
 hipError_t dispatch_short(int K, dim3 g, hipStream_t s, const FeArgs &a)
 {
-#define AFS_SHORT(KK) case KK: hipLaunchKernelGGL((fe_grad_short<KK, PART, FE>), g, dim3(kBlock), 0, s, a); break;
+#define AFS_SHORT(KK) case KK: hipLaunchKernelGGL((fe_grad_short<KK>), g, dim3(kBlock), 0, s, a); break;
     switch (K) {
         AFS_SHORT(1) AFS_SHORT(2) AFS_SHORT(3) AFS_SHORT(4) AFS_SHORT(5) AFS_SHORT(6)
         AFS_SHORT(7) AFS_SHORT(8) AFS_SHORT(9) AFS_SHORT(10) AFS_SHORT(11) AFS_SHORT(12)
@@ -343,14 +457,30 @@ hipError_t dispatch_short(int K, dim3 g, hipStream_t s, const FeArgs &a)
     return hipGetLastError();
 }
 
-template <bool PART, bool FE>
+template <int J>
+hipError_t dispatch_seg_s(int S, dim3 g, hipStream_t s, const FeArgs &a)
+{
+    switch (S) {
+    case 8: hipLaunchKernelGGL((fe_grad_seg<J, 8>), g, dim3(kBlock), 0, s, a); break;
+    case 16: hipLaunchKernelGGL((fe_grad_seg<J, 16>), g, dim3(kBlock), 0, s, a); break;
+    case 24: hipLaunchKernelGGL((fe_grad_seg<J, 24>), g, dim3(kBlock), 0, s, a); break;
+    case 32: hipLaunchKernelGGL((fe_grad_seg<J, 32>), g, dim3(kBlock), 0, s, a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 hipError_t dispatch_seg(int J, int S, dim3 g, hipStream_t s, const FeArgs &a)
 {
-#define AFS_SEG(JJ, SS) if (J == JJ && S == SS) { hipLaunchKernelGGL((fe_grad_seg<JJ, SS, PART, FE>), g, dim3(kBlock), 0, s, a); return hipGetLastError(); }
-    AFS_SEG(2, 12) AFS_SEG(2, 16) AFS_SEG(4, 12) AFS_SEG(4, 16) AFS_SEG(8, 12) AFS_SEG(8, 16)
-    AFS_SEG(16, 12) AFS_SEG(16, 16) AFS_SEG(32, 12) AFS_SEG(32, 16) AFS_SEG(64, 12) AFS_SEG(64, 16)
-#undef AFS_SEG
-    return hipErrorInvalidValue;
+    switch (J) {
+    case 2: return dispatch_seg_s<2>(S, g, s, a);
+    case 4: return dispatch_seg_s<4>(S, g, s, a);
+    case 8: return dispatch_seg_s<8>(S, g, s, a);
+    case 16: return dispatch_seg_s<16>(S, g, s, a);
+    case 32: return dispatch_seg_s<32>(S, g, s, a);
+    case 64: return dispatch_seg_s<64>(S, g, s, a);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -624,17 +754,7 @@ hipError_t launch_fe_grad(const DevInstance &I, const BucketLaunch &bk, int B, i
     const int64_t groups = (B + R - 1) / R;
     a.items = groups * bk.ntiles;
     const dim3 g = grid_for_waves(a.items);
-    const bool P = part != nullptr, F = fe != nullptr;
-    if (bk.J == 1) {
-        if (P && F) return dispatch_short<true, true>(bk.S, g, s, a);
-        if (P) return dispatch_short<true, false>(bk.S, g, s, a);
-        if (F) return dispatch_short<false, true>(bk.S, g, s, a);
-        return dispatch_short<false, false>(bk.S, g, s, a);
-    }
-    if (P && F) return dispatch_seg<true, true>(bk.J, bk.S, g, s, a);
-    if (P) return dispatch_seg<true, false>(bk.J, bk.S, g, s, a);
-    if (F) return dispatch_seg<false, true>(bk.J, bk.S, g, s, a);
-    return dispatch_seg<false, false>(bk.J, bk.S, g, s, a);
+    return bk.J == 1 ? dispatch_short(bk.S, g, s, a) : dispatch_seg(bk.J, bk.S, g, s, a);
 }
 
 static ScatterArgs scatter_args(const DevInstance &I, int B, int Bp, const float *adj)

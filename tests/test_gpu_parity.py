@@ -72,6 +72,42 @@ def test_long_every_bucket_shape():
     check(inst, x, "long k17-1024 B=70")
 
 
+@pytest.mark.parametrize("J", [2, 4, 8, 16, 32, 64])
+def test_every_segment_kernel_shape(J):
+    """Each (lanes J, literals per lane S) instantiation, forced through the shape
+    option, on lengths that fill it exactly, leave one lane short, and leave most
+    lanes padding."""
+    rng = np.random.default_rng(100 + J)
+    for S in (8, 16, 24, 32):
+        cap = J * S
+        if cap > 1024 or cap <= 16:
+            continue
+        ks = sorted({cap, max(17, cap - 5), max(17, cap // 2 + 1)})
+        parts = [W.random_instance(rng, n=1200, count=2, k_lo=k, k_hi=k) for k in ks]
+        inst = concat(parts, n=1200)
+        x = rng.uniform(-1, 1, size=(inst.n, 70)).astype(np.float32)
+        x[:, :3] = np.sign(x[:, :3]) * (1 - 1e-3)
+        log("case: forced shape J=%d S=%d lengths %s" % (J, S, ks))
+        d = afsat.Instance.from_arrays(inst, shapes=[(cap, J, S)])
+        assert all((b.lanes_per_restart, b.lits_per_lane) == (J, S) for b in d.buckets())
+        gpu = parity.gpu_eval(d, x)
+        orc = oracle.eval(inst, x, fe=True, adj=True, grad=True)
+        parity.compare(inst, d, gpu, orc, "J=%d S=%d" % (J, S))
+
+
+def test_autotuner_shapes_are_valid_and_exact():
+    from paper_2606_06641_amd import autotune
+    rng = np.random.default_rng(21)
+    inst = concat([W.random_instance(rng, n=800, count=6, k_lo=20, k_hi=150),
+                   W.random_instance(rng, n=800, count=50, k_lo=2, k_hi=8)], n=800)
+    shapes, report = autotune.tune(inst, 64, reps=2, log=log)
+    assert shapes and all(J * S >= kh for kh, J, S in shapes)
+    assert [s[0] for s in shapes] == sorted(s[0] for s in shapes)
+    x = rng.uniform(-1, 1, size=(inst.n, 64)).astype(np.float32)
+    d = afsat.Instance.from_arrays(inst, shapes=shapes)
+    parity.compare(inst, d, parity.gpu_eval(d, x), oracle.eval(inst, x, fe=True, adj=True, grad=True), "tuned")
+
+
 def test_adversarial_points():
     rng = np.random.default_rng(12)
     parts = [W.random_instance(rng, n=1200, count=60, k_lo=1, k_hi=16),

@@ -125,16 +125,36 @@ def test_packing_layout():
 
 
 def test_bucket_shapes_cover_lengths():
-    # long constraints: J lanes x S literals, S in {12, 16}, J a power of two, tightest fit
+    # long constraints: J lanes x S literals, S in {8, 16, 24, 32}, J a power of two
     rng = np.random.default_rng(1)
     for k in [17, 24, 25, 32, 33, 100, 129, 256, 257, 512, 1000, 1024]:
         inst = W.random_instance(rng, n=2000, count=1, k_lo=k, k_hi=k)
         (b,) = host_instance(inst).buckets()
         J, S = b.lanes_per_restart, b.lits_per_lane
-        assert J & (J - 1) == 0 and 2 <= J <= 64 and S in (12, 16)
+        assert J & (J - 1) == 0 and 2 <= J <= 64 and S in (8, 16, 24, 32)
         assert J * S >= k
-        caps = sorted(j * s for j in (2, 4, 8, 16, 32, 64) for s in (12, 16))
-        assert J * S == min(c for c in caps if c >= k)
+
+
+def test_shape_overrides_and_tiles():
+    rng = np.random.default_rng(2)
+    parts = [W.random_instance(rng, n=3000, count=5, k_lo=k, k_hi=k) for k in (20, 60, 150, 700)]
+    lits = np.concatenate([p.lits for p in parts])
+    con_off = np.concatenate([[0], np.cumsum(np.concatenate([np.diff(p.con_off) for p in parts]))])
+    types = np.concatenate([p.types for p in parts])
+    params = np.concatenate([p.params for p in parts])
+    shapes = [(64, 4, 16), (200, 16, 16)]
+    H = afsat.Instance(3000, con_off, lits, types, params, device=-1, shapes=shapes, tile_long=3)
+    def shape_of(k):
+        (b,) = [b for b in H.buckets() if b.k_lo <= k <= b.k_hi]
+        return b.lanes_per_restart, b.lits_per_lane
+    assert shape_of(20) == (4, 16) and shape_of(60) == (4, 16)
+    assert shape_of(150) == (16, 16)
+    J, S = shape_of(700)
+    assert J * S >= 700                               # past the last override: default model
+    for bad in ([(10, 2, 8)], [(64, 3, 32)], [(64, 4, 12)], [(100, 2, 32)], [(64, 4, 16), (64, 8, 8)]):
+        with pytest.raises(afsat.AfsError) as e:
+            afsat.Instance(3000, con_off, lits, types, params, device=-1, shapes=bad)
+        assert e.value.status == afsat.AFS_EINVAL
 
 
 def _create(n, con_off, lits, types, params=None):

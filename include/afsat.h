@@ -197,6 +197,21 @@ afs_status afs_fe_grad(afs_instance *inst, int32_t B, const float *x, void *ws, 
 afs_status afs_scatter(afs_instance *inst, int32_t B, void *ws, size_t ws_bytes,
                        float *obj, float *grad, void *stream);
 
+/* ---- differentiation (the objective as a differentiable function of x) ---------- */
+
+/* Forward: obj[b] = sum_c w_c FE_c(x_b) and optionally fe [C][B], with no adjoint
+ * work (each root's product chain runs once, nothing is stored for a backward
+ * pass).  obj: device f32 [B] (required); fe may be NULL. */
+afs_status afs_eval_fwd(afs_instance *inst, int32_t B, const float *x, void *ws, size_t ws_bytes,
+                        float *obj, float *fe, void *stream);
+
+/* Backward (adjoint): grad[v][b] = dobj[b] * dF_b/dx[v][b], the vector-Jacobian
+ * product of afs_eval_fwd.  The products are recomputed from x (nothing is kept
+ * from the forward).  dobj: device f32 [B], or NULL for all ones; grad: device
+ * f32 [n][B] (overwritten). */
+afs_status afs_eval_adjoint(afs_instance *inst, int32_t B, const float *x, const float *dobj,
+                            void *ws, size_t ws_bytes, float *grad, void *stream);
+
 /* ---- Algorithm 1 --------------------------------------------------------------- */
 
 /* Projected gradient step with constant step length (Algorithm 1,

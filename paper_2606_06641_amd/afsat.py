@@ -73,6 +73,8 @@ SIGNATURES = [
     ("afs_eval", ctypes.c_int, [_vp, _i32, _vp, _vp, ctypes.c_size_t, _vp, _vp, _vp, _vp, _vp]),
     ("afs_fe_grad", ctypes.c_int, [_vp, _i32, _vp, _vp, ctypes.c_size_t, _i32, _i32, _i32, _vp, _vp]),
     ("afs_scatter", ctypes.c_int, [_vp, _i32, _vp, ctypes.c_size_t, _vp, _vp, _vp]),
+    ("afs_eval_fwd", ctypes.c_int, [_vp, _i32, _vp, _vp, ctypes.c_size_t, _vp, _vp, _vp]),
+    ("afs_eval_adjoint", ctypes.c_int, [_vp, _i32, _vp, _vp, _vp, ctypes.c_size_t, _vp, _vp]),
     ("afs_step", ctypes.c_int, [_vp, _i32, _vp, _vp, ctypes.c_float, _vp, _vp, _vp]),
     ("afs_round_verify", ctypes.c_int, [_vp, _i32, _vp, _vp, _vp, ctypes.c_size_t, _vp, _vp, _vp]),
     ("afs_pgd_init", ctypes.c_int, [_vp, _i32, _vp, _vp, ctypes.c_size_t, ctypes.POINTER(_PgdState), _vp]),
@@ -268,6 +270,31 @@ class Instance:
         _check(lib().afs_scatter(self._h, int(B), _ptr(ws), ws.numel(), _ptr(obj), _ptr(grad),
                                  _stream(self._dev())))
 
+    # -- differentiation -----------------------------------------------------------
+    def eval_fwd(self, x, fe=False, ws=None):
+        """Objective per restart without adjoint work: obj (B,) [, fe (C, B)]."""
+        B = self._check_x(x)
+        dev = self._dev()
+        ws = self.workspace(B) if ws is None else ws
+        obj = torch.empty(B, dtype=torch.float32, device=dev)
+        fe_t = torch.empty((self.n_cons, B), dtype=torch.float32, device=dev) if fe else None
+        _check(lib().afs_eval_fwd(self._h, B, _ptr(x), _ptr(ws), ws.numel(), _ptr(obj), _ptr(fe_t),
+                                  _stream(dev)))
+        return (obj, fe_t) if fe else obj
+
+    def eval_adjoint(self, x, dobj=None, ws=None):
+        """grad[v][b] = dobj[b] * dF_b/dx[v][b] (products recomputed from x)."""
+        B = self._check_x(x)
+        dev = self._dev()
+        if dobj is not None and not (dobj.dtype == torch.float32 and dobj.is_cuda and dobj.numel() == B
+                                     and dobj.is_contiguous()):
+            raise ValueError("dobj must be a contiguous float32 CUDA tensor of B elements")
+        ws = self.workspace(B) if ws is None else ws
+        grad = torch.empty((self.n, B), dtype=torch.float32, device=dev)
+        _check(lib().afs_eval_adjoint(self._h, B, _ptr(x), _ptr(dobj), _ptr(ws), ws.numel(), _ptr(grad),
+                                      _stream(dev)))
+        return grad
+
     # -- Algorithm 1 -------------------------------------------------------------------
     def step(self, x, grad, lr, fixed=None, done=None):
         """x <- clip(x - lr*grad, -1, 1) in place, except fixed variables / done restarts."""
@@ -321,22 +348,57 @@ class Instance:
         _check(lib().afs_pgd_update(self._h, B, _ptr(x), float(lr), _ptr(fixed), _ptr(ws), ws.numel(),
                                     ctypes.byref(s), _stream(self._dev())))
 
-    def pgd(self, x, lr, steps, fixed=None, poll=10, stop_on_sat=True):
+    def pgd(self, x, lr, steps, fixed=None, poll=10, stop_on_sat=True, graph=False):
         """Algorithm 1 with constant step length on the columns of x (updated in place).
 
         Stops after ``steps`` iterations, or (``stop_on_sat``) once any restart
-        verifies; the host reads the 'done' counter every ``poll`` iterations."""
+        verifies; the host reads the 'done' counter every ``poll`` iterations.
+        With ``graph``, ``poll`` iterations are captured once in a HIP graph
+        (every launch of an iteration is allocation- and sync-free) and replayed."""
         B = self._check_x(x)
         st = self.pgd_state(B)
         ws = self.workspace(B)
         self.pgd_init(x, st, ws)
+        g = None
+        if graph and steps >= poll:
+            g = torch.cuda.CUDAGraph()
+            torch.cuda.synchronize(self.device)
+            with torch.cuda.graph(g):
+                for _ in range(poll):
+                    self.pgd_step(x, st, lr, fixed, ws)
         t = 0
         while t < steps:
             if stop_on_sat and int(st["counter"][1].item()) > 0:
                 break
-            for _ in range(min(poll, steps - t)):
-                self.pgd_step(x, st, lr, fixed, ws)
-                t += 1
+            if g is not None and steps - t >= poll:
+                g.replay()
+                t += poll
+            else:
+                for _ in range(min(poll, steps - t)):
+                    self.pgd_step(x, st, lr, fixed, ws)
+                    t += 1
         st["x"] = x
         st["iters"] = int(st["counter"][0].item())
+        st["graph"] = g
         return st
+
+
+class FEObjective(torch.autograd.Function):
+    """F(x) = sum_c w_c FE_c(x) per restart, differentiable in x.
+
+    ``obj = FEObjective.apply(x, inst)`` with x a float32 CUDA tensor (n, B) gives
+    obj (B,); the backward pass runs the library's adjoint kernels, recomputing the
+    products from x (only x is saved)."""
+
+    @staticmethod
+    def forward(ctx, x, inst):
+        x = x.contiguous()
+        ctx.inst = inst
+        ctx.save_for_backward(x)
+        return inst.eval_fwd(x)
+
+    @staticmethod
+    def backward(ctx, gobj):
+        (x,) = ctx.saved_tensors
+        g = ctx.inst.eval_adjoint(x, gobj.contiguous().to(torch.float32))
+        return g, None

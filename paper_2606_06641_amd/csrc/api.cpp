@@ -126,13 +126,15 @@ template <class T>
 T *at(void *ws, size_t off) { return reinterpret_cast<T *>(static_cast<char *>(ws) + off); }
 
 afs_status fe_grad_range(afs_instance *I, int B, const float *x, void *ws, const WsLayout &l,
-                         int lo, int hi, bool want_part, float *fe, hipStream_t s)
+                         int lo, int hi, bool want_part, float *fe, hipStream_t s,
+                         const float *dobj = nullptr, bool grad = true)
 {
     for (int bi = lo; bi < hi; ++bi) {
         const afs::Bucket &b = I->H.buckets[bi];
         afs::BucketLaunch bl{b.J, b.S, b.c0, b.nc, b.tile, b.ntiles, b.tile0};
         hipError_t e = afs::launch_fe_grad(I->D, bl, B, l.Bp, x, at<float>(ws, l.adj),
-                                           want_part ? at<float>(ws, l.part) : nullptr, fe, s);
+                                           want_part ? at<float>(ws, l.part) : nullptr, fe, dobj,
+                                           grad, s);
         if (e != hipSuccess) return dev_fail(e, "fe_grad launch");
     }
     return AFS_OK;
@@ -352,6 +354,41 @@ afs_status afs_eval(afs_instance *I, int32_t B, const float *x, void *ws, size_t
     if (adj && (e = afs::launch_permute_adj(I->D, B, l.Bp, at<float>(ws, l.adj), adj, s)) != hipSuccess)
         return dev_fail(e, "adjoint permute launch");
     return AFS_OK;
+}
+
+afs_status afs_eval_fwd(afs_instance *I, int32_t B, const float *x, void *ws, size_t ws_bytes,
+                        float *obj, float *fe, void *stream)
+{
+    afs_status st = check_call(I, B);
+    if (st != AFS_OK) return st;
+    WsLayout l;
+    if ((st = check_ws(I, B, ws, ws_bytes, l)) != AFS_OK) return st;
+    if (B > 0 && (!x || !obj)) return fail(AFS_EINVAL, "x or obj is NULL");
+    DeviceGuard g(I->device);
+    if (g.error() != hipSuccess) return dev_fail(g.error(), "hipSetDevice");
+    hipStream_t s = (hipStream_t)stream;
+    st = fe_grad_range(I, B, x, ws, l, 0, (int)I->H.buckets.size(), true, fe, s, nullptr, false);
+    if (st != AFS_OK) return st;
+    hipError_t e = afs::launch_obj_reduce(I->H.total_tiles, B, l.Bp, at<float>(ws, l.part),
+                                          at<float>(ws, l.part2), obj, s);
+    return e == hipSuccess ? AFS_OK : dev_fail(e, "objective reduction launch");
+}
+
+afs_status afs_eval_adjoint(afs_instance *I, int32_t B, const float *x, const float *dobj, void *ws,
+                            size_t ws_bytes, float *grad, void *stream)
+{
+    afs_status st = check_call(I, B);
+    if (st != AFS_OK) return st;
+    WsLayout l;
+    if ((st = check_ws(I, B, ws, ws_bytes, l)) != AFS_OK) return st;
+    if (B > 0 && (!x || !grad)) return fail(AFS_EINVAL, "x or grad is NULL");
+    DeviceGuard g(I->device);
+    if (g.error() != hipSuccess) return dev_fail(g.error(), "hipSetDevice");
+    hipStream_t s = (hipStream_t)stream;
+    st = fe_grad_range(I, B, x, ws, l, 0, (int)I->H.buckets.size(), false, nullptr, s, dobj, true);
+    if (st != AFS_OK) return st;
+    hipError_t e = afs::launch_scatter(I->D, B, l.Bp, at<float>(ws, l.adj), grad, s);
+    return e == hipSuccess ? AFS_OK : dev_fail(e, "scatter launch");
 }
 
 afs_status afs_step(afs_instance *I, int32_t B, float *x, const float *grad, float lr,

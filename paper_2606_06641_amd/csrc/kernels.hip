@@ -55,6 +55,7 @@ __device__ __forceinline__ void cmul(float &ar, float &ai, float br, float bi)
 struct FeArgs {
     const float *x;
     float *adj, *part, *fe;
+    const float *dobj;          // per-restart seed of the adjoint (NULL: 1)
     const int32_t *bc_slot0, *bc_k, *bc_tab, *bc_orig;
     const float *bc_w;
     const int32_t *slot_lit;
@@ -86,7 +87,7 @@ __device__ __forceinline__ void mul_unit(float &r, float &i, float z)
 // whole constraint in registers.  A wave takes 64 restarts and a tile of
 // constraints of the bucket.
 // ---------------------------------------------------------------------------
-template <int K>
+template <int K, bool GRAD>
 __global__ __launch_bounds__(kBlock) void fe_grad_short(FeArgs A)
 {
     const int64_t item = xcd_block() * kWavesPerBlock + wave_id();
@@ -99,11 +100,13 @@ __global__ __launch_bounds__(kBlock) void fe_grad_short(FeArgs A)
     const int bl = valid ? b : A.B - 1;
     const int cbeg = A.c0 + tile * A.tile;
     const int cend = min(cbeg + A.tile, A.c0 + A.nc);
+    const float seed = (GRAD && A.dobj) ? A.dobj[bl] : 1.0f;
     float objacc = 0.f;
     for (int c = cbeg; c < cend; ++c) {
         const int slot0 = A.bc_slot0[c];
         const int tab = A.bc_tab[c];
         const float w = A.bc_w[c];
+        const float wg = w * seed;
         int lit[K];
         float y[K], adj[K];
 #pragma unroll
@@ -133,14 +136,16 @@ __global__ __launch_bounds__(kBlock) void fe_grad_short(FeArgs A)
                 mul_unit(ur, ui, z[i]);
             }
             fe = fmaf(2.0f, ra.x * ur - ra.y * ui, fe);
-            float sr = w * ra.z, si = w * ra.w;
+            if (GRAD) {
+                float sr = wg * ra.z, si = wg * ra.w;
 #pragma unroll
-            for (int i = K - 1; i >= 0; --i) {
-                adj[i] = fmaf(pr[i], sr, adj[i]);
-                adj[i] = fmaf(-pi[i], si, adj[i]);
-                if (i > 0) {
-                    mul_unit(sr, si, z[i]);
-                    if (i % 8 == 0) cmul(sr, si, rb.x, rb.y);
+                for (int i = K - 1; i >= 0; --i) {
+                    adj[i] = fmaf(pr[i], sr, adj[i]);
+                    adj[i] = fmaf(-pi[i], si, adj[i]);
+                    if (i > 0) {
+                        mul_unit(sr, si, z[i]);
+                        if (i % 8 == 0) cmul(sr, si, rb.x, rb.y);
+                    }
                 }
             }
         }
@@ -153,17 +158,21 @@ __global__ __launch_bounds__(kBlock) void fe_grad_short(FeArgs A)
                 h *= y[i];
             }
             fe = fmaf(dh, h, fe);
-            float hs = w * dh;
+            if (GRAD) {
+                float hs = wg * dh;
 #pragma unroll
-            for (int i = K - 1; i >= 0; --i) {
-                adj[i] = fmaf(hp[i], hs, adj[i]);
-                hs *= y[i];
+                for (int i = K - 1; i >= 0; --i) {
+                    adj[i] = fmaf(hp[i], hs, adj[i]);
+                    hs *= y[i];
+                }
             }
         }
         if (valid) {
+            if (GRAD) {
 #pragma unroll
-            for (int i = 0; i < K; ++i)
-                A.adj[(int64_t)(slot0 + i) * A.Bp + b] = lit[i] > 0 ? adj[i] : -adj[i];
+                for (int i = 0; i < K; ++i)
+                    A.adj[(int64_t)(slot0 + i) * A.Bp + b] = lit[i] > 0 ? adj[i] : -adj[i];
+            }
             if (A.fe) A.fe[(int64_t)A.bc_orig[c] * A.B + b] = fe;
         }
         objacc = fmaf(w, fe, objacc);
@@ -332,7 +341,7 @@ __device__ __forceinline__ void scan_suffix_real(float &r, int lane, int j)
 // suffix chain, which accumulates the adjoint of each literal the lane owns:
 // no cross-lane reduction, deterministic order.
 // ---------------------------------------------------------------------------
-template <int J, int S>
+template <int J, int S, bool GRAD>
 __global__ __launch_bounds__(kBlock) void fe_grad_seg(FeArgs A)
 {
     static_assert(S % 8 == 0 && S <= 32, "segment length must be 8, 16, 24 or 32");
@@ -349,12 +358,14 @@ __global__ __launch_bounds__(kBlock) void fe_grad_seg(FeArgs A)
     const int cbeg = A.c0 + tile * A.tile;
     const int cend = min(cbeg + A.tile, A.c0 + A.nc);
     const int base = j * S;
+    const float seed = (GRAD && A.dobj) ? A.dobj[bl] : 1.0f;
     float objacc = 0.f;
     for (int c = cbeg; c < cend; ++c) {
         const int slot0 = A.bc_slot0[c];
         const int k = A.bc_k[c];
         const int tab = A.bc_tab[c];
         const float w = A.bc_w[c];
+        const float wg = w * seed;
         unsigned neg = 0;            // bit s: literal s of this lane is negated
         float y[S], adj[S];
 #pragma unroll
@@ -390,21 +401,23 @@ __global__ __launch_bounds__(kBlock) void fe_grad_seg(FeArgs A)
             cmul(ur, ui, rb.x, rb.y);                   // the segment's product
             float er = ur, ei = ui;
             scan_prefix<J>(er, ei, lane, j);
-            float fr = ur, fi = ui;
-            scan_suffix<J>(fr, fi, lane, j);
             fe = fmaf(2.0f, ra.x * er - ra.y * ei, fe);  // lane J-1: d G
-            const float exr = prev_lane<J>(er, 1.0f, j), exi = prev_lane<J>(ei, 0.0f, j);
-            const float fxr = next_lane<J>(fr, 1.0f, j), fxi = next_lane<J>(fi, 0.0f, j);
-            float sr = w * ra.z, si = w * ra.w;
-            cmul(sr, si, exr, exi);
-            cmul(sr, si, fxr, fxi);
+            if (GRAD) {
+                float fr = ur, fi = ui;
+                scan_suffix<J>(fr, fi, lane, j);
+                const float exr = prev_lane<J>(er, 1.0f, j), exi = prev_lane<J>(ei, 0.0f, j);
+                const float fxr = next_lane<J>(fr, 1.0f, j), fxi = next_lane<J>(fi, 0.0f, j);
+                float sr = wg * ra.z, si = wg * ra.w;
+                cmul(sr, si, exr, exi);
+                cmul(sr, si, fxr, fxi);
 #pragma unroll
-            for (int s = S - 1; s >= 0; --s) {
-                adj[s] = fmaf(pr[s], sr, adj[s]);
-                adj[s] = fmaf(-pi[s], si, adj[s]);
-                if (s > 0) {
-                    mul_unit(sr, si, z[s]);
-                    if (s % 8 == 0) cmul(sr, si, rb.x, rb.y);
+                for (int s = S - 1; s >= 0; --s) {
+                    adj[s] = fmaf(pr[s], sr, adj[s]);
+                    adj[s] = fmaf(-pi[s], si, adj[s]);
+                    if (s > 0) {
+                        mul_unit(sr, si, z[s]);
+                        if (s % 8 == 0) cmul(sr, si, rb.x, rb.y);
+                    }
                 }
             }
         }
@@ -413,30 +426,35 @@ __global__ __launch_bounds__(kBlock) void fe_grad_seg(FeArgs A)
             float q = y[0];
 #pragma unroll
             for (int s = 1; s < S; ++s) q *= y[s];
-            float e = q, f = q;
+            float e = q;
             scan_prefix_real<J>(e, lane, j);
-            scan_suffix_real<J>(f, lane, j);
             fe = fmaf(dh, e, fe);                       // lane J-1: product of all y
-            e = prev_lane<J>(e, 1.0f, j);
-            f = next_lane<J>(f, 1.0f, j);
-            float hp[S], h = e;
+            if (GRAD) {
+                float f = q;
+                scan_suffix_real<J>(f, lane, j);
+                e = prev_lane<J>(e, 1.0f, j);
+                f = next_lane<J>(f, 1.0f, j);
+                float hp[S], h = e;
 #pragma unroll
-            for (int s = 0; s < S; ++s) {
-                hp[s] = h;
-                h *= y[s];
-            }
-            float hs = w * dh * f;
+                for (int s = 0; s < S; ++s) {
+                    hp[s] = h;
+                    h *= y[s];
+                }
+                float hs = wg * dh * f;
 #pragma unroll
-            for (int s = S - 1; s >= 0; --s) {
-                adj[s] = fmaf(hp[s], hs, adj[s]);
-                hs *= y[s];
+                for (int s = S - 1; s >= 0; --s) {
+                    adj[s] = fmaf(hp[s], hs, adj[s]);
+                    hs *= y[s];
+                }
             }
         }
         if (valid) {
+            if (GRAD) {
 #pragma unroll
-            for (int s = 0; s < S; ++s)
-                if (base + s < k)
-                    A.adj[(int64_t)(slot0 + base + s) * A.Bp + b] = ((neg >> s) & 1u) ? -adj[s] : adj[s];
+                for (int s = 0; s < S; ++s)
+                    if (base + s < k)
+                        A.adj[(int64_t)(slot0 + base + s) * A.Bp + b] = ((neg >> s) & 1u) ? -adj[s] : adj[s];
+            }
             if (A.fe && j == J - 1) A.fe[(int64_t)A.bc_orig[c] * A.B + b] = fe;
         }
         objacc = fmaf(w, fe, objacc);
@@ -444,9 +462,10 @@ __global__ __launch_bounds__(kBlock) void fe_grad_seg(FeArgs A)
     if (A.part && j == J - 1) A.part[(int64_t)(A.tile0 + tile) * A.Bp + b] = objacc;
 }
 
+template <bool GRAD>
 hipError_t dispatch_short(int K, dim3 g, hipStream_t s, const FeArgs &a)
 {
-#define AFS_SHORT(KK) case KK: hipLaunchKernelGGL((fe_grad_short<KK>), g, dim3(kBlock), 0, s, a); break;
+#define AFS_SHORT(KK) case KK: hipLaunchKernelGGL((fe_grad_short<KK, GRAD>), g, dim3(kBlock), 0, s, a); break;
     switch (K) {
         AFS_SHORT(1) AFS_SHORT(2) AFS_SHORT(3) AFS_SHORT(4) AFS_SHORT(5) AFS_SHORT(6)
         AFS_SHORT(7) AFS_SHORT(8) AFS_SHORT(9) AFS_SHORT(10) AFS_SHORT(11) AFS_SHORT(12)
@@ -457,28 +476,29 @@ hipError_t dispatch_short(int K, dim3 g, hipStream_t s, const FeArgs &a)
     return hipGetLastError();
 }
 
-template <int J>
+template <int J, bool GRAD>
 hipError_t dispatch_seg_s(int S, dim3 g, hipStream_t s, const FeArgs &a)
 {
     switch (S) {
-    case 8: hipLaunchKernelGGL((fe_grad_seg<J, 8>), g, dim3(kBlock), 0, s, a); break;
-    case 16: hipLaunchKernelGGL((fe_grad_seg<J, 16>), g, dim3(kBlock), 0, s, a); break;
-    case 24: hipLaunchKernelGGL((fe_grad_seg<J, 24>), g, dim3(kBlock), 0, s, a); break;
-    case 32: hipLaunchKernelGGL((fe_grad_seg<J, 32>), g, dim3(kBlock), 0, s, a); break;
+    case 8: hipLaunchKernelGGL((fe_grad_seg<J, 8, GRAD>), g, dim3(kBlock), 0, s, a); break;
+    case 16: hipLaunchKernelGGL((fe_grad_seg<J, 16, GRAD>), g, dim3(kBlock), 0, s, a); break;
+    case 24: hipLaunchKernelGGL((fe_grad_seg<J, 24, GRAD>), g, dim3(kBlock), 0, s, a); break;
+    case 32: hipLaunchKernelGGL((fe_grad_seg<J, 32, GRAD>), g, dim3(kBlock), 0, s, a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
+template <bool GRAD>
 hipError_t dispatch_seg(int J, int S, dim3 g, hipStream_t s, const FeArgs &a)
 {
     switch (J) {
-    case 2: return dispatch_seg_s<2>(S, g, s, a);
-    case 4: return dispatch_seg_s<4>(S, g, s, a);
-    case 8: return dispatch_seg_s<8>(S, g, s, a);
-    case 16: return dispatch_seg_s<16>(S, g, s, a);
-    case 32: return dispatch_seg_s<32>(S, g, s, a);
-    case 64: return dispatch_seg_s<64>(S, g, s, a);
+    case 2: return dispatch_seg_s<2, GRAD>(S, g, s, a);
+    case 4: return dispatch_seg_s<4, GRAD>(S, g, s, a);
+    case 8: return dispatch_seg_s<8, GRAD>(S, g, s, a);
+    case 16: return dispatch_seg_s<16, GRAD>(S, g, s, a);
+    case 32: return dispatch_seg_s<32, GRAD>(S, g, s, a);
+    case 64: return dispatch_seg_s<64, GRAD>(S, g, s, a);
     default: return hipErrorInvalidValue;
     }
 }
@@ -741,11 +761,12 @@ inline dim3 grid_for_waves(int64_t items)
 }  // namespace
 
 hipError_t launch_fe_grad(const DevInstance &I, const BucketLaunch &bk, int B, int Bp,
-                          const float *x, float *adj, float *part, float *fe, hipStream_t s)
+                          const float *x, float *adj, float *part, float *fe, const float *dobj,
+                          bool grad, hipStream_t s)
 {
     if (bk.nc == 0 || B == 0) return hipSuccess;
     FeArgs a;
-    a.x = x; a.adj = adj; a.part = part; a.fe = fe;
+    a.x = x; a.adj = adj; a.part = part; a.fe = fe; a.dobj = dobj;
     a.bc_slot0 = I.bc_slot0; a.bc_k = I.bc_k; a.bc_tab = I.bc_tab; a.bc_orig = I.bc_orig;
     a.bc_w = I.bc_w; a.slot_lit = I.slot_lit; a.tab = I.tab;
     a.B = B; a.Bp = Bp;
@@ -754,7 +775,8 @@ hipError_t launch_fe_grad(const DevInstance &I, const BucketLaunch &bk, int B, i
     const int64_t groups = (B + R - 1) / R;
     a.items = groups * bk.ntiles;
     const dim3 g = grid_for_waves(a.items);
-    return bk.J == 1 ? dispatch_short(bk.S, g, s, a) : dispatch_seg(bk.J, bk.S, g, s, a);
+    if (grad) return bk.J == 1 ? dispatch_short<true>(bk.S, g, s, a) : dispatch_seg<true>(bk.J, bk.S, g, s, a);
+    return bk.J == 1 ? dispatch_short<false>(bk.S, g, s, a) : dispatch_seg<false>(bk.J, bk.S, g, s, a);
 }
 
 static ScatterArgs scatter_args(const DevInstance &I, int B, int Bp, const float *adj)

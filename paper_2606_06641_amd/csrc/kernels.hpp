@@ -28,10 +28,13 @@ struct BucketLaunch {
     int32_t c0, nc, tile, ntiles, tile0;
 };
 
-// Per-literal adjoints and objective partials for one length bucket.
-//   adj  [L][Bp] (slot order), part [tiles][Bp] (may be null), fe [C][B] (may be null)
+// FE (and with grad, per-literal adjoints) of one length bucket.
+//   adj  [L][Bp] (slot order, written when grad), part [tiles][Bp] objective partials
+//   (may be null), fe [C][B] (may be null), dobj [B] per-restart seed of the adjoint
+//   (may be null: 1).
 hipError_t launch_fe_grad(const DevInstance &I, const BucketLaunch &bk, int B, int Bp,
-                          const float *x, float *adj, float *part, float *fe, hipStream_t s);
+                          const float *x, float *adj, float *part, float *fe, const float *dobj,
+                          bool grad, hipStream_t s);
 
 // grad[v][b] = sum of adj over the slots of v, ascending.
 hipError_t launch_scatter(const DevInstance &I, int B, int Bp, const float *adj, float *grad,

@@ -1,0 +1,128 @@
+"""Differentiation: the hand-written adjoint behind torch.autograd.Function
+(forward = FE only, backward = recomputed products seeded by dL/dF per restart),
+checked against the FP64 oracle's gradient and against central differences of
+the oracle's objective (exact for a function affine in each coordinate)."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import parity
+from paper_2606_06641_amd import afsat
+from paper_2606_06641_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    afsat.lib()
+
+
+def log(*a):
+    print(*a, flush=True)
+
+
+def grad_tol(inst):
+    lit_w = np.repeat(np.ones(inst.n_cons), np.diff(inst.con_off))
+    deg = np.zeros(inst.n)
+    np.add.at(deg, np.abs(inst.lits) - 1, lit_w)
+    return 1e-4 * max(deg.max(), 1.0)
+
+
+def test_forward_and_vjp_match_eval_and_oracle():
+    rng = np.random.default_rng(30)
+    parts = [W.random_instance(rng, n=500, count=400, k_lo=1, k_hi=16),
+             W.random_instance(rng, n=500, count=12, k_lo=17, k_hi=400)]
+    inst = W.Instance(n=500, con_off=np.concatenate([parts[0].con_off, parts[1].con_off[1:] + parts[0].n_lits]),
+                      lits=np.concatenate([p.lits for p in parts]), types=np.concatenate([p.types for p in parts]),
+                      params=np.concatenate([p.params for p in parts]))
+    B = 45
+    x32 = rng.uniform(-1, 1, size=(inst.n, B)).astype(np.float32)
+    d = afsat.Instance.from_arrays(inst)
+    x = parity.to_dev(x32).requires_grad_(True)
+    obj = afsat.FEObjective.apply(x, d)
+    gobj = torch.from_numpy(rng.normal(size=B).astype(np.float32)).cuda()
+    (obj * gobj).sum().backward()
+    torch.cuda.synchronize()
+    orc = oracle.eval(inst, x32, grad=True)
+    assert np.max(np.abs(obj.detach().cpu().numpy() - orc["obj"])) <= 1e-4 * inst.n_cons
+    want = orc["grad"] * gobj.cpu().numpy()[None, :].astype(np.float64)
+    got = x.grad.cpu().numpy()
+    tol = grad_tol(inst) * float(np.max(np.abs(gobj.cpu().numpy())))
+    assert np.max(np.abs(got - want)) <= tol
+    # the forward-only objective equals the full evaluation's, and the unseeded
+    # adjoint equals the gradient of afs_eval bit for bit (same kernels, same order)
+    e = d.eval(x.detach(), obj=True, grad=True)
+    assert torch.allclose(obj.detach(), e["obj"], rtol=0, atol=1e-5)
+    assert torch.equal(d.eval_adjoint(x.detach()), e["grad"])
+
+
+def test_config4_long_card_autograd():
+    """n=50k, 200k clauses (k 3-10) and 1,000 CARD (k 256-1,024), 512 restarts,
+    FE and gradient through FEObjective; oracle gradient on 8 sampled restarts and
+    FP64 central differences (h = 1e-3) at 48 sampled (variable, restart) pairs."""
+    inst = W.long_card_50k()
+    B = 512
+    x32 = W.uniform_x0(inst.n, B, workload=4)
+    log("case: config-4 autograd n=50k B=512")
+    d = afsat.Instance.from_arrays(inst)
+    x = parity.to_dev(x32).requires_grad_(True)
+    obj = afsat.FEObjective.apply(x, d)
+    obj.sum().backward()
+    torch.cuda.synchronize()
+    g = x.grad.cpu().numpy()
+    rng = np.random.default_rng(40)
+    cols = rng.choice(B, size=8, replace=False)
+    orc = oracle.eval(inst, x32[:, cols], grad=True)
+    tol = grad_tol(inst)
+    err = np.max(np.abs(g[:, cols] - orc["grad"]))
+    log("max |grad - oracle grad| = %.3e (tol %.1e)" % (err, tol))
+    assert err <= tol
+    assert np.max(np.abs(obj.detach().cpu().numpy()[cols] - orc["obj"])) <= 1e-4 * inst.n_cons
+    # central differences of the oracle objective, variables of the long constraints first
+    h = 1e-3
+    card_vars = np.unique(np.abs(inst.lits[inst.con_off[np.nonzero(inst.types == W.CARD_GE)[0][0]]:
+                                           inst.con_off[np.nonzero(inst.types == W.CARD_GE)[0][0] + 1]]) - 1)
+    vs = np.concatenate([rng.choice(card_vars, size=24, replace=False), rng.choice(inst.n, size=24, replace=False)])
+    bs = rng.choice(B, size=48)
+    X = np.repeat(x32[:, bs].astype(np.float64), 2, axis=1)
+    for j, v in enumerate(vs):
+        X[v, 2 * j] += h
+        X[v, 2 * j + 1] -= h
+    F = oracle.eval(inst, X, grad=False)["obj"]
+    fd = (F[0::2] - F[1::2]) / (2 * h)
+    ferr = np.max(np.abs(fd - g[vs, bs]))
+    log("max |grad - central difference| = %.3e" % ferr)
+    assert ferr <= tol
+
+
+def test_graph_replay_equals_eager():
+    """PGD iterations captured in a HIP graph and replayed give the same bits as
+    eager launches (every replay checked, with eager work and syncs between)."""
+    inst = W.planted_3sat(instance=2)
+    B = 32
+    x0 = W.uniform_x0(inst.n, B, workload=1, instance=2)
+    d = afsat.Instance.from_arrays(inst)
+    xa = parity.to_dev(x0)
+    ra = d.pgd(xa, lr=0.1, steps=40, poll=10, stop_on_sat=False, graph=False)
+    xb = parity.to_dev(x0)
+    rb = d.pgd(xb, lr=0.1, steps=40, poll=10, stop_on_sat=False, graph=True)
+    assert rb["graph"] is not None
+    torch.cuda.synchronize()
+    assert torch.equal(xa, xb)
+    for k in ("unsat", "done", "first_sat", "counter"):
+        assert torch.equal(ra[k], rb[k]), k
+    # replay the captured graph again, three times, checking against eager steps
+    g = rb["graph"]
+    for rep in range(3):
+        for _ in range(10):
+            d.pgd_step(xa, ra, 0.1, None, d.workspace(B))
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(xa, xb), rep
+        assert torch.equal(ra["unsat"], rb["unsat"]) and torch.equal(ra["counter"], rb["counter"])

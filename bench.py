@@ -92,12 +92,29 @@ def copy_probe(mib):
     print(json.dumps({"copy_probe_bytes": n * 4, "launches": 5}), flush=True)
 
 
+def build_workload(name, W):
+    """(instance or parts, restarts, description) of a named workload."""
+    if name == "mixed10k":
+        return W.mixed_10k(), 1024, ("planted mixed n=10000: 30000 clauses k3-8, 2000 XOR k3-5, "
+                                     "500 CARD>=K k20-200; 1024 restarts; one PGD iteration per step")
+    if name == "batch64":
+        return W.uneven_batch(64), 256, ("64 planted instances, n log-uniform 500-50000, constraints/n "
+                                         "3.5-4.2, 70% clauses k2-8, 10% NAE k2-8, 10% XOR k2-6, 10% "
+                                         "CARD>=K k8-256 log-uniform; 256 restarts each, one block-diagonal "
+                                         "batch; one PGD iteration per step")
+    if name == "longcard50k":
+        return W.long_card_50k(), 512, ("planted n=50000: 200000 clauses k3-10, 1000 CARD>=K k256-1024; "
+                                        "512 restarts; one forward + adjoint (autograd) pass per step")
+    raise SystemExit("unknown workload %r" % name)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--restarts", type=int, default=1024)
+    ap.add_argument("--workload", default="mixed10k", choices=["mixed10k", "batch64", "longcard50k"])
+    ap.add_argument("--restarts", type=int, default=0, help="override the workload's restart count")
     ap.add_argument("--lr", type=float, default=0.1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
@@ -121,17 +138,28 @@ def main():
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
-    inst = W.mixed_10k()
-    B = args.restarts
-    x0 = W.uniform_x0(inst.n, B, workload=2)
+    t_setup = time.perf_counter()
+    work, B, desc = build_workload(args.workload, W)
+    B = args.restarts or B
+    parts = work if isinstance(work, list) else None
+    if parts is not None:
+        inst = _concat(parts, W)          # the block-diagonal instance (for lengths and tuning)
+    else:
+        inst = work
+    x0 = W.uniform_x0(inst.n, B, workload={"mixed10k": 2, "batch64": 3, "longcard50k": 4}[args.workload])
     shapes = []
     if not args.no_autotune:
         from paper_2606_06641_amd import autotune
         out = os.path.join(ROOT, "gpurun_out", "tuned_shapes.json")
         os.makedirs(os.path.dirname(out), exist_ok=True)
         shapes, _ = autotune.tune(inst, B, cache_path=autotune.DEFAULT_CACHE, out_path=out,
-                                  log=lambda m: print(m, file=sys.stderr, flush=True))
-    d = afsat.Instance.from_arrays(inst, device=0, shapes=shapes)
+                                  log=lambda m: print(m, file=sys.stderr, flush=True), max_cons=400)
+    if parts is not None:
+        d = afsat.Instance.batch(parts, device=0, shapes=shapes)
+    else:
+        d = afsat.Instance.from_arrays(inst, device=0, shapes=shapes)
+    print("setup %.1f s: n=%d C=%d L=%d B=%d parts=%d" % (time.perf_counter() - t_setup, d.n, d.n_cons,
+          d.n_lits, B, d.n_inst), file=sys.stderr, flush=True)
     x = torch.from_numpy(x0).to(dev)
     ws = d.workspace(B)
     st = d.pgd_state(B)
@@ -139,8 +167,22 @@ def main():
     stream = torch.cuda.current_stream(dev)
     buckets = d.buckets()
     nb = len(buckets)
+    autograd = args.workload == "longcard50k"
+    if autograd:
+        x.requires_grad_(True)
 
     def step(ev=None, dom=None):
+        if autograd:
+            # forward (FE only) + backward (adjoint, recomputed) through FEObjective;
+            # the dominant adjoint kernel is bracketed inside eval_adjoint's launches
+            obj = afsat.FEObjective.apply(x, d)
+            if ev is not None:
+                ev[0].record(stream)
+            x.grad = None
+            obj.sum().backward()
+            if ev is not None:
+                ev[1].record(stream)
+            return
         if ev is None:
             d.fe_grad(x, ws, 0, nb)
         else:
@@ -157,12 +199,13 @@ def main():
     for _ in range(max(1, args.warmup)):
         step()
     torch.cuda.synchronize()
+    xd = x.detach()
     per_bucket = []
     for i in range(nb):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
         for _ in range(3):
-            d.fe_grad(x, ws, i, i + 1)
+            d.fe_grad(xd, ws, i, i + 1)
         e1.record(stream)
         torch.cuda.synchronize()
         per_bucket.append(e0.elapsed_time(e1) / 3)
@@ -182,33 +225,36 @@ def main():
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     dom_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
-    value = B * inst.n_lits / (ms_per_step * 1e-3)
+    value = B * d.n_lits / (ms_per_step * 1e-3)
 
     # roofline of the dominant kernel
-    lens = inst.lengths()
+    lens = np.diff(np.asarray(inst.con_off))
     smap = d.slot_map()
-    # the bucket's constraints: those whose first literal's slot falls in the bucket
     slot_of_lit = np.empty_like(smap)
     slot_of_lit[smap] = np.arange(len(smap))
-    first_slot = slot_of_lit[inst.con_off[:-1]]
+    first_slot = slot_of_lit[np.asarray(inst.con_off[:-1])]
     in_b = (first_slot >= bk.slot0) & (first_slot < bk.slot0 + bk.n_lits)
     kb = lens[in_b]
-    if bk.lanes_per_restart == 1 and bk.k_hi <= 8:
+    kname = "fe_grad_seg<%d,%d>" % (bk.lanes_per_restart, bk.lits_per_lane) if bk.lanes_per_restart > 1 \
+        else "fe_grad_short<%d>" % bk.k_hi
+    if autograd:
+        # the bracketed region is the whole adjoint pass (every bucket + gradient sum)
+        flops = float(B * sum(algorithmic_flops(int(k)) for k in lens))
+        achieved = flops / (dom_ms * 1e-3) / 1e12
+        roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                "kernel": "adjoint pass (all fe_grad buckets + scatter)"}
+    elif bk.lanes_per_restart == 1 and bk.k_hi <= 8:
         bytes_per_launch = 8.0 * B * kb.sum()
         achieved = bytes_per_launch / (dom_ms * 1e-3) / 1e9
-        roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s"}
+        roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s", "kernel": kname}
     else:
         flops_per_launch = float(B * sum(algorithmic_flops(int(k)) for k in kb))
         achieved = flops_per_launch / (dom_ms * 1e-3) / 1e12
-        roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s"}
+        roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "kernel": kname}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    kname = "fe_grad_seg<%d,%d>" % (bk.lanes_per_restart, bk.lits_per_lane) if bk.lanes_per_restart > 1 \
-        else "fe_grad_short<%d>" % bk.k_hi
-    roof["kernel"] = kname
     roof["ms_per_launch"] = dom_ms
-    roof["traffic"] = stored_traffic(kname)
+    roof["traffic"] = None if autograd else stored_traffic(kname)
 
-    done = int(st["counter"][1].item())
     line = {
         "metric": "FE+grad literal-evals/s",
         "value": value,
@@ -222,17 +268,31 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "planted mixed n=10000: 30000 clauses k3-8, 2000 XOR k3-5, "
-                               "500 CARD>=K k20-200; %d restarts; one PGD iteration per step" % B,
-                   "n_vars": inst.n, "n_cons": inst.n_cons, "n_lits": inst.n_lits, "restarts": B,
-                   "lr": args.lr, "shapes": [list(sh) for sh in shapes]},
+        "config": {"workload": desc, "n_vars": d.n, "n_cons": d.n_cons, "n_lits": d.n_lits, "restarts": B,
+                   "parts": d.n_inst, "lr": args.lr, "shapes": [list(sh) for sh in shapes]},
         "roofline": roof,
     }
-    print("restarts verified after %d iterations: %d" % (int(st["counter"][0].item()), done),
-          file=sys.stderr, flush=True)
-    if not args.no_cpu_baseline:
+    if not autograd:
+        print("(part, restart) pairs verified after %d iterations: %d" % (int(st["counter"][0].item()),
+              int(st["counter"][1].item())), file=sys.stderr, flush=True)
+    if not args.no_cpu_baseline and args.workload == "mixed10k":
         line["cpu_baseline"] = cpu_baseline(inst, x0, args.lr, args.cpu_seconds)
     print(json.dumps(line), flush=True)
+
+
+def _concat(parts, W):
+    import numpy as np
+    offs, lits, types, params = [np.zeros(1, np.int64)], [], [], []
+    base = v0 = 0
+    for p in parts:
+        offs.append(np.asarray(p.con_off[1:], np.int64) + base)
+        base += p.n_lits
+        lits.append(np.where(p.lits > 0, p.lits + v0, p.lits - v0).astype(np.int32))
+        types.append(p.types)
+        params.append(p.params)
+        v0 += p.n
+    return W.Instance(n=v0, con_off=np.concatenate(offs), lits=np.concatenate(lits),
+                      types=np.concatenate(types), params=np.concatenate(params))
 
 
 if __name__ == "__main__":

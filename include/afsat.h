@@ -78,6 +78,7 @@ typedef struct {
     int32_t n_tables;    /* distinct (type, k, param) coefficient tables */
     int32_t max_k;
     int32_t device;      /* HIP device ordinal, or -1 for a host-only instance */
+    int32_t n_inst;      /* sub-instances: 1, or the number of parts of a batch */
 } afs_info;
 
 /* One length bucket: constraints of lengths [k_lo, k_hi] evaluated by one kernel
@@ -141,6 +142,21 @@ afs_status afs_instance_create_ex(int32_t n_vars, int32_t n_cons, const int64_t 
                                   const int32_t *lits, const int32_t *types,
                                   const int32_t *params, const float *weights,
                                   const afs_options *opts, int32_t device, afs_instance **out);
+
+/* Block-diagonal batch of independent instances, evaluated together: the
+ * variables and constraints of parts[0..n_parts) are concatenated (variables of
+ * part p follow those of parts 0..p-1), so every kernel launch covers all parts
+ * and one restart column b of the batch holds restart b of every part.  FE,
+ * gradient and step are exactly those of the parts; unsat / done / first_sat
+ * become per (part, restart): arrays [n_parts][B] (see afs_pgd_state).  The
+ * parts are read (their host copies), not retained; they may be host-only.
+ * Many uneven instances run in one set of launches this way, with one shape
+ * choice per length range across all of them. */
+afs_status afs_batch_create(const afs_instance *const *parts, int32_t n_parts, const afs_options *opts,
+                            int32_t device, afs_instance **out);
+
+/* First variable of each part of a batch: var0 int32 [n_inst+1] (host). */
+afs_status afs_batch_var_offsets(const afs_instance *inst, int32_t *var0);
 
 /* Free the instance and its device tables.  NULL is accepted.  The caller must
  * make sure no enqueued work still uses it. */
@@ -217,9 +233,10 @@ afs_status afs_eval_adjoint(afs_instance *inst, int32_t B, const float *x, const
 /* Projected gradient step with constant step length (Algorithm 1,
  * projectToBounds onto [-1,1]^n):  x <- min(1, max(-1, x - lr * grad)) in FP32,
  * skipped for variables with fixed[v] != 0 (partial assignment, Sec. 3.4) and
- * restarts with done[b] != 0 (finished candidates do no-ops, Sec. 3.3).
+ * restarts with done != 0 (finished candidates do no-ops, Sec. 3.3).
  *   x: device f32 [n][B] updated in place; grad: device f32 [n][B];
- *   fixed: device u8 [n] or NULL; done: device u8 [B] or NULL. */
+ *   fixed: device u8 [n] or NULL; done: device u8 [P][B] or NULL (P as in
+ *   afs_pgd_state; variable v of part p is frozen where done[p][b] != 0). */
 afs_status afs_step(afs_instance *inst, int32_t B, float *x, const float *grad, float lr,
                     const uint8_t *fixed, const uint8_t *done, void *stream);
 
@@ -228,19 +245,21 @@ afs_status afs_step(afs_instance *inst, int32_t B, float *x, const float *grad, 
  *   bits : device u32 [n][ceil(B/32)]: bit (b % 32) of word b/32 = (x[v][b] < 0)
  *          (NULL: not returned; a workspace copy is used)
  *   ws   : workspace as for afs_eval
- *   unsat: device i32 [B] (required)
- *   done : device u8 [B] or NULL; set to 1 where unsat == 0 (never cleared) */
+ *   unsat: device i32 [P][B] (required; P = 1, or the parts of a batch)
+ *   done : device u8 [P][B] or NULL; set to 1 where unsat == 0 (never cleared) */
 afs_status afs_round_verify(afs_instance *inst, int32_t B, const float *x, uint32_t *bits,
                             void *ws, size_t ws_bytes, int32_t *unsat, uint8_t *done,
                             void *stream);
 
-/* Device state of a batched run of Algorithm 1 (all caller-owned device arrays). */
+/* Device state of a batched run of Algorithm 1 (all caller-owned device arrays).
+ * For a batch of P parts the per-restart arrays are [P][B] (part-major); a plain
+ * instance has P = 1. */
 typedef struct {
-    int32_t *unsat;      /* [B] unsat count at the current point                    */
-    uint8_t *done;       /* [B] 1 once the restart has verified (then frozen)       */
-    int32_t *first_sat;  /* [B] iteration at which it verified, -1 if not yet       */
-    int32_t *counter;    /* [2] {iteration t, number of restarts done}; t counts
-                            completed iterations                                     */
+    int32_t *unsat;      /* [P][B] unsat count at the current point                 */
+    uint8_t *done;       /* [P][B] 1 once the restart has verified (then frozen)    */
+    int32_t *first_sat;  /* [P][B] iteration at which it verified, -1 if not yet    */
+    int32_t *counter;    /* [2] {iteration t, number of (part, restart) pairs done};
+                            t counts completed iterations                            */
 } afs_pgd_state;
 
 /* Reset the state and check the initial point X_(0): unsat, done and first_sat = 0

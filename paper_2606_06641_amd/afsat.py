@@ -37,7 +37,7 @@ class AfsError(RuntimeError):
 class _Info(ctypes.Structure):
     _fields_ = [("n_vars", ctypes.c_int32), ("n_cons", ctypes.c_int32), ("n_lits", ctypes.c_int64),
                 ("n_buckets", ctypes.c_int32), ("n_tables", ctypes.c_int32),
-                ("max_k", ctypes.c_int32), ("device", ctypes.c_int32)]
+                ("max_k", ctypes.c_int32), ("device", ctypes.c_int32), ("n_inst", ctypes.c_int32)]
 
 
 class _BucketInfo(ctypes.Structure):
@@ -64,6 +64,9 @@ SIGNATURES = [
                                            ctypes.POINTER(_vp)]),
     ("afs_instance_create_ex", ctypes.c_int, [_i32, _i32, _i64p, _i32p, _i32p, _i32p, _f32p,
                                               ctypes.POINTER(_Options), _i32, ctypes.POINTER(_vp)]),
+    ("afs_batch_create", ctypes.c_int, [ctypes.POINTER(_vp), _i32, ctypes.POINTER(_Options), _i32,
+                                        ctypes.POINTER(_vp)]),
+    ("afs_batch_var_offsets", ctypes.c_int, [_vp, _i32p]),
     ("afs_instance_destroy", None, [_vp]),
     ("afs_instance_info", ctypes.c_int, [_vp, ctypes.POINTER(_Info)]),
     ("afs_bucket_info_get", ctypes.c_int, [_vp, _i32, ctypes.POINTER(_BucketInfo)]),
@@ -153,16 +156,38 @@ class Instance:
         params = None if params is None else np.ascontiguousarray(params, dtype=np.int32)
         weights = None if weights is None else np.ascontiguousarray(weights, dtype=np.float32)
         shapes = list(shapes or [])
-        kh = np.array([s[0] for s in shapes], dtype=np.int32)
-        ln = np.array([s[1] for s in shapes], dtype=np.int32)
-        sg = np.array([s[2] for s in shapes], dtype=np.int32)
-        opts = _Options(len(shapes), _np_ptr(kh, _i32p), _np_ptr(ln, _i32p), _np_ptr(sg, _i32p),
-                        int(tile_short), int(tile_long))
+        opts, keep = self._options(shapes, tile_short, tile_long)
         h = ctypes.c_void_p()
         _check(lib().afs_instance_create_ex(int(n), len(types), _np_ptr(con_off, _i64p), _np_ptr(lits, _i32p),
                                             _np_ptr(types, _i32p), _np_ptr(params, _i32p),
                                             _np_ptr(weights, _f32p), ctypes.byref(opts), int(device),
                                             ctypes.byref(h)))
+        self._attach(h, shapes)
+
+    @staticmethod
+    def _options(shapes, tile_short, tile_long):
+        shapes = list(shapes or [])
+        arrs = [np.array([sh[i] for sh in shapes], dtype=np.int32) for i in range(3)]
+        opts = _Options(len(shapes), _np_ptr(arrs[0], _i32p), _np_ptr(arrs[1], _i32p), _np_ptr(arrs[2], _i32p),
+                        int(tile_short), int(tile_long))
+        return opts, arrs
+
+    @classmethod
+    def batch(cls, parts, device=0, shapes=None, tile_short=0, tile_long=0):
+        """Block-diagonal batch of independent instances (each an object with
+        ``n, con_off, lits, types, params, weights`` or an ``Instance``): one set
+        of launches covers all of them; per-restart state is [n_inst][B]."""
+        made = [p if isinstance(p, Instance) else cls.from_arrays(p, device=-1) for p in parts]
+        handles = (ctypes.c_void_p * len(made))(*[m._h.value for m in made])
+        opts, keep = cls._options(shapes, tile_short, tile_long)
+        h = ctypes.c_void_p()
+        _check(lib().afs_batch_create(ctypes.cast(handles, ctypes.POINTER(_vp)), len(made), ctypes.byref(opts),
+                                      int(device), ctypes.byref(h)))
+        self = cls.__new__(cls)
+        self._attach(h, list(shapes or []))
+        return self
+
+    def _attach(self, h, shapes):
         self.shapes = shapes
         self._h = h
         info = _Info()
@@ -174,6 +199,7 @@ class Instance:
         self.n_tables = info.n_tables
         self.max_k = info.max_k
         self.device = info.device
+        self.n_inst = info.n_inst
         self._ws = {}
 
     @classmethod
@@ -202,6 +228,12 @@ class Instance:
             out.append(BucketInfo(bi.k_lo, bi.k_hi, bi.n_cons, bi.n_lits, bi.lanes_per_restart,
                                   bi.lits_per_lane, bi.slot0))
         return out
+
+    def var_offsets(self):
+        """First variable of each part (int32 [n_inst+1]); [0, n] for a plain instance."""
+        a = np.zeros(self.n_inst + 1, dtype=np.int32)
+        _check(lib().afs_batch_var_offsets(self._h, _np_ptr(a, _i32p)))
+        return a
 
     def slot_map(self):
         a = np.zeros(self.n_lits, dtype=np.int64)
@@ -305,10 +337,11 @@ class Instance:
         return x
 
     def round_verify(self, x, want_bits=False, done=None):
-        """Exact unsat count per restart (int32 [B]); optionally the packed bits."""
+        """Exact unsat count per restart (int32 [B], or [n_inst, B] for a batch);
+        optionally the packed bits."""
         B = self._check_x(x)
         dev = self._dev()
-        unsat = torch.empty(B, dtype=torch.int32, device=dev)
+        unsat = torch.empty((self.n_inst, B) if self.n_inst > 1 else (B,), dtype=torch.int32, device=dev)
         bits = torch.empty((self.n, (B + 31) // 32), dtype=torch.int32, device=dev) if want_bits else None
         ws = self.workspace(B)
         _check(lib().afs_round_verify(self._h, B, _ptr(x), _ptr(bits), _ptr(ws), ws.numel(), _ptr(unsat),
@@ -316,10 +349,13 @@ class Instance:
         return (unsat, bits) if want_bits else unsat
 
     def pgd_state(self, B):
+        """Device state of Algorithm 1: per-(part, restart) arrays shaped (B,) for a
+        plain instance and (n_inst, B) for a batch."""
         dev = self._dev()
-        return {"unsat": torch.zeros(B, dtype=torch.int32, device=dev),
-                "done": torch.zeros(B, dtype=torch.uint8, device=dev),
-                "first_sat": torch.full((B,), -1, dtype=torch.int32, device=dev),
+        shp = (self.n_inst, B) if self.n_inst > 1 else (B,)
+        return {"unsat": torch.zeros(shp, dtype=torch.int32, device=dev),
+                "done": torch.zeros(shp, dtype=torch.uint8, device=dev),
+                "first_sat": torch.full(shp, -1, dtype=torch.int32, device=dev),
                 "counter": torch.zeros(2, dtype=torch.int32, device=dev)}
 
     @staticmethod

@@ -140,6 +140,76 @@ afs_status fe_grad_range(afs_instance *I, int B, const float *x, void *ws, const
     return AFS_OK;
 }
 
+
+afs_status read_options(const afs_options *opts, afs::PackOptions &po)
+{
+    if (!opts) return AFS_OK;
+    if (opts->n_shapes < 0 || (opts->n_shapes > 0 && (!opts->shape_k_hi || !opts->shape_lanes || !opts->shape_seg)))
+        return fail(AFS_EINVAL, "invalid shape arrays");
+    for (int32_t e = 0; e < opts->n_shapes; ++e) {
+        po.k_hi.push_back(opts->shape_k_hi[e]);
+        po.lanes.push_back(opts->shape_lanes[e]);
+        po.seg.push_back(opts->shape_seg[e]);
+    }
+    po.tile_short = opts->tile_short;
+    po.tile_long = opts->tile_long;
+    return AFS_OK;
+}
+
+// Upload the packed host instance to `device` (or keep it host-only for device < 0).
+afs_status finish_create(afs_instance *I, int32_t device, afs_instance **out)
+{
+    if (device < 0) {
+        I->device = -1;
+        *out = I;
+        return AFS_OK;
+    }
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || device >= count) {
+        delete I;
+        return fail(AFS_EINVAL, "no HIP device " + std::to_string(device));
+    }
+    I->device = device;
+    DeviceGuard g(device);
+    if (g.error() != hipSuccess) {
+        I->device = -1;
+        delete I;
+        return dev_fail(g.error(), "hipSetDevice");
+    }
+    const afs::HostInstance &H = I->H;
+    afs::DevInstance &D = I->D;
+    D.n = H.n; D.C = H.C; D.L = H.L; D.n_inst = H.n_inst;
+    std::vector<int32_t> con_off32(H.C + 1);
+    for (int32_t c = 0; c <= H.C; ++c) con_off32[c] = (int32_t)H.con_off[c];
+    std::vector<float4> tab(H.tab.size());
+    for (size_t i = 0; i < H.tab.size(); ++i) tab[i] = make_float4(H.tab[i].x, H.tab[i].y, H.tab[i].z, H.tab[i].w);
+    afs_status st = AFS_OK;
+    if (st == AFS_OK) st = upload(I, H.bc_slot0, &D.bc_slot0);
+    if (st == AFS_OK) st = upload(I, H.bc_k, &D.bc_k);
+    if (st == AFS_OK) st = upload(I, H.bc_tab, &D.bc_tab);
+    if (st == AFS_OK) st = upload(I, H.bc_orig, &D.bc_orig);
+    if (st == AFS_OK) st = upload(I, H.bc_w, &D.bc_w);
+    if (st == AFS_OK) st = upload(I, H.slot_lit, &D.slot_lit);
+    if (st == AFS_OK) st = upload(I, H.slot_to_lit, &D.slot_to_lit);
+    if (st == AFS_OK) st = upload(I, tab, &D.tab);
+    if (st == AFS_OK) st = upload(I, H.voff, &D.voff);
+    if (st == AFS_OK) st = upload(I, H.vslot, &D.vslot);
+    if (st == AFS_OK) st = upload(I, con_off32, &D.con_off);
+    if (st == AFS_OK) st = upload(I, H.lits, &D.lits);
+    if (st == AFS_OK) st = upload(I, H.types, &D.types);
+    if (st == AFS_OK) st = upload(I, H.params, &D.params);
+    if (st == AFS_OK) st = upload(I, H.con_inst, &D.con_inst);
+    if (st == AFS_OK) st = upload(I, H.var_inst, &D.var_inst);
+    if (st != AFS_OK) {
+        const std::string msg = g_err;
+        release(I);
+        g_err = msg;
+        return st;
+    }
+    *out = I;
+    return AFS_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -171,17 +241,8 @@ afs_status afs_instance_create_ex(int32_t n_vars, int32_t n_cons, const int64_t 
     if (!out) return fail(AFS_EINVAL, "out is NULL");
     *out = nullptr;
     afs::PackOptions po;
-    if (opts) {
-        if (opts->n_shapes < 0 || (opts->n_shapes > 0 && (!opts->shape_k_hi || !opts->shape_lanes || !opts->shape_seg)))
-            return fail(AFS_EINVAL, "invalid shape arrays");
-        for (int32_t e = 0; e < opts->n_shapes; ++e) {
-            po.k_hi.push_back(opts->shape_k_hi[e]);
-            po.lanes.push_back(opts->shape_lanes[e]);
-            po.seg.push_back(opts->shape_seg[e]);
-        }
-        po.tile_short = opts->tile_short;
-        po.tile_long = opts->tile_long;
-    }
+    afs_status st = read_options(opts, po);
+    if (st != AFS_OK) return st;
     afs_instance *I = new (std::nothrow) afs_instance();
     if (!I) return fail(AFS_ENOMEM, "host allocation failed");
     std::string err;
@@ -195,52 +256,46 @@ afs_status afs_instance_create_ex(int32_t n_vars, int32_t n_cons, const int64_t 
         delete I;
         return fail(AFS_EINVAL, err);
     }
-    if (device < 0) {
-        I->device = -1;
-        *out = I;
-        return AFS_OK;
+    return finish_create(I, device, out);
+}
+
+afs_status afs_batch_create(const afs_instance *const *parts, int32_t n_parts, const afs_options *opts,
+                            int32_t device, afs_instance **out)
+{
+    if (!out) return fail(AFS_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!parts || n_parts < 1) return fail(AFS_EINVAL, "a batch needs at least one instance");
+    afs::PackOptions po;
+    afs_status st = read_options(opts, po);
+    if (st != AFS_OK) return st;
+    std::vector<afs::PartRef> refs(n_parts);
+    for (int32_t i = 0; i < n_parts; ++i) {
+        if (!parts[i]) return fail(AFS_EINVAL, "part " + std::to_string(i) + " is NULL");
+        const afs::HostInstance &P = parts[i]->H;
+        if (P.n_inst != 1) return fail(AFS_EINVAL, "parts must be plain instances, not batches");
+        refs[i] = afs::PartRef{P.n, P.C, P.con_off.data(), P.lits.data(), P.types.data(), P.params.data(),
+                               P.weights.data()};
     }
-    int count = 0;
-    if (hipGetDeviceCount(&count) != hipSuccess || device >= count) {
+    afs_instance *I = new (std::nothrow) afs_instance();
+    if (!I) return fail(AFS_ENOMEM, "host allocation failed");
+    std::string err;
+    try {
+        err = afs::build_batch(refs, po, I->H);
+    } catch (const std::bad_alloc &) {
         delete I;
-        return fail(AFS_EINVAL, "no HIP device " + std::to_string(device));
+        return fail(AFS_ENOMEM, "host allocation failed");
     }
-    I->device = device;
-    DeviceGuard g(device);
-    if (g.error() != hipSuccess) {
-        I->device = -1;
+    if (!err.empty()) {
         delete I;
-        return dev_fail(g.error(), "hipSetDevice");
+        return fail(AFS_EINVAL, err);
     }
-    const afs::HostInstance &H = I->H;
-    afs::DevInstance &D = I->D;
-    D.n = H.n; D.C = H.C; D.L = H.L;
-    std::vector<int32_t> con_off32(H.C + 1);
-    for (int32_t c = 0; c <= H.C; ++c) con_off32[c] = (int32_t)H.con_off[c];
-    std::vector<float4> tab(H.tab.size());
-    for (size_t i = 0; i < H.tab.size(); ++i) tab[i] = make_float4(H.tab[i].x, H.tab[i].y, H.tab[i].z, H.tab[i].w);
-    afs_status st = AFS_OK;
-    if (st == AFS_OK) st = upload(I, H.bc_slot0, &D.bc_slot0);
-    if (st == AFS_OK) st = upload(I, H.bc_k, &D.bc_k);
-    if (st == AFS_OK) st = upload(I, H.bc_tab, &D.bc_tab);
-    if (st == AFS_OK) st = upload(I, H.bc_orig, &D.bc_orig);
-    if (st == AFS_OK) st = upload(I, H.bc_w, &D.bc_w);
-    if (st == AFS_OK) st = upload(I, H.slot_lit, &D.slot_lit);
-    if (st == AFS_OK) st = upload(I, H.slot_to_lit, &D.slot_to_lit);
-    if (st == AFS_OK) st = upload(I, tab, &D.tab);
-    if (st == AFS_OK) st = upload(I, H.voff, &D.voff);
-    if (st == AFS_OK) st = upload(I, H.vslot, &D.vslot);
-    if (st == AFS_OK) st = upload(I, con_off32, &D.con_off);
-    if (st == AFS_OK) st = upload(I, H.lits, &D.lits);
-    if (st == AFS_OK) st = upload(I, H.types, &D.types);
-    if (st == AFS_OK) st = upload(I, H.params, &D.params);
-    if (st != AFS_OK) {
-        const std::string msg = g_err;
-        release(I);
-        g_err = msg;
-        return st;
-    }
-    *out = I;
+    return finish_create(I, device, out);
+}
+
+afs_status afs_batch_var_offsets(const afs_instance *I, int32_t *var0)
+{
+    if (!I || !var0) return fail(AFS_EINVAL, "NULL argument");
+    for (int32_t i = 0; i <= I->H.n_inst; ++i) var0[i] = I->H.inst_var0[i];
     return AFS_OK;
 }
 
@@ -256,6 +311,7 @@ afs_status afs_instance_info(const afs_instance *I, afs_info *out)
     out->n_tables = I->H.n_tables;
     out->max_k = I->H.max_k;
     out->device = I->device;
+    out->n_inst = I->H.n_inst;
     return AFS_OK;
 }
 
@@ -399,7 +455,7 @@ afs_status afs_step(afs_instance *I, int32_t B, float *x, const float *grad, flo
     if (B > 0 && (!x || !grad)) return fail(AFS_EINVAL, "x or grad is NULL");
     DeviceGuard g(I->device);
     if (g.error() != hipSuccess) return dev_fail(g.error(), "hipSetDevice");
-    hipError_t e = afs::launch_step(I->H.n, B, x, grad, lr, fixed, done, (hipStream_t)stream);
+    hipError_t e = afs::launch_step(I->D, B, x, grad, lr, fixed, done, (hipStream_t)stream);
     return e == hipSuccess ? AFS_OK : dev_fail(e, "step launch");
 }
 
@@ -417,9 +473,10 @@ afs_status afs_round_verify(afs_instance *I, int32_t B, const float *x, uint32_t
     DeviceGuard g(I->device);
     if (g.error() != hipSuccess) return dev_fail(g.error(), "hipSetDevice");
     hipStream_t s = (hipStream_t)stream;
-    hipError_t e = afs::launch_round(I->H.n, B, x, bits, unsat, s);
+    const int pairs = I->H.n_inst * B;
+    hipError_t e = afs::launch_round(I->D, B, x, bits, unsat, s);
     if (e == hipSuccess) e = afs::launch_verify(I->D, B, bits, unsat, s);
-    if (e == hipSuccess && done) e = afs::launch_finalize(B, unsat, done, nullptr, nullptr, afs::FIN_VERIFY, s);
+    if (e == hipSuccess && done) e = afs::launch_finalize(pairs, unsat, done, nullptr, nullptr, afs::FIN_VERIFY, s);
     return e == hipSuccess ? AFS_OK : dev_fail(e, "round/verify launch");
 }
 
@@ -436,9 +493,10 @@ afs_status afs_pgd_init(afs_instance *I, int32_t B, const float *x, void *ws, si
     if (g.error() != hipSuccess) return dev_fail(g.error(), "hipSetDevice");
     hipStream_t s = (hipStream_t)stream;
     uint32_t *bits = at<uint32_t>(ws, l.bits);
-    hipError_t e = afs::launch_round(I->H.n, B, x, bits, P->unsat, s);
+    hipError_t e = afs::launch_round(I->D, B, x, bits, P->unsat, s);
     if (e == hipSuccess) e = afs::launch_verify(I->D, B, bits, P->unsat, s);
-    if (e == hipSuccess) e = afs::launch_finalize(B, P->unsat, P->done, P->first_sat, P->counter, afs::FIN_INIT, s);
+    if (e == hipSuccess)
+        e = afs::launch_finalize(I->H.n_inst * B, P->unsat, P->done, P->first_sat, P->counter, afs::FIN_INIT, s);
     return e == hipSuccess ? AFS_OK : dev_fail(e, "PGD init launch");
 }
 
@@ -462,7 +520,8 @@ static afs_status pgd_call(afs_instance *I, int32_t B, float *x, float lr, const
     hipError_t e = afs::launch_scatter_step(I->D, B, l.Bp, at<float>(ws, l.adj), x, lr, fixed, P->done,
                                             bits, P->unsat, s);
     if (e == hipSuccess) e = afs::launch_verify(I->D, B, bits, P->unsat, s);
-    if (e == hipSuccess) e = afs::launch_finalize(B, P->unsat, P->done, P->first_sat, P->counter, afs::FIN_STEP, s);
+    if (e == hipSuccess)
+        e = afs::launch_finalize(I->H.n_inst * B, P->unsat, P->done, P->first_sat, P->counter, afs::FIN_STEP, s);
     return e == hipSuccess ? AFS_OK : dev_fail(e, "PGD step launch");
 }
 

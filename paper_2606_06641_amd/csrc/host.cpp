@@ -317,6 +317,60 @@ std::string build_instance(int32_t n, int32_t C, const int64_t *con_off, const i
         const int v = std::abs(H.slot_lit[s]) - 1;
         H.vslot[fill[v]++] = (int32_t)s;
     }
+    H.n_inst = 1;
+    H.inst_var0 = {0, n};
+    H.con_inst.assign(C, 0);
+    H.var_inst.assign(n, 0);
+    return std::string();
+}
+
+std::string build_batch(const std::vector<PartRef> &parts, const PackOptions &opts, HostInstance &H)
+{
+    if (parts.empty()) return "a batch needs at least one instance";
+    int64_t n = 0, C = 0, L = 0;
+    for (const PartRef &p : parts) {
+        if (p.n < 1 || p.C < 0 || !p.con_off) return "invalid part";
+        n += p.n;
+        C += p.C;
+        L += p.C > 0 ? p.con_off[p.C] : 0;
+    }
+    if (n >= ((int64_t)1 << 31) || C >= ((int64_t)1 << 31) || L >= ((int64_t)1 << 31))
+        return "batch too large";
+    std::vector<int64_t> con_off(C + 1, 0);
+    std::vector<int32_t> lits(L), types(C), params(C);
+    std::vector<float> weights(C);
+    std::vector<int32_t> inst_var0(parts.size() + 1, 0), con_inst(C), var_inst(n);
+    int64_t c0 = 0, l0 = 0;
+    int32_t v0 = 0;
+    for (size_t pi = 0; pi < parts.size(); ++pi) {
+        const PartRef &p = parts[pi];
+        const int64_t pl = p.C > 0 ? p.con_off[p.C] : 0;
+        if (p.C > 0 && (!p.types || (pl > 0 && !p.lits))) return "invalid part arrays";
+        for (int32_t c = 0; c < p.C; ++c) {
+            con_off[c0 + c + 1] = l0 + p.con_off[c + 1];
+            types[c0 + c] = p.types[c];
+            params[c0 + c] = p.params ? p.params[c] : 0;
+            weights[c0 + c] = p.weights ? p.weights[c] : 1.0f;
+            con_inst[c0 + c] = (int32_t)pi;
+        }
+        for (int64_t i = 0; i < pl; ++i) {
+            const int32_t l = p.lits[i];
+            if (l == 0 || l > p.n || l < -p.n) return "literal out of range in part " + std::to_string(pi);
+            lits[l0 + i] = l > 0 ? l + v0 : l - v0;
+        }
+        for (int32_t v = 0; v < p.n; ++v) var_inst[v0 + v] = (int32_t)pi;
+        c0 += p.C;
+        l0 += pl;
+        v0 += p.n;
+        inst_var0[pi + 1] = v0;
+    }
+    std::string e = build_instance((int32_t)n, (int32_t)C, con_off.data(), lits.data(), types.data(),
+                                   params.data(), weights.data(), opts, H);
+    if (!e.empty()) return e;
+    H.n_inst = (int32_t)parts.size();
+    H.inst_var0 = std::move(inst_var0);
+    H.con_inst = std::move(con_inst);
+    H.var_inst = std::move(var_inst);
     return std::string();
 }
 

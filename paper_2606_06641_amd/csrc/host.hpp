@@ -65,7 +65,14 @@ struct HostInstance {
     // variable -> slot transpose (ascending slots per variable)
     std::vector<int32_t> voff;          // [n+1]
     std::vector<int32_t> vslot;         // [L]
+    // sub-instances of a block-diagonal batch (one for a plain instance)
+    int32_t n_inst = 1;
+    std::vector<int32_t> inst_var0;     // [n_inst+1] first variable of each sub-instance
+    std::vector<int32_t> con_inst;      // [C] sub-instance of each constraint (input order)
+    std::vector<int32_t> var_inst;      // [n] sub-instance of each variable
 };
+
+
 
 // Truth predicate of a constraint with t true literals out of k (Table 1 and
 // Table 2; CARD normalised to ">= K" or "< K" as in Appendix A).
@@ -97,5 +104,18 @@ void bucket_shape(int k, int &J, int &S);
 
 // Shape for a length k under the options (overrides, else the default).
 void bucket_shape(int k, const PackOptions &o, int &J, int &S);
+
+// One sub-instance of a batch, given by its own CSR arrays (variables 1..n).
+struct PartRef {
+    int32_t n = 0, C = 0;
+    const int64_t *con_off = nullptr;
+    const int32_t *lits = nullptr, *types = nullptr, *params = nullptr;
+    const float *weights = nullptr;
+};
+
+// Block-diagonal batch: variables and constraints of the parts concatenated (the
+// variables of part p are shifted by the variables of parts 0..p-1), packed as one
+// instance, with the part of every constraint and variable recorded.
+std::string build_batch(const std::vector<PartRef> &parts, const PackOptions &opts, HostInstance &out);
 
 }  // namespace afs

@@ -511,7 +511,8 @@ hipError_t dispatch_seg(int J, int S, dim3 g, hipStream_t s, const FeArgs &a)
 struct ScatterArgs {
     const float *adj;
     float *grad, *x;
-    const int32_t *voff, *vslot;
+    const int32_t *voff, *vslot, *var_inst;
+    int n_inst;
     const uint8_t *fixed, *done;
     uint32_t *bits;
     int32_t *unsat;
@@ -580,12 +581,12 @@ __global__ __launch_bounds__(kBlock) void scatter_step_kernel(ScatterArgs A)
     if (valid) {
         const int64_t at = (int64_t)v * A.B + b;
         xv = A.x[at];
-        const bool frozen = (A.fixed && A.fixed[v]) || (A.done && A.done[b]);
+        const bool frozen = (A.fixed && A.fixed[v]) || (A.done && A.done[(int64_t)A.var_inst[v] * A.B + b]);
         if (!frozen) {
             xv = project_step(xv, g, A.lr);
             A.x[at] = xv;
         }
-        if (v == 0) A.unsat[b] = 0;
+        if (v < A.n_inst) A.unsat[(int64_t)v * A.B + b] = 0;
     }
     store_bits(A.bits, v, A.W, chunk, valid && xv < 0.0f);
 }
@@ -596,6 +597,8 @@ __global__ __launch_bounds__(kBlock) void scatter_step_kernel(ScatterArgs A)
 struct EltArgs {
     float *x;
     const float *xin, *grad;
+    const int32_t *var_inst;
+    int n_inst;
     const uint8_t *fixed, *done;
     uint32_t *bits;
     int32_t *unsat;
@@ -611,7 +614,7 @@ __global__ __launch_bounds__(kBlock) void step_kernel(EltArgs A)
     const int v = (int)(item / A.nchunks), chunk = (int)(item % A.nchunks);
     const int b = chunk * kWave + (threadIdx.x & 63);
     if (b >= A.B) return;
-    if ((A.fixed && A.fixed[v]) || (A.done && A.done[b])) return;
+    if ((A.fixed && A.fixed[v]) || (A.done && A.done[(int64_t)A.var_inst[v] * A.B + b])) return;
     const int64_t at = (int64_t)v * A.B + b;
     A.x[at] = project_step(A.x[at], A.grad[at], A.lr);
 }
@@ -624,7 +627,7 @@ __global__ __launch_bounds__(kBlock) void round_kernel(EltArgs A)
     const int b = chunk * kWave + (threadIdx.x & 63);
     const bool valid = b < A.B;
     const float xv = valid ? A.xin[(int64_t)v * A.B + b] : 0.f;
-    if (valid && v == 0) A.unsat[b] = 0;
+    if (valid && v < A.n_inst) A.unsat[(int64_t)v * A.B + b] = 0;
     store_bits(A.bits, v, A.W, chunk, valid && xv < 0.0f);
 }
 
@@ -635,7 +638,7 @@ __global__ __launch_bounds__(kBlock) void round_kernel(EltArgs A)
 struct VerifyArgs {
     const uint32_t *bits;
     int32_t *unsat;
-    const int32_t *con_off, *lits, *types, *params;
+    const int32_t *con_off, *lits, *types, *params, *con_inst;
     int B, W, C, tile, ntiles;
     int64_t items;
 };
@@ -665,7 +668,14 @@ __global__ __launch_bounds__(kBlock) void verify_kernel(VerifyArgs A)
     const int sh = b & 31;
     const int cbeg = tile * A.tile, cend = min(cbeg + A.tile, A.C);
     int cnt = 0;
+    int inst = cbeg < cend ? A.con_inst[cbeg] : 0;
     for (int c = cbeg; c < cend; ++c) {
+        const int ci = A.con_inst[c];
+        if (ci != inst) {                        // constraints of one sub-instance are contiguous
+            if (valid && cnt) atomicAdd(&A.unsat[(int64_t)inst * A.B + b], cnt);
+            cnt = 0;
+            inst = ci;
+        }
         const int o0 = A.con_off[c], o1 = A.con_off[c + 1];
         int t = 0;
 #pragma unroll 4
@@ -677,18 +687,18 @@ __global__ __launch_bounds__(kBlock) void verify_kernel(VerifyArgs A)
         }
         cnt += sat_pred(A.types[c], o1 - o0, A.params[c], t) ? 0 : 1;
     }
-    if (valid && cnt) atomicAdd(&A.unsat[b], cnt);
+    if (valid && cnt) atomicAdd(&A.unsat[(int64_t)inst * A.B + b], cnt);
 }
 
 // One block: done / first_sat bookkeeping and the {t, number done} counter.
-__global__ __launch_bounds__(1024) void finalize_kernel(int B, const int32_t *unsat, uint8_t *done,
+__global__ __launch_bounds__(1024) void finalize_kernel(int count, const int32_t *unsat, uint8_t *done,
                                                         int32_t *first_sat, int32_t *counter, int mode)
 {
     __shared__ int red[1024 / kWave];
     const int t = (mode == FIN_STEP) ? counter[0] + 1 : 0;
     __syncthreads();
     int cnt = 0;
-    for (int b = threadIdx.x; b < B; b += blockDim.x) {
+    for (int b = threadIdx.x; b < count; b += blockDim.x) {
         const bool ok = unsat[b] == 0;
         if (mode == FIN_INIT) {
             done[b] = ok ? 1 : 0;
@@ -783,7 +793,7 @@ static ScatterArgs scatter_args(const DevInstance &I, int B, int Bp, const float
 {
     ScatterArgs a{};
     a.adj = adj;
-    a.voff = I.voff; a.vslot = I.vslot;
+    a.voff = I.voff; a.vslot = I.vslot; a.var_inst = I.var_inst; a.n_inst = I.n_inst;
     a.B = B; a.Bp = Bp; a.W = (B + 31) / 32;
     a.nchunks = Bp / kWave;
     a.items = (int64_t)I.n * a.nchunks;
@@ -833,21 +843,24 @@ static EltArgs elt_args(int n, int B)
     return a;
 }
 
-hipError_t launch_step(int n, int B, float *x, const float *grad, float lr, const uint8_t *fixed,
-                       const uint8_t *done, hipStream_t s)
+hipError_t launch_step(const DevInstance &I, int B, float *x, const float *grad, float lr,
+                       const uint8_t *fixed, const uint8_t *done, hipStream_t s)
 {
     if (B == 0) return hipSuccess;
-    EltArgs a = elt_args(n, B);
+    EltArgs a = elt_args(I.n, B);
     a.x = x; a.grad = grad; a.lr = lr; a.fixed = fixed; a.done = done;
+    a.var_inst = I.var_inst; a.n_inst = I.n_inst;
     hipLaunchKernelGGL(step_kernel, grid_for_waves(a.items), dim3(kBlock), 0, s, a);
     return hipGetLastError();
 }
 
-hipError_t launch_round(int n, int B, const float *x, uint32_t *bits, int32_t *unsat, hipStream_t s)
+hipError_t launch_round(const DevInstance &I, int B, const float *x, uint32_t *bits, int32_t *unsat,
+                        hipStream_t s)
 {
     if (B == 0) return hipSuccess;
-    EltArgs a = elt_args(n, B);
+    EltArgs a = elt_args(I.n, B);
     a.xin = x; a.bits = bits; a.unsat = unsat;
+    a.var_inst = I.var_inst; a.n_inst = I.n_inst;
     hipLaunchKernelGGL(round_kernel, grid_for_waves(a.items), dim3(kBlock), 0, s, a);
     return hipGetLastError();
 }
@@ -859,6 +872,7 @@ hipError_t launch_verify(const DevInstance &I, int B, const uint32_t *bits, int3
     VerifyArgs a{};
     a.bits = bits; a.unsat = unsat;
     a.con_off = I.con_off; a.lits = I.lits; a.types = I.types; a.params = I.params;
+    a.con_inst = I.con_inst;
     a.B = B; a.W = (B + 31) / 32; a.C = I.C;
     a.tile = 32;
     a.ntiles = (I.C + a.tile - 1) / a.tile;
@@ -867,11 +881,11 @@ hipError_t launch_verify(const DevInstance &I, int B, const uint32_t *bits, int3
     return hipGetLastError();
 }
 
-hipError_t launch_finalize(int B, const int32_t *unsat, uint8_t *done, int32_t *first_sat,
+hipError_t launch_finalize(int count, const int32_t *unsat, uint8_t *done, int32_t *first_sat,
                            int32_t *counter, int mode, hipStream_t s)
 {
-    if (B == 0) return hipSuccess;
-    hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(1024), 0, s, B, unsat, done, first_sat, counter, mode);
+    if (count == 0) return hipSuccess;
+    hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(1024), 0, s, count, unsat, done, first_sat, counter, mode);
     return hipGetLastError();
 }
 

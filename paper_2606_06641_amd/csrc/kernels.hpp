@@ -21,6 +21,9 @@ struct DevInstance {
     const int32_t *voff = nullptr, *vslot = nullptr;
     // original-order constraints (verification)
     const int32_t *con_off = nullptr, *lits = nullptr, *types = nullptr, *params = nullptr;
+    // block-diagonal batches: sub-instance of each constraint / variable
+    int32_t n_inst = 1;
+    const int32_t *con_inst = nullptr, *var_inst = nullptr;
 };
 
 struct BucketLaunch {
@@ -40,7 +43,8 @@ hipError_t launch_fe_grad(const DevInstance &I, const BucketLaunch &bk, int B, i
 hipError_t launch_scatter(const DevInstance &I, int B, int Bp, const float *adj, float *grad,
                           hipStream_t s);
 
-// Fused: gradient sum, projected step, rounding into bits [n][W] and unsat[b] = 0.
+// Per-(sub-instance, restart) arrays (unsat, done, first_sat) are [n_inst][B].
+// Fused: gradient sum, projected step, rounding into bits [n][W] and unsat = 0.
 hipError_t launch_scatter_step(const DevInstance &I, int B, int Bp, const float *adj, float *x,
                                float lr, const uint8_t *fixed, const uint8_t *done,
                                uint32_t *bits, int32_t *unsat, hipStream_t s);
@@ -49,18 +53,20 @@ hipError_t launch_scatter_step(const DevInstance &I, int B, int Bp, const float 
 hipError_t launch_obj_reduce(int tiles, int B, int Bp, const float *part, float *part2,
                              float *obj, hipStream_t s);
 
-hipError_t launch_step(int n, int B, float *x, const float *grad, float lr, const uint8_t *fixed,
-                       const uint8_t *done, hipStream_t s);
+hipError_t launch_step(const DevInstance &I, int B, float *x, const float *grad, float lr,
+                       const uint8_t *fixed, const uint8_t *done, hipStream_t s);
 
-// bits from x and unsat[b] = 0.
-hipError_t launch_round(int n, int B, const float *x, uint32_t *bits, int32_t *unsat, hipStream_t s);
+// bits from x and unsat = 0.
+hipError_t launch_round(const DevInstance &I, int B, const float *x, uint32_t *bits, int32_t *unsat,
+                        hipStream_t s);
 
 // unsat[b] += number of violated constraints (unsat must be zeroed before).
 hipError_t launch_verify(const DevInstance &I, int B, const uint32_t *bits, int32_t *unsat,
                          hipStream_t s);
 
 enum FinalizeMode { FIN_INIT = 0, FIN_STEP = 1, FIN_VERIFY = 2 };
-hipError_t launch_finalize(int B, const int32_t *unsat, uint8_t *done, int32_t *first_sat,
+// over all n_inst * B (sub-instance, restart) pairs
+hipError_t launch_finalize(int count, const int32_t *unsat, uint8_t *done, int32_t *first_sat,
                            int32_t *counter, int mode, hipStream_t s);
 
 // adj_out[slot_to_lit[s]][b] = adj[s][b]

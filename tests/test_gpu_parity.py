@@ -306,3 +306,38 @@ def concat(parts, n):
         params.append(p.params)
     return W.Instance(n=n, con_off=np.concatenate(offs), lits=np.concatenate(lits),
                       types=np.concatenate(types), params=np.concatenate(params))
+
+
+def test_batch_of_uneven_instances():
+    """A block-diagonal batch of instances of different sizes and types: FE and
+    gradient match the oracle on the concatenation, verification is exact per
+    (part, restart), and PGD freezes exactly the (part, restart) pairs that verify."""
+    rng = np.random.default_rng(50)
+    parts = [W.planted_3sat(n=60, m=250, instance=7),
+             W.random_instance(rng, n=300, count=200, k_lo=2, k_hi=30),
+             W.planted_3sat(n=100, m=426, instance=8),
+             W.random_instance(rng, n=900, count=40, k_lo=17, k_hi=300),
+             W.planted_3sat(n=40, m=120, instance=9)]
+    Bt = afsat.Instance.batch(parts)
+    off = Bt.var_offsets()
+    cat = concat([W.Instance(n=p.n, con_off=p.con_off, lits=np.where(p.lits > 0, p.lits + o, p.lits - o).astype(np.int32),
+                             types=p.types, params=p.params) for p, o in zip(parts, off[:-1])], n=int(off[-1]))
+    B = 40
+    x = rng.uniform(-1, 1, size=(cat.n, B)).astype(np.float32)
+    parity.compare(cat, Bt, parity.gpu_eval(Bt, x), oracle.eval(cat, x, fe=True, adj=True, grad=True), "batch")
+    xd = parity.to_dev(x)
+    u = Bt.round_verify(xd).cpu().numpy()
+    assert u.shape == (len(parts), B)
+    for p, part in enumerate(parts):
+        assert np.array_equal(u[p], oracle.verify(part, x[off[p]:off[p + 1]]))
+    res = Bt.pgd(xd, lr=0.1, steps=60, stop_on_sat=False)
+    xs = xd.cpu().numpy()
+    done = res["done"].cpu().numpy().astype(bool)
+    fs = res["first_sat"].cpu().numpy()
+    assert done.shape == (len(parts), B) and np.all((fs >= 0) == done)
+    for p, part in enumerate(parts):
+        up = oracle.verify(part, xs[off[p]:off[p + 1]])
+        assert np.array_equal(up, res["unsat"].cpu().numpy()[p])
+        assert np.all(up[done[p]] == 0)
+    assert done.sum() == int(res["counter"][1])
+    assert done[0].any() or done[2].any() or done[4].any()     # small planted parts get solved

@@ -203,3 +203,21 @@ def test_tables_shared_between_equal_truth_tables():
     H = _create(6, [0, 3, 6, 9, 12], [1, 2, 3, 4, 5, 6, 1, 2, 3, 4, 5, 6],
                 [W.CARD_GE, W.CARD_GE, W.XOR, W.XOR], [0, -5, 1, 3])
     assert H.n_tables == 2
+
+
+def test_batch_packing_concatenates_parts():
+    rng = np.random.default_rng(5)
+    parts = [W.random_instance(rng, n=n, count=c, k_lo=1, k_hi=40) for n, c in [(50, 30), (200, 10), (80, 60)]]
+    Bt = afsat.Instance.batch(parts, device=-1)
+    assert Bt.n_inst == 3 and Bt.n == 330 and Bt.n_cons == 100
+    assert list(Bt.var_offsets()) == [0, 50, 250, 330]
+    # literal slots hold the parts' literals shifted by their variable offsets
+    smap = Bt.slot_map()
+    want = np.concatenate([np.where(p.lits > 0, p.lits + o, p.lits - o)
+                           for p, o in zip(parts, [0, 50, 250])])
+    voff, vslot = Bt.transpose()
+    lit_of_slot = want[smap]
+    for v in range(Bt.n):
+        assert np.all(np.abs(lit_of_slot[vslot[voff[v]:voff[v + 1]]]) == v + 1)
+    with pytest.raises(afsat.AfsError):
+        afsat.Instance.batch([Bt], device=-1)          # batches do not nest

@@ -113,7 +113,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="mixed10k", choices=["mixed10k", "batch64", "longcard50k"])
+    ap.add_argument("--workload", default="mixed10k",
+                    choices=["mixed10k", "batch64", "longcard50k", "learned3sat", "learned5k"])
+    ap.add_argument("--train", type=int, default=0, help="learned-init workloads: training instances")
+    ap.add_argument("--test", type=int, default=0, help="learned-init workloads: held-out test instances")
     ap.add_argument("--restarts", type=int, default=0, help="override the workload's restart count")
     ap.add_argument("--lr", type=float, default=0.1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -138,6 +141,9 @@ def main():
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    if args.workload.startswith("learned"):
+        learned_init_bench(args, W)
+        return
     t_setup = time.perf_counter()
     work, B, desc = build_workload(args.workload, W)
     B = args.restarts or B
@@ -277,6 +283,65 @@ def main():
               int(st["counter"][1].item())), file=sys.stderr, flush=True)
     if not args.no_cpu_baseline and args.workload == "mixed10k":
         line["cpu_baseline"] = cpu_baseline(inst, x0, args.lr, args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+
+
+def learned_init_bench(args, W):
+    """Time to a verified assignment from learned vs uniform random starting points.
+
+    learned3sat: planted random 3-SAT, n = 100, 426 clauses (ratio 4.26), which
+    Algorithm 1 solves; learned5k: planted mixed instances of the n = 10k workload's
+    shape at n = 5,000 (15,000 clauses k3-8, 1,000 XOR k3-5, 250 CARD>=K k20-200).
+    The network (3 rounds, width 64) trains on targets the solver itself produces
+    on the training instances; the way its output is turned into starting points
+    (sign sampling temperature) is chosen on separate validation instances; both
+    arms then run on held-out test instances with the same noise seed."""
+    import numpy as np
+    import torch
+    from paper_2606_06641_amd import gnn
+    log = lambda m: print(m, file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    if args.workload == "learned3sat":
+        n_train, n_val, n_test = args.train or 512, 32, args.test or 100
+        make = lambda i: W.planted_3sat(n=100, m=426, instance=i)
+        B, max_steps, target_steps, train_steps = 1024, 300, 150, 800
+        desc = "planted 3-SAT n=100 m=426"
+    else:
+        n_train, n_val, n_test = args.train or 64, 8, args.test or 16
+        make = lambda i: W.mixed_5k(instance=i)
+        B, max_steps, target_steps, train_steps = 1024, 300, 200, 400
+        desc = ("planted mixed n=5000: 15000 clauses k3-8, 1000 XOR k3-5, 250 CARD>=K k20-200")
+    train_set = [make(10000 + i) for i in range(n_train)]
+    val_set = [make(20000 + i) for i in range(n_val)]
+    test_set = [make(30000 + i) for i in range(n_test)]
+    log("generated %d/%d/%d instances in %.1f s" % (n_train, n_val, n_test, time.perf_counter() - t0))
+    targets, verified = gnn.collect_targets(train_set, B=256, steps=target_steps)
+    log("targets: %d of %d verified (%.1f s)" % (verified, n_train, time.perf_counter() - t0))
+    net = gnn.GNN(rounds=3, seed=1)
+    losses = gnn.train(net, train_set, targets, train_steps, log=log)
+    log("trained (%.1f s)" % (time.perf_counter() - t0))
+    variants = [dict(sample=True, temperature=T) for T in (1.0, 2.0, 4.0)] + [dict(mix=0.8)]
+    best, best_key = None, None
+    for v in variants:
+        res = gnn.compare(net, val_set, B, max_steps, v, seed=1)
+        s = gnn.summarize(res, max_steps)["learned"]
+        key = (-s["solved"], s["median_iters"], s["mean_best_unsat_unsolved"])
+        log("validation %s: %s" % (v, s))
+        if best_key is None or key < best_key:
+            best, best_key = v, key
+    res = gnn.compare(net, test_set, B, max_steps, best, seed=2)
+    summ = gnn.summarize(res, max_steps)
+    timeout = summ["timeout_s"]
+    line = {"metric": "median time to a verified assignment, learned init", "value": summ["learned"]["median_s"],
+            "unit": "s", "higher_is_better": False, "n_gpus": 1, "dtype": "f32 (solver), bf16 MFMA (network)",
+            "data": "synthetic",
+            "config": {"workload": desc, "train": n_train, "validation": n_val, "test": n_test, "restarts": B,
+                       "max_iterations": max_steps, "lr": 0.1, "training_targets_verified": verified,
+                       "train_steps": train_steps, "inference": best,
+                       "final_loss": losses[-1][1] if losses else None},
+            "learned": summ["learned"], "random": summ["random"],
+            "vs_random_median": summ["learned"]["median_s"] / summ["random"]["median_s"],
+            "timeout_s_for_par2": timeout, "wall_s": time.perf_counter() - t0}
     print(json.dumps(line), flush=True)
 
 

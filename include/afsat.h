@@ -284,6 +284,64 @@ afs_status afs_pgd_step(afs_instance *inst, int32_t B, float *x, float lr, const
 afs_status afs_pgd_update(afs_instance *inst, int32_t B, float *x, float lr, const uint8_t *fixed,
                           void *ws, size_t ws_bytes, const afs_pgd_state *st, void *stream);
 
+/* ---- learned initialisation: message-passing network ---------------------------- */
+
+/* A network over the variable-constraint graph of an instance (3 rounds by
+ * default, hidden width 64) that maps uniform random starting points x0 [n][B]
+ * to starting points xhat in (-1,1) for Algorithm 1; trained by its own forward,
+ * backward (BCE on a target assignment) and Adam kernels.  Dense layers run on
+ * BF16 MFMA with FP32 accumulation.  Parameters live on the device in one flat
+ * FP32 array (gradients and Adam moments alongside).  A network is used from one
+ * stream at a time. */
+typedef struct afs_gnn afs_gnn;
+
+/* Create with seeded He-normal weights; rounds 1..8. */
+afs_status afs_gnn_create(int32_t rounds, uint64_t seed, int32_t device, afs_gnn **out);
+void afs_gnn_destroy(afs_gnn *net);
+afs_status afs_gnn_num_params(const afs_gnn *net, int64_t *count);
+/* Synchronous host copies of the flat arrays: which = 0 parameters, 1 gradients,
+ * 2 and 3 the Adam moments; host holds afs_gnn_num_params floats. */
+afs_status afs_gnn_get(const afs_gnn *net, int32_t which, float *host);
+afs_status afs_gnn_set(afs_gnn *net, int32_t which, const float *host);
+
+/* Host copy of the input features and signed incidence lists of an instance:
+ * fcon [C][16], fvar [n][16], var_off int32 [n+1], var_con int32 [L] (constraint
+ * of each occurrence, grouped by variable), var_sgn [L] (+1 / -1).  The last three
+ * may be NULL. */
+afs_status afs_gnn_features(afs_instance *inst, float *fcon, float *fvar, int32_t *var_off,
+                            int32_t *var_con, float *var_sgn);
+
+/* Workspace bytes for an instance and B restarts (caller-owned, 256-byte aligned). */
+afs_status afs_gnn_workspace_bytes(const afs_gnn *net, const afs_instance *inst, int32_t B,
+                                   size_t *bytes);
+
+/* xhat [n][B] (device) from x0 [n][B] (device). */
+afs_status afs_gnn_forward(afs_gnn *net, afs_instance *inst, int32_t B, const float *x0, void *ws,
+                           size_t ws_bytes, float *xhat, void *stream);
+
+/* Forward, then the mean binary cross-entropy against target [n] (device u8, 1 =
+ * variable True) over all (v, b), written to loss [1] (device), and its gradient
+ * accumulated into the network's gradient array. */
+afs_status afs_gnn_backward(afs_gnn *net, afs_instance *inst, int32_t B, const float *x0,
+                            const uint8_t *target, void *ws, size_t ws_bytes, float *loss,
+                            void *stream);
+
+afs_status afs_gnn_zero_grad(afs_gnn *net, void *stream);
+
+/* One Adam step (bias-corrected, step number t >= 1). */
+afs_status afs_gnn_adam(afs_gnn *net, float lr, float beta1, float beta2, float eps, int32_t t,
+                        void *stream);
+
+/* The network's dense-layer kernel on its own: C[M][N] = A B with A(m,k) =
+ * A[m*sam + k*sak] and B(k,n) = B[k*sbk + n*sbn] (device f32, element strides),
+ * both rounded to BF16, FP32 accumulation, C row stride ldc. */
+afs_status afs_gnn_gemm_bf16(int32_t M, int32_t N, int32_t K, const float *A, int64_t sam, int64_t sak,
+                             const float *B, int64_t sbk, int64_t sbn, float *C, int64_t ldc,
+                             void *stream);
+
+/* Thread-local message for the last non-OK status of an afs_gnn_* call. */
+const char *afs_gnn_last_error(void);
+
 /* Thread-local message describing the last non-OK status. */
 const char *afs_last_error(void);
 

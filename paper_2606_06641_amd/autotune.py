@@ -86,9 +86,10 @@ def tune(inst, B, device=0, reps=7, cache_path=None, out_path=None, log=None, ma
               getattr(inst, "weights", None))
     lens = np.diff(arrays[1])
     cache = {}
-    if cache_path and os.path.exists(cache_path):
-        with open(cache_path) as f:
-            cache = json.load(f)
+    for path in (cache_path, out_path):
+        if path and os.path.exists(path):
+            with open(path) as f:
+                cache.update(json.load(f))
     arch = arch_name(device)
     shapes, report = [], []
     for lo, hi in length_ranges():

@@ -27,6 +27,7 @@ SOURCES = [
     ("host.cpp", ["g++"] + COMMON),
     ("api.cpp", [HIPCC] + COMMON + ["-x", "c++", "-D__HIP_PLATFORM_AMD__", "-I", "/opt/rocm/include"]),
     ("kernels.hip", [HIPCC] + COMMON + DEVICE),
+    ("gnn.hip", [HIPCC] + COMMON + DEVICE),
 ]
 
 

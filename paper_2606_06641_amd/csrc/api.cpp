@@ -9,14 +9,9 @@
 #include <vector>
 
 #include "host.hpp"
+#include "instance.hpp"
 #include "kernels.hpp"
 
-struct afs_instance {
-    afs::HostInstance H;
-    afs::DevInstance D;
-    int device = -1;
-    std::vector<void *> allocs;
-};
 
 namespace {
 

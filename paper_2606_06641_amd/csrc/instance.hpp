@@ -1,0 +1,29 @@
+// instance.hpp -- the opaque afs_instance (shared by the C ABI translation units).
+#pragma once
+
+#include <cstdint>
+#include <vector>
+
+#include "host.hpp"
+#include "kernels.hpp"
+
+// Device copy of the variable-constraint graph used by the message-passing
+// network (built on first use, owned by the instance).
+struct GnnGraph {
+    bool built = false;
+    const float *fcon = nullptr;     // [C][16] constraint features
+    const float *fvar = nullptr;     // [n][16] variable features
+    const int32_t *var_off = nullptr; // [n+1] incidences of each variable
+    const int32_t *var_con = nullptr; // [L] constraint of each incidence
+    const float *var_sgn = nullptr;   // [L] literal sign (+1 / -1)
+    const float *inv_k = nullptr;     // [C] 1 / constraint length
+    const float *inv_deg = nullptr;   // [n] 1 / max(1, occurrences)
+};
+
+struct afs_instance {
+    afs::HostInstance H;
+    afs::DevInstance D;
+    int device = -1;
+    std::vector<void *> allocs;      // every device allocation, freed at destroy
+    GnnGraph gnn;
+};

@@ -1,0 +1,124 @@
+"""Learned initialisation on the GPU: the network's own kernels against the FP64
+NumPy reference (BF16 operands emulated there), training, and the effect of the
+trained network on Algorithm 1."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import gnn as G
+import parity
+from paper_2606_06641_amd import afsat, gnn
+from paper_2606_06641_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    gnn.lib()
+
+
+def log(*a):
+    print(*a, flush=True)
+
+
+@pytest.mark.parametrize("M,N,K,transA,transB", [(37, 70, 50, False, False), (128, 64, 2000, True, False),
+                                                  (16, 16, 16, False, True), (200, 128, 64, False, True)])
+def test_gemm_bf16(M, N, K, transA, transB):
+    rng = np.random.default_rng(M + N + K)
+    A = rng.normal(size=(M, K)).astype(np.float32)
+    Bm = rng.normal(size=(K, N)).astype(np.float32)
+    At = torch.from_numpy(np.ascontiguousarray(A.T)).cuda().t() if transA else torch.from_numpy(A).cuda()
+    Bt = torch.from_numpy(np.ascontiguousarray(Bm.T)).cuda().t() if transB else torch.from_numpy(Bm).cuda()
+    C = gnn.gemm_bf16(At, Bt).cpu().numpy()
+    want = G.bf16(A) @ G.bf16(Bm)
+    err = np.max(np.abs(C - want)) / max(1.0, np.max(np.abs(want)))
+    log("gemm", M, N, K, transA, transB, "rel err %.2e" % err)
+    assert err <= 1e-5
+
+
+def mixed_small(seed):
+    rng = np.random.default_rng(seed)
+    a = W.random_instance(rng, n=90, count=120, k_lo=1, k_hi=9)
+    b = W.random_instance(rng, n=90, count=6, k_lo=20, k_hi=60)
+    return W.Instance(n=90, con_off=np.concatenate([a.con_off, b.con_off[1:] + a.n_lits]),
+                      lits=np.concatenate([a.lits, b.lits]), types=np.concatenate([a.types, b.types]),
+                      params=np.concatenate([a.params, b.params]))
+
+
+def test_forward_backward_match_reference():
+    inst = mixed_small(3)
+    d = afsat.Instance.from_arrays(inst)
+    net = gnn.GNN(rounds=3, seed=7)
+    rng = np.random.default_rng(4)
+    B = 37
+    x0 = rng.uniform(-1, 1, size=(inst.n, B)).astype(np.float32)
+    target = rng.integers(0, 2, size=inst.n).astype(np.uint8)
+    xd = parity.to_dev(x0)
+    xhat = net.forward(d, xd).cpu().numpy()
+    net.zero_grad()
+    loss = float(net.loss_backward(d, xd, torch.from_numpy(target).cuda()).item())
+    grads = net.get(1).astype(np.float64)
+    params = net.get(0).astype(np.float64)
+    rl, rg, rx = G.loss_and_grad(params, inst, x0, target, R=3, bf16_ops=True)
+    xerr = np.max(np.abs(xhat - rx))
+    log("xhat max err %.2e  loss %.6f vs %.6f" % (xerr, loss, rl))
+    assert xerr <= 2e-3
+    assert abs(loss - rl) <= 1e-4 * max(1.0, abs(rl))
+    lay, _ = G.layout(3)
+    for name, (o, shp) in lay.items():
+        g1 = grads[o:o + int(np.prod(shp))]
+        g2 = rg[o:o + int(np.prod(shp))]
+        rel = np.linalg.norm(g1 - g2) / max(np.linalg.norm(g2), 1e-12)
+        log("grad %-4s rel-L2 %.2e  |g| %.2e" % (name, rel, np.linalg.norm(g2)))
+        assert rel <= 2e-2, name
+    # gradients accumulate across calls; zero_grad clears them
+    net.loss_backward(d, xd, torch.from_numpy(target).cuda())
+    assert np.allclose(net.get(1), 2 * grads, rtol=1e-5, atol=1e-9)
+    net.zero_grad()
+    assert np.all(net.get(1) == 0)
+
+
+def test_training_reduces_loss_and_batches_work():
+    parts = [W.planted_3sat(n=80, m=340, instance=20 + i) for i in range(4)]
+    bt = afsat.Instance.batch(parts)
+    target = torch.from_numpy(np.concatenate([p.hidden for p in parts]).astype(np.uint8)).cuda()
+    net = gnn.GNN(rounds=3, seed=1)
+    gen = torch.Generator(device="cuda").manual_seed(0)
+    losses = []
+    for step in range(80):
+        x0 = gnn.uniform_start(bt.n, 16, gen)
+        net.zero_grad()
+        losses.append(float(net.loss_backward(bt, x0, target).item()))
+        net.adam(lr=3e-3)
+    log("loss %.4f -> %.4f" % (losses[0], losses[-1]))
+    assert np.mean(losses[-10:]) < 0.8 * np.mean(losses[:5])
+    # the trained network agrees with the planted assignment better than chance
+    xhat = net.forward(bt, gnn.uniform_start(bt.n, 64, gen))
+    agree = ((xhat < 0).float().mean(dim=1).cpu().numpy() > 0.5) == np.concatenate([p.hidden for p in parts])
+    log("agreement with hidden assignment %.3f" % agree.mean())
+    assert agree.mean() > 0.6
+
+
+def test_learned_init_helps_on_held_out_instances():
+    """Train on solver-produced targets (the best restart of Algorithm 1 on each
+    training instance), then compare learned starting points (signs sampled from
+    the network's softened marginals) with uniform random ones on held-out
+    planted 3-SAT: the learned arm solves at least as many and needs no more
+    iterations (median) to its first verified assignment."""
+    train = [W.planted_3sat(n=100, m=426, instance=1000 + i) for i in range(160)]
+    targets, ok = gnn.collect_targets(train, B=256, steps=150)
+    log("training targets verified: %d / %d" % (ok, len(train)))
+    net = gnn.GNN(rounds=3, seed=2)
+    gnn.train(net, train, targets, 500)
+    tests = [W.planted_3sat(n=100, m=426, instance=5000 + i) for i in range(24)]
+    res = gnn.compare(net, tests, 256, 300, dict(sample=True, temperature=2.0), seed=3)
+    s = gnn.summarize(res, 300)
+    log("held-out: random %s" % s["random"])
+    log("held-out: learned %s" % s["learned"])
+    assert s["learned"]["solved"] >= s["random"]["solved"]
+    assert s["learned"]["median_iters"] <= s["random"]["median_iters"]

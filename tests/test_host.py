@@ -29,7 +29,7 @@ HEADER = os.path.join(ROOT, "include", "afsat.h")
 def declared_functions():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(afs_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(afs_[a-z_0-9]+)\s*\(", text)))
 
 
 def test_library_exports_every_declared_function():
@@ -38,8 +38,11 @@ def test_library_exports_every_declared_function():
     assert len(names) >= 15
     for name in names:
         assert hasattr(L, name), name
-    # and the binding's signature list is exactly the header's
-    assert sorted(n for n, _, _ in afsat.SIGNATURES) == names
+    # and the bindings' signature lists are exactly the header's
+    from paper_2606_06641_amd import gnn
+    bound = [n for n, _, _ in afsat.SIGNATURES] + [n for n, _, _ in gnn.GNN_SIGNATURES]
+    assert sorted(bound) == names
+    gnn.lib()
 
 
 def g_table(ctype, k, param):
@@ -221,3 +224,14 @@ def test_batch_packing_concatenates_parts():
         assert np.all(np.abs(lit_of_slot[vslot[voff[v]:voff[v + 1]]]) == v + 1)
     with pytest.raises(afsat.AfsError):
         afsat.Instance.batch([Bt], device=-1)          # batches do not nest
+
+
+def test_gnn_host_features_match_reference_definition():
+    from oracle import gnn as G
+    from paper_2606_06641_amd import gnn
+    rng = np.random.default_rng(9)
+    inst = W.random_instance(rng, n=60, count=80, k_lo=1, k_hi=30)
+    inst.weights = rng.uniform(0.5, 2, size=inst.n_cons).astype(np.float32)
+    fc, fv = gnn.features(afsat.Instance.from_arrays(inst, device=-1))
+    rc, rv = G.features(inst)
+    assert np.array_equal(fc.astype(np.float64), rc) and np.array_equal(fv.astype(np.float64), rv)

@@ -92,7 +92,7 @@ void bucket_shape(int k, int &J, int &S)
         int lg = 0;
         while ((1 << lg) < j) ++lg;
         const double scan = 14.0 * lg + 30.0 + (j > 16 ? 40.0 : 0.0);
-        for (int s = 8; s <= kMaxSeg; s += 8) {
+        for (int s = 8; s <= kMaxSeg; s += 4) {
             if (j * s < k) continue;
             const double cost = j * (8.0 * s + scan) / k;
             if (cost < best - 1e-9) { best = cost; J = j; S = s; }
@@ -100,27 +100,41 @@ void bucket_shape(int k, int &J, int &S)
     }
 }
 
-// Rows m = 1..floor(k/2) of a coefficient table (two float4 rows per root).
+// Rows m = 1..floor(k/2) of a coefficient table.
 // With alpha_m = (1 + omega^m)/2 = c e^{i h} (h = pi m / N, c = cos h) every factor is
 // a = alpha_m (1 + i z), z = -tan(h) y.  Kernels multiply the unit-real-part
-// factors (1 + i z) and restore the alpha powers with a rescale by alpha^8 after
-// every 8 literals, so the stored prefix at literal s lacks alpha^(s mod 8) and
-// the stored suffix alpha^(C - s mod 8); their product lacks alpha^C for every s,
-// and the constant
+// factors (1 + i z).  A segment kernel (S literals per lane) multiplies its running
+// prefix and suffix products by alpha^RP at the positions RP, 2 RP, ... < S (RP = 16
+// when every length in its bucket is <= 256, else 8): the stored prefix at literal s
+// lacks alpha^p(s) and the suffix alpha^q(s) with p(s) + q(s) = C = F - 1 for every s,
+// where F = S - RP floor((S-1)/RP) is the number of unscaled factors left in the
+// segment product (restored by alpha^F).  The constant
 //     Kc = 2 d_m beta_m alpha^C,  beta_m = (1 - omega^m)/2,
-// turns prefix * suffix into the adjoint term.  The FE term uses dF = d_m alpha^F
-// where F is the number of unscaled factors left in the final product.
-//   row A: {Re dF, Im dF, Re Kc, Im Kc}     row B: {Re alpha^8, Im alpha^8, -tan h, 0}
-// Short kernels (one lane per restart, k <= 16): C = k-1-8[k>8], F = k-8[k>8].
-// Segment kernels (S a multiple of 8): C = 7, F = 0 (they rescale the segment
-// product by alpha^8 themselves).
-void append_root_rows(int k, const double *re, const double *im, std::vector<TabRow> &tab)
+// turns prefix * suffix into the adjoint term.  Rows per root:
+//   short kernel (k <= 16, one lane per restart, no rescaling, C = k-1):
+//     {Re(d alpha^k), Im(d alpha^k), Re Kc, Im Kc}, {0, 0, -tan h, 0}
+//   segment kernel:
+//     {Re d, Im d, Re Kc, Im Kc}, {Re alpha^RP, Im alpha^RP, Re alpha^F, Im alpha^F},
+//     {-tan h, 0, 0, 0}
+// (The magnitudes stay in FP32 range: |1 + i z| <= 1/c <= 1/sin(pi/(2N)), so 16
+// unscaled factors stay below 2^128 up to k = 256 and 8 up to k = 1024.)
+int rescale_period(int J, int S) { return J * S <= 256 ? 16 : 8; }
+
+
+void append_root_rows(int k, int J, int S, const double *re, const double *im, std::vector<TabRow> &tab)
 {
     const int N = k + 1;
     const int M = k / 2;
     const bool shrt = k <= kShortMax;
-    const int Cpow = shrt ? k - 1 - (k > 8 ? 8 : 0) : 7;
-    const int Fpow = shrt ? k - (k > 8 ? 8 : 0) : 0;
+    int Cpow, Fpow, RP = 8;
+    if (shrt) {
+        Cpow = k - 1;
+        Fpow = k;
+    } else {
+        RP = rescale_period(J, S);
+        Fpow = S - RP * ((S - 1) / RP);
+        Cpow = Fpow - 1;
+    }
     const long double pi = 3.141592653589793238462643383279502884L;
     // alpha^n = c^n e^{i n h}; the angle n*h = pi (m n mod 2N) / N is reduced exactly.
     auto alpha_pow = [&](int m, int n, long double &ar, long double &ai) {
@@ -135,17 +149,24 @@ void append_root_rows(int k, const double *re, const double *im, std::vector<Tab
         const long double sh = sinl(h), ch = cosl(h);
         // beta = (1 - omega)/2 = -i sin(h) e^{i h} = (sin^2 h, -sin h cos h)
         const long double br = sh * sh, bi = -sh * ch;
-        long double cr, ci, fr, fi, a8r, a8i;
+        long double cr, ci, fr, fi, ar, ai;
         alpha_pow(m, Cpow, cr, ci);
         alpha_pow(m, Fpow, fr, fi);
-        alpha_pow(m, 8, a8r, a8i);
+        alpha_pow(m, RP, ar, ai);
         const long double dr = re[m], di = im[m];
         // Kc = 2 d beta alpha^C
         const long double tr = dr * br - di * bi, ti = dr * bi + di * br;
         const long double kr = 2.0L * (tr * cr - ti * ci), ki = 2.0L * (tr * ci + ti * cr);
-        const long double dfr = dr * fr - di * fi, dfi = dr * fi + di * fr;
-        tab.push_back({(float)dfr, (float)dfi, (float)kr, (float)ki});
-        tab.push_back({(float)a8r, (float)a8i, (float)(-sh / ch), 0.0f});
+        const float mt = (float)(-sh / ch);
+        if (shrt) {
+            const long double dfr = dr * fr - di * fi, dfi = dr * fi + di * fr;
+            tab.push_back({(float)dfr, (float)dfi, (float)kr, (float)ki});
+            tab.push_back({0.0f, 0.0f, mt, 0.0f});
+        } else {
+            tab.push_back({(float)dr, (float)di, (float)kr, (float)ki});
+            tab.push_back({(float)ar, (float)ai, (float)fr, (float)fi});
+            tab.push_back({mt, 0.0f, 0.0f, 0.0f});
+        }
     }
 }
 
@@ -167,7 +188,7 @@ std::string check_options(const PackOptions &o)
         if (kh <= prev) return "shape_k_hi must be ascending and > 16";
         if (kh > kMaxLen) return "shape_k_hi exceeds the maximum length";
         if (J < 2 || J > 64 || (J & (J - 1))) return "shape_lanes must be 2, 4, 8, 16, 32 or 64";
-        if (S < 8 || S > kMaxSeg || S % 8) return "shape_seg must be 8, 16, 24 or 32";
+        if (S < 8 || S > kMaxSeg || S % 4) return "shape_seg must be 8, 12, 16, 20, 24, 28 or 32";
         if (J * S < kh) return "shape_lanes * shape_seg is smaller than shape_k_hi";
         prev = kh;
     }
@@ -243,8 +264,10 @@ std::string build_instance(int32_t n, int32_t C, const int64_t *con_off, const i
         coefficients(types[c], k, p, re.data(), im.data());
         const int N = k + 1;
         const double dhalf = (N % 2 == 0) ? re[N / 2] : 0.0;
+        int J, S;
+        bucket_shape(k, opts, J, S);
         H.tab.push_back({(float)re[0], (float)dhalf, 0.0f, 0.0f});
-        append_root_rows(k, re.data(), im.data(), H.tab);
+        append_root_rows(k, J, S, re.data(), im.data(), H.tab);
         ++H.n_tables;
     }
 

@@ -20,15 +20,18 @@ constexpr int kShortMax = 16;
 constexpr int kMaxSeg = 32;
 
 // One row of a coefficient table, consumed by the kernels as a float4.
-//   row 0                : {d_0, d_half, 0, 0}  (d_half = d_{N/2} when N = k+1 is even, else 0)
-//   rows 2m-1, 2m (m>=1) : the complex root omega^m, see append_root_rows
+//   row 0             : {d_0, d_half, 0, 0}  (d_half = d_{N/2} when N = k+1 is even, else 0)
+//   rows of root m>=1 : 2 (short kernel) or 3 (segment kernel) rows, see append_root_rows
 struct TabRow {
     float x, y, z, w;
 };
 
-// Append the two rows of each complex root m = 1..floor(k/2) of a table whose
-// coefficient vector is (re, im) (length k+1).
-void append_root_rows(int k, const double *re, const double *im, std::vector<TabRow> &tab);
+// Rescale period of a segment kernel with J lanes of S literals.
+int rescale_period(int J, int S);
+
+// Append the rows of each complex root m = 1..floor(k/2) of a table whose
+// coefficient vector is (re, im) (length k+1), for the kernel shape (J, S) of k.
+void append_root_rows(int k, int J, int S, const double *re, const double *im, std::vector<TabRow> &tab);
 
 struct Bucket {
     int k_lo = 0, k_hi = 0;

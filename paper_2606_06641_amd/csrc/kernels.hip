@@ -70,9 +70,10 @@ struct FeArgs {
 // alpha = (1 + omega^m)/2 = c e^{i h}, the factor of a literal with value y is
 //     a = (1-p) + p omega^m = alpha (1 + i z),   z = -tan(h) y,
 // so one step of a product chain multiplies by (1 + i z): two FMAs.  Since
-// |1 + i z| <= 1/c, the running products are multiplied by alpha^8 after every
-// 8 literals, and the remaining constant alpha powers are folded into the table
-// (host.cpp, append_root_rows).  Padding literals hold y = +1, whose factor
+// |1 + i z| <= 1/c, the segment kernels multiply their running products by
+// alpha^RP after every RP literals (RP = 16 for lengths <= 256, else 8), and the
+// remaining constant alpha powers are folded into the table (host.cpp,
+// append_root_rows).  Padding literals hold y = +1, whose factor
 // alpha (1 - i tan h) is exactly 1.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void mul_unit(float &r, float &i, float z)
@@ -122,15 +123,14 @@ __global__ __launch_bounds__(kBlock) void fe_grad_short(FeArgs A)
         // Roots one at a time (unrolling them multiplies register use by K/2).
 #pragma unroll 1
         for (int m = 1; m <= K / 2; ++m) {
-            const float4 ra = A.tab[tab + 2 * m - 1];   // {dF, Kc}
-            const float4 rb = A.tab[tab + 2 * m];       // {alpha^8, -tan h}
+            const float4 ra = A.tab[tab + 2 * m - 1];   // {d alpha^K, Kc}
+            const float4 rb = A.tab[tab + 2 * m];       // {-, -, -tan h, -}
             float z[K], pr[K], pi[K];
 #pragma unroll
             for (int i = 0; i < K; ++i) z[i] = rb.z * y[i];
-            float ur = 1.0f, ui = 0.0f;
+            float ur = 1.0f, ui = 0.0f;       // |1 + i z|^K stays far below 2^128 for K <= 16
 #pragma unroll
             for (int i = 0; i < K; ++i) {
-                if (i > 0 && i % 8 == 0) cmul(ur, ui, rb.x, rb.y);
                 pr[i] = ur;
                 pi[i] = ui;
                 mul_unit(ur, ui, z[i]);
@@ -142,10 +142,7 @@ __global__ __launch_bounds__(kBlock) void fe_grad_short(FeArgs A)
                 for (int i = K - 1; i >= 0; --i) {
                     adj[i] = fmaf(pr[i], sr, adj[i]);
                     adj[i] = fmaf(-pi[i], si, adj[i]);
-                    if (i > 0) {
-                        mul_unit(sr, si, z[i]);
-                        if (i % 8 == 0) cmul(sr, si, rb.x, rb.y);
-                    }
+                    if (i > 0) mul_unit(sr, si, z[i]);
                 }
             }
         }
@@ -344,8 +341,9 @@ __device__ __forceinline__ void scan_suffix_real(float &r, int lane, int j)
 template <int J, int S, bool GRAD>
 __global__ __launch_bounds__(kBlock) void fe_grad_seg(FeArgs A)
 {
-    static_assert(S % 8 == 0 && S <= 32, "segment length must be 8, 16, 24 or 32");
+    static_assert(S % 4 == 0 && S >= 8 && S <= 32, "segment length must be 8, 12, ..., 32");
     constexpr int R = kWave / J;
+    constexpr int RP = J * S <= 256 ? 16 : 8;     // rescale period (see the table rows)
     const int64_t item = xcd_block() * kWavesPerBlock + wave_id();
     if (item >= A.items) return;
     const int lane = threadIdx.x & 63;
@@ -385,20 +383,21 @@ __global__ __launch_bounds__(kBlock) void fe_grad_seg(FeArgs A)
         float fe = r0.x;
         const int M = k >> 1;
         for (int m = 1; m <= M; ++m) {
-            const float4 ra = A.tab[tab + 2 * m - 1];   // {d, Kc}
-            const float4 rb = A.tab[tab + 2 * m];       // {alpha^8, -tan h}
+            const float4 ra = A.tab[tab + 3 * m - 2];   // {d, Kc}
+            const float4 rb = A.tab[tab + 3 * m - 1];   // {alpha^RP, alpha^F}
+            const float mt = A.tab[tab + 3 * m].x;      // -tan h
             float z[S], pr[S], pi[S];
 #pragma unroll
-            for (int s = 0; s < S; ++s) z[s] = rb.z * y[s];
+            for (int s = 0; s < S; ++s) z[s] = mt * y[s];
             float ur = 1.0f, ui = 0.0f;
 #pragma unroll
             for (int s = 0; s < S; ++s) {
-                if (s > 0 && s % 8 == 0) cmul(ur, ui, rb.x, rb.y);
+                if (s > 0 && s % RP == 0) cmul(ur, ui, rb.x, rb.y);
                 pr[s] = ur;
                 pi[s] = ui;
                 mul_unit(ur, ui, z[s]);
             }
-            cmul(ur, ui, rb.x, rb.y);                   // the segment's product
+            cmul(ur, ui, rb.z, rb.w);                   // the segment's product
             float er = ur, ei = ui;
             scan_prefix<J>(er, ei, lane, j);
             fe = fmaf(2.0f, ra.x * er - ra.y * ei, fe);  // lane J-1: d G
@@ -416,7 +415,7 @@ __global__ __launch_bounds__(kBlock) void fe_grad_seg(FeArgs A)
                     adj[s] = fmaf(-pi[s], si, adj[s]);
                     if (s > 0) {
                         mul_unit(sr, si, z[s]);
-                        if (s % 8 == 0) cmul(sr, si, rb.x, rb.y);
+                        if (s % RP == 0) cmul(sr, si, rb.x, rb.y);
                     }
                 }
             }
@@ -481,8 +480,11 @@ hipError_t dispatch_seg_s(int S, dim3 g, hipStream_t s, const FeArgs &a)
 {
     switch (S) {
     case 8: hipLaunchKernelGGL((fe_grad_seg<J, 8, GRAD>), g, dim3(kBlock), 0, s, a); break;
+    case 12: hipLaunchKernelGGL((fe_grad_seg<J, 12, GRAD>), g, dim3(kBlock), 0, s, a); break;
     case 16: hipLaunchKernelGGL((fe_grad_seg<J, 16, GRAD>), g, dim3(kBlock), 0, s, a); break;
+    case 20: hipLaunchKernelGGL((fe_grad_seg<J, 20, GRAD>), g, dim3(kBlock), 0, s, a); break;
     case 24: hipLaunchKernelGGL((fe_grad_seg<J, 24, GRAD>), g, dim3(kBlock), 0, s, a); break;
+    case 28: hipLaunchKernelGGL((fe_grad_seg<J, 28, GRAD>), g, dim3(kBlock), 0, s, a); break;
     case 32: hipLaunchKernelGGL((fe_grad_seg<J, 32, GRAD>), g, dim3(kBlock), 0, s, a); break;
     default: return hipErrorInvalidValue;
     }
@@ -642,6 +644,7 @@ struct VerifyArgs {
     int B, W, C, tile, ntiles;
     int64_t items;
 };
+
 
 __device__ __forceinline__ bool sat_pred(int type, int k, int param, int t)
 {

@@ -134,7 +134,7 @@ def test_bucket_shapes_cover_lengths():
         inst = W.random_instance(rng, n=2000, count=1, k_lo=k, k_hi=k)
         (b,) = host_instance(inst).buckets()
         J, S = b.lanes_per_restart, b.lits_per_lane
-        assert J & (J - 1) == 0 and 2 <= J <= 64 and S in (8, 16, 24, 32)
+        assert J & (J - 1) == 0 and 2 <= J <= 64 and S in (8, 12, 16, 20, 24, 28, 32)
         assert J * S >= k
 
 
@@ -154,7 +154,7 @@ def test_shape_overrides_and_tiles():
     assert shape_of(150) == (16, 16)
     J, S = shape_of(700)
     assert J * S >= 700                               # past the last override: default model
-    for bad in ([(10, 2, 8)], [(64, 3, 32)], [(64, 4, 12)], [(100, 2, 32)], [(64, 4, 16), (64, 8, 8)]):
+    for bad in ([(10, 2, 8)], [(64, 3, 32)], [(64, 4, 13)], [(100, 2, 32)], [(64, 4, 16), (64, 8, 8)]):
         with pytest.raises(afsat.AfsError) as e:
             afsat.Instance(3000, con_off, lits, types, params, device=-1, shapes=bad)
         assert e.value.status == afsat.AFS_EINVAL

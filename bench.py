@@ -38,7 +38,7 @@ def algorithmic_flops(k):
 
 
 def kernel_source_hash():
-    with open(os.path.join(ROOT, "paper_2606_06641_amd", "csrc", "kernels.hip"), "rb") as f:
+    with open(os.path.join(ROOT, "paper_2606_06641_amd", "csrc", "fe_kernels.hip"), "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
@@ -52,7 +52,7 @@ def stored_traffic(kernel_name):
     except (OSError, ValueError):
         return None
     e = t.get(kernel_name)
-    if not e or e.get("kernels_hip_sha256_16") != kernel_source_hash():
+    if not e or e.get("fe_kernels_sha256_16") != kernel_source_hash():
         return None
     return e.get("bytes_per_launch")
 

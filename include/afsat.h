@@ -244,7 +244,8 @@ afs_status afs_step(afs_instance *inst, int32_t B, float *x, const float *grad, 
  *   x    : device f32 [n][B]
  *   bits : device u32 [n][ceil(B/32)]: bit (b % 32) of word b/32 = (x[v][b] < 0)
  *          (NULL: not returned; a workspace copy is used)
- *   ws   : workspace as for afs_eval
+ *   ws   : workspace as for afs_eval (required: it holds the per-constraint
+ *          violation masks of the count)
  *   unsat: device i32 [P][B] (required; P = 1, or the parts of a batch)
  *   done : device u8 [P][B] or NULL; set to 1 where unsat == 0 (never cleared) */
 afs_status afs_round_verify(afs_instance *inst, int32_t B, const float *x, uint32_t *bits,

@@ -5,10 +5,11 @@ an instance in that range are packed alone into a sub-instance once per
 candidate shape (J lanes per restart x S literals per lane, J*S >= the range's
 upper length), the FE+gradient kernel of that bucket is timed on the device
 (median of several launches, HIP events on the launch stream), and the fastest
-shape wins.  Results are cached in JSON keyed by (GPU architecture, restarts,
-length range), so other instances with constraints in the same ranges reuse
-them.  The chosen list is passed to ``Instance(..., shapes=...)``.
+shape wins.  Results are cached in JSON keyed by (GPU architecture, kernel
+source revision, restarts, length range), so other instances with constraints
+in the same ranges reuse them, and a change to the kernels invalidates them.  The chosen list is passed to ``Instance(..., shapes=...)``.
 """
+import hashlib
 import json
 import os
 import time
@@ -70,6 +71,13 @@ def _time_bucket(sub, shape, B, device, reps):
     return float(np.median(times))
 
 
+def kernel_revision():
+    """First 12 hex digits of the SHA-256 of the FE kernels' source."""
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc", "fe_kernels.hip")
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:12]
+
+
 def arch_name(device=0):
     return torch.cuda.get_device_properties(device).gcnArchName.split(":")[0]
 
@@ -91,12 +99,13 @@ def tune(inst, B, device=0, reps=7, cache_path=None, out_path=None, log=None, ma
             with open(path) as f:
                 cache.update(json.load(f))
     arch = arch_name(device)
+    rev = kernel_revision()
     shapes, report = [], []
     for lo, hi in length_ranges():
         cons = np.nonzero((lens >= lo) & (lens <= hi))[0]
         if cons.size == 0:
             continue
-        key = "%s|B=%d|k=%d-%d" % (arch, B, lo, hi)
+        key = "%s|%s|B=%d|k=%d-%d" % (arch, rev, B, lo, hi)
         if key in cache:
             best = tuple(cache[key]["shape"])
             shapes.append((hi,) + best)
@@ -121,6 +130,7 @@ def tune(inst, B, device=0, reps=7, cache_path=None, out_path=None, log=None, ma
         if log:
             log("autotune k %d-%d: %s  (%s)" % (lo, hi, best, ", ".join("%s %.3f" % kv for kv in sorted(timings.items(), key=lambda kv: kv[1]))))
     out_path = out_path or cache_path
+    cache = {k: v for k, v in cache.items() if k.split("|")[1:2] == [rev]}   # drop stale revisions
     if out_path:
         tmp = out_path + ".tmp%d" % os.getpid()
         with open(tmp, "w") as f:

@@ -19,14 +19,15 @@ ARCH = os.environ.get("AFS_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-I", INCLUDE, "-I", CSRC]
-# Device code: no packed-FP32 instructions ("Numerics").
+# Device code is built without packed-FP32 instructions.
 DEVICE = ["--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-munsafe-fp-atomics"]
 
 SOURCES = [
     ("host.cpp", ["g++"] + COMMON),
     ("api.cpp", [HIPCC] + COMMON + ["-x", "c++", "-D__HIP_PLATFORM_AMD__", "-I", "/opt/rocm/include"]),
-    ("kernels.hip", [HIPCC] + COMMON + DEVICE),
+    ("fe_kernels.hip", [HIPCC] + COMMON + DEVICE),
+    ("update_kernels.hip", [HIPCC] + COMMON + DEVICE),
     ("gnn.hip", [HIPCC] + COMMON + DEVICE),
 ]
 

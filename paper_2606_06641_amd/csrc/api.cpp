@@ -51,7 +51,7 @@ size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 struct WsLayout {
     int Bp = 0, W = 0;
-    size_t adj = 0, part = 0, part2 = 0, bits = 0, total = 0;
+    size_t adj = 0, part = 0, part2 = 0, bits = 0, viol = 0, total = 0;
 };
 
 WsLayout ws_layout(const afs::HostInstance &H, int B)
@@ -68,6 +68,8 @@ WsLayout ws_layout(const afs::HostInstance &H, int B)
     off = align256(off + (size_t)((H.total_tiles + 31) / 32) * l.Bp * sizeof(float));
     l.bits = off;
     off = align256(off + (size_t)H.n * l.W * sizeof(uint32_t));
+    l.viol = off;
+    off = align256(off + (size_t)(H.C + 3) / 4 * 4 * l.W * sizeof(uint32_t));
     l.total = off;
     return l;
 }
@@ -190,11 +192,18 @@ afs_status finish_create(afs_instance *I, int32_t device, afs_instance **out)
     if (st == AFS_OK) st = upload(I, H.voff, &D.voff);
     if (st == AFS_OK) st = upload(I, H.vslot, &D.vslot);
     if (st == AFS_OK) st = upload(I, con_off32, &D.con_off);
-    if (st == AFS_OK) st = upload(I, H.lits, &D.lits);
+    std::vector<int32_t> lits_pad(H.lits);
+    lits_pad.resize(H.lits.size() + afs::kLitPad, 0);
+    if (st == AFS_OK) st = upload(I, lits_pad, &D.lits);
     if (st == AFS_OK) st = upload(I, H.types, &D.types);
     if (st == AFS_OK) st = upload(I, H.params, &D.params);
     if (st == AFS_OK) st = upload(I, H.con_inst, &D.con_inst);
     if (st == AFS_OK) st = upload(I, H.var_inst, &D.var_inst);
+    std::vector<int32_t> counted;
+    for (int32_t c = 0; c < (int32_t)H.types.size(); ++c)
+        if (H.types[c] == AFS_CARD_GE || H.types[c] == AFS_CARD_LT || H.types[c] == AFS_EK) counted.push_back(c);
+    D.n_counted = (int32_t)counted.size();
+    if (st == AFS_OK) st = upload(I, counted, &D.counted);
     if (st != AFS_OK) {
         const std::string msg = g_err;
         release(I);
@@ -460,17 +469,15 @@ afs_status afs_round_verify(afs_instance *I, int32_t B, const float *x, uint32_t
     afs_status st = check_call(I, B);
     if (st != AFS_OK) return st;
     if (B > 0 && (!x || !unsat)) return fail(AFS_EINVAL, "x or unsat is NULL");
-    if (!bits) {
-        WsLayout l;
-        if ((st = check_ws(I, B, ws, ws_bytes, l)) != AFS_OK) return st;
-        bits = at<uint32_t>(ws, l.bits);
-    }
+    WsLayout l;
+    if ((st = check_ws(I, B, ws, ws_bytes, l)) != AFS_OK) return st;
+    if (!bits) bits = at<uint32_t>(ws, l.bits);
     DeviceGuard g(I->device);
     if (g.error() != hipSuccess) return dev_fail(g.error(), "hipSetDevice");
     hipStream_t s = (hipStream_t)stream;
     const int pairs = I->H.n_inst * B;
     hipError_t e = afs::launch_round(I->D, B, x, bits, unsat, s);
-    if (e == hipSuccess) e = afs::launch_verify(I->D, B, bits, unsat, s);
+    if (e == hipSuccess) e = afs::launch_verify(I->D, B, bits, at<uint32_t>(ws, l.viol), unsat, s);
     if (e == hipSuccess && done) e = afs::launch_finalize(pairs, unsat, done, nullptr, nullptr, afs::FIN_VERIFY, s);
     return e == hipSuccess ? AFS_OK : dev_fail(e, "round/verify launch");
 }
@@ -489,7 +496,7 @@ afs_status afs_pgd_init(afs_instance *I, int32_t B, const float *x, void *ws, si
     hipStream_t s = (hipStream_t)stream;
     uint32_t *bits = at<uint32_t>(ws, l.bits);
     hipError_t e = afs::launch_round(I->D, B, x, bits, P->unsat, s);
-    if (e == hipSuccess) e = afs::launch_verify(I->D, B, bits, P->unsat, s);
+    if (e == hipSuccess) e = afs::launch_verify(I->D, B, bits, at<uint32_t>(ws, l.viol), P->unsat, s);
     if (e == hipSuccess)
         e = afs::launch_finalize(I->H.n_inst * B, P->unsat, P->done, P->first_sat, P->counter, afs::FIN_INIT, s);
     return e == hipSuccess ? AFS_OK : dev_fail(e, "PGD init launch");
@@ -514,7 +521,7 @@ static afs_status pgd_call(afs_instance *I, int32_t B, float *x, float lr, const
     uint32_t *bits = at<uint32_t>(ws, l.bits);
     hipError_t e = afs::launch_scatter_step(I->D, B, l.Bp, at<float>(ws, l.adj), x, lr, fixed, P->done,
                                             bits, P->unsat, s);
-    if (e == hipSuccess) e = afs::launch_verify(I->D, B, bits, P->unsat, s);
+    if (e == hipSuccess) e = afs::launch_verify(I->D, B, bits, at<uint32_t>(ws, l.viol), P->unsat, s);
     if (e == hipSuccess)
         e = afs::launch_finalize(I->H.n_inst * B, P->unsat, P->done, P->first_sat, P->counter, afs::FIN_STEP, s);
     return e == hipSuccess ? AFS_OK : dev_fail(e, "PGD step launch");

@@ -1,0 +1,46 @@
+// device_common.hpp -- launch geometry and lane helpers shared by the kernels (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace afs {
+namespace dev {
+
+constexpr int kWave = 64;
+constexpr int kBlock = 256;
+constexpr int kWavesPerBlock = kBlock / kWave;
+constexpr int kXcds = 8;
+
+// Workgroups are handed to the 8 XCDs round-robin.  Renumber them so that each
+// XCD receives one contiguous range of logical blocks (and with it a contiguous
+// range of restart columns, whose x rows then stay in that XCD's L2).
+__device__ __forceinline__ int64_t xcd_block()
+{
+    const int64_t nb = gridDim.x;
+    const int64_t i = blockIdx.x;
+    const int64_t xcd = i % kXcds, idx = i / kXcds;
+    const int64_t base = nb / kXcds, extra = nb % kXcds;
+    return xcd * base + (xcd < extra ? xcd : extra) + idx;
+}
+
+__device__ __forceinline__ int wave_id()
+{
+    return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+}
+
+inline dim3 grid_for_waves(int64_t items)
+{
+    return dim3((unsigned)((items + kWavesPerBlock - 1) / kWavesPerBlock));
+}
+
+// DPP lane move of v (all lanes active; lanes whose source lies outside the
+// row keep their own value)
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
+}  // namespace dev
+}  // namespace afs

@@ -1,0 +1,404 @@
+// fe_kernels.hip -- FE and adjoint kernels for gfx950 (CDNA4, wave64).
+//
+// Evaluation of a symmetric constraint of length k at a real point (Sec. 2.1.2).
+// With p_i = (1 - y_i)/2 the probability that literal i is true, the generating
+// function of the number of true literals is prod_i ((1-p_i) + p_i z); its values
+// at the N = k+1 roots of unity z = omega^m are G_m = prod_i a_{i,m}, and
+// FE = sum_m d_m G_m with d = inverse DFT of the truth table.  Because d and G are
+// conjugate symmetric and G_0 = 1,
+//     FE = d_0 + 2 sum_{m=1..M} Re(d_m G_m) + [k odd] d_{N/2} prod_i y_i,  M = floor(k/2).
+// The gradient is taken by prefix and suffix products (no division):
+//     dFE/dy_i = 2 sum_m Re(d_m beta_m prod_{l != i} a_{l,m}) + [k odd] d_{N/2} prod_{l != i} y_l
+// with beta_m = (1 - omega^m)/2 = da/dy.  Every true factor has |a| <= 1, so the
+// true products cannot overflow at any length; the kernels carry them in the
+// rotated form described above mul_unit.
+//
+// Layouts: x [n][B] f32 (restart contiguous); adj [L][Bp] f32 in slot order with
+// Bp = B rounded up to 64; constraint and literal metadata are wave-uniform and
+// are read through the scalar cache.
+
+#include "kernels.hpp"
+
+#include "device_common.hpp"
+
+namespace afs {
+
+namespace {
+
+using namespace dev;
+
+__device__ __forceinline__ void cmul(float &ar, float &ai, float br, float bi)
+{
+    const float r = ar * br - ai * bi;
+    ai = ar * bi + ai * br;
+    ar = r;
+}
+
+struct FeArgs {
+    const float *x;
+    float *adj, *part, *fe;
+    const float *dobj;          // per-restart seed of the adjoint (NULL: 1)
+    const int32_t *bc_slot0, *bc_k, *bc_tab, *bc_orig;
+    const float *bc_w;
+    const int32_t *slot_lit;
+    const float4 *tab;
+    int B, Bp;
+    int32_t c0, nc, tile, ntiles, tile0;
+    int64_t items;
+};
+
+// ---------------------------------------------------------------------------
+// Factor form shared by the FE kernels.  With h = pi m / N, c = cos h and
+// alpha = (1 + omega^m)/2 = c e^{i h}, the factor of a literal with value y is
+//     a = (1-p) + p omega^m = alpha (1 + i z),   z = -tan(h) y,
+// so one step of a product chain multiplies by (1 + i z): two FMAs.  Since
+// |1 + i z| <= 1/c, the segment kernels multiply their running products by
+// alpha^RP after every RP literals (RP = 16 for lengths <= 256, else 8), and the
+// remaining constant alpha powers are folded into the table (host.cpp,
+// append_root_rows).  Padding literals hold y = +1, whose factor
+// alpha (1 - i tan h) is exactly 1.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void mul_unit(float &r, float &i, float z)
+{
+    const float nr = fmaf(-i, z, r);
+    i = fmaf(r, z, i);
+    r = nr;
+}
+
+// ---------------------------------------------------------------------------
+// Short constraints (k <= 16): one lane per restart, k known at compile time, the
+// whole constraint in registers.  A wave takes 64 restarts and a tile of
+// constraints of the bucket.
+// ---------------------------------------------------------------------------
+template <int K, bool GRAD>
+__global__ __launch_bounds__(kBlock) void fe_grad_short(FeArgs A)
+{
+    const int64_t item = xcd_block() * kWavesPerBlock + wave_id();
+    if (item >= A.items) return;
+    const int lane = threadIdx.x & 63;
+    const int group = (int)(item / A.ntiles);
+    const int tile = (int)(item % A.ntiles);
+    const int b = group * kWave + lane;
+    const bool valid = b < A.B;
+    const int bl = valid ? b : A.B - 1;
+    const int cbeg = A.c0 + tile * A.tile;
+    const int cend = min(cbeg + A.tile, A.c0 + A.nc);
+    const float seed = (GRAD && A.dobj) ? A.dobj[bl] : 1.0f;
+    float objacc = 0.f;
+    for (int c = cbeg; c < cend; ++c) {
+        const int slot0 = A.bc_slot0[c];
+        const int tab = A.bc_tab[c];
+        const float w = A.bc_w[c];
+        const float wg = w * seed;
+        int lit[K];
+        float y[K], adj[K];
+#pragma unroll
+        for (int i = 0; i < K; ++i) {
+            lit[i] = A.slot_lit[slot0 + i];
+            const int v = (lit[i] > 0 ? lit[i] : -lit[i]) - 1;
+            const float xv = A.x[(int64_t)v * A.B + bl];
+            y[i] = lit[i] > 0 ? xv : -xv;
+            adj[i] = 0.f;
+        }
+        const float4 r0 = A.tab[tab];
+        float fe = r0.x;
+        // Roots one at a time (unrolling them multiplies register use by K/2).
+#pragma unroll 1
+        for (int m = 1; m <= K / 2; ++m) {
+            const float4 ra = A.tab[tab + 2 * m - 1];   // {d alpha^K, Kc}
+            const float4 rb = A.tab[tab + 2 * m];       // {-, -, -tan h, -}
+            float z[K], pr[K], pi[K];
+#pragma unroll
+            for (int i = 0; i < K; ++i) z[i] = rb.z * y[i];
+            float ur = 1.0f, ui = 0.0f;       // |1 + i z|^K stays far below 2^128 for K <= 16
+#pragma unroll
+            for (int i = 0; i < K; ++i) {
+                pr[i] = ur;
+                pi[i] = ui;
+                mul_unit(ur, ui, z[i]);
+            }
+            fe = fmaf(2.0f, ra.x * ur - ra.y * ui, fe);
+            if (GRAD) {
+                float sr = wg * ra.z, si = wg * ra.w;
+#pragma unroll
+                for (int i = K - 1; i >= 0; --i) {
+                    adj[i] = fmaf(pr[i], sr, adj[i]);
+                    adj[i] = fmaf(-pi[i], si, adj[i]);
+                    if (i > 0) mul_unit(sr, si, z[i]);
+                }
+            }
+        }
+        if (K & 1) {                       // real root omega^(N/2) = -1: factor y_i
+            const float dh = r0.y;
+            float hp[K], h = 1.0f;
+#pragma unroll
+            for (int i = 0; i < K; ++i) {
+                hp[i] = h;
+                h *= y[i];
+            }
+            fe = fmaf(dh, h, fe);
+            if (GRAD) {
+                float hs = wg * dh;
+#pragma unroll
+                for (int i = K - 1; i >= 0; --i) {
+                    adj[i] = fmaf(hp[i], hs, adj[i]);
+                    hs *= y[i];
+                }
+            }
+        }
+        if (valid) {
+            if (GRAD) {
+#pragma unroll
+                for (int i = 0; i < K; ++i)
+                    __builtin_nontemporal_store(lit[i] > 0 ? adj[i] : -adj[i], A.adj + (int64_t)(slot0 + i) * A.Bp + b);
+            }
+            if (A.fe) A.fe[(int64_t)A.bc_orig[c] * A.B + b] = fe;
+        }
+        objacc = fmaf(w, fe, objacc);
+    }
+    if (A.part) A.part[(int64_t)(A.tile0 + tile) * A.Bp + b] = objacc;
+}
+
+// ---------------------------------------------------------------------------
+// Cross-lane products over the J lanes that share one restart, as a butterfly:
+// at level D every lane takes the running product of the partner half-group
+// (lanes differing in bit D) and multiplies it both into the group total and
+// into the product of the lanes other than itself.  The partner half-groups of
+// the log2(J) levels partition the other lanes, so afterwards every lane holds
+// the total and the product of all segments but its own -- the two quantities
+// the FE and the adjoint need -- without separate prefix and suffix scans.
+// Levels 1, 2, 4 and 8 stay inside a 16-lane row (DPP quad_perm and the row
+// mirrors); 16 uses ds_swizzle, 32 a bpermute.
+// ---------------------------------------------------------------------------
+// value held by some lane of the other half of this lane's 2D-group
+template <int D>
+__device__ __forceinline__ float partner(float v)
+{
+    if constexpr (D == 1) return dpp_mov<0xB1>(v);         // quad_perm [1,0,3,2]
+    else if constexpr (D == 2) return dpp_mov<0x4E>(v);    // quad_perm [2,3,0,1]
+    else if constexpr (D == 4) return dpp_mov<0x141>(v);   // row_half_mirror: i -> 7-i
+    else if constexpr (D == 8) return dpp_mov<0x140>(v);   // row_mirror: i -> 15-i
+    else if constexpr (D == 16)                            // swizzle xor 16 within 32 lanes
+        return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x401F));
+    else return __shfl_xor(v, 32);
+}
+
+// (gr, gi): own segment product in, group total out; (xr, xi): product of the other lanes
+template <int J, int D = 1>
+__device__ __forceinline__ void butterfly(float &gr, float &gi, float &xr, float &xi)
+{
+    if constexpr (D < J) {
+        const float wr = partner<D>(gr), wi = partner<D>(gi);
+        if constexpr (D == 1) {
+            xr = wr;
+            xi = wi;
+        } else {
+            cmul(xr, xi, wr, wi);
+        }
+        cmul(gr, gi, wr, wi);
+        butterfly<J, 2 * D>(gr, gi, xr, xi);
+    }
+}
+
+// Real-valued version for the root omega^(N/2) = -1 (factor y).
+template <int J, int D = 1>
+__device__ __forceinline__ void butterfly_real(float &g, float &x)
+{
+    if constexpr (D < J) {
+        const float w = partner<D>(g);
+        x = D == 1 ? w : x * w;
+        g *= w;
+        butterfly_real<J, 2 * D>(g, x);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Long constraints: J lanes per restart (64/J restarts per wave), lane j holding
+// literals [j*S, j*S + S), S a multiple of 4 in [8, 32].  Per root, each lane
+// runs its local prefix chain (storing the prefixes) and forms its segment's
+// product; the butterfly gives every lane the total and the product of the other
+// lanes' segments, which seeds the lane's suffix chain; that chain accumulates
+// the adjoint of each literal the lane owns: no cross-lane reduction of
+// adjoints, deterministic order.
+// ---------------------------------------------------------------------------
+template <int J, int S, bool GRAD>
+__global__ __launch_bounds__(kBlock) void fe_grad_seg(FeArgs A)
+{
+    static_assert(S % 4 == 0 && S >= 8 && S <= 32, "segment length must be 8, 12, ..., 32");
+    constexpr int R = kWave / J;
+    constexpr int RP = J * S <= 256 ? 16 : 8;     // rescale period (see the table rows)
+    const int64_t item = xcd_block() * kWavesPerBlock + wave_id();
+    if (item >= A.items) return;
+    const int lane = threadIdx.x & 63;
+    const int group = (int)(item / A.ntiles);
+    const int tile = (int)(item % A.ntiles);
+    const int r = lane / J, j = lane % J;
+    const int b = group * R + r;
+    const bool valid = b < A.B;
+    const int bl = valid ? b : A.B - 1;
+    const int cbeg = A.c0 + tile * A.tile;
+    const int cend = min(cbeg + A.tile, A.c0 + A.nc);
+    const int base = j * S;
+    const float seed = (GRAD && A.dobj) ? A.dobj[bl] : 1.0f;
+    float objacc = 0.f;
+    for (int c = cbeg; c < cend; ++c) {
+        const int slot0 = A.bc_slot0[c];
+        const int k = A.bc_k[c];
+        const int tab = A.bc_tab[c];
+        const float w = A.bc_w[c];
+        const float wg = w * seed;
+        unsigned neg = 0;            // bit s: literal s of this lane is negated
+        float y[S], adj[S];
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            const int i = base + s;
+            y[s] = 1.0f;
+            adj[s] = 0.f;
+            if (i < k) {
+                const int lit = A.slot_lit[slot0 + i];
+                const int v = (lit > 0 ? lit : -lit) - 1;
+                const float xv = A.x[(int64_t)v * A.B + bl];
+                y[s] = lit > 0 ? xv : -xv;
+                neg |= (lit < 0 ? 1u : 0u) << s;
+            }
+        }
+        const float4 r0 = A.tab[tab];
+        float fe = r0.x;
+        const int M = k >> 1;
+        for (int m = 1; m <= M; ++m) {
+            const float4 ra = A.tab[tab + 3 * m - 2];   // {d, Kc}
+            const float4 rb = A.tab[tab + 3 * m - 1];   // {alpha^RP, alpha^F}
+            const float mt = A.tab[tab + 3 * m].x;      // -tan h
+            float z[S], pr[S], pi[S];
+#pragma unroll
+            for (int s = 0; s < S; ++s) z[s] = mt * y[s];
+            float ur = 1.0f, ui = 0.0f;
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                if (s > 0 && s % RP == 0) cmul(ur, ui, rb.x, rb.y);
+                pr[s] = ur;
+                pi[s] = ui;
+                mul_unit(ur, ui, z[s]);
+            }
+            cmul(ur, ui, rb.z, rb.w);                   // the segment's product
+            float gr = ur, gi = ui, xr = 1.0f, xi = 0.0f;
+            butterfly<J>(gr, gi, xr, xi);
+            fe = fmaf(2.0f, ra.x * gr - ra.y * gi, fe);  // d G
+            if (GRAD) {
+                float sr = wg * ra.z, si = wg * ra.w;
+                cmul(sr, si, xr, xi);
+#pragma unroll
+                for (int s = S - 1; s >= 0; --s) {
+                    adj[s] = fmaf(pr[s], sr, adj[s]);
+                    adj[s] = fmaf(-pi[s], si, adj[s]);
+                    if (s > 0) {
+                        mul_unit(sr, si, z[s]);
+                        if (s % RP == 0) cmul(sr, si, rb.x, rb.y);
+                    }
+                }
+            }
+        }
+        if (k & 1) {
+            const float dh = r0.y;
+            float q = y[0];
+#pragma unroll
+            for (int s = 1; s < S; ++s) q *= y[s];
+            float x = 1.0f;
+            butterfly_real<J>(q, x);
+            fe = fmaf(dh, q, fe);                       // d_{N/2} times the product of all y
+            if (GRAD) {
+                float hp[S], h = 1.0f;
+#pragma unroll
+                for (int s = 0; s < S; ++s) {
+                    hp[s] = h;
+                    h *= y[s];
+                }
+                float hs = wg * dh * x;
+#pragma unroll
+                for (int s = S - 1; s >= 0; --s) {
+                    adj[s] = fmaf(hp[s], hs, adj[s]);
+                    hs *= y[s];
+                }
+            }
+        }
+        if (valid) {
+            if (GRAD) {
+#pragma unroll
+                for (int s = 0; s < S; ++s)
+                    if (base + s < k)
+                        __builtin_nontemporal_store(((neg >> s) & 1u) ? -adj[s] : adj[s],
+                                                    A.adj + (int64_t)(slot0 + base + s) * A.Bp + b);
+            }
+            if (A.fe && j == J - 1) A.fe[(int64_t)A.bc_orig[c] * A.B + b] = fe;
+        }
+        objacc = fmaf(w, fe, objacc);
+    }
+    if (A.part && j == J - 1) A.part[(int64_t)(A.tile0 + tile) * A.Bp + b] = objacc;
+}
+
+template <bool GRAD>
+hipError_t dispatch_short(int K, dim3 g, hipStream_t s, const FeArgs &a)
+{
+#define AFS_SHORT(KK) case KK: hipLaunchKernelGGL((fe_grad_short<KK, GRAD>), g, dim3(kBlock), 0, s, a); break;
+    switch (K) {
+        AFS_SHORT(1) AFS_SHORT(2) AFS_SHORT(3) AFS_SHORT(4) AFS_SHORT(5) AFS_SHORT(6)
+        AFS_SHORT(7) AFS_SHORT(8) AFS_SHORT(9) AFS_SHORT(10) AFS_SHORT(11) AFS_SHORT(12)
+        AFS_SHORT(13) AFS_SHORT(14) AFS_SHORT(15) AFS_SHORT(16)
+    default: return hipErrorInvalidValue;
+    }
+#undef AFS_SHORT
+    return hipGetLastError();
+}
+
+template <int J, bool GRAD>
+hipError_t dispatch_seg_s(int S, dim3 g, hipStream_t s, const FeArgs &a)
+{
+    switch (S) {
+    case 8: hipLaunchKernelGGL((fe_grad_seg<J, 8, GRAD>), g, dim3(kBlock), 0, s, a); break;
+    case 12: hipLaunchKernelGGL((fe_grad_seg<J, 12, GRAD>), g, dim3(kBlock), 0, s, a); break;
+    case 16: hipLaunchKernelGGL((fe_grad_seg<J, 16, GRAD>), g, dim3(kBlock), 0, s, a); break;
+    case 20: hipLaunchKernelGGL((fe_grad_seg<J, 20, GRAD>), g, dim3(kBlock), 0, s, a); break;
+    case 24: hipLaunchKernelGGL((fe_grad_seg<J, 24, GRAD>), g, dim3(kBlock), 0, s, a); break;
+    case 28: hipLaunchKernelGGL((fe_grad_seg<J, 28, GRAD>), g, dim3(kBlock), 0, s, a); break;
+    case 32: hipLaunchKernelGGL((fe_grad_seg<J, 32, GRAD>), g, dim3(kBlock), 0, s, a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <bool GRAD>
+hipError_t dispatch_seg(int J, int S, dim3 g, hipStream_t s, const FeArgs &a)
+{
+    switch (J) {
+    case 2: return dispatch_seg_s<2, GRAD>(S, g, s, a);
+    case 4: return dispatch_seg_s<4, GRAD>(S, g, s, a);
+    case 8: return dispatch_seg_s<8, GRAD>(S, g, s, a);
+    case 16: return dispatch_seg_s<16, GRAD>(S, g, s, a);
+    case 32: return dispatch_seg_s<32, GRAD>(S, g, s, a);
+    case 64: return dispatch_seg_s<64, GRAD>(S, g, s, a);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_fe_grad(const DevInstance &I, const BucketLaunch &bk, int B, int Bp,
+                          const float *x, float *adj, float *part, float *fe, const float *dobj,
+                          bool grad, hipStream_t s)
+{
+    if (bk.nc == 0 || B == 0) return hipSuccess;
+    FeArgs a;
+    a.x = x; a.adj = adj; a.part = part; a.fe = fe; a.dobj = dobj;
+    a.bc_slot0 = I.bc_slot0; a.bc_k = I.bc_k; a.bc_tab = I.bc_tab; a.bc_orig = I.bc_orig;
+    a.bc_w = I.bc_w; a.slot_lit = I.slot_lit; a.tab = I.tab;
+    a.B = B; a.Bp = Bp;
+    a.c0 = bk.c0; a.nc = bk.nc; a.tile = bk.tile; a.ntiles = bk.ntiles; a.tile0 = bk.tile0;
+    const int R = kWave / bk.J;
+    const int64_t groups = (B + R - 1) / R;
+    a.items = groups * bk.ntiles;
+    const dim3 g = grid_for_waves(a.items);
+    if (grad) return bk.J == 1 ? dispatch_short<true>(bk.S, g, s, a) : dispatch_seg<true>(bk.J, bk.S, g, s, a);
+    return bk.J == 1 ? dispatch_short<false>(bk.S, g, s, a) : dispatch_seg<false>(bk.J, bk.S, g, s, a);
+}
+
+}  // namespace afs

@@ -24,7 +24,14 @@ struct DevInstance {
     // block-diagonal batches: sub-instance of each constraint / variable
     int32_t n_inst = 1;
     const int32_t *con_inst = nullptr, *var_inst = nullptr;
+    // constraints of the counted types (CARD >= K, CARD < K, EK), input order
+    int32_t n_counted = 0;
+    const int32_t *counted = nullptr;
 };
+
+// The device copy of the literal array carries kLitPad trailing zeros, so that
+// verification reads whole batches of literals without a bounds check.
+constexpr int kLitPad = 32;
 
 struct BucketLaunch {
     int J, S;
@@ -60,9 +67,10 @@ hipError_t launch_step(const DevInstance &I, int B, float *x, const float *grad,
 hipError_t launch_round(const DevInstance &I, int B, const float *x, uint32_t *bits, int32_t *unsat,
                         hipStream_t s);
 
-// unsat[b] += number of violated constraints (unsat must be zeroed before).
-hipError_t launch_verify(const DevInstance &I, int B, const uint32_t *bits, int32_t *unsat,
-                         hipStream_t s);
+// unsat[b] += number of violated constraints (unsat must be zeroed before);
+// viol [W][C rounded up to 4] is scratch for the per-constraint violation masks.
+hipError_t launch_verify(const DevInstance &I, int B, const uint32_t *bits, uint32_t *viol,
+                         int32_t *unsat, hipStream_t s);
 
 enum FinalizeMode { FIN_INIT = 0, FIN_STEP = 1, FIN_VERIFY = 2 };
 // over all n_inst * B (sub-instance, restart) pairs

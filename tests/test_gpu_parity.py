@@ -182,6 +182,34 @@ def test_verify_bit_exact():
     assert np.array_equal(bits.cpu().numpy().view(np.uint32), want_bits)
 
 
+@pytest.mark.parametrize("B", [1, 33, 2100])
+def test_verify_word_layouts_and_parameters(B):
+    """Restart counts that leave a partial 32-restart word, one word per lane group
+    (B = 33) and more than 64 words (B = 2100); lengths up to the maximum 1024;
+    parameters outside 0..k (negative, k+1, huge) as well as inside."""
+    rng = np.random.default_rng(B)
+    n = 1100
+    parts = [W.random_instance(rng, n=n, count=60, k_lo=1, k_hi=12),
+             W.random_instance(rng, n=n, count=12, k_lo=200, k_hi=1024)]
+    con_off = np.concatenate([parts[0].con_off, parts[1].con_off[1:] + parts[0].n_lits])
+    inst = W.Instance(n=n, con_off=con_off, lits=np.concatenate([p.lits for p in parts]),
+                      types=np.concatenate([p.types for p in parts]),
+                      params=np.concatenate([p.params for p in parts]))
+    lens = np.diff(inst.con_off)
+    odd = rng.random(len(lens)) < 0.3
+    inst.params[odd] = rng.choice([-5, -1, 0, 1, 2047, 4096, 1 << 30], size=int(odd.sum())).astype(np.int32)
+    edge = rng.random(len(lens)) < 0.2
+    inst.params[edge] = (lens[edge] + rng.integers(-1, 2, size=int(edge.sum()))).astype(np.int32)
+    # points near the thresholds: mostly one sign, so long CARD counts land near k
+    bias = rng.uniform(-1, 1, size=(n, 1))
+    x = np.clip(bias + rng.normal(0, 0.4, size=(n, B)), -1, 1).astype(np.float32)
+    d = afsat.Instance.from_arrays(inst)
+    log("case: verify B=%d C=%d max k=%d" % (B, len(lens), lens.max()))
+    unsat = d.round_verify(parity.to_dev(x)).cpu().numpy()
+    want = oracle.verify(inst, x)
+    assert np.array_equal(unsat, want)
+
+
 def test_verify_planted_witness():
     for inst in [W.planted_3sat(instance=3), W.mixed_10k()]:
         H = np.where(inst.hidden, -1.0, 1.0).astype(np.float32)

@@ -124,8 +124,8 @@ afs_status afs_instance_create(int32_t n_vars, int32_t n_cons, const int64_t *co
  *   n_shapes, shape_k_hi, shape_lanes, shape_seg: kernel shape per length range for
  *       constraints longer than 16: a constraint of length k uses the first entry
  *       with k <= shape_k_hi[e] (ascending), evaluated by shape_lanes[e] lanes per
- *       restart (2, 4, 8, 16, 32 or 64) holding shape_seg[e] literals each (8, 12,
- *       16, 20, 24, 28 or 32), with lanes * seg >= shape_k_hi[e].  Lengths past the last entry
+ *       restart (2, 4, 8, 16, 32 or 64) holding shape_seg[e] literals each (even,
+ *       8 to 32), with lanes * seg >= shape_k_hi[e].  Lengths past the last entry
  *       use the default shape model.  (These are what the autotuner picks.)
  *   tile_short / tile_long: constraints per work tile for lengths <= 16 / > 16. */
 typedef struct {

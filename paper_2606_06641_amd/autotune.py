@@ -22,7 +22,7 @@ from . import afsat
 DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned_shapes.json")
 
 LANES = (2, 4, 8, 16, 32, 64)
-SEGS = (8, 12, 16, 20, 24, 28, 32)
+SEGS = tuple(range(8, 33, 2))
 SHORT_MAX = 16
 MAX_LEN = 1024
 

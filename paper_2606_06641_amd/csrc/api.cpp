@@ -96,6 +96,9 @@ void release(afs_instance *I)
     if (I->device >= 0) {
         DeviceGuard g(I->device);
         for (void *p : I->allocs) (void)hipFree(p);
+        if (I->fork) (void)hipEventDestroy(I->fork);
+        if (I->join) (void)hipEventDestroy(I->join);
+        if (I->side) (void)hipStreamDestroy(I->side);
     }
     delete I;
 }
@@ -126,13 +129,31 @@ afs_status fe_grad_range(afs_instance *I, int B, const float *x, void *ws, const
                          int lo, int hi, bool want_part, float *fe, hipStream_t s,
                          const float *dobj = nullptr, bool grad = true)
 {
+    // Short buckets (one lane per restart, bound by memory traffic) go to the side
+    // stream when long buckets (bound by arithmetic) share the range, so the two
+    // kinds overlap.  They write disjoint adjoint rows and objective tiles.
+    bool has_short = false, has_long = false;
+    for (int bi = lo; bi < hi; ++bi) (I->H.buckets[bi].J == 1 ? has_short : has_long) = true;
+    const bool split = has_short && has_long && I->side;
+    std::unique_lock<std::mutex> lock(I->side_mu, std::defer_lock);
+    if (split) {
+        lock.lock();
+        hipError_t e = hipEventRecord(I->fork, s);
+        if (e == hipSuccess) e = hipStreamWaitEvent(I->side, I->fork, 0);
+        if (e != hipSuccess) return dev_fail(e, "fork to the side stream");
+    }
     for (int bi = lo; bi < hi; ++bi) {
         const afs::Bucket &b = I->H.buckets[bi];
         afs::BucketLaunch bl{b.J, b.S, b.c0, b.nc, b.tile, b.ntiles, b.tile0};
         hipError_t e = afs::launch_fe_grad(I->D, bl, B, l.Bp, x, at<float>(ws, l.adj),
                                            want_part ? at<float>(ws, l.part) : nullptr, fe, dobj,
-                                           grad, s);
+                                           grad, split && b.J == 1 ? I->side : s);
         if (e != hipSuccess) return dev_fail(e, "fe_grad launch");
+    }
+    if (split) {
+        hipError_t e = hipEventRecord(I->join, I->side);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s, I->join, 0);
+        if (e != hipSuccess) return dev_fail(e, "join from the side stream");
     }
     return AFS_OK;
 }
@@ -204,6 +225,12 @@ afs_status finish_create(afs_instance *I, int32_t device, afs_instance **out)
         if (H.types[c] == AFS_CARD_GE || H.types[c] == AFS_CARD_LT || H.types[c] == AFS_EK) counted.push_back(c);
     D.n_counted = (int32_t)counted.size();
     if (st == AFS_OK) st = upload(I, counted, &D.counted);
+    if (st == AFS_OK) {
+        hipError_t e = hipStreamCreateWithFlags(&I->side, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&I->fork, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&I->join, hipEventDisableTiming);
+        if (e != hipSuccess) st = dev_fail(e, "side stream");
+    }
     if (st != AFS_OK) {
         const std::string msg = g_err;
         release(I);

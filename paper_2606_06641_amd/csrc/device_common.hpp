@@ -15,12 +15,12 @@ constexpr int kXcds = 8;
 // Workgroups are handed to the 8 XCDs round-robin.  Renumber them so that each
 // XCD receives one contiguous range of logical blocks (and with it a contiguous
 // range of restart columns, whose x rows then stay in that XCD's L2).
-__device__ __forceinline__ int64_t xcd_block()
+__device__ __forceinline__ uint32_t xcd_block()
 {
-    const int64_t nb = gridDim.x;
-    const int64_t i = blockIdx.x;
-    const int64_t xcd = i % kXcds, idx = i / kXcds;
-    const int64_t base = nb / kXcds, extra = nb % kXcds;
+    const uint32_t nb = gridDim.x;
+    const uint32_t i = blockIdx.x;
+    const uint32_t xcd = i % kXcds, idx = i / kXcds;
+    const uint32_t base = nb / kXcds, extra = nb % kXcds;
     return xcd * base + (xcd < extra ? xcd : extra) + idx;
 }
 

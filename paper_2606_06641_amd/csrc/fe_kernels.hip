@@ -19,6 +19,8 @@
 
 #include "kernels.hpp"
 
+#include <cstdint>
+
 #include "device_common.hpp"
 
 namespace afs {
@@ -66,97 +68,156 @@ __device__ __forceinline__ void mul_unit(float &r, float &i, float z)
 }
 
 // ---------------------------------------------------------------------------
-// Short constraints (k <= 16): one lane per restart, k known at compile time, the
-// whole constraint in registers.  A wave takes 64 restarts and a tile of
-// constraints of the bucket.
+// Short constraints (k <= 16): one lane per RPL consecutive restarts, k known at
+// compile time, the whole constraint in registers.  A wave takes 64*RPL restarts
+// and a tile of constraints of the bucket; with RPL = 4 (B a multiple of 4) the
+// x rows are read and the adjoint rows written as 16-byte vectors and the
+// constraint's metadata and table rows serve four restarts.  The weight (and the
+// adjoint seed) multiplies each literal's adjoint once, after the roots.
 // ---------------------------------------------------------------------------
-template <int K, bool GRAD>
+template <int RPL>
+struct Lanes {
+    float v[RPL];
+};
+
+template <int RPL>
+__device__ __forceinline__ void load_lanes(const float *p, Lanes<RPL> &out)
+{
+    if constexpr (RPL == 4) {
+        const float4 q = *reinterpret_cast<const float4 *>(p);
+        out.v[0] = q.x; out.v[1] = q.y; out.v[2] = q.z; out.v[3] = q.w;
+    } else {
+#pragma unroll
+        for (int e = 0; e < RPL; ++e) out.v[e] = p[e];
+    }
+}
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+template <int RPL>
+__device__ __forceinline__ void store_lanes_stream(float *p, const Lanes<RPL> &in)
+{
+    if constexpr (RPL == 4) {
+        f32x4 q = {in.v[0], in.v[1], in.v[2], in.v[3]};
+        __builtin_nontemporal_store(q, reinterpret_cast<f32x4 *>(p));
+    } else {
+#pragma unroll
+        for (int e = 0; e < RPL; ++e) __builtin_nontemporal_store(in.v[e], p + e);
+    }
+}
+
+template <int K, int RPL, bool GRAD>
 __global__ __launch_bounds__(kBlock) void fe_grad_short(FeArgs A)
 {
-    const int64_t item = xcd_block() * kWavesPerBlock + wave_id();
-    if (item >= A.items) return;
+    const uint32_t item = xcd_block() * kWavesPerBlock + wave_id();
+    if (item >= (uint32_t)A.items) return;
     const int lane = threadIdx.x & 63;
-    const int group = (int)(item / A.ntiles);
-    const int tile = (int)(item % A.ntiles);
-    const int b = group * kWave + lane;
-    const bool valid = b < A.B;
-    const int bl = valid ? b : A.B - 1;
+    const uint32_t group = item / (uint32_t)A.ntiles;
+    const int tile = (int)(item - group * (uint32_t)A.ntiles);
+    const int b0 = ((int)group * kWave + lane) * RPL;          // first restart of the lane
+    const bool valid = b0 < A.B;                               // RPL divides B
+    const int bl = valid ? b0 : A.B - RPL;
     const int cbeg = A.c0 + tile * A.tile;
     const int cend = min(cbeg + A.tile, A.c0 + A.nc);
-    const float seed = (GRAD && A.dobj) ? A.dobj[bl] : 1.0f;
-    float objacc = 0.f;
+    Lanes<RPL> seed;
+#pragma unroll
+    for (int e = 0; e < RPL; ++e) seed.v[e] = (GRAD && A.dobj) ? A.dobj[bl + e] : 1.0f;
+    float objacc[RPL];
+#pragma unroll
+    for (int e = 0; e < RPL; ++e) objacc[e] = 0.f;
     for (int c = cbeg; c < cend; ++c) {
         const int slot0 = A.bc_slot0[c];
         const int tab = A.bc_tab[c];
         const float w = A.bc_w[c];
-        const float wg = w * seed;
         int lit[K];
-        float y[K], adj[K];
+        Lanes<RPL> y[K], adj[K];
 #pragma unroll
         for (int i = 0; i < K; ++i) {
             lit[i] = A.slot_lit[slot0 + i];
             const int v = (lit[i] > 0 ? lit[i] : -lit[i]) - 1;
-            const float xv = A.x[(int64_t)v * A.B + bl];
-            y[i] = lit[i] > 0 ? xv : -xv;
-            adj[i] = 0.f;
+            load_lanes<RPL>(A.x + (int64_t)v * A.B + bl, y[i]);
+#pragma unroll
+            for (int e = 0; e < RPL; ++e) {
+                y[i].v[e] = lit[i] > 0 ? y[i].v[e] : -y[i].v[e];
+                adj[i].v[e] = 0.f;
+            }
         }
         const float4 r0 = A.tab[tab];
-        float fe = r0.x;
+        float fe[RPL];
+#pragma unroll
+        for (int e = 0; e < RPL; ++e) fe[e] = r0.x;
         // Roots one at a time (unrolling them multiplies register use by K/2).
 #pragma unroll 1
         for (int m = 1; m <= K / 2; ++m) {
             const float4 ra = A.tab[tab + 2 * m - 1];   // {d alpha^K, Kc}
             const float4 rb = A.tab[tab + 2 * m];       // {-, -, -tan h, -}
-            float z[K], pr[K], pi[K];
 #pragma unroll
-            for (int i = 0; i < K; ++i) z[i] = rb.z * y[i];
-            float ur = 1.0f, ui = 0.0f;       // |1 + i z|^K stays far below 2^128 for K <= 16
+            for (int e = 0; e < RPL; ++e) {
+                float z[K], pr[K], pi[K];
 #pragma unroll
-            for (int i = 0; i < K; ++i) {
-                pr[i] = ur;
-                pi[i] = ui;
-                mul_unit(ur, ui, z[i]);
-            }
-            fe = fmaf(2.0f, ra.x * ur - ra.y * ui, fe);
-            if (GRAD) {
-                float sr = wg * ra.z, si = wg * ra.w;
+                for (int i = 0; i < K; ++i) z[i] = rb.z * y[i].v[e];
+                float ur = 1.0f, ui = 0.0f;   // |1 + i z|^K stays far below 2^128 for K <= 16
 #pragma unroll
-                for (int i = K - 1; i >= 0; --i) {
-                    adj[i] = fmaf(pr[i], sr, adj[i]);
-                    adj[i] = fmaf(-pi[i], si, adj[i]);
-                    if (i > 0) mul_unit(sr, si, z[i]);
+                for (int i = 0; i < K; ++i) {
+                    pr[i] = ur;
+                    pi[i] = ui;
+                    mul_unit(ur, ui, z[i]);
+                }
+                fe[e] = fmaf(2.0f, ra.x * ur - ra.y * ui, fe[e]);
+                if (GRAD) {
+                    float sr = ra.z, si = ra.w;
+#pragma unroll
+                    for (int i = K - 1; i >= 0; --i) {
+                        adj[i].v[e] = fmaf(pr[i], sr, adj[i].v[e]);
+                        adj[i].v[e] = fmaf(-pi[i], si, adj[i].v[e]);
+                        if (i > 0) mul_unit(sr, si, z[i]);
+                    }
                 }
             }
         }
         if (K & 1) {                       // real root omega^(N/2) = -1: factor y_i
             const float dh = r0.y;
-            float hp[K], h = 1.0f;
 #pragma unroll
-            for (int i = 0; i < K; ++i) {
-                hp[i] = h;
-                h *= y[i];
-            }
-            fe = fmaf(dh, h, fe);
-            if (GRAD) {
-                float hs = wg * dh;
+            for (int e = 0; e < RPL; ++e) {
+                float hp[K], h = 1.0f;
 #pragma unroll
-                for (int i = K - 1; i >= 0; --i) {
-                    adj[i] = fmaf(hp[i], hs, adj[i]);
-                    hs *= y[i];
+                for (int i = 0; i < K; ++i) {
+                    hp[i] = h;
+                    h *= y[i].v[e];
+                }
+                fe[e] = fmaf(dh, h, fe[e]);
+                if (GRAD) {
+                    float hs = dh;
+#pragma unroll
+                    for (int i = K - 1; i >= 0; --i) {
+                        adj[i].v[e] = fmaf(hp[i], hs, adj[i].v[e]);
+                        hs *= y[i].v[e];
+                    }
                 }
             }
         }
         if (valid) {
             if (GRAD) {
 #pragma unroll
-                for (int i = 0; i < K; ++i)
-                    __builtin_nontemporal_store(lit[i] > 0 ? adj[i] : -adj[i], A.adj + (int64_t)(slot0 + i) * A.Bp + b);
+                for (int i = 0; i < K; ++i) {
+                    const float ws = lit[i] > 0 ? w : -w;
+#pragma unroll
+                    for (int e = 0; e < RPL; ++e) adj[i].v[e] *= ws * seed.v[e];
+                    store_lanes_stream<RPL>(A.adj + (int64_t)(slot0 + i) * A.Bp + b0, adj[i]);
+                }
             }
-            if (A.fe) A.fe[(int64_t)A.bc_orig[c] * A.B + b] = fe;
+            if (A.fe) {
+#pragma unroll
+                for (int e = 0; e < RPL; ++e) A.fe[(int64_t)A.bc_orig[c] * A.B + b0 + e] = fe[e];
+            }
         }
-        objacc = fmaf(w, fe, objacc);
+#pragma unroll
+        for (int e = 0; e < RPL; ++e) objacc[e] = fmaf(w, fe[e], objacc[e]);
     }
-    if (A.part) A.part[(int64_t)(A.tile0 + tile) * A.Bp + b] = objacc;
+    if (A.part && valid) {
+#pragma unroll
+        for (int e = 0; e < RPL; ++e) A.part[(int64_t)(A.tile0 + tile) * A.Bp + b0 + e] = objacc[e];
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -214,7 +275,7 @@ __device__ __forceinline__ void butterfly_real(float &g, float &x)
 
 // ---------------------------------------------------------------------------
 // Long constraints: J lanes per restart (64/J restarts per wave), lane j holding
-// literals [j*S, j*S + S), S a multiple of 4 in [8, 32].  Per root, each lane
+// literals [j*S, j*S + S), S even in [8, 32].  Per root, each lane
 // runs its local prefix chain (storing the prefixes) and forms its segment's
 // product; the butterfly gives every lane the total and the product of the other
 // lanes' segments, which seeds the lane's suffix chain; that chain accumulates
@@ -224,14 +285,15 @@ __device__ __forceinline__ void butterfly_real(float &g, float &x)
 template <int J, int S, bool GRAD>
 __global__ __launch_bounds__(kBlock) void fe_grad_seg(FeArgs A)
 {
-    static_assert(S % 4 == 0 && S >= 8 && S <= 32, "segment length must be 8, 12, ..., 32");
+    static_assert(S % 2 == 0 && S >= 8 && S <= 32, "segment length must be even, 8 to 32");
     constexpr int R = kWave / J;
     constexpr int RP = J * S <= 256 ? 16 : 8;     // rescale period (see the table rows)
-    const int64_t item = xcd_block() * kWavesPerBlock + wave_id();
-    if (item >= A.items) return;
+    const uint32_t item = xcd_block() * kWavesPerBlock + wave_id();
+    if (item >= (uint32_t)A.items) return;
     const int lane = threadIdx.x & 63;
-    const int group = (int)(item / A.ntiles);
-    const int tile = (int)(item % A.ntiles);
+    const uint32_t group32 = item / (uint32_t)A.ntiles;
+    const int group = (int)group32;
+    const int tile = (int)(item - group32 * (uint32_t)A.ntiles);
     const int r = lane / J, j = lane % J;
     const int b = group * R + r;
     const bool valid = b < A.B;
@@ -285,7 +347,7 @@ __global__ __launch_bounds__(kBlock) void fe_grad_seg(FeArgs A)
             butterfly<J>(gr, gi, xr, xi);
             fe = fmaf(2.0f, ra.x * gr - ra.y * gi, fe);  // d G
             if (GRAD) {
-                float sr = wg * ra.z, si = wg * ra.w;
+                float sr = ra.z, si = ra.w;
                 cmul(sr, si, xr, xi);
 #pragma unroll
                 for (int s = S - 1; s >= 0; --s) {
@@ -313,7 +375,7 @@ __global__ __launch_bounds__(kBlock) void fe_grad_seg(FeArgs A)
                     hp[s] = h;
                     h *= y[s];
                 }
-                float hs = wg * dh * x;
+                float hs = dh * x;
 #pragma unroll
                 for (int s = S - 1; s >= 0; --s) {
                     adj[s] = fmaf(hp[s], hs, adj[s]);
@@ -326,7 +388,7 @@ __global__ __launch_bounds__(kBlock) void fe_grad_seg(FeArgs A)
 #pragma unroll
                 for (int s = 0; s < S; ++s)
                     if (base + s < k)
-                        __builtin_nontemporal_store(((neg >> s) & 1u) ? -adj[s] : adj[s],
+                        __builtin_nontemporal_store(((neg >> s) & 1u) ? -wg * adj[s] : wg * adj[s],
                                                     A.adj + (int64_t)(slot0 + base + s) * A.Bp + b);
             }
             if (A.fe && j == J - 1) A.fe[(int64_t)A.bc_orig[c] * A.B + b] = fe;
@@ -337,9 +399,17 @@ __global__ __launch_bounds__(kBlock) void fe_grad_seg(FeArgs A)
 }
 
 template <bool GRAD>
-hipError_t dispatch_short(int K, dim3 g, hipStream_t s, const FeArgs &a)
+hipError_t dispatch_short(int K, int rpl, dim3 g, hipStream_t s, const FeArgs &a)
 {
-#define AFS_SHORT(KK) case KK: hipLaunchKernelGGL((fe_grad_short<KK, GRAD>), g, dim3(kBlock), 0, s, a); break;
+#define AFS_SHORT(KK) case KK:                                                                        \
+    if constexpr (KK <= 8) {                                                                         \
+        if (rpl == 4) {                                                                              \
+            hipLaunchKernelGGL((fe_grad_short<KK, 4, GRAD>), g, dim3(kBlock), 0, s, a);              \
+            break;                                                                                   \
+        }                                                                                            \
+    }                                                                                                \
+    hipLaunchKernelGGL((fe_grad_short<KK, 1, GRAD>), g, dim3(kBlock), 0, s, a);                      \
+    break;
     switch (K) {
         AFS_SHORT(1) AFS_SHORT(2) AFS_SHORT(3) AFS_SHORT(4) AFS_SHORT(5) AFS_SHORT(6)
         AFS_SHORT(7) AFS_SHORT(8) AFS_SHORT(9) AFS_SHORT(10) AFS_SHORT(11) AFS_SHORT(12)
@@ -355,11 +425,17 @@ hipError_t dispatch_seg_s(int S, dim3 g, hipStream_t s, const FeArgs &a)
 {
     switch (S) {
     case 8: hipLaunchKernelGGL((fe_grad_seg<J, 8, GRAD>), g, dim3(kBlock), 0, s, a); break;
+    case 10: hipLaunchKernelGGL((fe_grad_seg<J, 10, GRAD>), g, dim3(kBlock), 0, s, a); break;
     case 12: hipLaunchKernelGGL((fe_grad_seg<J, 12, GRAD>), g, dim3(kBlock), 0, s, a); break;
+    case 14: hipLaunchKernelGGL((fe_grad_seg<J, 14, GRAD>), g, dim3(kBlock), 0, s, a); break;
     case 16: hipLaunchKernelGGL((fe_grad_seg<J, 16, GRAD>), g, dim3(kBlock), 0, s, a); break;
+    case 18: hipLaunchKernelGGL((fe_grad_seg<J, 18, GRAD>), g, dim3(kBlock), 0, s, a); break;
     case 20: hipLaunchKernelGGL((fe_grad_seg<J, 20, GRAD>), g, dim3(kBlock), 0, s, a); break;
+    case 22: hipLaunchKernelGGL((fe_grad_seg<J, 22, GRAD>), g, dim3(kBlock), 0, s, a); break;
     case 24: hipLaunchKernelGGL((fe_grad_seg<J, 24, GRAD>), g, dim3(kBlock), 0, s, a); break;
+    case 26: hipLaunchKernelGGL((fe_grad_seg<J, 26, GRAD>), g, dim3(kBlock), 0, s, a); break;
     case 28: hipLaunchKernelGGL((fe_grad_seg<J, 28, GRAD>), g, dim3(kBlock), 0, s, a); break;
+    case 30: hipLaunchKernelGGL((fe_grad_seg<J, 30, GRAD>), g, dim3(kBlock), 0, s, a); break;
     case 32: hipLaunchKernelGGL((fe_grad_seg<J, 32, GRAD>), g, dim3(kBlock), 0, s, a); break;
     default: return hipErrorInvalidValue;
     }
@@ -393,12 +469,16 @@ hipError_t launch_fe_grad(const DevInstance &I, const BucketLaunch &bk, int B, i
     a.bc_w = I.bc_w; a.slot_lit = I.slot_lit; a.tab = I.tab;
     a.B = B; a.Bp = Bp;
     a.c0 = bk.c0; a.nc = bk.nc; a.tile = bk.tile; a.ntiles = bk.ntiles; a.tile0 = bk.tile0;
-    const int R = kWave / bk.J;
-    const int64_t groups = (B + R - 1) / R;
+    // several restarts per lane for short constraints when the rows allow 16-byte access
+    const int rpl = (bk.J == 1 && bk.S <= 8 && B % 4 == 0 && reinterpret_cast<uintptr_t>(x) % 16 == 0 &&
+                     (!dobj || reinterpret_cast<uintptr_t>(dobj) % 16 == 0)) ? 4 : 1;
+    const int R = bk.J == 1 ? kWave * rpl : kWave / bk.J;      // restarts per wave
+    const int64_t groups = bk.J == 1 ? (B + R - 1) / R : (B + (kWave / bk.J) - 1) / (kWave / bk.J);
     a.items = groups * bk.ntiles;
+    if (a.items > INT32_MAX) return hipErrorInvalidValue;
     const dim3 g = grid_for_waves(a.items);
-    if (grad) return bk.J == 1 ? dispatch_short<true>(bk.S, g, s, a) : dispatch_seg<true>(bk.J, bk.S, g, s, a);
-    return bk.J == 1 ? dispatch_short<false>(bk.S, g, s, a) : dispatch_seg<false>(bk.J, bk.S, g, s, a);
+    if (grad) return bk.J == 1 ? dispatch_short<true>(bk.S, rpl, g, s, a) : dispatch_seg<true>(bk.J, bk.S, g, s, a);
+    return bk.J == 1 ? dispatch_short<false>(bk.S, rpl, g, s, a) : dispatch_seg<false>(bk.J, bk.S, g, s, a);
 }
 
 }  // namespace afs

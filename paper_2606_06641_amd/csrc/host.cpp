@@ -84,17 +84,17 @@ void bucket_shape(int k, int &J, int &S)
 {
     if (k <= kShortMax) { J = 1; S = k; return; }
     // Cheapest (J, S) with J*S >= k by a simple instruction model: per lane and root,
-    // 8 VALU instructions per literal slot plus the two cross-lane scans; per useful
-    // literal that is J * (8 S + scan(J)) / k.
+    // about 9 VALU instructions per literal slot plus the butterfly's log2(J) levels
+    // and a fixed part; per useful literal that is J * (9 S + 13 log2 J + 16) / k.
     double best = 1e30;
     J = 64; S = 16;
     for (int j = 2; j <= 64; j *= 2) {
         int lg = 0;
         while ((1 << lg) < j) ++lg;
-        const double scan = 14.0 * lg + 30.0 + (j > 16 ? 40.0 : 0.0);
-        for (int s = 8; s <= kMaxSeg; s += 4) {
+        const double lanes = 13.0 * lg + 16.0 + (j > 16 ? 20.0 : 0.0);
+        for (int s = 8; s <= kMaxSeg; s += 2) {
             if (j * s < k) continue;
-            const double cost = j * (8.0 * s + scan) / k;
+            const double cost = j * (9.0 * s + lanes) / k;
             if (cost < best - 1e-9) { best = cost; J = j; S = s; }
         }
     }
@@ -188,7 +188,7 @@ std::string check_options(const PackOptions &o)
         if (kh <= prev) return "shape_k_hi must be ascending and > 16";
         if (kh > kMaxLen) return "shape_k_hi exceeds the maximum length";
         if (J < 2 || J > 64 || (J & (J - 1))) return "shape_lanes must be 2, 4, 8, 16, 32 or 64";
-        if (S < 8 || S > kMaxSeg || S % 4) return "shape_seg must be 8, 12, 16, 20, 24, 28 or 32";
+        if (S < 8 || S > kMaxSeg || S % 2) return "shape_seg must be even, 8 to 32";
         if (J * S < kh) return "shape_lanes * shape_seg is smaller than shape_k_hi";
         prev = kh;
     }
@@ -198,8 +198,8 @@ std::string check_options(const PackOptions &o)
 
 static int tile_for(int J, const PackOptions &o)
 {
-    if (J == 1) return o.tile_short > 0 ? o.tile_short : 16;
-    return o.tile_long > 0 ? o.tile_long : std::max(1, 16 / J);
+    if (J == 1) return o.tile_short > 0 ? o.tile_short : 4;
+    return o.tile_long > 0 ? o.tile_long : (J >= 8 ? 1 : 8 / J);
 }
 
 std::string build_instance(int32_t n, int32_t C, const int64_t *con_off, const int32_t *lits,

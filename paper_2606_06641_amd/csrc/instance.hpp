@@ -2,7 +2,10 @@
 #pragma once
 
 #include <cstdint>
+#include <mutex>
 #include <vector>
+
+#include <hip/hip_runtime_api.h>
 
 #include "host.hpp"
 #include "kernels.hpp"
@@ -26,4 +29,11 @@ struct afs_instance {
     int device = -1;
     std::vector<void *> allocs;      // every device allocation, freed at destroy
     GnnGraph gnn;
+    // Second stream for the short-constraint buckets (memory-bound), which then
+    // run beside the long ones (ALU-bound) on the caller's stream; fork and join
+    // events order it against the caller's stream.  The mutex keeps one call's
+    // record / wait pairs together when several host threads use the instance.
+    hipStream_t side = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+    std::mutex side_mu;
 };

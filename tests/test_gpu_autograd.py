@@ -101,10 +101,14 @@ def test_config4_long_card_autograd():
     assert ferr <= tol
 
 
-def test_graph_replay_equals_eager():
+@pytest.mark.parametrize("kind", ["3sat", "mixed"])
+def test_graph_replay_equals_eager(kind):
     """PGD iterations captured in a HIP graph and replayed give the same bits as
-    eager launches (every replay checked, with eager work and syncs between)."""
-    inst = W.planted_3sat(instance=2)
+    eager launches (every replay checked, with eager work and syncs between).
+    The mixed instance has short and long buckets, whose launches fork to a second
+    stream and join back inside the captured graph."""
+    inst = W.planted_3sat(instance=2) if kind == "3sat" else W.mixed_10k()
+    log("case: graph replay %s" % kind)
     B = 32
     x0 = W.uniform_x0(inst.n, B, workload=1, instance=2)
     d = afsat.Instance.from_arrays(inst)

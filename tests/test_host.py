@@ -128,13 +128,13 @@ def test_packing_layout():
 
 
 def test_bucket_shapes_cover_lengths():
-    # long constraints: J lanes x S literals, S in {8, 16, 24, 32}, J a power of two
+    # long constraints: J lanes x S literals, S even in 8..32, J a power of two
     rng = np.random.default_rng(1)
     for k in [17, 24, 25, 32, 33, 100, 129, 256, 257, 512, 1000, 1024]:
         inst = W.random_instance(rng, n=2000, count=1, k_lo=k, k_hi=k)
         (b,) = host_instance(inst).buckets()
         J, S = b.lanes_per_restart, b.lits_per_lane
-        assert J & (J - 1) == 0 and 2 <= J <= 64 and S in (8, 12, 16, 20, 24, 28, 32)
+        assert J & (J - 1) == 0 and 2 <= J <= 64 and S % 2 == 0 and 8 <= S <= 32
         assert J * S >= k
 
 

@@ -192,11 +192,13 @@ def main():
         if ev is None:
             d.fe_grad(x, ws, 0, nb)
         else:
-            if dom > 0:
-                d.fe_grad(x, ws, 0, dom)
+            # the dominant bucket first, between the events; then the other buckets
+            # (the short ones overlap the long ones on the library's second stream)
             ev[0].record(stream)
             d.fe_grad(x, ws, dom, dom + 1)
             ev[1].record(stream)
+            if dom > 0:
+                d.fe_grad(x, ws, 0, dom)
             if dom + 1 < nb:
                 d.fe_grad(x, ws, dom + 1, nb)
         d.pgd_update(x, st, args.lr, None, ws)

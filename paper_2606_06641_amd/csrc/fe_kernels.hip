@@ -388,8 +388,7 @@ __global__ __launch_bounds__(kBlock) void fe_grad_seg(FeArgs A)
 #pragma unroll
                 for (int s = 0; s < S; ++s)
                     if (base + s < k)
-                        __builtin_nontemporal_store(((neg >> s) & 1u) ? -wg * adj[s] : wg * adj[s],
-                                                    A.adj + (int64_t)(slot0 + base + s) * A.Bp + b);
+                        A.adj[(int64_t)(slot0 + base + s) * A.Bp + b] = ((neg >> s) & 1u) ? -wg * adj[s] : wg * adj[s];
             }
             if (A.fe && j == J - 1) A.fe[(int64_t)A.bc_orig[c] * A.B + b] = fe;
         }

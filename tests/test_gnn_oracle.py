@@ -62,3 +62,59 @@ def test_features_definition():
     # variable 1: two positive occurrences; variable 2: one negative, one positive; variable 3: one positive
     assert np.isclose(fv[0, 1], 1.0) and np.isclose(fv[1, 1], 0.0) and np.isclose(fv[2, 1], 1.0)
     assert np.isclose(fv[0, 0], np.log2(3) / 10)
+
+
+def _dense_forward(flat, inst, x0, R):
+    """The network written with dense incidence matrices instead of scatter-adds."""
+    p = G.unpack(np.asarray(flat, np.float64), R)
+    fc, fv = G.features(inst)
+    n, C = int(inst.n), len(inst.types)
+    Ac = np.zeros((C, n))                 # Ac[c, v] = sum of signs of v in c, / k_c
+    Av = np.zeros((n, C))                 # Av[v, c] = sum of signs of v in c, / deg_v
+    off = np.asarray(inst.con_off)
+    deg = np.zeros(n)
+    for c in range(C):
+        for l in inst.lits[off[c]:off[c + 1]]:
+            v = abs(int(l)) - 1
+            Ac[c, v] += np.sign(l) / (off[c + 1] - off[c])
+            Av[v, c] += np.sign(l)
+            deg[v] += 1
+    Av /= np.maximum(deg, 1)[:, None]
+    relu = lambda a: np.maximum(a, 0)
+    hv = relu(fv @ p["Wv0"] + p["bv0"])
+    hc = relu(fc @ p["Wc0"] + p["bc0"])
+    for r in range(R):
+        hc = relu(np.hstack([hc, Ac @ hv]) @ p["U"][r] + p["bu"][r])
+        hv = relu(np.hstack([hv, Av @ hc]) @ p["V"][r] + p["bv"][r])
+    P = hv @ p["Wh"] + p["bh"]
+    z = relu(P[:, None, :] + np.asarray(x0)[:, :, None] * p["wx"]) @ p["wo"] + p["bo"][0]
+    return np.tanh(z)
+
+
+def test_forward_matches_dense_incidence_form():
+    inst = small_instance(3)
+    R = 3
+    _, total = G.layout(R)
+    rng = np.random.default_rng(5)
+    flat = rng.normal(0, 0.3, size=total)
+    x0 = rng.uniform(-1, 1, size=(inst.n, 4))
+    got, _ = G.forward(flat, inst, x0, R=R, bf16_ops=False)
+    assert np.allclose(got, _dense_forward(flat, inst, x0, R), rtol=1e-12, atol=1e-12)
+
+
+def test_variable_relabelling_permutes_outputs():
+    inst = small_instance(4)
+    R = 2
+    _, total = G.layout(R)
+    rng = np.random.default_rng(6)
+    flat = rng.normal(0, 0.3, size=total)
+    x0 = rng.uniform(-1, 1, size=(inst.n, 3))
+    perm = rng.permutation(inst.n)                 # new index of old variable v is perm[v]
+    lits = np.asarray(inst.lits)
+    relab = (np.sign(lits) * (perm[np.abs(lits) - 1] + 1)).astype(np.int32)
+    inst2 = W.Instance(n=inst.n, con_off=inst.con_off, lits=relab, types=inst.types, params=inst.params)
+    x2 = np.empty_like(x0)
+    x2[perm] = x0
+    a, _ = G.forward(flat, inst, x0, R=R, bf16_ops=False)
+    b, _ = G.forward(flat, inst2, x2, R=R, bf16_ops=False)
+    assert np.allclose(b[perm], a, rtol=1e-12, atol=1e-12)

@@ -107,7 +107,7 @@ __device__ __forceinline__ void store_lanes_stream(float *p, const Lanes<RPL> &i
 }
 
 template <int K, int RPL, bool GRAD>
-__global__ __launch_bounds__(kBlock) void fe_grad_short(FeArgs A)
+__global__ __launch_bounds__(kBlock) void fe_grad_short(FeArgs A, const float4 *__restrict__ T)
 {
     const uint32_t item = xcd_block() * kWavesPerBlock + wave_id();
     if (item >= (uint32_t)A.items) return;
@@ -142,23 +142,25 @@ __global__ __launch_bounds__(kBlock) void fe_grad_short(FeArgs A)
                 adj[i].v[e] = 0.f;
             }
         }
-        const float4 r0 = A.tab[tab];
+        const float4 r0 = T[tab];
         float fe[RPL];
 #pragma unroll
         for (int e = 0; e < RPL; ++e) fe[e] = r0.x;
         // Roots one at a time (unrolling them multiplies register use by K/2).
 #pragma unroll 1
         for (int m = 1; m <= K / 2; ++m) {
-            const float4 ra = A.tab[tab + 2 * m - 1];   // {d alpha^K, Kc}
-            const float4 rb = A.tab[tab + 2 * m];       // {-, -, -tan h, -}
+            const float4 ra = T[tab + 2 * m - 1];       // {d alpha^K, Kc}
+            const float4 rb = T[tab + 2 * m];           // {-, -, -tan h, -}
 #pragma unroll
             for (int e = 0; e < RPL; ++e) {
                 float z[K], pr[K], pi[K];
 #pragma unroll
                 for (int i = 0; i < K; ++i) z[i] = rb.z * y[i].v[e];
-                float ur = 1.0f, ui = 0.0f;   // |1 + i z|^K stays far below 2^128 for K <= 16
+                // |1 + i z|^K stays far below 2^128 for K <= 16; the prefix of literal 0
+                // is exactly 1 and the running product after it exactly (1, z_0)
+                float ur = 1.0f, ui = z[0];
 #pragma unroll
-                for (int i = 0; i < K; ++i) {
+                for (int i = 1; i < K; ++i) {
                     pr[i] = ur;
                     pi[i] = ui;
                     mul_unit(ur, ui, z[i]);
@@ -167,11 +169,12 @@ __global__ __launch_bounds__(kBlock) void fe_grad_short(FeArgs A)
                 if (GRAD) {
                     float sr = ra.z, si = ra.w;
 #pragma unroll
-                    for (int i = K - 1; i >= 0; --i) {
+                    for (int i = K - 1; i >= 1; --i) {
                         adj[i].v[e] = fmaf(pr[i], sr, adj[i].v[e]);
                         adj[i].v[e] = fmaf(-pi[i], si, adj[i].v[e]);
-                        if (i > 0) mul_unit(sr, si, z[i]);
+                        mul_unit(sr, si, z[i]);
                     }
+                    adj[0].v[e] += sr;
                 }
             }
         }
@@ -283,7 +286,7 @@ __device__ __forceinline__ void butterfly_real(float &g, float &x)
 // adjoints, deterministic order.
 // ---------------------------------------------------------------------------
 template <int J, int S, bool GRAD>
-__global__ __launch_bounds__(kBlock) void fe_grad_seg(FeArgs A)
+__global__ __launch_bounds__(kBlock) void fe_grad_seg(FeArgs A, const float4 *__restrict__ T)
 {
     static_assert(S % 2 == 0 && S >= 8 && S <= 32, "segment length must be even, 8 to 32");
     constexpr int R = kWave / J;
@@ -324,20 +327,22 @@ __global__ __launch_bounds__(kBlock) void fe_grad_seg(FeArgs A)
                 neg |= (lit < 0 ? 1u : 0u) << s;
             }
         }
-        const float4 r0 = A.tab[tab];
+        const float4 r0 = T[tab];
         float fe = r0.x;
         const int M = k >> 1;
         for (int m = 1; m <= M; ++m) {
-            const float4 ra = A.tab[tab + 3 * m - 2];   // {d, Kc}
-            const float4 rb = A.tab[tab + 3 * m - 1];   // {alpha^RP, alpha^F}
-            const float mt = A.tab[tab + 3 * m].x;      // -tan h
+            const float4 ra = T[tab + 3 * m - 2];       // {d, Kc}
+            const float4 rb = T[tab + 3 * m - 1];       // {alpha^RP, alpha^F}
+            const float mt = T[tab + 3 * m].x;          // -tan h
             float z[S], pr[S], pi[S];
 #pragma unroll
             for (int s = 0; s < S; ++s) z[s] = mt * y[s];
-            float ur = 1.0f, ui = 0.0f;
+            // prefix chain; the prefix of literal 0 is exactly 1, and after it the
+            // running product is exactly (1, z_0)
+            float ur = 1.0f, ui = z[0];
 #pragma unroll
-            for (int s = 0; s < S; ++s) {
-                if (s > 0 && s % RP == 0) cmul(ur, ui, rb.x, rb.y);
+            for (int s = 1; s < S; ++s) {
+                if (s % RP == 0) cmul(ur, ui, rb.x, rb.y);
                 pr[s] = ur;
                 pi[s] = ui;
                 mul_unit(ur, ui, z[s]);
@@ -350,14 +355,13 @@ __global__ __launch_bounds__(kBlock) void fe_grad_seg(FeArgs A)
                 float sr = ra.z, si = ra.w;
                 cmul(sr, si, xr, xi);
 #pragma unroll
-                for (int s = S - 1; s >= 0; --s) {
+                for (int s = S - 1; s >= 1; --s) {
                     adj[s] = fmaf(pr[s], sr, adj[s]);
                     adj[s] = fmaf(-pi[s], si, adj[s]);
-                    if (s > 0) {
-                        mul_unit(sr, si, z[s]);
-                        if (s % RP == 0) cmul(sr, si, rb.x, rb.y);
-                    }
+                    mul_unit(sr, si, z[s]);
+                    if (s % RP == 0) cmul(sr, si, rb.x, rb.y);
                 }
+                adj[0] += sr;                           // prefix of literal 0: exactly 1
             }
         }
         if (k & 1) {
@@ -403,11 +407,11 @@ hipError_t dispatch_short(int K, int rpl, dim3 g, hipStream_t s, const FeArgs &a
 #define AFS_SHORT(KK) case KK:                                                                        \
     if constexpr (KK <= 8) {                                                                         \
         if (rpl == 4) {                                                                              \
-            hipLaunchKernelGGL((fe_grad_short<KK, 4, GRAD>), g, dim3(kBlock), 0, s, a);              \
+            hipLaunchKernelGGL((fe_grad_short<KK, 4, GRAD>), g, dim3(kBlock), 0, s, a, a.tab);              \
             break;                                                                                   \
         }                                                                                            \
     }                                                                                                \
-    hipLaunchKernelGGL((fe_grad_short<KK, 1, GRAD>), g, dim3(kBlock), 0, s, a);                      \
+    hipLaunchKernelGGL((fe_grad_short<KK, 1, GRAD>), g, dim3(kBlock), 0, s, a, a.tab);                      \
     break;
     switch (K) {
         AFS_SHORT(1) AFS_SHORT(2) AFS_SHORT(3) AFS_SHORT(4) AFS_SHORT(5) AFS_SHORT(6)
@@ -423,19 +427,19 @@ template <int J, bool GRAD>
 hipError_t dispatch_seg_s(int S, dim3 g, hipStream_t s, const FeArgs &a)
 {
     switch (S) {
-    case 8: hipLaunchKernelGGL((fe_grad_seg<J, 8, GRAD>), g, dim3(kBlock), 0, s, a); break;
-    case 10: hipLaunchKernelGGL((fe_grad_seg<J, 10, GRAD>), g, dim3(kBlock), 0, s, a); break;
-    case 12: hipLaunchKernelGGL((fe_grad_seg<J, 12, GRAD>), g, dim3(kBlock), 0, s, a); break;
-    case 14: hipLaunchKernelGGL((fe_grad_seg<J, 14, GRAD>), g, dim3(kBlock), 0, s, a); break;
-    case 16: hipLaunchKernelGGL((fe_grad_seg<J, 16, GRAD>), g, dim3(kBlock), 0, s, a); break;
-    case 18: hipLaunchKernelGGL((fe_grad_seg<J, 18, GRAD>), g, dim3(kBlock), 0, s, a); break;
-    case 20: hipLaunchKernelGGL((fe_grad_seg<J, 20, GRAD>), g, dim3(kBlock), 0, s, a); break;
-    case 22: hipLaunchKernelGGL((fe_grad_seg<J, 22, GRAD>), g, dim3(kBlock), 0, s, a); break;
-    case 24: hipLaunchKernelGGL((fe_grad_seg<J, 24, GRAD>), g, dim3(kBlock), 0, s, a); break;
-    case 26: hipLaunchKernelGGL((fe_grad_seg<J, 26, GRAD>), g, dim3(kBlock), 0, s, a); break;
-    case 28: hipLaunchKernelGGL((fe_grad_seg<J, 28, GRAD>), g, dim3(kBlock), 0, s, a); break;
-    case 30: hipLaunchKernelGGL((fe_grad_seg<J, 30, GRAD>), g, dim3(kBlock), 0, s, a); break;
-    case 32: hipLaunchKernelGGL((fe_grad_seg<J, 32, GRAD>), g, dim3(kBlock), 0, s, a); break;
+    case 8: hipLaunchKernelGGL((fe_grad_seg<J, 8, GRAD>), g, dim3(kBlock), 0, s, a, a.tab); break;
+    case 10: hipLaunchKernelGGL((fe_grad_seg<J, 10, GRAD>), g, dim3(kBlock), 0, s, a, a.tab); break;
+    case 12: hipLaunchKernelGGL((fe_grad_seg<J, 12, GRAD>), g, dim3(kBlock), 0, s, a, a.tab); break;
+    case 14: hipLaunchKernelGGL((fe_grad_seg<J, 14, GRAD>), g, dim3(kBlock), 0, s, a, a.tab); break;
+    case 16: hipLaunchKernelGGL((fe_grad_seg<J, 16, GRAD>), g, dim3(kBlock), 0, s, a, a.tab); break;
+    case 18: hipLaunchKernelGGL((fe_grad_seg<J, 18, GRAD>), g, dim3(kBlock), 0, s, a, a.tab); break;
+    case 20: hipLaunchKernelGGL((fe_grad_seg<J, 20, GRAD>), g, dim3(kBlock), 0, s, a, a.tab); break;
+    case 22: hipLaunchKernelGGL((fe_grad_seg<J, 22, GRAD>), g, dim3(kBlock), 0, s, a, a.tab); break;
+    case 24: hipLaunchKernelGGL((fe_grad_seg<J, 24, GRAD>), g, dim3(kBlock), 0, s, a, a.tab); break;
+    case 26: hipLaunchKernelGGL((fe_grad_seg<J, 26, GRAD>), g, dim3(kBlock), 0, s, a, a.tab); break;
+    case 28: hipLaunchKernelGGL((fe_grad_seg<J, 28, GRAD>), g, dim3(kBlock), 0, s, a, a.tab); break;
+    case 30: hipLaunchKernelGGL((fe_grad_seg<J, 30, GRAD>), g, dim3(kBlock), 0, s, a, a.tab); break;
+    case 32: hipLaunchKernelGGL((fe_grad_seg<J, 32, GRAD>), g, dim3(kBlock), 0, s, a, a.tab); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -117,7 +117,9 @@ void bucket_shape(int k, int &J, int &S)
 //     {Re d, Im d, Re Kc, Im Kc}, {Re alpha^RP, Im alpha^RP, Re alpha^F, Im alpha^F},
 //     {-tan h, 0, 0, 0}
 // (The magnitudes stay in FP32 range: |1 + i z| <= 1/c <= 1/sin(pi/(2N)), so 16
-// unscaled factors stay below 2^128 up to k = 256 and 8 up to k = 1024.)
+// unscaled factors stay below 2^128 up to k = 256 and 8 up to k = 1024; and
+// c^RP stays above the smallest normal, 2^-126, at those lengths, which is why
+// alpha^RP and alpha^F are applied as separate factors.)
 int rescale_period(int J, int S) { return J * S <= 256 ? 16 : 8; }
 
 

@@ -54,11 +54,11 @@ struct FeArgs {
 // alpha = (1 + omega^m)/2 = c e^{i h}, the factor of a literal with value y is
 //     a = (1-p) + p omega^m = alpha (1 + i z),   z = -tan(h) y,
 // so one step of a product chain multiplies by (1 + i z): two FMAs.  Since
-// |1 + i z| <= 1/c, the segment kernels multiply their running products by
-// alpha^RP after every RP literals (RP = 16 for lengths <= 256, else 8), and the
-// remaining constant alpha powers are folded into the table (host.cpp,
-// append_root_rows).  Padding literals hold y = +1, whose factor
-// alpha (1 - i tan h) is exactly 1.
+// |1 + i z| <= 1/c, the segment kernels multiply their running products by the
+// real c^RP after every RP literals (RP = 16 for lengths <= 256, else 8) and by
+// c^F at the end of the segment; every phase e^{i n h} of the alpha powers is a
+// constant folded into the table rows (host.cpp, append_root_rows).  Padding
+// literals hold y = +1, whose factor alpha (1 - i tan h) is exactly 1.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void mul_unit(float &r, float &i, float z)
 {
@@ -149,7 +149,7 @@ __global__ __launch_bounds__(kBlock) void fe_grad_short(FeArgs A, const float4 *
         // Roots one at a time (unrolling them multiplies register use by K/2).
 #pragma unroll 1
         for (int m = 1; m <= K / 2; ++m) {
-            const float4 ra = T[tab + 2 * m - 1];       // {d alpha^K, Kc}
+            const float4 ra = T[tab + 2 * m - 1];       // {2 d alpha^K, Kc}
             const float4 rb = T[tab + 2 * m];           // {-, -, -tan h, -}
 #pragma unroll
             for (int e = 0; e < RPL; ++e) {
@@ -165,7 +165,8 @@ __global__ __launch_bounds__(kBlock) void fe_grad_short(FeArgs A, const float4 *
                     pi[i] = ui;
                     mul_unit(ur, ui, z[i]);
                 }
-                fe[e] = fmaf(2.0f, ra.x * ur - ra.y * ui, fe[e]);
+                fe[e] = fmaf(ra.x, ur, fe[e]);          // Re(2 d alpha^K G)
+                fe[e] = fmaf(-ra.y, ui, fe[e]);
                 if (GRAD) {
                     float sr = ra.z, si = ra.w;
 #pragma unroll
@@ -331,9 +332,9 @@ __global__ __launch_bounds__(kBlock) void fe_grad_seg(FeArgs A, const float4 *__
         float fe = r0.x;
         const int M = k >> 1;
         for (int m = 1; m <= M; ++m) {
-            const float4 ra = T[tab + 3 * m - 2];       // {d, Kc}
-            const float4 rb = T[tab + 3 * m - 1];       // {alpha^RP, alpha^F}
-            const float mt = T[tab + 3 * m].x;          // -tan h
+            const float4 ra = T[tab + 2 * m - 1];       // {2 d', Kc}
+            const float4 rb = T[tab + 2 * m];           // {-tan h, c^RP, c^F, 0}
+            const float mt = rb.x;
             float z[S], pr[S], pi[S];
 #pragma unroll
             for (int s = 0; s < S; ++s) z[s] = mt * y[s];
@@ -342,15 +343,20 @@ __global__ __launch_bounds__(kBlock) void fe_grad_seg(FeArgs A, const float4 *__
             float ur = 1.0f, ui = z[0];
 #pragma unroll
             for (int s = 1; s < S; ++s) {
-                if (s % RP == 0) cmul(ur, ui, rb.x, rb.y);
+                if (s % RP == 0) {                      // real rescale; its phase is in the rows
+                    ur *= rb.y;
+                    ui *= rb.y;
+                }
                 pr[s] = ur;
                 pi[s] = ui;
                 mul_unit(ur, ui, z[s]);
             }
-            cmul(ur, ui, rb.z, rb.w);                   // the segment's product
+            ur *= rb.z;                                 // the segment's product, scaled by c^F
+            ui *= rb.z;
             float gr = ur, gi = ui, xr = 1.0f, xi = 0.0f;
             butterfly<J>(gr, gi, xr, xi);
-            fe = fmaf(2.0f, ra.x * gr - ra.y * gi, fe);  // d G
+            fe = fmaf(ra.x, gr, fe);                    // Re(2 d' G)
+            fe = fmaf(-ra.y, gi, fe);
             if (GRAD) {
                 float sr = ra.z, si = ra.w;
                 cmul(sr, si, xr, xi);
@@ -359,7 +365,10 @@ __global__ __launch_bounds__(kBlock) void fe_grad_seg(FeArgs A, const float4 *__
                     adj[s] = fmaf(pr[s], sr, adj[s]);
                     adj[s] = fmaf(-pi[s], si, adj[s]);
                     mul_unit(sr, si, z[s]);
-                    if (s % RP == 0) cmul(sr, si, rb.x, rb.y);
+                    if (s % RP == 0) {
+                        sr *= rb.y;
+                        si *= rb.y;
+                    }
                 }
                 adj[0] += sr;                           // prefix of literal 0: exactly 1
             }

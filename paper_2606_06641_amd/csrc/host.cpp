@@ -103,23 +103,24 @@ void bucket_shape(int k, int &J, int &S)
 // Rows m = 1..floor(k/2) of a coefficient table.
 // With alpha_m = (1 + omega^m)/2 = c e^{i h} (h = pi m / N, c = cos h) every factor is
 // a = alpha_m (1 + i z), z = -tan(h) y.  Kernels multiply the unit-real-part
-// factors (1 + i z).  A segment kernel (S literals per lane) multiplies its running
-// prefix and suffix products by alpha^RP at the positions RP, 2 RP, ... < S (RP = 16
-// when every length in its bucket is <= 256, else 8): the stored prefix at literal s
-// lacks alpha^p(s) and the suffix alpha^q(s) with p(s) + q(s) = C = F - 1 for every s,
-// where F = S - RP floor((S-1)/RP) is the number of unscaled factors left in the
-// segment product (restored by alpha^F).  The constant
-//     Kc = 2 d_m beta_m alpha^C,  beta_m = (1 - omega^m)/2,
-// turns prefix * suffix into the adjoint term.  Rows per root:
-//   short kernel (k <= 16, one lane per restart, no rescaling, C = k-1):
-//     {Re(d alpha^k), Im(d alpha^k), Re Kc, Im Kc}, {0, 0, -tan h, 0}
-//   segment kernel:
-//     {Re d, Im d, Re Kc, Im Kc}, {Re alpha^RP, Im alpha^RP, Re alpha^F, Im alpha^F},
-//     {-tan h, 0, 0, 0}
+// factors (1 + i z) and keep the magnitudes in range with real scale factors;
+// the phases e^{i n h} of the alpha powers are constants folded into the rows.
+//   Short kernel (k <= 16, one lane per restart, no scaling): the FE uses
+//     2 d alpha^k, and the adjoint constant is Kc = 2 d beta alpha^(k-1),
+//     beta = (1 - omega^m)/2.
+//   Segment kernel (J lanes of S literals): a lane multiplies its running prefix
+//     and suffix products by c^RP at the positions RP, 2 RP, ... < S (RP = 16
+//     when every length in its bucket is <= 256, else 8) and its segment product
+//     by c^F, F = S - RP floor((S-1)/RP); each lane product then carries c^S and
+//     no phase.  So the FE uses 2 d' with d' = d e^{i J S h}, and the adjoint
+//     constant, which restores what prefix * suffix * (other lanes) lacks, is
+//     Kc = 2 d beta c^(F-1) e^{i (J S - 1) h}.
+// Rows per root:
+//   short:   {Re(2 d alpha^k), Im(2 d alpha^k), Re Kc, Im Kc}, {0, 0, -tan h, 0}
+//   segment: {Re 2d', Im 2d', Re Kc, Im Kc}, {-tan h, c^RP, c^F, 0}
 // (The magnitudes stay in FP32 range: |1 + i z| <= 1/c <= 1/sin(pi/(2N)), so 16
-// unscaled factors stay below 2^128 up to k = 256 and 8 up to k = 1024; and
-// c^RP stays above the smallest normal, 2^-126, at those lengths, which is why
-// alpha^RP and alpha^F are applied as separate factors.)
+// unscaled factors stay below 2^128 up to k = 256 and 8 up to k = 1024, and c^RP
+// stays above the smallest normal, 2^-126, at those lengths.)
 int rescale_period(int J, int S) { return J * S <= 256 ? 16 : 8; }
 
 
@@ -128,46 +129,42 @@ void append_root_rows(int k, int J, int S, const double *re, const double *im, s
     const int N = k + 1;
     const int M = k / 2;
     const bool shrt = k <= kShortMax;
-    int Cpow, Fpow, RP = 8;
-    if (shrt) {
-        Cpow = k - 1;
-        Fpow = k;
-    } else {
-        RP = rescale_period(J, S);
-        Fpow = S - RP * ((S - 1) / RP);
-        Cpow = Fpow - 1;
-    }
     const long double pi = 3.141592653589793238462643383279502884L;
-    // alpha^n = c^n e^{i n h}; the angle n*h = pi (m n mod 2N) / N is reduced exactly.
-    auto alpha_pow = [&](int m, int n, long double &ar, long double &ai) {
-        const long double c = cosl(pi * (long double)m / (long double)N);
-        const long double mag = powl(c, (long double)n);
+    // e^{i n h} with the angle n*h = pi (m n mod 2N) / N reduced exactly
+    auto phase = [&](int m, int64_t n, long double &pr, long double &pim) {
         const long double ang = pi * (long double)(((int64_t)m * n) % (2 * N)) / (long double)N;
-        ar = mag * cosl(ang);
-        ai = mag * sinl(ang);
+        pr = cosl(ang);
+        pim = sinl(ang);
     };
     for (int m = 1; m <= M; ++m) {
         const long double h = pi * (long double)m / (long double)N;
         const long double sh = sinl(h), ch = cosl(h);
         // beta = (1 - omega)/2 = -i sin(h) e^{i h} = (sin^2 h, -sin h cos h)
         const long double br = sh * sh, bi = -sh * ch;
-        long double cr, ci, fr, fi, ar, ai;
-        alpha_pow(m, Cpow, cr, ci);
-        alpha_pow(m, Fpow, fr, fi);
-        alpha_pow(m, RP, ar, ai);
         const long double dr = re[m], di = im[m];
-        // Kc = 2 d beta alpha^C
-        const long double tr = dr * br - di * bi, ti = dr * bi + di * br;
-        const long double kr = 2.0L * (tr * cr - ti * ci), ki = 2.0L * (tr * ci + ti * cr);
+        const long double tr = 2.0L * (dr * br - di * bi), ti = 2.0L * (dr * bi + di * br);   // 2 d beta
         const float mt = (float)(-sh / ch);
+        long double er, ei, kmag;      // FE phase and magnitude, adjoint phase (e) and magnitude
+        long double fr, fi;
         if (shrt) {
-            const long double dfr = dr * fr - di * fi, dfi = dr * fi + di * fr;
+            phase(m, k, er, ei);                          // alpha^k = c^k e^{i k h}
+            const long double ck = powl(ch, (long double)k);
+            const long double dfr = 2.0L * ck * (dr * er - di * ei), dfi = 2.0L * ck * (dr * ei + di * er);
+            phase(m, k - 1, fr, fi);                      // alpha^(k-1)
+            kmag = powl(ch, (long double)(k - 1));
+            const long double kr = kmag * (tr * fr - ti * fi), ki = kmag * (tr * fi + ti * fr);
             tab.push_back({(float)dfr, (float)dfi, (float)kr, (float)ki});
             tab.push_back({0.0f, 0.0f, mt, 0.0f});
         } else {
-            tab.push_back({(float)dr, (float)di, (float)kr, (float)ki});
-            tab.push_back({(float)ar, (float)ai, (float)fr, (float)fi});
-            tab.push_back({mt, 0.0f, 0.0f, 0.0f});
+            const int RP = rescale_period(J, S);
+            const int F = S - RP * ((S - 1) / RP);
+            phase(m, (int64_t)J * S, er, ei);             // d' = d e^{i J S h}
+            const long double dr2 = 2.0L * (dr * er - di * ei), di2 = 2.0L * (dr * ei + di * er);
+            phase(m, (int64_t)J * S - 1, fr, fi);         // Kc = 2 d beta c^(F-1) e^{i (J S - 1) h}
+            kmag = powl(ch, (long double)(F - 1));
+            const long double kr = kmag * (tr * fr - ti * fi), ki = kmag * (tr * fi + ti * fr);
+            tab.push_back({(float)dr2, (float)di2, (float)kr, (float)ki});
+            tab.push_back({mt, (float)powl(ch, (long double)RP), (float)powl(ch, (long double)F), 0.0f});
         }
     }
 }

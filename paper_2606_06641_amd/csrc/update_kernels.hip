@@ -110,13 +110,20 @@ __device__ __forceinline__ uint32_t dpp_mov_u(uint32_t v)
     return (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, CTRL, 0xF, 0xF, false);
 }
 
-// 256 restarts per wave, four per lane (nibble): eight lanes form one word,
-// gathered by row shifts inside the 16-lane row; lane 8q stores word q.
-__device__ __forceinline__ void store_bits4(uint32_t *bits, int v, int W, int chunk, uint32_t nib)
+// Four restarts per lane (a nibble): the eight lanes 8q..8q+7 form one 32-bit
+// word, gathered by row shifts inside the 16-lane row; lane 8q ends up with it.
+__device__ __forceinline__ uint32_t gather_nibbles(uint32_t nib)
 {
     uint32_t t = nib | (dpp_mov_u<0x101>(nib) << 4);      // row_shl:1
     t |= dpp_mov_u<0x102>(t) << 8;                        // row_shl:2
     t |= dpp_mov_u<0x104>(t) << 16;                       // row_shl:4
+    return t;
+}
+
+// 256 restarts per wave; lane 8q stores word q of the chunk.
+__device__ __forceinline__ void store_bits4(uint32_t *bits, int v, int W, int chunk, uint32_t nib)
+{
+    const uint32_t t = gather_nibbles(nib);
     const int lane = threadIdx.x & 63;
     const int w = chunk * (kScatterChunk / 32) + (lane >> 3);
     if ((lane & 7) == 0 && w < W) bits[(int64_t)v * W + w] = t;
@@ -213,9 +220,9 @@ __global__ __launch_bounds__(kBlock) void round_kernel(EltArgs A)
 // all (t == k), two (t >= 2) and the parity of t, which decide OR, XOR, NAE,
 // AMO and EO.
 //
-// violation_count_kernel (CARD >= K, CARD < K, EK): one lane per restart and
-// one constraint per wave, the count t summed in an integer; the predicate's
-// ballot gives the masks of the wave's two words.
+// violation_count_kernel (CARD >= K, CARD < K, EK): one constraint and 256
+// restarts per wave, four restarts per lane, the counts t summed in integers;
+// the predicates' nibbles of eight lanes form one word of the mask.
 //
 // Both read the literals of a constraint in batches (16, and kLitPad for the
 // counted kernel) so that every load of a batch is in flight at once; the
@@ -290,12 +297,12 @@ __global__ __launch_bounds__(kBlock) void violation_count_kernel(ViolArgs A)
     if (item >= A.items) return;
     const int c = A.counted[item / A.nchunks];
     const int chunk = (int)(item % A.nchunks);
-    const int b = chunk * kWave + (threadIdx.x & 63);
-    const bool valid = b < A.B;
-    const int wi = (valid ? b : A.B - 1) >> 5;
-    const int sh = b & 31;
+    const int lane = threadIdx.x & 63;
+    const int b0 = chunk * kScatterChunk + lane * kRestartsPerLane;   // four restarts per lane
+    const int wi = (b0 < A.B ? b0 : A.B - 1) >> 5;
+    const int sh = b0 & 31;
     const int o0 = A.con_off[c], o1 = A.con_off[c + 1];
-    int t = 0;
+    int t[kRestartsPerLane] = {0, 0, 0, 0};
     for (int o = o0; o < o1; o += kLitPad) {
         int l[kLitPad];
         uint32_t tv[kLitPad];
@@ -307,17 +314,24 @@ __global__ __launch_bounds__(kBlock) void violation_count_kernel(ViolArgs A)
             tv[i] = A.bits[(int64_t)(v > 0 ? v : 0) * A.W + wi];
         }
 #pragma unroll
-        for (int i = 0; i < kLitPad; ++i)
-            if (o + i < o1) t += (int)((tv[i] >> sh) & 1u) ^ (l[i] < 0 ? 1 : 0);
+        for (int i = 0; i < kLitPad; ++i) {
+            if (o + i < o1) {
+                const uint32_t nib = ((tv[i] >> sh) ^ (l[i] < 0 ? 0xFu : 0u)) & 0xFu;   // 1: literal True
+#pragma unroll
+                for (int e = 0; e < kRestartsPerLane; ++e) t[e] += (int)((nib >> e) & 1u);
+            }
+        }
     }
     const int type = A.types[c], K = A.params[c];
-    const bool sat = type == AFS_CARD_GE ? t >= K : type == AFS_CARD_LT ? t < K : t == K;
-    const unsigned long long m = __ballot(valid && !sat);
-    if ((threadIdx.x & 63) == 0) {
-        const int w0 = chunk * 2;
-        if (w0 < A.W) A.viol[(int64_t)w0 * A.Cp + c] = (uint32_t)m;
-        if (w0 + 1 < A.W) A.viol[(int64_t)(w0 + 1) * A.Cp + c] = (uint32_t)(m >> 32);
+    uint32_t nib = 0;
+#pragma unroll
+    for (int e = 0; e < kRestartsPerLane; ++e) {
+        const bool sat = type == AFS_CARD_GE ? t[e] >= K : type == AFS_CARD_LT ? t[e] < K : t[e] == K;
+        nib |= (b0 + e < A.B && !sat ? 1u : 0u) << e;
     }
+    const uint32_t word = gather_nibbles(nib);
+    const int w = chunk * (kScatterChunk / 32) + (lane >> 3);
+    if ((lane & 7) == 0 && w < A.W) A.viol[(int64_t)w * A.Cp + c] = word;
 }
 
 struct CountArgs {
@@ -567,7 +581,7 @@ hipError_t launch_verify(const DevInstance &I, int B, const uint32_t *bits, uint
     v.items = (int64_t)((I.C + v.cpw - 1) / v.cpw) * v.wchunks;
     hipLaunchKernelGGL(violation_kernel, grid_for_waves(v.items), dim3(kBlock), 0, s, v);
     if (I.n_counted > 0) {
-        v.nchunks = (B + kWave - 1) / kWave;
+        v.nchunks = (B + kScatterChunk - 1) / kScatterChunk;
         v.items = (int64_t)I.n_counted * v.nchunks;
         hipLaunchKernelGGL(violation_count_kernel, grid_for_waves(v.items), dim3(kBlock), 0, s, v);
     }

@@ -285,6 +285,33 @@ afs_status afs_pgd_step(afs_instance *inst, int32_t B, float *x, float lr, const
 afs_status afs_pgd_update(afs_instance *inst, int32_t B, float *x, float lr, const uint8_t *fixed,
                           void *ws, size_t ws_bytes, const afs_pgd_state *st, void *stream);
 
+/* Parameters of afs_pgd. */
+typedef struct {
+    float lr;               /* constant step length (Algorithm 1 with lineSearch fixed)   */
+    int32_t max_iters;      /* iteration budget d (>= 0)                                  */
+    int32_t poll;           /* iterations between reads of the done counter (>= 1)        */
+    int32_t stop_on_sat;    /* != 0: stop at the first read that finds a verified restart */
+    int32_t use_graph;      /* != 0: capture `poll` iterations once in a HIP graph and
+                               replay it (the iterations are identical either way)        */
+    const uint8_t *fixed;   /* device u8 [n] or NULL: variables held at their value
+                               (partial assignment, Sec. 3.4)                              */
+} afs_pgd_params;
+
+/* Algorithm 1 with constant step length on the B columns of x (device f32 [n][B],
+ * updated in place to the final point): afs_pgd_init, then up to max_iters
+ * iterations of afs_pgd_step, reading the device counter every `poll` iterations
+ * and stopping when stop_on_sat is set and some (part, restart) has verified.
+ * On return st holds unsat / done / first_sat / counter as after those calls,
+ * obj (device f32 [B] or NULL) the objective F at the final point (Eq. 2), and
+ * *iters (host, or NULL) the number of iterations run.  The work runs on a
+ * stream private to the instance, ordered after the caller's stream on entry
+ * and before it on return; the call synchronises with that private stream when
+ * it reads the counter, and with use_graph it builds and frees a graph, so it is
+ * not itself capturable (capture afs_pgd_step instead).  Concurrent calls on one
+ * instance are serialised. */
+afs_status afs_pgd(afs_instance *inst, int32_t B, float *x, const afs_pgd_params *params, void *ws,
+                   size_t ws_bytes, const afs_pgd_state *st, float *obj, int32_t *iters, void *stream);
+
 /* ---- learned initialisation: message-passing network ---------------------------- */
 
 /* A network over the variable-constraint graph of an instance (3 rounds by

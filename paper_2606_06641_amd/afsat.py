@@ -51,6 +51,11 @@ class _Options(ctypes.Structure):
                 ("shape_seg", _i32p), ("tile_short", ctypes.c_int32), ("tile_long", ctypes.c_int32)]
 
 
+class _PgdParams(ctypes.Structure):
+    _fields_ = [("lr", ctypes.c_float), ("max_iters", ctypes.c_int32), ("poll", ctypes.c_int32),
+                ("stop_on_sat", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("fixed", ctypes.c_void_p)]
+
+
 class _PgdState(ctypes.Structure):
     _fields_ = [("unsat", _vp), ("done", _vp), ("first_sat", _vp), ("counter", _vp)]
 
@@ -85,6 +90,8 @@ SIGNATURES = [
                                     ctypes.POINTER(_PgdState), _vp]),
     ("afs_pgd_update", ctypes.c_int, [_vp, _i32, _vp, ctypes.c_float, _vp, _vp, ctypes.c_size_t,
                                       ctypes.POINTER(_PgdState), _vp]),
+    ("afs_pgd", ctypes.c_int, [_vp, _i32, _vp, ctypes.POINTER(_PgdParams), _vp, ctypes.c_size_t,
+                               ctypes.POINTER(_PgdState), _vp, ctypes.POINTER(_i32), _vp]),
 ]
 
 _lib = None
@@ -384,38 +391,30 @@ class Instance:
         _check(lib().afs_pgd_update(self._h, B, _ptr(x), float(lr), _ptr(fixed), _ptr(ws), ws.numel(),
                                     ctypes.byref(s), _stream(self._dev())))
 
-    def pgd(self, x, lr, steps, fixed=None, poll=10, stop_on_sat=True, graph=False):
-        """Algorithm 1 with constant step length on the columns of x (updated in place).
+    def pgd(self, x, lr, steps, fixed=None, poll=10, stop_on_sat=True, graph=True, obj=False):
+        """Algorithm 1 with constant step length on the columns of x (updated in
+        place), run by the library's driver (afs_pgd).
 
         Stops after ``steps`` iterations, or (``stop_on_sat``) once any restart
-        verifies; the host reads the 'done' counter every ``poll`` iterations.
-        With ``graph``, ``poll`` iterations are captured once in a HIP graph
-        (every launch of an iteration is allocation- and sync-free) and replayed."""
+        verifies; the driver reads the done counter every ``poll`` iterations.
+        With ``graph`` the driver captures ``poll`` iterations once in a HIP graph
+        and replays it.  Returns the state (unsat, done, first_sat, counter), x,
+        the number of iterations and, with ``obj``, the objective at the final
+        point."""
         B = self._check_x(x)
         st = self.pgd_state(B)
         ws = self.workspace(B)
-        self.pgd_init(x, st, ws)
-        g = None
-        if graph and steps >= poll:
-            g = torch.cuda.CUDAGraph()
-            torch.cuda.synchronize(self.device)
-            with torch.cuda.graph(g):
-                for _ in range(poll):
-                    self.pgd_step(x, st, lr, fixed, ws)
-        t = 0
-        while t < steps:
-            if stop_on_sat and int(st["counter"][1].item()) > 0:
-                break
-            if g is not None and steps - t >= poll:
-                g.replay()
-                t += poll
-            else:
-                for _ in range(min(poll, steps - t)):
-                    self.pgd_step(x, st, lr, fixed, ws)
-                    t += 1
+        prm = _PgdParams(float(lr), int(steps), int(poll), int(bool(stop_on_sat)), int(bool(graph)),
+                         None if fixed is None else fixed.data_ptr())
+        s = self._state_struct(st)
+        o = torch.empty(B, dtype=torch.float32, device=self._dev()) if obj else None
+        iters = _i32(0)
+        _check(lib().afs_pgd(self._h, B, _ptr(x), ctypes.byref(prm), _ptr(ws), ws.numel(), ctypes.byref(s),
+                             _ptr(o), ctypes.byref(iters), _stream(self._dev())))
         st["x"] = x
-        st["iters"] = int(st["counter"][0].item())
-        st["graph"] = g
+        st["iters"] = int(iters.value)
+        if obj:
+            st["obj"] = o
         return st
 
 

@@ -99,6 +99,9 @@ void release(afs_instance *I)
         if (I->fork) (void)hipEventDestroy(I->fork);
         if (I->join) (void)hipEventDestroy(I->join);
         if (I->side) (void)hipStreamDestroy(I->side);
+        if (I->drive_in) (void)hipEventDestroy(I->drive_in);
+        if (I->drive_out) (void)hipEventDestroy(I->drive_out);
+        if (I->drive) (void)hipStreamDestroy(I->drive);
     }
     delete I;
 }
@@ -229,7 +232,10 @@ afs_status finish_create(afs_instance *I, int32_t device, afs_instance **out)
         hipError_t e = hipStreamCreateWithFlags(&I->side, hipStreamNonBlocking);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&I->fork, hipEventDisableTiming);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&I->join, hipEventDisableTiming);
-        if (e != hipSuccess) st = dev_fail(e, "side stream");
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&I->drive, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&I->drive_in, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&I->drive_out, hipEventDisableTiming);
+        if (e != hipSuccess) st = dev_fail(e, "side streams");
     }
     if (st != AFS_OK) {
         const std::string msg = g_err;
@@ -564,6 +570,80 @@ afs_status afs_pgd_update(afs_instance *I, int32_t B, float *x, float lr, const 
                           size_t ws_bytes, const afs_pgd_state *P, void *stream)
 {
     return pgd_call(I, B, x, lr, fixed, ws, ws_bytes, P, stream, false);
+}
+
+afs_status afs_pgd(afs_instance *I, int32_t B, float *x, const afs_pgd_params *prm, void *ws, size_t ws_bytes,
+                   const afs_pgd_state *P, float *obj, int32_t *iters, void *stream)
+{
+    afs_status st = check_call(I, B);
+    if (st != AFS_OK) return st;
+    if (!prm) return fail(AFS_EINVAL, "params is NULL");
+    if (prm->max_iters < 0 || prm->poll < 1) return fail(AFS_EINVAL, "max_iters must be >= 0 and poll >= 1");
+    WsLayout l;
+    if ((st = check_ws(I, B, ws, ws_bytes, l)) != AFS_OK) return st;
+    if (!P || !P->unsat || !P->done || !P->first_sat || !P->counter) return fail(AFS_EINVAL, "incomplete PGD state");
+    if (B > 0 && !x) return fail(AFS_EINVAL, "x is NULL");
+    DeviceGuard g(I->device);
+    if (g.error() != hipSuccess) return dev_fail(g.error(), "hipSetDevice");
+    std::lock_guard<std::mutex> lock(I->drive_mu);
+    hipStream_t caller = (hipStream_t)stream, s = I->drive;
+    hipError_t e = hipEventRecord(I->drive_in, caller);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s, I->drive_in, 0);
+    if (e != hipSuccess) return dev_fail(e, "ordering the driver stream");
+
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    auto finish = [&](afs_status result) {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        // the caller's stream continues after everything enqueued here
+        hipError_t e2 = hipEventRecord(I->drive_out, s);
+        if (e2 == hipSuccess) e2 = hipStreamWaitEvent(caller, I->drive_out, 0);
+        if (result == AFS_OK && e2 != hipSuccess) return dev_fail(e2, "ordering the caller's stream");
+        return result;
+    };
+    auto read_counter = [&](int32_t *host) {
+        hipError_t e2 = hipMemcpyAsync(host, P->counter, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s);
+        if (e2 == hipSuccess) e2 = hipStreamSynchronize(s);
+        return e2;
+    };
+
+    if ((st = afs_pgd_init(I, B, x, ws, ws_bytes, P, s)) != AFS_OK) return finish(st);
+    int32_t counter[2] = {0, 0};
+    for (int32_t t = 0; t < prm->max_iters;) {
+        if (prm->stop_on_sat) {
+            if ((e = read_counter(counter)) != hipSuccess) return finish(dev_fail(e, "reading the counter"));
+            if (counter[1] > 0) break;
+        }
+        const int32_t n = std::min(prm->poll, prm->max_iters - t);
+        if (prm->use_graph && n == prm->poll) {
+            if (!exec) {
+                // capture `poll` iterations once; every launch in them is allocation- and sync-free
+                if ((e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+                    return finish(dev_fail(e, "hipStreamBeginCapture"));
+                afs_status cs = AFS_OK;
+                for (int32_t i = 0; i < n && cs == AFS_OK; ++i)
+                    cs = pgd_call(I, B, x, prm->lr, prm->fixed, ws, ws_bytes, P, s, true);
+                const hipError_t ec = hipStreamEndCapture(s, &graph);
+                if (cs != AFS_OK) return finish(cs);
+                if (ec != hipSuccess) return finish(dev_fail(ec, "hipStreamEndCapture"));
+                if ((e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0)) != hipSuccess)
+                    return finish(dev_fail(e, "hipGraphInstantiate"));
+            }
+            if ((e = hipGraphLaunch(exec, s)) != hipSuccess) return finish(dev_fail(e, "hipGraphLaunch"));
+        } else {
+            for (int32_t i = 0; i < n; ++i)
+                if ((st = pgd_call(I, B, x, prm->lr, prm->fixed, ws, ws_bytes, P, s, true)) != AFS_OK)
+                    return finish(st);
+        }
+        t += n;
+    }
+    if (obj && (st = afs_eval_fwd(I, B, x, ws, ws_bytes, obj, nullptr, s)) != AFS_OK) return finish(st);
+    if (iters) {
+        if ((e = read_counter(counter)) != hipSuccess) return finish(dev_fail(e, "reading the counter"));
+        *iters = counter[0];
+    }
+    return finish(AFS_OK);
 }
 
 }  // extern "C"

@@ -36,4 +36,9 @@ struct afs_instance {
     hipStream_t side = nullptr;
     hipEvent_t fork = nullptr, join = nullptr;
     std::mutex side_mu;
+    // Private stream of the Algorithm 1 driver (afs_pgd), which captures its
+    // iterations in a graph there; events order it against the caller's stream.
+    hipStream_t drive = nullptr;
+    hipEvent_t drive_in = nullptr, drive_out = nullptr;
+    std::mutex drive_mu;
 };

@@ -175,7 +175,7 @@ def solver_target(dinst, x0, steps, lr=0.1, poll=10):
     restart (a verified one if any, else the fewest unsatisfied constraints) as a
     uint8 CUDA tensor (1 = True), plus whether it verified."""
     x = x0.clone()
-    st = dinst.pgd(x, lr=lr, steps=steps, poll=poll, stop_on_sat=True)
+    st = dinst.pgd(x, lr=lr, steps=steps, poll=poll, stop_on_sat=True, graph=False)
     unsat = st["unsat"].reshape(-1)
     best = int(torch.argmin(unsat).item())
     return (x[:, best] < 0).to(torch.uint8).contiguous(), int(unsat[best].item()) == 0
@@ -216,7 +216,7 @@ def time_to_sat(dinst, make_start, B, max_steps, lr=0.1, poll=10):
     torch.cuda.synchronize(dinst.device)
     t0 = time.perf_counter()
     x0 = make_start()
-    st = dinst.pgd(x0, lr=lr, steps=max_steps, poll=poll, stop_on_sat=True)
+    st = dinst.pgd(x0, lr=lr, steps=max_steps, poll=poll, stop_on_sat=True, graph=False)
     solved = int(st["counter"][1].item()) > 0
     torch.cuda.synchronize(dinst.device)
     t1 = time.perf_counter()
@@ -236,7 +236,7 @@ def collect_targets(parts, B=256, steps=150, lr=0.1, chunk=32):
         group = parts[i:i + chunk]
         bt = afsat.Instance.batch(group)
         x = uniform_start(bt.n, B)
-        st = bt.pgd(x, lr=lr, steps=steps, poll=10, stop_on_sat=False)
+        st = bt.pgd(x, lr=lr, steps=steps, poll=10, stop_on_sat=False, graph=False)
         unsat = st["unsat"].reshape(len(group), B)
         best = torch.argmin(unsat, dim=1)
         off = bt.var_offsets()
@@ -273,7 +273,7 @@ def run_arm(dinst, make_start, max_steps, lr=0.1, poll=10):
     torch.cuda.synchronize(dinst.device)
     t0 = time.perf_counter()
     x0 = make_start()
-    st = dinst.pgd(x0, lr=lr, steps=max_steps, poll=poll, stop_on_sat=True)
+    st = dinst.pgd(x0, lr=lr, steps=max_steps, poll=poll, stop_on_sat=True, graph=False)
     torch.cuda.synchronize(dinst.device)
     t1 = time.perf_counter()
     fs = st["first_sat"].reshape(-1)

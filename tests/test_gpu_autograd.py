@@ -103,30 +103,41 @@ def test_config4_long_card_autograd():
 
 @pytest.mark.parametrize("kind", ["3sat", "mixed"])
 def test_graph_replay_equals_eager(kind):
-    """PGD iterations captured in a HIP graph and replayed give the same bits as
-    eager launches (every replay checked, with eager work and syncs between).
-    The mixed instance has short and long buckets, whose launches fork to a second
-    stream and join back inside the captured graph."""
+    """Algorithm 1 through the library's driver with and without its internal HIP
+    graph gives the same bits; and afs_pgd_step captured by the caller (a torch
+    CUDA graph) and replayed, with eager work and syncs between replays, matches
+    eager steps at every replay.  The mixed instance has short and long buckets,
+    whose launches fork to a second stream and join back inside the graphs."""
     inst = W.planted_3sat(instance=2) if kind == "3sat" else W.mixed_10k()
     log("case: graph replay %s" % kind)
     B = 32
     x0 = W.uniform_x0(inst.n, B, workload=1, instance=2)
     d = afsat.Instance.from_arrays(inst)
     xa = parity.to_dev(x0)
-    ra = d.pgd(xa, lr=0.1, steps=40, poll=10, stop_on_sat=False, graph=False)
+    ra = d.pgd(xa, lr=0.1, steps=40, poll=10, stop_on_sat=False, graph=False, obj=True)
     xb = parity.to_dev(x0)
-    rb = d.pgd(xb, lr=0.1, steps=40, poll=10, stop_on_sat=False, graph=True)
-    assert rb["graph"] is not None
+    rb = d.pgd(xb, lr=0.1, steps=40, poll=10, stop_on_sat=False, graph=True, obj=True)
     torch.cuda.synchronize()
+    assert ra["iters"] == rb["iters"] == 40
     assert torch.equal(xa, xb)
-    for k in ("unsat", "done", "first_sat", "counter"):
+    for k in ("unsat", "done", "first_sat", "counter", "obj"):
         assert torch.equal(ra[k], rb[k]), k
-    # replay the captured graph again, three times, checking against eager steps
-    g = rb["graph"]
+    # caller-side capture of afs_pgd_step
+    ws_c, ws_e = d.workspace(B), d.workspace(B)
+    xc, xe = parity.to_dev(x0), parity.to_dev(x0)
+    sc, se = d.pgd_state(B), d.pgd_state(B)
+    d.pgd_init(xc, sc, ws_c)
+    d.pgd_init(xe, se, ws_e)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        for _ in range(10):
+            d.pgd_step(xc, sc, 0.1, None, ws_c)
     for rep in range(3):
         for _ in range(10):
-            d.pgd_step(xa, ra, 0.1, None, d.workspace(B))
+            d.pgd_step(xe, se, 0.1, None, ws_e)
         g.replay()
         torch.cuda.synchronize()
-        assert torch.equal(xa, xb), rep
-        assert torch.equal(ra["unsat"], rb["unsat"]) and torch.equal(ra["counter"], rb["counter"])
+        assert torch.equal(xc, xe), rep
+        for k in ("unsat", "done", "first_sat", "counter"):
+            assert torch.equal(sc[k], se[k]), (rep, k)

@@ -299,6 +299,32 @@ def test_pgd_done_bookkeeping():
     assert int(st["counter"][0]) == 30 and int(st["counter"][1]) == done.sum()
 
 
+@pytest.mark.parametrize("graph", [False, True])
+def test_pgd_driver_stops_on_first_verified_restart(graph):
+    """afs_pgd with stop_on_sat: it stops at the first counter read (every poll
+    iterations) that finds a verified restart, the iteration count is a multiple
+    of poll, every done restart verifies on the CPU, and the objective it returns
+    is the one afs_eval gives at the final point."""
+    inst = W.planted_3sat(n=100, m=340, instance=4)      # ratio 3.4: the oracle's PGD solves it
+    d = afsat.Instance.from_arrays(inst)
+    x0 = W.uniform_x0(inst.n, 64, workload=1, instance=4)
+    xd = parity.to_dev(x0)
+    res = d.pgd(xd, lr=0.1, steps=300, poll=5, stop_on_sat=True, graph=graph, obj=True)
+    torch.cuda.synchronize()
+    it, ndone = res["iters"], int(res["counter"][1])
+    log("stopped after %d iterations with %d restarts done" % (it, ndone))
+    assert ndone > 0 and it < 300 and it % 5 == 0 and int(res["counter"][0]) == it
+    xs = xd.cpu().numpy()
+    u = oracle.verify(inst, xs)
+    done = res["done"].cpu().numpy().astype(bool)
+    assert np.all(u[done] == 0) and np.array_equal(u, res["unsat"].cpu().numpy())
+    fs = res["first_sat"].cpu().numpy()
+    # the stop comes at the first read after a restart verifies: within the last poll window
+    assert np.all((fs[done] > it - 5) & (fs[done] <= it))
+    ev = d.eval(xd)
+    assert torch.allclose(res["obj"], ev["obj"], rtol=0, atol=1e-5)
+
+
 def test_config1_end_to_end_solves():
     """Algorithm 1 on planted 3-SAT (n=100, m=426, the 4.26 threshold ratio), 32
     restarts, lr 0.1, 200 steps.  Trajectories are chaotic, so success is compared

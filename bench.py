@@ -156,7 +156,7 @@ def main():
     shapes = []
     if not args.no_autotune:
         from paper_2606_06641_amd import autotune
-        out = os.path.join(ROOT, "gpurun_out", "tuned_shapes.json")
+        out = os.path.join(ROOT, "gpurun_out", "tuned_shapes.txt")
         os.makedirs(os.path.dirname(out), exist_ok=True)
         shapes, _ = autotune.tune(inst, B, cache_path=autotune.DEFAULT_CACHE, out_path=out,
                                   log=lambda m: print(m, file=sys.stderr, flush=True), max_cons=400)

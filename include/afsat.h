@@ -312,6 +312,32 @@ typedef struct {
 afs_status afs_pgd(afs_instance *inst, int32_t B, float *x, const afs_pgd_params *params, void *ws,
                    size_t ws_bytes, const afs_pgd_state *st, float *obj, int32_t *iters, void *stream);
 
+/* Autotuner for the segment-kernel shape of long constraints.  Sec. 4.2 finds
+ * throughput governed by the maximum constraint length and tunes the batch size
+ * for it; here the shape of the kernel that evaluates each length is tuned on the
+ * device instead (the shapes returned are what afs_options' shape arrays take).
+ * For every length
+ * range between consecutive candidate capacities J*S (J in {2, ..., 64}, S even
+ * in 8..32) that holds constraints of inst (a plain instance or a batch, device
+ * or host-only), the constraints in that range -- an evenly spaced sample of at
+ * most max_cons (<= 0: all) -- are packed alone once per candidate shape with
+ * J*S >= the range's upper length, and their FE+gradient pass at B restarts is
+ * timed on `device` (median of reps launches after one warm-up, HIP events on a
+ * private stream).  The fastest shape wins.
+ *   cache_in, cache_out: text files (either may be NULL) with one line per
+ *     result, "<arch> <revision> <B> <k_lo> <k_hi> <lanes> <seg> <ms> <timed>";
+ *     results found in either are reused, and cache_out is rewritten with them
+ *     plus the new ones, keeping only the current kernel revision.
+ *   k_lo, k_hi, lanes, seg: host int32 [max_ranges]; ms: host float [max_ranges]
+ *     or NULL (the winner's median, -1 when it came from a cache); *n_ranges:
+ *     the number of ranges the instance has (entries past max_ranges are not
+ *     written).
+ * Allocates device memory, synchronises `device`, and restores the caller's
+ * current device. */
+afs_status afs_autotune(const afs_instance *inst, int32_t device, int32_t B, int32_t reps, int32_t max_cons,
+                        const char *cache_in, const char *cache_out, int32_t max_ranges, int32_t *k_lo,
+                        int32_t *k_hi, int32_t *lanes, int32_t *seg, float *ms, int32_t *n_ranges);
+
 /* ---- learned initialisation: message-passing network ---------------------------- */
 
 /* A network over the variable-constraint graph of an instance (3 rounds by

@@ -23,9 +23,21 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-I", INCLUDE, "-I", CSRC]
 DEVICE = ["--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-munsafe-fp-atomics"]
 
+
+
+def fe_revision():
+    """First 12 hex digits of the SHA-256 of the FE kernels' source: the revision
+    that keys the autotuner's cache."""
+    import hashlib
+    with open(os.path.join(CSRC, "fe_kernels.hip"), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:12]
+
+
+HOST_HIP = [HIPCC] + COMMON + ["-x", "c++", "-D__HIP_PLATFORM_AMD__", "-I", "/opt/rocm/include"]
 SOURCES = [
     ("host.cpp", ["g++"] + COMMON),
-    ("api.cpp", [HIPCC] + COMMON + ["-x", "c++", "-D__HIP_PLATFORM_AMD__", "-I", "/opt/rocm/include"]),
+    ("api.cpp", HOST_HIP),
+    ("autotune.cpp", HOST_HIP + ['-DAFS_FE_REV="%s"' % fe_revision()]),
     ("fe_kernels.hip", [HIPCC] + COMMON + DEVICE),
     ("update_kernels.hip", [HIPCC] + COMMON + DEVICE),
     ("gnn.hip", [HIPCC] + COMMON + DEVICE),

@@ -249,6 +249,13 @@ afs_status finish_create(afs_instance *I, int32_t device, afs_instance **out)
 
 }  // namespace
 
+namespace afs {
+afs_status set_last_error(afs_status s, const std::string &msg)
+{
+    return fail(s, msg);
+}
+}  // namespace afs
+
 extern "C" {
 
 const char *afs_last_error(void) { return g_err.c_str(); }

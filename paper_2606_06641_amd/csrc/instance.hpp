@@ -3,10 +3,12 @@
 
 #include <cstdint>
 #include <mutex>
+#include <string>
 #include <vector>
 
 #include <hip/hip_runtime_api.h>
 
+#include "afsat.h"
 #include "host.hpp"
 #include "kernels.hpp"
 
@@ -22,6 +24,11 @@ struct GnnGraph {
     const float *inv_k = nullptr;     // [C] 1 / constraint length
     const float *inv_deg = nullptr;   // [n] 1 / max(1, occurrences)
 };
+
+namespace afs {
+// Set the thread-local message returned by afs_last_error; returns s.
+afs_status set_last_error(afs_status s, const std::string &msg);
+}  // namespace afs
 
 struct afs_instance {
     afs::HostInstance H;

@@ -95,14 +95,20 @@ def test_every_segment_kernel_shape(J):
         parity.compare(inst, d, gpu, orc, "J=%d S=%d" % (J, S))
 
 
-def test_autotuner_shapes_are_valid_and_exact():
+def test_autotuner_shapes_are_valid_and_exact(tmp_path):
+    """The tuned shapes cover their ranges, give results within the parity bar,
+    and the cache file round-trips: a second call finds every range cached."""
     from paper_2606_06641_amd import autotune
     rng = np.random.default_rng(21)
     inst = concat([W.random_instance(rng, n=800, count=6, k_lo=20, k_hi=150),
                    W.random_instance(rng, n=800, count=50, k_lo=2, k_hi=8)], n=800)
-    shapes, report = autotune.tune(inst, 64, reps=2, log=log)
+    cache = str(tmp_path / "shapes.txt")
+    shapes, report = autotune.tune(inst, 64, reps=2, log=log, out_path=cache)
     assert shapes and all(J * S >= kh for kh, J, S in shapes)
     assert [s[0] for s in shapes] == sorted(s[0] for s in shapes)
+    assert not any(r["cached"] for r in report)
+    shapes2, report2 = autotune.tune(inst, 64, reps=2, cache_path=cache)
+    assert shapes2 == shapes and all(r["cached"] for r in report2)
     x = rng.uniform(-1, 1, size=(inst.n, 64)).astype(np.float32)
     d = afsat.Instance.from_arrays(inst, shapes=shapes)
     parity.compare(inst, d, parity.gpu_eval(d, x), oracle.eval(inst, x, fe=True, adj=True, grad=True), "tuned")

@@ -21,7 +21,7 @@ constexpr int kMaxSeg = 32;
 
 // One row of a coefficient table, consumed by the kernels as a float4.
 //   row 0             : {d_0, d_half, 0, 0}  (d_half = d_{N/2} when N = k+1 is even, else 0)
-//   rows of root m>=1 : 2 (short kernel) or 3 (segment kernel) rows, see append_root_rows
+//   rows of root m>=1 : 2 rows, see append_root_rows
 struct TabRow {
     float x, y, z, w;
 };

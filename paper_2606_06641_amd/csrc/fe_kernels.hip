@@ -295,9 +295,14 @@ __global__ __launch_bounds__(kBlock) void fe_grad_seg(FeArgs A, const float4 *__
     const uint32_t item = xcd_block() * kWavesPerBlock + wave_id();
     if (item >= (uint32_t)A.items) return;
     const int lane = threadIdx.x & 63;
-    const uint32_t group32 = item / (uint32_t)A.ntiles;
-    const int group = (int)group32;
-    const int tile = (int)(item - group32 * (uint32_t)A.ntiles);
+    // The kWavesPerBlock waves of a block take consecutive restart groups of one
+    // tile, so that together they write whole 128-byte lines of each adjoint row;
+    // blocks then run over the tiles, and over groups of kWavesPerBlock groups last.
+    const uint32_t per = kWavesPerBlock * (uint32_t)A.ntiles;
+    const uint32_t gb = item / per, rem = item - gb * per;
+    const int tile = (int)(rem / kWavesPerBlock);
+    const int group = (int)(gb * kWavesPerBlock + rem % kWavesPerBlock);
+    if (group * R >= A.B) return;                 // padding group past the last restart
     const int r = lane / J, j = lane % J;
     const int b = group * R + r;
     const bool valid = b < A.B;
@@ -485,7 +490,8 @@ hipError_t launch_fe_grad(const DevInstance &I, const BucketLaunch &bk, int B, i
     const int rpl = (bk.J == 1 && bk.S <= 8 && B % 4 == 0 && reinterpret_cast<uintptr_t>(x) % 16 == 0 &&
                      (!dobj || reinterpret_cast<uintptr_t>(dobj) % 16 == 0)) ? 4 : 1;
     const int R = bk.J == 1 ? kWave * rpl : kWave / bk.J;      // restarts per wave
-    const int64_t groups = bk.J == 1 ? (B + R - 1) / R : (B + (kWave / bk.J) - 1) / (kWave / bk.J);
+    int64_t groups = (B + R - 1) / R;
+    if (bk.J > 1) groups = (groups + kWavesPerBlock - 1) / kWavesPerBlock * kWavesPerBlock;
     a.items = groups * bk.ntiles;
     if (a.items > INT32_MAX) return hipErrorInvalidValue;
     const dim3 g = grid_for_waves(a.items);

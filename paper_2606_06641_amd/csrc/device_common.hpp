@@ -34,6 +34,24 @@ inline dim3 grid_for_waves(int64_t items)
     return dim3((unsigned)((items + kWavesPerBlock - 1) / kWavesPerBlock));
 }
 
+// One dispatch covers fewer than 2^32 work-items (its grid size is a 32-bit
+// count).  Launchers of one-wave-per-item kernels therefore split the items into
+// launches of at most kMaxLaunchWaves waves; each kernel adds its launch's first
+// item (item0) to the item it derives from the block and wave index.
+constexpr int64_t kMaxLaunchWaves = int64_t(1) << 24;
+
+template <class Launch>
+hipError_t for_launch_chunks(int64_t items, Launch launch)
+{
+    for (int64_t first = 0; first < items; first += kMaxLaunchWaves) {
+        const int64_t count = items - first < kMaxLaunchWaves ? items - first : kMaxLaunchWaves;
+        launch(first, count);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 // DPP lane move of v (all lanes active; lanes whose source lies outside the
 // row keep their own value)
 template <int CTRL>

@@ -46,7 +46,7 @@ struct FeArgs {
     const float4 *tab;
     int B, Bp;
     int32_t c0, nc, tile, ntiles, tile0;
-    int64_t items;
+    int64_t items, item0;        // all items; first item of this launch
 };
 
 // ---------------------------------------------------------------------------
@@ -109,7 +109,7 @@ __device__ __forceinline__ void store_lanes_stream(float *p, const Lanes<RPL> &i
 template <int K, int RPL, bool GRAD>
 __global__ __launch_bounds__(kBlock) void fe_grad_short(FeArgs A, const float4 *__restrict__ T)
 {
-    const uint32_t item = xcd_block() * kWavesPerBlock + wave_id();
+    const uint32_t item = (uint32_t)A.item0 + xcd_block() * kWavesPerBlock + wave_id();
     if (item >= (uint32_t)A.items) return;
     const int lane = threadIdx.x & 63;
     const uint32_t group = item / (uint32_t)A.ntiles;
@@ -292,7 +292,7 @@ __global__ __launch_bounds__(kBlock) void fe_grad_seg(FeArgs A, const float4 *__
     static_assert(S % 2 == 0 && S >= 8 && S <= 32, "segment length must be even, 8 to 32");
     constexpr int R = kWave / J;
     constexpr int RP = J * S <= 256 ? 16 : 8;     // rescale period (see the table rows)
-    const uint32_t item = xcd_block() * kWavesPerBlock + wave_id();
+    const uint32_t item = (uint32_t)A.item0 + xcd_block() * kWavesPerBlock + wave_id();
     if (item >= (uint32_t)A.items) return;
     const int lane = threadIdx.x & 63;
     // The kWavesPerBlock waves of a block take consecutive restart groups of one
@@ -494,9 +494,16 @@ hipError_t launch_fe_grad(const DevInstance &I, const BucketLaunch &bk, int B, i
     if (bk.J > 1) groups = (groups + kWavesPerBlock - 1) / kWavesPerBlock * kWavesPerBlock;
     a.items = groups * bk.ntiles;
     if (a.items > INT32_MAX) return hipErrorInvalidValue;
-    const dim3 g = grid_for_waves(a.items);
-    if (grad) return bk.J == 1 ? dispatch_short<true>(bk.S, rpl, g, s, a) : dispatch_seg<true>(bk.J, bk.S, g, s, a);
-    return bk.J == 1 ? dispatch_short<false>(bk.S, rpl, g, s, a) : dispatch_seg<false>(bk.J, bk.S, g, s, a);
+    hipError_t err = hipSuccess;
+    const hipError_t e = for_launch_chunks(a.items, [&](int64_t first, int64_t count) {
+        a.item0 = first;
+        const dim3 g = grid_for_waves(count);
+        hipError_t r;
+        if (grad) r = bk.J == 1 ? dispatch_short<true>(bk.S, rpl, g, s, a) : dispatch_seg<true>(bk.J, bk.S, g, s, a);
+        else r = bk.J == 1 ? dispatch_short<false>(bk.S, rpl, g, s, a) : dispatch_seg<false>(bk.J, bk.S, g, s, a);
+        if (r != hipSuccess && err == hipSuccess) err = r;
+    });
+    return err != hipSuccess ? err : e;
 }
 
 }  // namespace afs

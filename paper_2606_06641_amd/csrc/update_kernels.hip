@@ -37,7 +37,7 @@ struct ScatterArgs {
     int32_t *unsat;
     float lr;
     int B, Bp, W, nchunks;
-    int64_t items;
+    int64_t items, item0;        // all items; first item of this launch
 };
 
 __device__ __forceinline__ void add4(float4 &g, const float4 a)
@@ -131,7 +131,7 @@ __device__ __forceinline__ void store_bits4(uint32_t *bits, int v, int W, int ch
 
 __global__ __launch_bounds__(kBlock) void scatter_grad_kernel(ScatterArgs A)
 {
-    const int64_t item = (int64_t)blockIdx.x * kWavesPerBlock + wave_id();
+    const int64_t item = A.item0 + (int64_t)blockIdx.x * kWavesPerBlock + wave_id();
     if (item >= A.items) return;
     const int v = (int)(item / A.nchunks), chunk = (int)(item % A.nchunks);
     const int b0 = chunk * kScatterChunk + (threadIdx.x & 63) * kRestartsPerLane;
@@ -143,7 +143,7 @@ __global__ __launch_bounds__(kBlock) void scatter_grad_kernel(ScatterArgs A)
 
 __global__ __launch_bounds__(kBlock) void scatter_step_kernel(ScatterArgs A)
 {
-    const int64_t item = (int64_t)blockIdx.x * kWavesPerBlock + wave_id();
+    const int64_t item = A.item0 + (int64_t)blockIdx.x * kWavesPerBlock + wave_id();
     if (item >= A.items) return;
     const int v = (int)(item / A.nchunks), chunk = (int)(item % A.nchunks);
     const int b0 = chunk * kScatterChunk + (threadIdx.x & 63) * kRestartsPerLane;
@@ -181,12 +181,12 @@ struct EltArgs {
     int32_t *unsat;
     float lr;
     int B, W, nchunks;
-    int64_t items;
+    int64_t items, item0;        // all items; first item of this launch
 };
 
 __global__ __launch_bounds__(kBlock) void step_kernel(EltArgs A)
 {
-    const int64_t item = (int64_t)blockIdx.x * kWavesPerBlock + wave_id();
+    const int64_t item = A.item0 + (int64_t)blockIdx.x * kWavesPerBlock + wave_id();
     if (item >= A.items) return;
     const int v = (int)(item / A.nchunks), chunk = (int)(item % A.nchunks);
     const int b = chunk * kWave + (threadIdx.x & 63);
@@ -198,7 +198,7 @@ __global__ __launch_bounds__(kBlock) void step_kernel(EltArgs A)
 
 __global__ __launch_bounds__(kBlock) void round_kernel(EltArgs A)
 {
-    const int64_t item = (int64_t)blockIdx.x * kWavesPerBlock + wave_id();
+    const int64_t item = A.item0 + (int64_t)blockIdx.x * kWavesPerBlock + wave_id();
     if (item >= A.items) return;
     const int v = (int)(item / A.nchunks), chunk = (int)(item % A.nchunks);
     const int b = chunk * kWave + (threadIdx.x & 63);
@@ -244,12 +244,12 @@ struct ViolArgs {
     uint32_t *viol;
     const int32_t *con_off, *lits, *types, *params, *counted;
     int B, W, C, Cp, wpw, cpw, wchunks, nchunks;
-    int64_t items;
+    int64_t items, item0;        // all items; first item of this launch
 };
 
 __global__ __launch_bounds__(kBlock) void violation_kernel(ViolArgs A)
 {
-    const int64_t item = (int64_t)blockIdx.x * kWavesPerBlock + wave_id();
+    const int64_t item = A.item0 + (int64_t)blockIdx.x * kWavesPerBlock + wave_id();
     if (item >= A.items) return;
     const int lane = threadIdx.x & 63;
     const int cl = lane / A.wpw, wl = lane % A.wpw;
@@ -293,7 +293,7 @@ __global__ __launch_bounds__(kBlock) void violation_kernel(ViolArgs A)
 
 __global__ __launch_bounds__(kBlock) void violation_count_kernel(ViolArgs A)
 {
-    const int64_t item = (int64_t)blockIdx.x * kWavesPerBlock + wave_id();
+    const int64_t item = A.item0 + (int64_t)blockIdx.x * kWavesPerBlock + wave_id();
     if (item >= A.items) return;
     const int c = A.counted[item / A.nchunks];
     const int chunk = (int)(item % A.nchunks);
@@ -478,9 +478,9 @@ __global__ __launch_bounds__(kBlock) void obj_reduce2(int groups, int B, int Bp,
 
 __global__ __launch_bounds__(kBlock) void permute_adj_kernel(const float *adj, float *out,
                                                              const int32_t *slot_to_lit, int B, int Bp,
-                                                             int nchunks, int64_t items)
+                                                             int nchunks, int64_t items, int64_t item0)
 {
-    const int64_t item = (int64_t)blockIdx.x * kWavesPerBlock + wave_id();
+    const int64_t item = item0 + (int64_t)blockIdx.x * kWavesPerBlock + wave_id();
     if (item >= items) return;
     const int64_t s = item / nchunks;
     const int chunk = (int)(item % nchunks);
@@ -507,8 +507,10 @@ hipError_t launch_scatter(const DevInstance &I, int B, int Bp, const float *adj,
     if (B == 0) return hipSuccess;
     ScatterArgs a = scatter_args(I, B, Bp, adj);
     a.grad = grad;
-    hipLaunchKernelGGL(scatter_grad_kernel, grid_for_waves(a.items), dim3(kBlock), 0, s, a);
-    return hipGetLastError();
+    return for_launch_chunks(a.items, [&](int64_t first, int64_t count) {
+        a.item0 = first;
+        hipLaunchKernelGGL(scatter_grad_kernel, grid_for_waves(count), dim3(kBlock), 0, s, a);
+    });
 }
 
 hipError_t launch_scatter_step(const DevInstance &I, int B, int Bp, const float *adj, float *x,
@@ -518,8 +520,10 @@ hipError_t launch_scatter_step(const DevInstance &I, int B, int Bp, const float 
     if (B == 0) return hipSuccess;
     ScatterArgs a = scatter_args(I, B, Bp, adj);
     a.x = x; a.lr = lr; a.fixed = fixed; a.done = done; a.bits = bits; a.unsat = unsat;
-    hipLaunchKernelGGL(scatter_step_kernel, grid_for_waves(a.items), dim3(kBlock), 0, s, a);
-    return hipGetLastError();
+    return for_launch_chunks(a.items, [&](int64_t first, int64_t count) {
+        a.item0 = first;
+        hipLaunchKernelGGL(scatter_step_kernel, grid_for_waves(count), dim3(kBlock), 0, s, a);
+    });
 }
 
 hipError_t launch_obj_reduce(int tiles, int B, int Bp, const float *part, float *part2,
@@ -551,8 +555,10 @@ hipError_t launch_step(const DevInstance &I, int B, float *x, const float *grad,
     EltArgs a = elt_args(I.n, B);
     a.x = x; a.grad = grad; a.lr = lr; a.fixed = fixed; a.done = done;
     a.var_inst = I.var_inst; a.n_inst = I.n_inst;
-    hipLaunchKernelGGL(step_kernel, grid_for_waves(a.items), dim3(kBlock), 0, s, a);
-    return hipGetLastError();
+    return for_launch_chunks(a.items, [&](int64_t first, int64_t count) {
+        a.item0 = first;
+        hipLaunchKernelGGL(step_kernel, grid_for_waves(count), dim3(kBlock), 0, s, a);
+    });
 }
 
 hipError_t launch_round(const DevInstance &I, int B, const float *x, uint32_t *bits, int32_t *unsat,
@@ -562,8 +568,10 @@ hipError_t launch_round(const DevInstance &I, int B, const float *x, uint32_t *b
     EltArgs a = elt_args(I.n, B);
     a.xin = x; a.bits = bits; a.unsat = unsat;
     a.var_inst = I.var_inst; a.n_inst = I.n_inst;
-    hipLaunchKernelGGL(round_kernel, grid_for_waves(a.items), dim3(kBlock), 0, s, a);
-    return hipGetLastError();
+    return for_launch_chunks(a.items, [&](int64_t first, int64_t count) {
+        a.item0 = first;
+        hipLaunchKernelGGL(round_kernel, grid_for_waves(count), dim3(kBlock), 0, s, a);
+    });
 }
 
 hipError_t launch_verify(const DevInstance &I, int B, const uint32_t *bits, uint32_t *viol,
@@ -579,11 +587,19 @@ hipError_t launch_verify(const DevInstance &I, int B, const uint32_t *bits, uint
     v.cpw = kWave / v.wpw;
     v.wchunks = (v.W + kWave - 1) / kWave;
     v.items = (int64_t)((I.C + v.cpw - 1) / v.cpw) * v.wchunks;
-    hipLaunchKernelGGL(violation_kernel, grid_for_waves(v.items), dim3(kBlock), 0, s, v);
+    hipError_t e = for_launch_chunks(v.items, [&](int64_t first, int64_t count) {
+        v.item0 = first;
+        hipLaunchKernelGGL(violation_kernel, grid_for_waves(count), dim3(kBlock), 0, s, v);
+    });
+    if (e != hipSuccess) return e;
     if (I.n_counted > 0) {
         v.nchunks = (B + kScatterChunk - 1) / kScatterChunk;
         v.items = (int64_t)I.n_counted * v.nchunks;
-        hipLaunchKernelGGL(violation_count_kernel, grid_for_waves(v.items), dim3(kBlock), 0, s, v);
+        e = for_launch_chunks(v.items, [&](int64_t first, int64_t count) {
+            v.item0 = first;
+            hipLaunchKernelGGL(violation_count_kernel, grid_for_waves(count), dim3(kBlock), 0, s, v);
+        });
+        if (e != hipSuccess) return e;
     }
     CountArgs a{};
     a.viol = viol; a.unsat = unsat; a.con_inst = I.con_inst; a.n_inst = I.n_inst;
@@ -611,9 +627,10 @@ hipError_t launch_permute_adj(const DevInstance &I, int B, int Bp, const float *
     if (B == 0 || I.L == 0) return hipSuccess;
     const int nchunks = Bp / kWave;
     const int64_t items = I.L * nchunks;
-    hipLaunchKernelGGL(permute_adj_kernel, grid_for_waves(items), dim3(kBlock), 0, s, adj, adj_out,
-                       I.slot_to_lit, B, Bp, nchunks, items);
-    return hipGetLastError();
+    return for_launch_chunks(items, [&](int64_t first, int64_t count) {
+        hipLaunchKernelGGL(permute_adj_kernel, grid_for_waves(count), dim3(kBlock), 0, s, adj, adj_out,
+                           I.slot_to_lit, B, Bp, nchunks, items, first);
+    });
 }
 
 }  // namespace afs

@@ -126,27 +126,35 @@ def _draw_group(rng, n: int, hidden: np.ndarray, count: int, k: int, ctype: int,
 
 
 def _assemble(n: int, groups, hidden, name: str, rng, shuffle: bool = True) -> Instance:
-    """groups: list of (ctype, vars [c,k], neg [c,k], params [c])."""
-    rows = []
+    """groups: list of (ctype, vars [c,k], neg [c,k], params [c]).  The rows of all
+    groups, in group order, are permuted by one draw of ``rng`` and concatenated."""
+    lit_rows, row_len, row_type, row_par, row_src = [], [], [], [], []
+    base = 0
     for ctype, v, s, p in groups:
-        for i in range(v.shape[0]):
-            rows.append((ctype, v[i], s[i], int(p[i])))
-    order = rng.permutation(len(rows)) if shuffle else np.arange(len(rows))
-    lens = np.array([len(rows[i][1]) for i in order], dtype=np.int64)
-    con_off = np.zeros(len(rows) + 1, dtype=np.int64)
-    np.cumsum(lens, out=con_off[1:])
-    lits = np.empty(int(con_off[-1]), dtype=np.int32)
-    types = np.empty(len(rows), dtype=np.int32)
-    params = np.empty(len(rows), dtype=np.int32)
-    for j, i in enumerate(order):
-        ctype, v, s, p = rows[i]
+        c, k = v.shape
         lit = (v + 1).astype(np.int32)
         lit[s] = -lit[s]
-        lits[con_off[j]:con_off[j + 1]] = lit
-        types[j] = ctype
-        params[j] = p
-    return Instance(n=n, con_off=con_off, lits=lits, types=types, params=params,
-                    weights=None, hidden=hidden, name=name)
+        lit_rows.append(lit.reshape(-1))
+        row_len.append(np.full(c, k, dtype=np.int64))
+        row_type.append(np.full(c, ctype, dtype=np.int32))
+        row_par.append(np.asarray(p, dtype=np.int32))
+        row_src.append(base + np.arange(c, dtype=np.int64) * k)    # start of each row in the flat lits
+        base += c * k
+    total_rows = sum(len(x) for x in row_len)
+    flat = np.concatenate(lit_rows) if lit_rows else np.zeros(0, np.int32)
+    lens_all = np.concatenate(row_len) if row_len else np.zeros(0, np.int64)
+    src_all = np.concatenate(row_src) if row_src else np.zeros(0, np.int64)
+    order = rng.permutation(total_rows) if shuffle else np.arange(total_rows)
+    lens = lens_all[order]
+    con_off = np.zeros(total_rows + 1, dtype=np.int64)
+    np.cumsum(lens, out=con_off[1:])
+    # every output literal's index in the flat array: its row's source start plus its position
+    pos = np.arange(int(con_off[-1]), dtype=np.int64) - np.repeat(con_off[:-1], lens)
+    lits = flat[np.repeat(src_all[order], lens) + pos].astype(np.int32)
+    types = (np.concatenate(row_type) if row_type else np.zeros(0, np.int32))[order]
+    params = (np.concatenate(row_par) if row_par else np.zeros(0, np.int32))[order]
+    return Instance(n=n, con_off=con_off, lits=lits, types=types.astype(np.int32),
+                    params=params.astype(np.int32), weights=None, hidden=hidden, name=name)
 
 
 def _by_length(rng, count: int, lo: int, hi: int, log_uniform: bool = False) -> dict:

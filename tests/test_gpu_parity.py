@@ -173,6 +173,37 @@ def test_config4_long_card_sampled():
     log(parity.format_rows(rows))
 
 
+def test_config3_batch64_full_size_sampled():
+    """The 64-instance uneven batch at full size (n log-uniform 500-50,000, 27.8M
+    literal occurrences) and 256 restarts, packed block-diagonally with the tuned
+    shapes exactly as the bench runs it; the oracle checks 8 sampled restart
+    columns of FE, adjoints, gradient and objective (columns are independent), and
+    the exact unsat counts of every part at those columns."""
+    from paper_2606_06641_amd import autotune
+    parts = W.uneven_batch()
+    off = np.cumsum([0] + [p.n for p in parts])
+    cat = concat([W.Instance(n=p.n, con_off=p.con_off, lits=np.where(p.lits > 0, p.lits + o, p.lits - o).astype(np.int32),
+                             types=p.types, params=p.params) for p, o in zip(parts, off[:-1])], n=int(off[-1]))
+    B = 256
+    shapes, _ = autotune.tune(cat, B, cache_path=autotune.DEFAULT_CACHE, max_cons=400)
+    Bt = afsat.Instance.batch(parts, shapes=shapes)
+    x = W.uniform_x0(cat.n, B, workload=3)
+    cols = np.sort(np.random.default_rng(33).choice(B, size=8, replace=False))
+    log("case: batch64 full size, L=%d, B=%d, columns %s" % (cat.n_lits, B, cols.tolist()))
+    xd = parity.to_dev(x)
+    out = Bt.eval(xd, obj=True, grad=True, fe=True, adj=True)
+    ci = torch.from_numpy(cols).cuda()
+    gpu = {k: v.index_select(v.dim() - 1, ci).cpu().numpy().astype(np.float64) for k, v in out.items()}
+    del out
+    torch.cuda.empty_cache()
+    orc = oracle.eval(cat, x[:, cols], fe=True, adj=True, grad=True)
+    rows = parity.compare(cat, Bt, gpu, orc, "batch64 sampled")
+    log(parity.format_rows(rows))
+    u = Bt.round_verify(xd).cpu().numpy()
+    for p, part in enumerate(parts):
+        assert np.array_equal(u[p][cols], oracle.verify(part, x[off[p]:off[p + 1]][:, cols])), p
+
+
 def test_verify_bit_exact():
     rng = np.random.default_rng(14)
     inst = W.random_instance(rng, n=200, count=900, k_lo=1, k_hi=40)

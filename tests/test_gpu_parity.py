@@ -52,12 +52,15 @@ def adversarial_points(n, rng):
     return np.stack(cols, axis=1).astype(np.float32)
 
 
-def test_short_all_types_ragged_batch():
+@pytest.mark.parametrize("B", [37, 64, 300])
+def test_short_all_types_ragged_batch(B):
+    """Every type, lengths 1-16, weighted; B = 37 takes one restart per lane, B = 64
+    and 300 four restarts per lane for k <= 8 (300 leaves a partial wave)."""
     rng = np.random.default_rng(10)
     inst = W.random_instance(rng, n=300, count=500, k_lo=1, k_hi=16)
     inst.weights = rng.uniform(0.5, 2.0, size=inst.n_cons).astype(np.float32)
-    x = rng.uniform(-1, 1, size=(inst.n, 37)).astype(np.float32)
-    check(inst, x, "short k1-16 B=37 weighted")
+    x = rng.uniform(-1, 1, size=(inst.n, B)).astype(np.float32)
+    check(inst, x, "short k1-16 B=%d weighted" % B)
 
 
 def test_long_every_bucket_shape():
@@ -68,8 +71,9 @@ def test_long_every_bucket_shape():
     for k in ks:
         parts.append(W.random_instance(rng, n=1500, count=3, k_lo=k, k_hi=k))
     inst = concat(parts, n=1500)
+    inst.weights = rng.uniform(0.5, 2.0, size=inst.n_cons).astype(np.float32)
     x = rng.uniform(-1, 1, size=(inst.n, 70)).astype(np.float32)
-    check(inst, x, "long k17-1024 B=70")
+    check(inst, x, "long k17-1024 B=70 weighted")
 
 
 @pytest.mark.parametrize("J", [2, 4, 8, 16, 32, 64])
@@ -360,6 +364,22 @@ def test_pgd_driver_stops_on_first_verified_restart(graph):
     assert np.all((fs[done] > it - 5) & (fs[done] <= it))
     ev = d.eval(xd)
     assert torch.allclose(res["obj"], ev["obj"], rtol=0, atol=1e-5)
+
+
+def test_pgd_driver_keeps_fixed_variables():
+    """A partial assignment (Sec. 3.4): variables marked fixed keep their values
+    through the driver's iterations; the others move."""
+    inst = W.mixed_10k()
+    d = afsat.Instance.from_arrays(inst)
+    rng = np.random.default_rng(40)
+    fixed = (rng.random(inst.n) < 0.3).astype(np.uint8)
+    x0 = W.uniform_x0(inst.n, 64, workload=2, instance=1)
+    xd = parity.to_dev(x0)
+    d.pgd(xd, lr=0.1, steps=20, poll=5, stop_on_sat=False, fixed=torch.from_numpy(fixed).cuda())
+    xs = xd.cpu().numpy()
+    f = fixed.astype(bool)
+    assert np.array_equal(xs[f], x0[f])
+    assert np.mean(xs[~f] != x0[~f]) > 0.9
 
 
 def test_config1_end_to_end_solves():

@@ -49,7 +49,7 @@ extern "C" {
 typedef enum {
     AFS_OK = 0,
     AFS_EINVAL = -1,   /* invalid argument or instance */
-    AFS_EUNSAT = -2,   /* reserved: conflicting unit literals at ingestion */
+    AFS_EUNSAT = -2,   /* input proven unsatisfiable while parsing (afs_parse_*) */
     AFS_ENOMEM = -3,   /* host or device allocation failed */
     AFS_EDEVICE = -4,  /* HIP runtime or kernel launch error */
     AFS_ESTATE = -5    /* call not valid for this instance (e.g. host-only) */
@@ -392,6 +392,47 @@ afs_status afs_gnn_adam(afs_gnn *net, float lr, float beta1, float beta2, float 
 afs_status afs_gnn_gemm_bf16(int32_t M, int32_t N, int32_t K, const float *A, int64_t sam, int64_t sak,
                              const float *B, int64_t sbk, int64_t sbn, float *C, int64_t ldc,
                              void *stream);
+
+/* ---- Input files (App. A) ----
+ * DIMACS CNF and the hybrid symmetric-constraint format: an optional 'h' marker,
+ * an optional type identifier (x/xor, n/nae, a/amo, e/eo, k/ek K, d/card T with
+ * T = K (K > 0: at least K; K < 0: fewer than |K|) or >=K, >K, <K, <=K) and
+ * literals, ended by 0; comment lines start with 'c' or '*'; text after a
+ * constraint's 0 is a comment; "p cnf <vars> <constraints>" is optional.  CARD
+ * thresholds are normalised to AFS_CARD_GE / AFS_CARD_LT and XOR to odd parity.
+ * The simplifications of App. A are applied: one-literal OR and EO constraints
+ * and CARD >= k / EK k over k literals fix their literals True, EK 0 fixes its
+ * literals False, one-literal AMO and CARD >= 0 are dropped, CARD >= 1 becomes
+ * OR and EK 1 becomes EO; fixing a variable both ways returns AFS_EUNSAT, as
+ * does a threshold no assignment meets (CARD >= K or EK K with K above the
+ * length, CARD < K with K <= 0).  CARD < K with K above the length is dropped,
+ * and a plain threshold 0 reads as ">= 0".  The operator may stand apart from
+ * its number ("d >= 2").  The fixed variables are returned as units (a partial
+ * assignment, Sec. 3.4) and not propagated further. */
+typedef struct afs_parsed afs_parsed;
+
+typedef struct {
+    int32_t n_vars;          /* from the problem line, else the largest variable */
+    int32_t n_cons;          /* constraints kept                                  */
+    int64_t n_lits;
+    int32_t n_units;         /* variables fixed by the simplifications            */
+    int32_t n_dropped;       /* constraints removed by the simplifications        */
+    int32_t declared_cons;   /* constraint count of the problem line, -1 if none  */
+} afs_parsed_info;
+
+/* Parse len bytes of text, or the file at path.  On error *out is NULL and the
+ * message (with the line number) is in afs_last_error(). */
+afs_status afs_parse_text(const char *text, size_t len, afs_parsed **out);
+afs_status afs_parse_file(const char *path, afs_parsed **out);
+afs_status afs_parsed_get_info(const afs_parsed *p, afs_parsed_info *out);
+
+/* Copy the kept constraints into host arrays sized from afs_parsed_get_info:
+ * con_off int64 [n_cons+1], lits int32 [n_lits], types int32 [n_cons], params
+ * int32 [n_cons] (the afs_instance_create arrays), and units int8 [n_vars]
+ * (+1 fixed True, -1 fixed False, 0 free).  Any pointer may be NULL. */
+afs_status afs_parsed_arrays(const afs_parsed *p, int64_t *con_off, int32_t *lits, int32_t *types,
+                             int32_t *params, int8_t *units);
+void afs_parsed_destroy(afs_parsed *p);
 
 /* Thread-local message for the last non-OK status of an afs_gnn_* call. */
 const char *afs_gnn_last_error(void);

@@ -60,6 +60,11 @@ class _PgdState(ctypes.Structure):
     _fields_ = [("unsat", _vp), ("done", _vp), ("first_sat", _vp), ("counter", _vp)]
 
 
+class _ParsedInfo(ctypes.Structure):
+    _fields_ = [("n_vars", ctypes.c_int32), ("n_cons", ctypes.c_int32), ("n_lits", ctypes.c_int64),
+                ("n_units", ctypes.c_int32), ("n_dropped", ctypes.c_int32), ("declared_cons", ctypes.c_int32)]
+
+
 # (name, restype, argtypes) of every exported function; the CPU tests check that
 # the library exports exactly these.
 SIGNATURES = [
@@ -95,6 +100,11 @@ SIGNATURES = [
     ("afs_autotune", ctypes.c_int, [_vp, _i32, _i32, _i32, _i32, ctypes.c_char_p, ctypes.c_char_p, _i32,
                                     _i32p, _i32p, _i32p, _i32p, ctypes.POINTER(ctypes.c_float),
                                     ctypes.POINTER(_i32)]),
+    ("afs_parse_text", ctypes.c_int, [ctypes.c_char_p, ctypes.c_size_t, ctypes.POINTER(_vp)]),
+    ("afs_parse_file", ctypes.c_int, [ctypes.c_char_p, ctypes.POINTER(_vp)]),
+    ("afs_parsed_get_info", ctypes.c_int, [_vp, ctypes.POINTER(_ParsedInfo)]),
+    ("afs_parsed_arrays", ctypes.c_int, [_vp, _i64p, _i32p, _i32p, _i32p, ctypes.POINTER(ctypes.c_int8)]),
+    ("afs_parsed_destroy", None, [_vp]),
 ]
 
 _lib = None
@@ -419,6 +429,70 @@ class Instance:
         if obj:
             st["obj"] = o
         return st
+
+
+@dataclass
+class Parsed:
+    """An input file after the reader's simplifications (App. A): the kept
+    constraints in the arrays ``Instance`` takes, and ``units`` (int8 [n]: +1
+    fixed True, -1 fixed False, 0 free), the partial assignment of Sec. 3.4."""
+    n: int
+    con_off: np.ndarray
+    lits: np.ndarray
+    types: np.ndarray
+    params: np.ndarray
+    units: np.ndarray
+    n_dropped: int
+    declared_cons: int
+    weights: Optional[np.ndarray] = None
+
+    def fixed_mask(self, device=0):
+        """u8 [n] device mask of the fixed variables (the ``fixed`` argument of
+        ``step`` and ``pgd``)."""
+        return torch.from_numpy((self.units != 0).astype(np.uint8)).to(device)
+
+    def apply_units(self, x):
+        """Set the fixed variables' rows of x (n, B) to their values in place
+        (True is -1, False is +1)."""
+        idx = np.nonzero(self.units)[0]
+        if idx.size:
+            vals = torch.from_numpy(-self.units[idx].astype(np.float32)).to(x.device)
+            x[torch.from_numpy(idx).to(x.device)] = vals[:, None].to(x.dtype)
+        return x
+
+
+def _take_parsed(h):
+    try:
+        info = _ParsedInfo()
+        _check(lib().afs_parsed_get_info(h, ctypes.byref(info)))
+        con_off = np.zeros(info.n_cons + 1, dtype=np.int64)
+        lits = np.zeros(info.n_lits, dtype=np.int32)
+        types = np.zeros(info.n_cons, dtype=np.int32)
+        params = np.zeros(info.n_cons, dtype=np.int32)
+        units = np.zeros(info.n_vars, dtype=np.int8)
+        _check(lib().afs_parsed_arrays(h, _np_ptr(con_off, _i64p), _np_ptr(lits, _i32p), _np_ptr(types, _i32p),
+                                       _np_ptr(params, _i32p), _np_ptr(units, ctypes.POINTER(ctypes.c_int8))))
+        return Parsed(int(info.n_vars), con_off, lits, types, params, units, int(info.n_dropped),
+                      int(info.declared_cons))
+    finally:
+        lib().afs_parsed_destroy(h)
+
+
+def parse_text(text):
+    """Parse DIMACS CNF or the hybrid format of App. A from a string or bytes.
+    Raises ``AfsError`` (status ``AFS_EUNSAT`` when the simplifications prove the
+    input unsatisfiable, ``AFS_EINVAL`` for malformed input)."""
+    data = text.encode() if isinstance(text, str) else bytes(text)
+    h = ctypes.c_void_p()
+    _check(lib().afs_parse_text(data, len(data), ctypes.byref(h)))
+    return _take_parsed(h)
+
+
+def parse_file(path):
+    """``parse_text`` of the file at ``path``."""
+    h = ctypes.c_void_p()
+    _check(lib().afs_parse_file(os.fsencode(path), ctypes.byref(h)))
+    return _take_parsed(h)
 
 
 class FEObjective(torch.autograd.Function):

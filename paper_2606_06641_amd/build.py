@@ -38,6 +38,7 @@ SOURCES = [
     ("host.cpp", ["g++"] + COMMON),
     ("api.cpp", HOST_HIP),
     ("autotune.cpp", HOST_HIP + ['-DAFS_FE_REV="%s"' % fe_revision()]),
+    ("parse.cpp", HOST_HIP),
     ("fe_kernels.hip", [HIPCC] + COMMON + DEVICE),
     ("update_kernels.hip", [HIPCC] + COMMON + DEVICE),
     ("gnn.hip", [HIPCC] + COMMON + DEVICE),

@@ -230,15 +230,22 @@ afs_status afs_eval_adjoint(afs_instance *inst, int32_t B, const float *x, const
 
 /* ---- Algorithm 1 --------------------------------------------------------------- */
 
+/* Partial assignments (Sec. 3.4).  Wherever a call takes `fixed, n_partial`,
+ * fixed is NULL (nothing fixed) or device u8 [n_partial][n] (n_partial 0 reads as
+ * 1): the B restarts are divided evenly among the rows, restart b using row
+ * b * n_partial / B, and variable v is held where that row's entry is nonzero.
+ * n_partial > B is rejected.  The values the variables are held at are those in
+ * x (afs_init_points writes them). */
+
 /* Projected gradient step with constant step length (Algorithm 1,
  * projectToBounds onto [-1,1]^n):  x <- min(1, max(-1, x - lr * grad)) in FP32,
- * skipped for variables with fixed[v] != 0 (partial assignment, Sec. 3.4) and
- * restarts with done != 0 (finished candidates do no-ops, Sec. 3.3).
+ * skipped for fixed variables (Sec. 3.4) and restarts with done != 0 (finished
+ * candidates do no-ops, Sec. 3.3).
  *   x: device f32 [n][B] updated in place; grad: device f32 [n][B];
- *   fixed: device u8 [n] or NULL; done: device u8 [P][B] or NULL (P as in
+ *   fixed, n_partial: as above; done: device u8 [P][B] or NULL (P as in
  *   afs_pgd_state; variable v of part p is frozen where done[p][b] != 0). */
 afs_status afs_step(afs_instance *inst, int32_t B, float *x, const float *grad, float lr,
-                    const uint8_t *fixed, const uint8_t *done, void *stream);
+                    const uint8_t *fixed, int32_t n_partial, const uint8_t *done, void *stream);
 
 /* Round and count unsatisfied constraints exactly (Algorithm 1's unsat_count).
  *   x    : device f32 [n][B]
@@ -257,10 +264,11 @@ afs_status afs_round_verify(afs_instance *inst, int32_t B, const float *x, uint3
  * instance has P = 1. */
 typedef struct {
     int32_t *unsat;      /* [P][B] unsat count at the current point                 */
-    uint8_t *done;       /* [P][B] 1 once the restart has verified (then frozen)    */
+    uint8_t *done;       /* [P][B] 0 searching, 1 verified, 2 converged (its step
+                            length fell below delta, Algorithm 1); either freezes it */
     int32_t *first_sat;  /* [P][B] iteration at which it verified, -1 if not yet    */
-    int32_t *counter;    /* [2] {iteration t, number of (part, restart) pairs done};
-                            t counts completed iterations                            */
+    int32_t *counter;    /* [4] {iteration t, pairs verified, pairs frozen (verified
+                            or converged), 0}; t counts completed iterations        */
 } afs_pgd_state;
 
 /* Reset the state and check the initial point X_(0): unsat, done and first_sat = 0
@@ -275,7 +283,8 @@ afs_status afs_pgd_init(afs_instance *inst, int32_t B, const float *x, void *ws,
  * number lives in st->counter), so a sequence of calls may be captured in a
  * HIP graph and replayed. */
 afs_status afs_pgd_step(afs_instance *inst, int32_t B, float *x, float lr, const uint8_t *fixed,
-                        void *ws, size_t ws_bytes, const afs_pgd_state *st, void *stream);
+                        int32_t n_partial, void *ws, size_t ws_bytes, const afs_pgd_state *st,
+                        void *stream);
 
 /* The part of afs_pgd_step that follows the FE kernels: with the per-literal
  * adjoints of X_(t-1) already in the workspace (afs_fe_grad over every bucket),
@@ -283,7 +292,49 @@ afs_status afs_pgd_step(afs_instance *inst, int32_t B, float *x, float lr, const
  * constraints and update the state.  afs_fe_grad(all buckets) followed by
  * afs_pgd_update is exactly afs_pgd_step. */
 afs_status afs_pgd_update(afs_instance *inst, int32_t B, float *x, float lr, const uint8_t *fixed,
-                          void *ws, size_t ws_bytes, const afs_pgd_state *st, void *stream);
+                          int32_t n_partial, void *ws, size_t ws_bytes, const afs_pgd_state *st,
+                          void *stream);
+
+/* Backtracking line search (Algorithm 1's lineSearch with maximum step s;
+ * Sec. 3.3: each restart picks its own step length).  Per restart: f0 = F(x) and
+ * g = grad F(x); trial j = 0..trials-1 takes eta = max_step * shrink^j and
+ * xt = clip(x - eta g, -1, 1) (fixed variables held) and accepts the first trial
+ * with F(xt) <= f0 + armijo * <g, xt - x> (sufficient decrease along the
+ * projection arc); when none is accepted eta = 0 and the restart does not move.
+ * F(xt) is the same FE kernels' forward pass; the sums are fixed-order. */
+typedef struct {
+    float max_step;         /* s > 0: the first trial step length                */
+    float shrink;           /* in (0,1): factor between consecutive trials        */
+    float armijo;           /* in [0,1): sufficient-decrease constant             */
+    int32_t trials;         /* trial step lengths per iteration, 1..64            */
+} afs_line_search;
+
+/* Bytes of the second workspace a line search needs for B restarts (gradient
+ * and trial point [n][B] and per-restart vectors); caller-owned, 256-byte
+ * aligned. */
+afs_status afs_search_workspace_bytes(const afs_instance *inst, int32_t B, size_t *bytes);
+
+/* One iteration of Algorithm 1 with the line search above: search, step to
+ * X_(t) with the chosen eta, rounding, exact unsat count and state update as in
+ * afs_pgd_step; then a restart that did not verify and whose eta < delta
+ * (delta > 0) converges (done = 2).  eta: device f32 [B] receiving the chosen
+ * step lengths, or NULL.  Plain instances only (a batch returns AFS_EINVAL).
+ * Launch-only, so a sequence of calls may be captured in a HIP graph. */
+afs_status afs_pgd_search_step(afs_instance *inst, int32_t B, float *x, const afs_line_search *ls,
+                               const uint8_t *fixed, int32_t n_partial, float delta, void *ws,
+                               size_t ws_bytes, void *search_ws, size_t search_ws_bytes,
+                               const afs_pgd_state *st, float *eta, void *stream);
+
+/* Starting points (Sec. 3.4: fixed variables across all restarts, the rest
+ * random).  x[v][b] = -1 where values[p][v] > 0 (True), +1 where it is < 0
+ * (False), with p = b * n_partial / B; elsewhere uniform on [-1, 1): the top 24
+ * bits u of the first word of Philox4x32-10 (Salmon et al., SC 2011) with key
+ * (seed low word, seed high word) and counter (b, v, 0, 0), x = u * 2^-23 - 1.
+ * values: device i8 [n_partial][n] or NULL (all random); a values array may
+ * serve as the fixed mask of the other calls (nonzero = fixed).  x: device
+ * f32 [n][B]. */
+afs_status afs_init_points(afs_instance *inst, int32_t B, uint64_t seed, const int8_t *values,
+                           int32_t n_partial, float *x, void *stream);
 
 /* Parameters of afs_pgd. */
 typedef struct {
@@ -293,14 +344,23 @@ typedef struct {
     int32_t stop_on_sat;    /* != 0: stop at the first read that finds a verified restart */
     int32_t use_graph;      /* != 0: capture `poll` iterations once in a HIP graph and
                                replay it (the iterations are identical either way)        */
-    const uint8_t *fixed;   /* device u8 [n] or NULL: variables held at their value
-                               (partial assignment, Sec. 3.4)                              */
+    const uint8_t *fixed;   /* device u8 [n_partial][n] or NULL: variables held at their
+                               value (partial assignments, Sec. 3.4)                       */
+    int32_t n_partial;      /* rows of fixed (0 reads as 1)                                 */
+    float delta;            /* > 0: a restart whose step length falls below delta
+                               converges and stops (Algorithm 1); 0: off                   */
+    const afs_line_search *search;  /* NULL: constant step lr; else the line search
+                               (plain instances only)                                       */
+    void *search_ws;        /* line-search workspace (afs_search_workspace_bytes)          */
+    size_t search_ws_bytes;
 } afs_pgd_params;
 
-/* Algorithm 1 with constant step length on the B columns of x (device f32 [n][B],
- * updated in place to the final point): afs_pgd_init, then up to max_iters
- * iterations of afs_pgd_step, reading the device counter every `poll` iterations
- * and stopping when stop_on_sat is set and some (part, restart) has verified.
+/* Algorithm 1 on the B columns of x (device f32 [n][B], updated in place to the
+ * final point): afs_pgd_init, then up to max_iters iterations of afs_pgd_step
+ * (constant step) or afs_pgd_search_step (line search), reading the device
+ * counter every `poll` iterations (when stop_on_sat is set or delta > 0) and
+ * stopping when stop_on_sat is set and some (part, restart) has verified, or
+ * when every (part, restart) has verified or converged.
  * On return st holds unsat / done / first_sat / counter as after those calls,
  * obj (device f32 [B] or NULL) the objective F at the final point (Eq. 2), and
  * *iters (host, or NULL) the number of iterations run.  The work runs on a
@@ -433,6 +493,14 @@ afs_status afs_parsed_get_info(const afs_parsed *p, afs_parsed_info *out);
 afs_status afs_parsed_arrays(const afs_parsed *p, int64_t *con_off, int32_t *lits, int32_t *types,
                              int32_t *params, int8_t *units);
 void afs_parsed_destroy(afs_parsed *p);
+
+/* Unit folding (Sec. 3.4): write the parsed units into each of n_partial partial
+ * assignments values (host i8 [n_partial][n_vars]: +1 True, -1 False, 0 free,
+ * updated in place).  A unit that contradicts a partial assignment returns
+ * AFS_EUNSAT naming the row and the variable (values is then unspecified).  With
+ * no partial assignments of its own a caller passes one zero row and receives the
+ * units as a partial assignment for every restart. */
+afs_status afs_parsed_fold_units(const afs_parsed *p, int32_t n_partial, int8_t *values);
 
 /* Thread-local message for the last non-OK status of an afs_gnn_* call. */
 const char *afs_gnn_last_error(void);

@@ -12,6 +12,11 @@ Functions follow the paper:
   * ``step``   -- the projected gradient step of Algorithm 1.
   * ``verify`` -- rounding and unsat_count of Algorithm 1, on FP32 points.
   * ``pgd``    -- Algorithm 1 with constant step length, FP64.
+  * ``line_search_step`` / ``pgd_search`` -- Algorithm 1 with lineSearch taken
+                  as backtracking from a maximum step s with the Armijo
+                  sufficient-decrease test along the projection arc, FP64.
+  * ``fixed_columns`` -- the partial-assignment slices of Sec. 3.4 (the restarts
+                  divided evenly among the rows of a fixed mask).
 """
 import ctypes
 import os
@@ -144,8 +149,54 @@ def verify(inst, x, want_bits=False):
     return (unsat, bits) if want_bits else unsat
 
 
-def pgd(inst, x0, lr, steps, fixed=None, nthreads=None):
-    """Algorithm 1 with constant step length ``lr``, FP64 throughout."""
+def fixed_columns(fixed, n, B):
+    """Boolean (n, B) mask of held variables for a fixed mask shaped (n,) or
+    (P, n): restart b uses row b*P//B (Sec. 3.4 divides the restarts evenly
+    among the partial assignments)."""
+    if fixed is None:
+        return np.zeros((n, B), dtype=bool)
+    f = np.asarray(fixed)
+    if f.ndim == 1:
+        f = f[None, :]
+    P = f.shape[0]
+    rows = (np.arange(B, dtype=np.int64) * P) // max(B, 1)
+    return (f[rows, :] != 0).T.copy()
+
+
+def _slices(fixed, B):
+    """(columns, row) pairs of the restarts that share one row of ``fixed``."""
+    f = np.asarray(fixed)
+    P = 1 if f.ndim == 1 else f.shape[0]
+    rows = (np.arange(B, dtype=np.int64) * P) // max(B, 1)
+    out = []
+    for p in range(P):
+        cols = np.nonzero(rows == p)[0]
+        if cols.size:
+            out.append((cols, f if f.ndim == 1 else f[p]))
+    return out
+
+
+def pgd(inst, x0, lr, steps, fixed=None, nthreads=None, delta=0.0):
+    """Algorithm 1 with constant step length ``lr``, FP64 throughout.
+
+    ``fixed`` may hold several partial assignments (P, n); the restarts are then
+    run slice by slice (restarts are independent).  With ``delta`` > lr every
+    restart that has not verified after the first iteration has converged
+    (eta = lr < delta) and stops there."""
+    if fixed is not None and np.asarray(fixed).ndim == 2:
+        x0 = np.asarray(x0)
+        out = {"x": np.array(x0, dtype=np.float64), "unsat": np.zeros(x0.shape[1], np.int32),
+               "first_sat": np.zeros(x0.shape[1], np.int32), "obj": np.zeros(x0.shape[1])}
+        for cols, row in _slices(fixed, x0.shape[1]):
+            r = pgd(inst, x0[:, cols], lr, steps, fixed=row, nthreads=nthreads, delta=delta)
+            for k in out:
+                if k == "x":
+                    out[k][:, cols] = r[k]
+                else:
+                    out[k][cols] = r[k]
+        return out
+    if delta > 0 and lr < delta:
+        steps = min(steps, 1)
     n, C, con_off, lits, types, params, w = _arrays(inst)
     x = np.array(x0, dtype=np.float64, order="C", copy=True)
     B = x.shape[1]
@@ -160,3 +211,83 @@ def pgd(inst, x0, lr, steps, fixed=None, nthreads=None):
     if rc:
         raise ValueError("orc_pgd failed with status %d" % rc)
     return {"x": x, "unsat": unsat, "first_sat": first, "obj": obj}
+
+
+def unsat_count(inst, x):
+    """unsat_count of Algorithm 1 on FP64 points (n, B): variable v True where
+    x[v] < 0; a literal is true when its variable's truth differs from its sign."""
+    n, C, con_off, lits, types, params, _ = _arrays(inst)
+    tv = np.asarray(x, dtype=np.float64) < 0.0
+    out = np.zeros(tv.shape[1], dtype=np.int32)
+    for c in range(C):
+        ls = lits[con_off[c]:con_off[c + 1]]
+        t = np.zeros(tv.shape[1], dtype=np.int64)
+        for l in ls:
+            t += tv[abs(int(l)) - 1] ^ (l < 0)
+        ok = np.array([sat(types[c], len(ls), params[c], tt) for tt in range(len(ls) + 1)])
+        out += ~ok[t]
+    return out
+
+
+def line_search_step(inst, x, search, fixed=None, done=None, nthreads=None):
+    """One iteration of Algorithm 1 with lineSearch as backtracking, FP64.
+
+    search = (s, beta, c, T).  Per restart: f0 = F(x), g = grad F(x); trial j
+    takes eta_j = s * beta^j and xt = clip(x - eta_j g, -1, 1) with the fixed
+    variables held, and the first trial with F(xt) <= f0 + c * <g, xt - x> is
+    taken; when none is, eta = 0.  Restarts with done != 0 keep eta = 0 and x.
+
+    Returns x (the new point), eta (B,), f0 (B,), g (n, B), and for every trial
+    (whether or not the restart had already decided) eta_trials (T,) and
+    margin (T, B) = f0 + c * <g, xt - x> - F(xt), so a caller can see how close
+    each decision was."""
+    s_max, beta, c, T = float(search[0]), float(search[1]), float(search[2]), int(search[3])
+    x = np.asarray(x, dtype=np.float64)
+    n, B = x.shape
+    held = fixed_columns(fixed, n, B)
+    r0 = eval(inst, x, grad=True, nthreads=nthreads)
+    f0, g = r0["obj"], r0["grad"]
+    gm = np.where(held, 0.0, g)
+    eta = np.zeros(B)
+    decided = np.zeros(B, dtype=bool) if done is None else np.asarray(done).reshape(B) != 0
+    etas, margins = [], []
+    e = s_max
+    for j in range(T):
+        xt = np.where(held, x, np.clip(x - e * g, -1.0, 1.0))
+        dot = np.sum(gm * (xt - x), axis=0)
+        ft = eval(inst, xt, grad=False, nthreads=nthreads)["obj"]
+        m = f0 + c * dot - ft
+        take = ~decided & (m >= 0.0)
+        eta[take] = e
+        decided |= take
+        etas.append(e)
+        margins.append(m)
+        e *= beta
+    x_new = np.where(held, x, np.clip(x - eta[None, :] * g, -1.0, 1.0))
+    if done is not None:
+        x_new[:, np.asarray(done).reshape(B) != 0] = x[:, np.asarray(done).reshape(B) != 0]
+    return {"x": x_new, "eta": eta, "f0": f0, "g": g, "eta_trials": np.array(etas),
+            "margin": np.array(margins)}
+
+
+def pgd_search(inst, x0, search, steps, fixed=None, delta=0.0, nthreads=None):
+    """Algorithm 1 with the backtracking lineSearch, FP64: at most ``steps``
+    iterations; a restart stops when its point verifies (unsat_count = 0) or,
+    with ``delta`` > 0, when its step length falls below delta."""
+    x = np.array(x0, dtype=np.float64, copy=True)
+    B = x.shape[1]
+    unsat = unsat_count(inst, x)
+    done = (unsat == 0).astype(np.uint8)
+    first = np.where(unsat == 0, 0, -1).astype(np.int32)
+    for t in range(1, steps + 1):
+        if done.all():
+            break
+        r = line_search_step(inst, x, search, fixed=fixed, done=done, nthreads=nthreads)
+        x = r["x"]
+        unsat = unsat_count(inst, x)
+        newly = (done == 0) & (unsat == 0)
+        first[newly] = t
+        done[newly] = 1
+        if delta > 0:
+            done[(done == 0) & (r["eta"] < delta)] = 2
+    return {"x": x, "unsat": unsat, "done": done, "first_sat": first}

@@ -7,7 +7,7 @@ not built this module raises on import instead of falling back to anything.
 """
 import ctypes
 import os
-from dataclasses import dataclass
+from dataclasses import dataclass, field
 from typing import Optional
 
 import numpy as np
@@ -51,9 +51,17 @@ class _Options(ctypes.Structure):
                 ("shape_seg", _i32p), ("tile_short", ctypes.c_int32), ("tile_long", ctypes.c_int32)]
 
 
+class _LineSearch(ctypes.Structure):
+    _fields_ = [("max_step", ctypes.c_float), ("shrink", ctypes.c_float), ("armijo", ctypes.c_float),
+                ("trials", ctypes.c_int32)]
+
+
 class _PgdParams(ctypes.Structure):
     _fields_ = [("lr", ctypes.c_float), ("max_iters", ctypes.c_int32), ("poll", ctypes.c_int32),
-                ("stop_on_sat", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("fixed", ctypes.c_void_p)]
+                ("stop_on_sat", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("fixed", ctypes.c_void_p),
+                ("n_partial", ctypes.c_int32), ("delta", ctypes.c_float),
+                ("search", ctypes.POINTER(_LineSearch)), ("search_ws", ctypes.c_void_p),
+                ("search_ws_bytes", ctypes.c_size_t)]
 
 
 class _PgdState(ctypes.Structure):
@@ -88,12 +96,12 @@ SIGNATURES = [
     ("afs_scatter", ctypes.c_int, [_vp, _i32, _vp, ctypes.c_size_t, _vp, _vp, _vp]),
     ("afs_eval_fwd", ctypes.c_int, [_vp, _i32, _vp, _vp, ctypes.c_size_t, _vp, _vp, _vp]),
     ("afs_eval_adjoint", ctypes.c_int, [_vp, _i32, _vp, _vp, _vp, ctypes.c_size_t, _vp, _vp]),
-    ("afs_step", ctypes.c_int, [_vp, _i32, _vp, _vp, ctypes.c_float, _vp, _vp, _vp]),
+    ("afs_step", ctypes.c_int, [_vp, _i32, _vp, _vp, ctypes.c_float, _vp, _i32, _vp, _vp]),
     ("afs_round_verify", ctypes.c_int, [_vp, _i32, _vp, _vp, _vp, ctypes.c_size_t, _vp, _vp, _vp]),
     ("afs_pgd_init", ctypes.c_int, [_vp, _i32, _vp, _vp, ctypes.c_size_t, ctypes.POINTER(_PgdState), _vp]),
-    ("afs_pgd_step", ctypes.c_int, [_vp, _i32, _vp, ctypes.c_float, _vp, _vp, ctypes.c_size_t,
+    ("afs_pgd_step", ctypes.c_int, [_vp, _i32, _vp, ctypes.c_float, _vp, _i32, _vp, ctypes.c_size_t,
                                     ctypes.POINTER(_PgdState), _vp]),
-    ("afs_pgd_update", ctypes.c_int, [_vp, _i32, _vp, ctypes.c_float, _vp, _vp, ctypes.c_size_t,
+    ("afs_pgd_update", ctypes.c_int, [_vp, _i32, _vp, ctypes.c_float, _vp, _i32, _vp, ctypes.c_size_t,
                                       ctypes.POINTER(_PgdState), _vp]),
     ("afs_pgd", ctypes.c_int, [_vp, _i32, _vp, ctypes.POINTER(_PgdParams), _vp, ctypes.c_size_t,
                                ctypes.POINTER(_PgdState), _vp, ctypes.POINTER(_i32), _vp]),
@@ -105,6 +113,12 @@ SIGNATURES = [
     ("afs_parsed_get_info", ctypes.c_int, [_vp, ctypes.POINTER(_ParsedInfo)]),
     ("afs_parsed_arrays", ctypes.c_int, [_vp, _i64p, _i32p, _i32p, _i32p, ctypes.POINTER(ctypes.c_int8)]),
     ("afs_parsed_destroy", None, [_vp]),
+    ("afs_parsed_fold_units", ctypes.c_int, [_vp, _i32, ctypes.POINTER(ctypes.c_int8)]),
+    ("afs_search_workspace_bytes", ctypes.c_int, [_vp, _i32, ctypes.POINTER(ctypes.c_size_t)]),
+    ("afs_pgd_search_step", ctypes.c_int, [_vp, _i32, _vp, ctypes.POINTER(_LineSearch), _vp, _i32, ctypes.c_float,
+                                           _vp, ctypes.c_size_t, _vp, ctypes.c_size_t, ctypes.POINTER(_PgdState),
+                                           _vp, _vp]),
+    ("afs_init_points", ctypes.c_int, [_vp, _i32, ctypes.c_uint64, _vp, _i32, _vp, _vp]),
 ]
 
 _lib = None
@@ -279,6 +293,16 @@ class Instance:
             self._ws = {B: ws}          # keep one workspace at a time
         return ws
 
+    def search_workspace(self, B):
+        """Second workspace of the line search (one kept at a time)."""
+        sws = getattr(self, "_sws", {}).get(B)
+        if sws is None:
+            nb = ctypes.c_size_t()
+            _check(lib().afs_search_workspace_bytes(self._h, int(B), ctypes.byref(nb)))
+            sws = torch.empty(max(nb.value, 256), dtype=torch.uint8, device=self._dev())
+            self._sws = {B: sws}
+        return sws
+
     def _dev(self):
         if self.device < 0:
             raise AfsError(AFS_ESTATE, "host-only instance")
@@ -348,12 +372,33 @@ class Instance:
         return grad
 
     # -- Algorithm 1 -------------------------------------------------------------------
+    def _fixed(self, fixed):
+        """(pointer, rows) of a fixed mask shaped (n,) or (n_partial, n), u8 or i8."""
+        if fixed is None:
+            return None, 0
+        if fixed.dtype not in (torch.uint8, torch.int8) or fixed.shape[-1] != self.n or fixed.dim() > 2:
+            raise ValueError("fixed must be u8/i8 shaped (n,) or (n_partial, n)")
+        if not fixed.is_contiguous() or fixed.device != self._dev():
+            raise ValueError("fixed must be contiguous on the instance's device")
+        return _ptr(fixed), (fixed.shape[0] if fixed.dim() == 2 else 1)
+
     def step(self, x, grad, lr, fixed=None, done=None):
         """x <- clip(x - lr*grad, -1, 1) in place, except fixed variables / done restarts."""
         B = self._check_x(x)
         self._check_x(grad, "grad")
-        _check(lib().afs_step(self._h, B, _ptr(x), _ptr(grad), float(lr), _ptr(fixed), _ptr(done),
+        fp, rows = self._fixed(fixed)
+        _check(lib().afs_step(self._h, B, _ptr(x), _ptr(grad), float(lr), fp, rows, _ptr(done),
                               _stream(self._dev())))
+        return x
+
+    def init_points(self, B, seed, values=None):
+        """Starting points (n, B): the rows ``values`` (i8 (n,) or (n_partial, n):
+        +1 True, -1 False, 0 random) fixed, the rest uniform on [-1, 1) from the
+        library's counter-based generator."""
+        x = torch.empty((self.n, B), dtype=torch.float32, device=self._dev())
+        vp, rows = self._fixed(values)
+        _check(lib().afs_init_points(self._h, int(B), int(seed) & (2 ** 64 - 1), vp, rows, _ptr(x),
+                                     _stream(self._dev())))
         return x
 
     def round_verify(self, x, want_bits=False, done=None):
@@ -376,7 +421,7 @@ class Instance:
         return {"unsat": torch.zeros(shp, dtype=torch.int32, device=dev),
                 "done": torch.zeros(shp, dtype=torch.uint8, device=dev),
                 "first_sat": torch.full(shp, -1, dtype=torch.int32, device=dev),
-                "counter": torch.zeros(2, dtype=torch.int32, device=dev)}
+                "counter": torch.zeros(4, dtype=torch.int32, device=dev)}
 
     @staticmethod
     def _state_struct(st):
@@ -394,31 +439,63 @@ class Instance:
         B = self._check_x(x)
         ws = self.workspace(B) if ws is None else ws
         s = self._state_struct(st)
-        _check(lib().afs_pgd_step(self._h, B, _ptr(x), float(lr), _ptr(fixed), _ptr(ws), ws.numel(),
+        fp, rows = self._fixed(fixed)
+        _check(lib().afs_pgd_step(self._h, B, _ptr(x), float(lr), fp, rows, _ptr(ws), ws.numel(),
                                   ctypes.byref(s), _stream(self._dev())))
 
     def pgd_update(self, x, st, lr, fixed=None, ws=None):
         B = self._check_x(x)
         ws = self.workspace(B) if ws is None else ws
         s = self._state_struct(st)
-        _check(lib().afs_pgd_update(self._h, B, _ptr(x), float(lr), _ptr(fixed), _ptr(ws), ws.numel(),
+        fp, rows = self._fixed(fixed)
+        _check(lib().afs_pgd_update(self._h, B, _ptr(x), float(lr), fp, rows, _ptr(ws), ws.numel(),
                                     ctypes.byref(s), _stream(self._dev())))
 
-    def pgd(self, x, lr, steps, fixed=None, poll=10, stop_on_sat=True, graph=True, obj=False):
-        """Algorithm 1 with constant step length on the columns of x (updated in
-        place), run by the library's driver (afs_pgd).
+    @staticmethod
+    def _search(search):
+        if isinstance(search, LineSearch):
+            search = (search.max_step, search.shrink, search.armijo, search.trials)
+        return _LineSearch(float(search[0]), float(search[1]), float(search[2]), int(search[3]))
+
+    def search_step(self, x, st, search, fixed=None, delta=0.0, eta=None, ws=None):
+        """One iteration of Algorithm 1 with the backtracking line search
+        (``search``: a ``LineSearch`` or (max_step, shrink, armijo, trials)).
+        ``eta`` (f32 (B,), optional) receives the chosen step lengths."""
+        B = self._check_x(x)
+        ws = self.workspace(B) if ws is None else ws
+        sws = self.search_workspace(B)
+        ls = self._search(search)
+        s = self._state_struct(st)
+        fp, rows = self._fixed(fixed)
+        _check(lib().afs_pgd_search_step(self._h, B, _ptr(x), ctypes.byref(ls), fp, rows, float(delta), _ptr(ws),
+                                         ws.numel(), _ptr(sws), sws.numel(), ctypes.byref(s), _ptr(eta),
+                                         _stream(self._dev())))
+
+    def pgd(self, x, lr, steps, fixed=None, poll=10, stop_on_sat=True, graph=True, obj=False, search=None,
+            delta=0.0):
+        """Algorithm 1 on the columns of x (updated in place), run by the
+        library's driver (afs_pgd): constant step ``lr``, or with ``search`` (a
+        ``LineSearch`` or (max_step, shrink, armijo, trials)) the backtracking
+        line search.  ``fixed``: u8/i8 (n,) or (n_partial, n) mask of held
+        variables, the restarts divided evenly among its rows; ``delta`` > 0
+        stops restarts whose step length falls below it.
 
         Stops after ``steps`` iterations, or (``stop_on_sat``) once any restart
-        verifies; the driver reads the done counter every ``poll`` iterations.
-        With ``graph`` the driver captures ``poll`` iterations once in a HIP graph
-        and replays it.  Returns the state (unsat, done, first_sat, counter), x,
-        the number of iterations and, with ``obj``, the objective at the final
-        point."""
+        verifies, or once every restart has verified or converged; the driver
+        reads the counter every ``poll`` iterations.  With ``graph`` the driver
+        captures ``poll`` iterations once in a HIP graph and replays it.
+        Returns the state (unsat, done, first_sat, counter), x, the number of
+        iterations and, with ``obj``, the objective at the final point."""
         B = self._check_x(x)
         st = self.pgd_state(B)
         ws = self.workspace(B)
+        fp, rows = self._fixed(fixed)
+        ls = self._search(search) if search is not None else None
+        sws = self.search_workspace(B) if search is not None else None
         prm = _PgdParams(float(lr), int(steps), int(poll), int(bool(stop_on_sat)), int(bool(graph)),
-                         None if fixed is None else fixed.data_ptr())
+                         None if fp is None else fp.value, int(rows), float(delta),
+                         ctypes.pointer(ls) if ls is not None else None,
+                         None if sws is None else sws.data_ptr(), 0 if sws is None else sws.numel())
         s = self._state_struct(st)
         o = torch.empty(B, dtype=torch.float32, device=self._dev()) if obj else None
         iters = _i32(0)
@@ -429,6 +506,15 @@ class Instance:
         if obj:
             st["obj"] = o
         return st
+
+
+@dataclass
+class LineSearch:
+    """Backtracking line search of Algorithm 1 (see ``afs_line_search``)."""
+    max_step: float = 1.0
+    shrink: float = 0.5
+    armijo: float = 1e-4
+    trials: int = 8
 
 
 @dataclass
@@ -445,11 +531,31 @@ class Parsed:
     n_dropped: int
     declared_cons: int
     weights: Optional[np.ndarray] = None
+    _h: Optional[ctypes.c_void_p] = field(default=None, repr=False, compare=False)
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.afs_parsed_destroy(self._h)
+            self._h = None
 
     def fixed_mask(self, device=0):
         """u8 [n] device mask of the fixed variables (the ``fixed`` argument of
         ``step`` and ``pgd``)."""
         return torch.from_numpy((self.units != 0).astype(np.uint8)).to(device)
+
+    def fold_units(self, partials=None):
+        """Partial assignments with the units written in (Sec. 3.4): i8
+        (n_partial, n) from ``partials`` (array-like (n,) or (n_partial, n), +1
+        True, -1 False, 0 free), or the units alone as one row.  Raises
+        ``AfsError`` (AFS_EUNSAT) when a unit contradicts a row."""
+        if partials is None:
+            vals = np.zeros((1, self.n), dtype=np.int8)
+        else:
+            vals = np.array(partials, dtype=np.int8, ndmin=2, order="C", copy=True)
+            if vals.ndim != 2 or vals.shape[1] != self.n:
+                raise ValueError("partials must be shaped (n,) or (n_partial, n)")
+        _check(lib().afs_parsed_fold_units(self._h, vals.shape[0], _np_ptr(vals, ctypes.POINTER(ctypes.c_int8))))
+        return vals
 
     def apply_units(self, x):
         """Set the fixed variables' rows of x (n, B) to their values in place
@@ -462,6 +568,8 @@ class Parsed:
 
 
 def _take_parsed(h):
+    """Parsed from a reader handle; the handle stays with the result (unit folding
+    reads it) and is freed with it."""
     try:
         info = _ParsedInfo()
         _check(lib().afs_parsed_get_info(h, ctypes.byref(info)))
@@ -472,10 +580,11 @@ def _take_parsed(h):
         units = np.zeros(info.n_vars, dtype=np.int8)
         _check(lib().afs_parsed_arrays(h, _np_ptr(con_off, _i64p), _np_ptr(lits, _i32p), _np_ptr(types, _i32p),
                                        _np_ptr(params, _i32p), _np_ptr(units, ctypes.POINTER(ctypes.c_int8))))
-        return Parsed(int(info.n_vars), con_off, lits, types, params, units, int(info.n_dropped),
-                      int(info.declared_cons))
-    finally:
+    except BaseException:
         lib().afs_parsed_destroy(h)
+        raise
+    return Parsed(int(info.n_vars), con_off, lits, types, params, units, int(info.n_dropped),
+                  int(info.declared_cons), None, h)
 
 
 def parse_text(text):

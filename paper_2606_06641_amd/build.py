@@ -41,6 +41,7 @@ SOURCES = [
     ("parse.cpp", HOST_HIP),
     ("fe_kernels.hip", [HIPCC] + COMMON + DEVICE),
     ("update_kernels.hip", [HIPCC] + COMMON + DEVICE),
+    ("search_kernels.hip", [HIPCC] + COMMON + DEVICE),
     ("gnn.hip", [HIPCC] + COMMON + DEVICE),
 ]
 

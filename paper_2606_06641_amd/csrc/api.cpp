@@ -4,6 +4,7 @@
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -73,6 +74,49 @@ WsLayout ws_layout(const afs::HostInstance &H, int B)
     l.total = off;
     return l;
 }
+
+// Line-search workspace: gradient and trial point [n][B], per-tile partial sums
+// of <g, xt - x> [vtiles][Bp] and their second-pass partials, per-restart f0,
+// F(xt), <g, xt - x>, step length and decision flags.
+struct SearchLayout {
+    int vtiles = 0;
+    size_t g = 0, xt = 0, dpart = 0, dpart2 = 0, f0 = 0, ft = 0, dot = 0, eta = 0, acc = 0, total = 0;
+};
+
+SearchLayout search_layout(const afs::HostInstance &H, int B)
+{
+    SearchLayout q;
+    const size_t Bp = (size_t)(B + 63) / 64 * 64;
+    q.vtiles = (H.n + afs::kTrialVars - 1) / afs::kTrialVars;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = align256(off + bytes);
+        return o;
+    };
+    q.g = take((size_t)H.n * B * sizeof(float));
+    q.xt = take((size_t)H.n * B * sizeof(float));
+    q.dpart = take((size_t)q.vtiles * Bp * sizeof(float));
+    q.dpart2 = take((size_t)((q.vtiles + 31) / 32) * Bp * sizeof(float));
+    q.f0 = take(Bp * sizeof(float));
+    q.ft = take(Bp * sizeof(float));
+    q.dot = take(Bp * sizeof(float));
+    q.eta = take(Bp * sizeof(float));
+    q.acc = take(Bp);
+    q.total = off;
+    return q;
+}
+
+// fixed / values hold n_partial rows (0 reads as 1), at most one per restart
+template <class T>
+afs_status check_partial(int32_t B, const T *fixed, int32_t n_partial)
+{
+    if (n_partial < 0) return fail(AFS_EINVAL, "n_partial must be >= 0");
+    if (fixed && B > 0 && n_partial > B) return fail(AFS_EINVAL, "more partial assignments than restarts");
+    return AFS_OK;
+}
+
+int partial_rows(int32_t n_partial) { return n_partial > 1 ? n_partial : 1; }
 
 template <class T>
 afs_status upload(afs_instance *I, const std::vector<T> &v, const T **out)
@@ -492,14 +536,15 @@ afs_status afs_eval_adjoint(afs_instance *I, int32_t B, const float *x, const fl
 }
 
 afs_status afs_step(afs_instance *I, int32_t B, float *x, const float *grad, float lr,
-                    const uint8_t *fixed, const uint8_t *done, void *stream)
+                    const uint8_t *fixed, int32_t n_partial, const uint8_t *done, void *stream)
 {
     afs_status st = check_call(I, B);
     if (st != AFS_OK) return st;
     if (B > 0 && (!x || !grad)) return fail(AFS_EINVAL, "x or grad is NULL");
+    if ((st = check_partial(B, fixed, n_partial)) != AFS_OK) return st;
     DeviceGuard g(I->device);
     if (g.error() != hipSuccess) return dev_fail(g.error(), "hipSetDevice");
-    hipError_t e = afs::launch_step(I->D, B, x, grad, lr, fixed, done, (hipStream_t)stream);
+    hipError_t e = afs::launch_step(I->D, B, x, grad, lr, fixed, partial_rows(n_partial), done, (hipStream_t)stream);
     return e == hipSuccess ? AFS_OK : dev_fail(e, "step launch");
 }
 
@@ -518,7 +563,8 @@ afs_status afs_round_verify(afs_instance *I, int32_t B, const float *x, uint32_t
     const int pairs = I->H.n_inst * B;
     hipError_t e = afs::launch_round(I->D, B, x, bits, unsat, s);
     if (e == hipSuccess) e = afs::launch_verify(I->D, B, bits, at<uint32_t>(ws, l.viol), unsat, s);
-    if (e == hipSuccess && done) e = afs::launch_finalize(pairs, unsat, done, nullptr, nullptr, afs::FIN_VERIFY, s);
+    if (e == hipSuccess && done)
+        e = afs::launch_finalize(pairs, B, unsat, done, nullptr, nullptr, afs::FIN_VERIFY, s);
     return e == hipSuccess ? AFS_OK : dev_fail(e, "round/verify launch");
 }
 
@@ -538,12 +584,12 @@ afs_status afs_pgd_init(afs_instance *I, int32_t B, const float *x, void *ws, si
     hipError_t e = afs::launch_round(I->D, B, x, bits, P->unsat, s);
     if (e == hipSuccess) e = afs::launch_verify(I->D, B, bits, at<uint32_t>(ws, l.viol), P->unsat, s);
     if (e == hipSuccess)
-        e = afs::launch_finalize(I->H.n_inst * B, P->unsat, P->done, P->first_sat, P->counter, afs::FIN_INIT, s);
+        e = afs::launch_finalize(I->H.n_inst * B, B, P->unsat, P->done, P->first_sat, P->counter, afs::FIN_INIT, s);
     return e == hipSuccess ? AFS_OK : dev_fail(e, "PGD init launch");
 }
 
-static afs_status pgd_call(afs_instance *I, int32_t B, float *x, float lr, const uint8_t *fixed, void *ws,
-                           size_t ws_bytes, const afs_pgd_state *P, void *stream, bool with_fe)
+static afs_status pgd_call(afs_instance *I, int32_t B, float *x, float lr, const uint8_t *fixed, int32_t n_partial,
+                           float delta, void *ws, size_t ws_bytes, const afs_pgd_state *P, void *stream, bool with_fe)
 {
     afs_status st = check_call(I, B);
     if (st != AFS_OK) return st;
@@ -551,6 +597,7 @@ static afs_status pgd_call(afs_instance *I, int32_t B, float *x, float lr, const
     if ((st = check_ws(I, B, ws, ws_bytes, l)) != AFS_OK) return st;
     if (!P || !P->unsat || !P->done || !P->first_sat || !P->counter) return fail(AFS_EINVAL, "incomplete PGD state");
     if (B > 0 && !x) return fail(AFS_EINVAL, "x is NULL");
+    if ((st = check_partial(B, fixed, n_partial)) != AFS_OK) return st;
     DeviceGuard g(I->device);
     if (g.error() != hipSuccess) return dev_fail(g.error(), "hipSetDevice");
     hipStream_t s = (hipStream_t)stream;
@@ -559,24 +606,119 @@ static afs_status pgd_call(afs_instance *I, int32_t B, float *x, float lr, const
         if (st != AFS_OK) return st;
     }
     uint32_t *bits = at<uint32_t>(ws, l.bits);
-    hipError_t e = afs::launch_scatter_step(I->D, B, l.Bp, at<float>(ws, l.adj), x, lr, fixed, P->done,
-                                            bits, P->unsat, s);
+    hipError_t e = afs::launch_scatter_step(I->D, B, l.Bp, at<float>(ws, l.adj), x, lr, fixed,
+                                            partial_rows(n_partial), P->done, bits, P->unsat, s);
     if (e == hipSuccess) e = afs::launch_verify(I->D, B, bits, at<uint32_t>(ws, l.viol), P->unsat, s);
     if (e == hipSuccess)
-        e = afs::launch_finalize(I->H.n_inst * B, P->unsat, P->done, P->first_sat, P->counter, afs::FIN_STEP, s);
+        e = afs::launch_finalize(I->H.n_inst * B, B, P->unsat, P->done, P->first_sat, P->counter, afs::FIN_STEP, s,
+                                 nullptr, lr, delta);
     return e == hipSuccess ? AFS_OK : dev_fail(e, "PGD step launch");
 }
 
-afs_status afs_pgd_step(afs_instance *I, int32_t B, float *x, float lr, const uint8_t *fixed, void *ws,
-                        size_t ws_bytes, const afs_pgd_state *P, void *stream)
+afs_status afs_pgd_step(afs_instance *I, int32_t B, float *x, float lr, const uint8_t *fixed, int32_t n_partial,
+                        void *ws, size_t ws_bytes, const afs_pgd_state *P, void *stream)
 {
-    return pgd_call(I, B, x, lr, fixed, ws, ws_bytes, P, stream, true);
+    return pgd_call(I, B, x, lr, fixed, n_partial, 0.0f, ws, ws_bytes, P, stream, true);
 }
 
-afs_status afs_pgd_update(afs_instance *I, int32_t B, float *x, float lr, const uint8_t *fixed, void *ws,
-                          size_t ws_bytes, const afs_pgd_state *P, void *stream)
+afs_status afs_pgd_update(afs_instance *I, int32_t B, float *x, float lr, const uint8_t *fixed, int32_t n_partial,
+                          void *ws, size_t ws_bytes, const afs_pgd_state *P, void *stream)
 {
-    return pgd_call(I, B, x, lr, fixed, ws, ws_bytes, P, stream, false);
+    return pgd_call(I, B, x, lr, fixed, n_partial, 0.0f, ws, ws_bytes, P, stream, false);
+}
+
+static afs_status check_search(const afs_line_search *ls)
+{
+    if (!ls) return fail(AFS_EINVAL, "line search parameters are NULL");
+    if (!(ls->max_step > 0.0f) || !std::isfinite(ls->max_step)) return fail(AFS_EINVAL, "max_step must be > 0 and finite");
+    if (!(ls->shrink > 0.0f && ls->shrink < 1.0f)) return fail(AFS_EINVAL, "shrink must lie in (0, 1)");
+    if (!(ls->armijo >= 0.0f && ls->armijo < 1.0f)) return fail(AFS_EINVAL, "armijo must lie in [0, 1)");
+    if (ls->trials < 1 || ls->trials > 64) return fail(AFS_EINVAL, "trials must lie in 1..64");
+    return AFS_OK;
+}
+
+afs_status afs_search_workspace_bytes(const afs_instance *I, int32_t B, size_t *bytes)
+{
+    if (!I || !bytes) return fail(AFS_EINVAL, "NULL argument");
+    if (B < 0) return fail(AFS_EINVAL, "B must be >= 0");
+    *bytes = search_layout(I->H, B).total;
+    return AFS_OK;
+}
+
+static afs_status search_call(afs_instance *I, int32_t B, float *x, const afs_line_search *ls, const uint8_t *fixed,
+                              int32_t n_partial, float delta, void *ws, size_t ws_bytes, void *sws,
+                              size_t sws_bytes, const afs_pgd_state *P, float *eta_out, hipStream_t s)
+{
+    afs_status st = check_call(I, B);
+    if (st != AFS_OK) return st;
+    if (I->H.n_inst != 1) return fail(AFS_EINVAL, "the line search takes a plain instance, not a batch");
+    if ((st = check_search(ls)) != AFS_OK) return st;
+    WsLayout l;
+    if ((st = check_ws(I, B, ws, ws_bytes, l)) != AFS_OK) return st;
+    const SearchLayout q = search_layout(I->H, B);
+    if (!sws) return fail(AFS_EINVAL, "search workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(sws) % 256) return fail(AFS_EINVAL, "search workspace is not 256-byte aligned");
+    if (sws_bytes < q.total)
+        return fail(AFS_EINVAL, "search workspace too small: need " + std::to_string(q.total) + " bytes");
+    if (!P || !P->unsat || !P->done || !P->first_sat || !P->counter) return fail(AFS_EINVAL, "incomplete PGD state");
+    if (B > 0 && !x) return fail(AFS_EINVAL, "x is NULL");
+    if ((st = check_partial(B, fixed, n_partial)) != AFS_OK) return st;
+    const int rows = partial_rows(n_partial);
+    const int nb = (int)I->H.buckets.size(), tiles = I->H.total_tiles;
+    float *g = at<float>(sws, q.g), *xt = at<float>(sws, q.xt);
+    float *f0 = at<float>(sws, q.f0), *ft = at<float>(sws, q.ft), *dot = at<float>(sws, q.dot);
+    float *eta = eta_out ? eta_out : at<float>(sws, q.eta);
+    uint8_t *acc = at<uint8_t>(sws, q.acc);
+    float *part = at<float>(ws, l.part), *part2 = at<float>(ws, l.part2);
+    // objective and gradient at x
+    if ((st = fe_grad_range(I, B, x, ws, l, 0, nb, true, nullptr, s)) != AFS_OK) return st;
+    hipError_t e = afs::launch_obj_reduce(tiles, B, l.Bp, part, part2, f0, s);
+    if (e == hipSuccess) e = afs::launch_scatter(I->D, B, l.Bp, at<float>(ws, l.adj), g, s);
+    if (e == hipSuccess) e = afs::launch_search_init(B, ls->max_step, P->done, eta, acc, s);
+    if (e != hipSuccess) return dev_fail(e, "line search launch");
+    for (int j = 0; j < ls->trials; ++j) {
+        e = afs::launch_trial(I->D, B, l.Bp, x, g, eta, acc, fixed, rows, xt, at<float>(sws, q.dpart), s);
+        if (e == hipSuccess)
+            e = afs::launch_obj_reduce(q.vtiles, B, l.Bp, at<float>(sws, q.dpart), at<float>(sws, q.dpart2), dot, s);
+        if (e != hipSuccess) return dev_fail(e, "line search trial launch");
+        if ((st = fe_grad_range(I, B, xt, ws, l, 0, nb, true, nullptr, s, nullptr, false)) != AFS_OK) return st;
+        e = afs::launch_obj_reduce(tiles, B, l.Bp, part, part2, ft, s);
+        if (e == hipSuccess)
+            e = afs::launch_accept(B, f0, ft, dot, ls->armijo, ls->shrink, j == ls->trials - 1, eta, acc, s);
+        if (e != hipSuccess) return dev_fail(e, "line search test launch");
+    }
+    uint32_t *bits = at<uint32_t>(ws, l.bits);
+    e = afs::launch_search_step(I->D, B, x, g, eta, fixed, rows, P->done, bits, P->unsat, s);
+    if (e == hipSuccess) e = afs::launch_verify(I->D, B, bits, at<uint32_t>(ws, l.viol), P->unsat, s);
+    if (e == hipSuccess)
+        e = afs::launch_finalize(B, B, P->unsat, P->done, P->first_sat, P->counter, afs::FIN_STEP, s, eta, 0.0f,
+                                 delta);
+    return e == hipSuccess ? AFS_OK : dev_fail(e, "line search step launch");
+}
+
+afs_status afs_pgd_search_step(afs_instance *I, int32_t B, float *x, const afs_line_search *ls,
+                               const uint8_t *fixed, int32_t n_partial, float delta, void *ws, size_t ws_bytes,
+                               void *sws, size_t sws_bytes, const afs_pgd_state *P, float *eta, void *stream)
+{
+    afs_status st = check_call(I, B);
+    if (st != AFS_OK) return st;
+    DeviceGuard g(I->device);
+    if (g.error() != hipSuccess) return dev_fail(g.error(), "hipSetDevice");
+    return search_call(I, B, x, ls, fixed, n_partial, delta, ws, ws_bytes, sws, sws_bytes, P, eta,
+                       (hipStream_t)stream);
+}
+
+afs_status afs_init_points(afs_instance *I, int32_t B, uint64_t seed, const int8_t *values, int32_t n_partial,
+                           float *x, void *stream)
+{
+    afs_status st = check_call(I, B);
+    if (st != AFS_OK) return st;
+    if (B > 0 && !x) return fail(AFS_EINVAL, "x is NULL");
+    if ((st = check_partial(B, values, n_partial)) != AFS_OK) return st;
+    DeviceGuard g(I->device);
+    if (g.error() != hipSuccess) return dev_fail(g.error(), "hipSetDevice");
+    hipError_t e = afs::launch_init_points(I->H.n, B, seed, values, partial_rows(n_partial), x, (hipStream_t)stream);
+    return e == hipSuccess ? AFS_OK : dev_fail(e, "start point launch");
 }
 
 afs_status afs_pgd(afs_instance *I, int32_t B, float *x, const afs_pgd_params *prm, void *ws, size_t ws_bytes,
@@ -586,6 +728,9 @@ afs_status afs_pgd(afs_instance *I, int32_t B, float *x, const afs_pgd_params *p
     if (st != AFS_OK) return st;
     if (!prm) return fail(AFS_EINVAL, "params is NULL");
     if (prm->max_iters < 0 || prm->poll < 1) return fail(AFS_EINVAL, "max_iters must be >= 0 and poll >= 1");
+    if (prm->search && (st = check_search(prm->search)) != AFS_OK) return st;
+    if (prm->search && I->H.n_inst != 1) return fail(AFS_EINVAL, "the line search takes a plain instance, not a batch");
+    if ((st = check_partial(B, prm->fixed, prm->n_partial)) != AFS_OK) return st;
     WsLayout l;
     if ((st = check_ws(I, B, ws, ws_bytes, l)) != AFS_OK) return st;
     if (!P || !P->unsat || !P->done || !P->first_sat || !P->counter) return fail(AFS_EINVAL, "incomplete PGD state");
@@ -610,17 +755,26 @@ afs_status afs_pgd(afs_instance *I, int32_t B, float *x, const afs_pgd_params *p
         return result;
     };
     auto read_counter = [&](int32_t *host) {
-        hipError_t e2 = hipMemcpyAsync(host, P->counter, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s);
+        hipError_t e2 = hipMemcpyAsync(host, P->counter, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, s);
         if (e2 == hipSuccess) e2 = hipStreamSynchronize(s);
         return e2;
     };
+    // one iteration: constant step, or the backtracking line search
+    auto iterate = [&]() {
+        if (prm->search)
+            return search_call(I, B, x, prm->search, prm->fixed, prm->n_partial, prm->delta, ws, ws_bytes,
+                               prm->search_ws, prm->search_ws_bytes, P, nullptr, s);
+        return pgd_call(I, B, x, prm->lr, prm->fixed, prm->n_partial, prm->delta, ws, ws_bytes, P, s, true);
+    };
 
     if ((st = afs_pgd_init(I, B, x, ws, ws_bytes, P, s)) != AFS_OK) return finish(st);
-    int32_t counter[2] = {0, 0};
+    int32_t counter[4] = {0, 0, 0, 0};
+    const int32_t pairs = I->H.n_inst * B;
     for (int32_t t = 0; t < prm->max_iters;) {
-        if (prm->stop_on_sat) {
+        if (prm->stop_on_sat || prm->delta > 0.0f) {
             if ((e = read_counter(counter)) != hipSuccess) return finish(dev_fail(e, "reading the counter"));
-            if (counter[1] > 0) break;
+            if (prm->stop_on_sat && counter[1] > 0) break;
+            if (counter[2] >= pairs) break;   // every restart verified or converged
         }
         const int32_t n = std::min(prm->poll, prm->max_iters - t);
         if (prm->use_graph && n == prm->poll) {
@@ -629,8 +783,7 @@ afs_status afs_pgd(afs_instance *I, int32_t B, float *x, const afs_pgd_params *p
                 if ((e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal)) != hipSuccess)
                     return finish(dev_fail(e, "hipStreamBeginCapture"));
                 afs_status cs = AFS_OK;
-                for (int32_t i = 0; i < n && cs == AFS_OK; ++i)
-                    cs = pgd_call(I, B, x, prm->lr, prm->fixed, ws, ws_bytes, P, s, true);
+                for (int32_t i = 0; i < n && cs == AFS_OK; ++i) cs = iterate();
                 const hipError_t ec = hipStreamEndCapture(s, &graph);
                 if (cs != AFS_OK) return finish(cs);
                 if (ec != hipSuccess) return finish(dev_fail(ec, "hipStreamEndCapture"));
@@ -640,8 +793,7 @@ afs_status afs_pgd(afs_instance *I, int32_t B, float *x, const afs_pgd_params *p
             if ((e = hipGraphLaunch(exec, s)) != hipSuccess) return finish(dev_fail(e, "hipGraphLaunch"));
         } else {
             for (int32_t i = 0; i < n; ++i)
-                if ((st = pgd_call(I, B, x, prm->lr, prm->fixed, ws, ws_bytes, P, s, true)) != AFS_OK)
-                    return finish(st);
+                if ((st = iterate()) != AFS_OK) return finish(st);
         }
         t += n;
     }

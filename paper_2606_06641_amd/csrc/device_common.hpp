@@ -60,5 +60,15 @@ __device__ __forceinline__ float dpp_mov(float v)
     return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), CTRL, 0xF, 0xF, false));
 }
 
+// Partial assignments (one row of fixed [n_partial][n] per slice of the restart
+// columns): restart b of B belongs to slice b * n_partial / B, so the slices are
+// as even as B allows.  fixed == nullptr fixes nothing.
+__device__ __forceinline__ bool is_fixed(const uint8_t *fixed, int n_partial, int n, int B, int v, int b)
+{
+    if (!fixed) return false;
+    const int p = n_partial > 1 ? (int)(((int64_t)b * n_partial) / B) : 0;
+    return fixed[(int64_t)p * n + v] != 0;
+}
+
 }  // namespace dev
 }  // namespace afs

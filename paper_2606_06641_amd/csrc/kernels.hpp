@@ -52,8 +52,9 @@ hipError_t launch_scatter(const DevInstance &I, int B, int Bp, const float *adj,
 
 // Per-(sub-instance, restart) arrays (unsat, done, first_sat) are [n_inst][B].
 // Fused: gradient sum, projected step, rounding into bits [n][W] and unsat = 0.
+// fixed [n_partial][n]: restart b uses row b * n_partial / B (nullptr: none fixed).
 hipError_t launch_scatter_step(const DevInstance &I, int B, int Bp, const float *adj, float *x,
-                               float lr, const uint8_t *fixed, const uint8_t *done,
+                               float lr, const uint8_t *fixed, int n_partial, const uint8_t *done,
                                uint32_t *bits, int32_t *unsat, hipStream_t s);
 
 // obj[b] = sum over tiles of part[t][b] (two fixed-order passes through part2).
@@ -61,7 +62,7 @@ hipError_t launch_obj_reduce(int tiles, int B, int Bp, const float *part, float 
                              float *obj, hipStream_t s);
 
 hipError_t launch_step(const DevInstance &I, int B, float *x, const float *grad, float lr,
-                       const uint8_t *fixed, const uint8_t *done, hipStream_t s);
+                       const uint8_t *fixed, int n_partial, const uint8_t *done, hipStream_t s);
 
 // bits from x and unsat = 0.
 hipError_t launch_round(const DevInstance &I, int B, const float *x, uint32_t *bits, int32_t *unsat,
@@ -73,9 +74,38 @@ hipError_t launch_verify(const DevInstance &I, int B, const uint32_t *bits, uint
                          int32_t *unsat, hipStream_t s);
 
 enum FinalizeMode { FIN_INIT = 0, FIN_STEP = 1, FIN_VERIFY = 2 };
-// over all n_inst * B (sub-instance, restart) pairs
-hipError_t launch_finalize(int count, const int32_t *unsat, uint8_t *done, int32_t *first_sat,
-                           int32_t *counter, int mode, hipStream_t s);
+// over all count = n_inst * B (sub-instance, restart) pairs.  done: 1 verified,
+// 2 converged (FIN_STEP: step length eta[b] (or eta_const when eta is null) below
+// delta > 0); counter = {t, verified pairs, frozen pairs, 0}.
+hipError_t launch_finalize(int count, int B, const int32_t *unsat, uint8_t *done, int32_t *first_sat,
+                           int32_t *counter, int mode, hipStream_t s, const float *eta = nullptr,
+                           float eta_const = 0.0f, float delta = 0.0f);
+
+// ---- line search (search_kernels.hip) ----
+// Trial point of the backtracking search for the restarts still searching
+// (acc[b] == 0): xt = x for fixed variables, else clip(x - eta[b] * g); other
+// restarts copy x.  dot_part [ceil(n / kTrialVars)][Bp] receives the per-tile
+// partial sums of g * (xt - x) (zero for b >= B).  g, x, xt: [n][B].
+constexpr int kTrialVars = 32;
+hipError_t launch_trial(const DevInstance &I, int B, int Bp, const float *x, const float *g, const float *eta,
+                        const uint8_t *acc, const uint8_t *fixed, int n_partial, float *xt, float *dot_part,
+                        hipStream_t s);
+// eta[b] = s, acc[b] = done[b] != 0 (done may be null)
+hipError_t launch_search_init(int B, float step, const uint8_t *done, float *eta, uint8_t *acc, hipStream_t s);
+// Armijo test of one trial for the restarts still searching: accept when
+// ft <= f0 + c * dot, else eta *= beta (after the last trial: eta = 0, no step).
+hipError_t launch_accept(int B, const float *f0, const float *ft, const float *dot, float c, float beta,
+                         bool last, float *eta, uint8_t *acc, hipStream_t s);
+// x <- clip(x - eta[b] * g) (not for fixed variables or done restarts), rounding
+// into bits and unsat = 0, as the fused step of the constant-step path.
+hipError_t launch_search_step(const DevInstance &I, int B, float *x, const float *g, const float *eta,
+                              const uint8_t *fixed, int n_partial, const uint8_t *done, uint32_t *bits,
+                              int32_t *unsat, hipStream_t s);
+// Starting points (Sec. 3.4): x[v][b] uniform in [-1, 1) from Philox4x32-10 keyed
+// by seed with counter (b, v, 0, 0), except where values[p][v] != 0 (row p =
+// b * n_partial / B): -1 for +1 (True), +1 for -1 (False).
+hipError_t launch_init_points(int n, int B, uint64_t seed, const int8_t *values, int n_partial, float *x,
+                              hipStream_t s);
 
 // adj_out[slot_to_lit[s]][b] = adj[s][b]
 hipError_t launch_permute_adj(const DevInstance &I, int B, int Bp, const float *adj,

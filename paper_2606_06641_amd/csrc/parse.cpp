@@ -333,4 +333,23 @@ void afs_parsed_destroy(afs_parsed *p)
     delete p;
 }
 
+afs_status afs_parsed_fold_units(const afs_parsed *p, int32_t n_partial, int8_t *values)
+{
+    if (!p || (!values && n_partial > 0)) return set_last_error(AFS_EINVAL, "NULL argument");
+    if (n_partial < 0) return set_last_error(AFS_EINVAL, "n_partial must be >= 0");
+    const int64_t n = p->n;
+    for (int32_t r = 0; r < n_partial; ++r) {
+        int8_t *row = values + (int64_t)r * n;
+        for (int64_t v = 0; v < n; ++v) {
+            const int8_t u = p->unit[(size_t)v];
+            if (!u) continue;
+            if (row[v] && (row[v] > 0) != (u > 0))
+                return set_last_error(AFS_EUNSAT, "partial assignment " + std::to_string(r) +
+                                                      " contradicts the unit on variable " + std::to_string(v + 1));
+            row[v] = u;
+        }
+    }
+    return AFS_OK;
+}
+
 }  // extern "C"

@@ -32,7 +32,8 @@ struct ScatterArgs {
     float *grad, *x;
     const int32_t *voff, *vslot, *var_inst;
     int n_inst;
-    const uint8_t *fixed, *done;
+    const uint8_t *fixed, *done;  // fixed [n_partial][n]
+    int n, n_partial;
     uint32_t *bits;
     int32_t *unsat;
     float lr;
@@ -148,7 +149,6 @@ __global__ __launch_bounds__(kBlock) void scatter_step_kernel(ScatterArgs A)
     const int v = (int)(item / A.nchunks), chunk = (int)(item % A.nchunks);
     const int b0 = chunk * kScatterChunk + (threadIdx.x & 63) * kRestartsPerLane;
     const float4 g = gather_sum4(A, v, b0);
-    const bool fixed = A.fixed && A.fixed[v];
     const uint8_t *done = A.done ? A.done + (int64_t)A.var_inst[v] * A.B : nullptr;
     uint32_t nib = 0;
 #pragma unroll
@@ -157,7 +157,7 @@ __global__ __launch_bounds__(kBlock) void scatter_step_kernel(ScatterArgs A)
         if (b < A.B) {
             const int64_t at = (int64_t)v * A.B + b;
             float xv = A.x[at];
-            if (!fixed && !(done && done[b])) {
+            if (!is_fixed(A.fixed, A.n_partial, A.n, A.B, v, b) && !(done && done[b])) {
                 xv = project_step(xv, elem(g, e), A.lr);
                 A.x[at] = xv;
             }
@@ -176,7 +176,8 @@ struct EltArgs {
     const float *xin, *grad;
     const int32_t *var_inst;
     int n_inst;
-    const uint8_t *fixed, *done;
+    const uint8_t *fixed, *done;  // fixed [n_partial][n]
+    int n, n_partial;
     uint32_t *bits;
     int32_t *unsat;
     float lr;
@@ -191,7 +192,8 @@ __global__ __launch_bounds__(kBlock) void step_kernel(EltArgs A)
     const int v = (int)(item / A.nchunks), chunk = (int)(item % A.nchunks);
     const int b = chunk * kWave + (threadIdx.x & 63);
     if (b >= A.B) return;
-    if ((A.fixed && A.fixed[v]) || (A.done && A.done[(int64_t)A.var_inst[v] * A.B + b])) return;
+    if (is_fixed(A.fixed, A.n_partial, A.n, A.B, v, b) || (A.done && A.done[(int64_t)A.var_inst[v] * A.B + b]))
+        return;
     const int64_t at = (int64_t)v * A.B + b;
     A.x[at] = project_step(A.x[at], A.grad[at], A.lr);
 }
@@ -416,39 +418,58 @@ __global__ __launch_bounds__(kCountWaves * kWave) void count_kernel(CountArgs A)
 }
 
 // One block: done / first_sat bookkeeping and the {t, number done} counter.
-__global__ __launch_bounds__(1024) void finalize_kernel(int count, const int32_t *unsat, uint8_t *done,
-                                                        int32_t *first_sat, int32_t *counter, int mode)
+// done: 0 searching, 1 verified, 2 converged (the step length fell below delta,
+// Algorithm 1's eta < delta); both freeze the restart.  counter = {t, verified,
+// frozen, 0}.  The step length of pair i is eta[i % B] (a line search on a
+// plain instance) or eta_const (constant step); delta <= 0 turns the test off.
+__global__ __launch_bounds__(1024) void finalize_kernel(int count, int B, const int32_t *unsat, uint8_t *done,
+                                                        int32_t *first_sat, int32_t *counter, int mode,
+                                                        const float *eta, float eta_const, float delta)
 {
-    __shared__ int red[1024 / kWave];
+    __shared__ int red[2][1024 / kWave];
     const int t = (mode == FIN_STEP) ? counter[0] + 1 : 0;
     __syncthreads();
-    int cnt = 0;
+    int nsat = 0, nfrozen = 0;
     for (int b = threadIdx.x; b < count; b += blockDim.x) {
         const bool ok = unsat[b] == 0;
         if (mode == FIN_INIT) {
             done[b] = ok ? 1 : 0;
             first_sat[b] = ok ? 0 : -1;
-            cnt += ok;
+            nsat += ok;
+            nfrozen += ok;
         } else if (mode == FIN_STEP) {
             uint8_t d = done[b];
             if (!d && ok) {
                 done[b] = d = 1;
                 first_sat[b] = t;
             }
-            cnt += d;
+            if (!d && delta > 0.0f && (eta ? eta[b % B] : eta_const) < delta) done[b] = d = 2;
+            nsat += d == 1;
+            nfrozen += d != 0;
         } else {
             if (ok) done[b] = 1;
         }
     }
     if (mode == FIN_VERIFY) return;
-    for (int off = 32; off > 0; off >>= 1) cnt += __shfl_down(cnt, off);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = cnt;
+    for (int off = 32; off > 0; off >>= 1) {
+        nsat += __shfl_down(nsat, off);
+        nfrozen += __shfl_down(nfrozen, off);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        red[0][threadIdx.x >> 6] = nsat;
+        red[1][threadIdx.x >> 6] = nfrozen;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
-        int total = 0;
-        for (int i = 0; i < (int)(blockDim.x / kWave); ++i) total += red[i];
+        int s0 = 0, s1 = 0;
+        for (int i = 0; i < (int)(blockDim.x / kWave); ++i) {
+            s0 += red[0][i];
+            s1 += red[1][i];
+        }
         counter[0] = t;
-        counter[1] = total;
+        counter[1] = s0;
+        counter[2] = s1;
+        counter[3] = 0;
     }
 }
 
@@ -514,12 +535,13 @@ hipError_t launch_scatter(const DevInstance &I, int B, int Bp, const float *adj,
 }
 
 hipError_t launch_scatter_step(const DevInstance &I, int B, int Bp, const float *adj, float *x,
-                               float lr, const uint8_t *fixed, const uint8_t *done,
+                               float lr, const uint8_t *fixed, int n_partial, const uint8_t *done,
                                uint32_t *bits, int32_t *unsat, hipStream_t s)
 {
     if (B == 0) return hipSuccess;
     ScatterArgs a = scatter_args(I, B, Bp, adj);
     a.x = x; a.lr = lr; a.fixed = fixed; a.done = done; a.bits = bits; a.unsat = unsat;
+    a.n = I.n; a.n_partial = n_partial;
     return for_launch_chunks(a.items, [&](int64_t first, int64_t count) {
         a.item0 = first;
         hipLaunchKernelGGL(scatter_step_kernel, grid_for_waves(count), dim3(kBlock), 0, s, a);
@@ -549,11 +571,12 @@ static EltArgs elt_args(int n, int B)
 }
 
 hipError_t launch_step(const DevInstance &I, int B, float *x, const float *grad, float lr,
-                       const uint8_t *fixed, const uint8_t *done, hipStream_t s)
+                       const uint8_t *fixed, int n_partial, const uint8_t *done, hipStream_t s)
 {
     if (B == 0) return hipSuccess;
     EltArgs a = elt_args(I.n, B);
     a.x = x; a.grad = grad; a.lr = lr; a.fixed = fixed; a.done = done;
+    a.n = I.n; a.n_partial = n_partial;
     a.var_inst = I.var_inst; a.n_inst = I.n_inst;
     return for_launch_chunks(a.items, [&](int64_t first, int64_t count) {
         a.item0 = first;
@@ -613,11 +636,13 @@ hipError_t launch_verify(const DevInstance &I, int B, const uint32_t *bits, uint
     return hipGetLastError();
 }
 
-hipError_t launch_finalize(int count, const int32_t *unsat, uint8_t *done, int32_t *first_sat,
-                           int32_t *counter, int mode, hipStream_t s)
+hipError_t launch_finalize(int count, int B, const int32_t *unsat, uint8_t *done, int32_t *first_sat,
+                           int32_t *counter, int mode, hipStream_t s, const float *eta, float eta_const,
+                           float delta)
 {
     if (count == 0) return hipSuccess;
-    hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(1024), 0, s, count, unsat, done, first_sat, counter, mode);
+    hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(1024), 0, s, count, B, unsat, done, first_sat, counter, mode,
+                       eta, eta_const, delta);
     return hipGetLastError();
 }
 

@@ -1,0 +1,251 @@
+"""GPU: line search, partial-assignment slices, convergence and start points
+(Algorithm 1, Sec. 3.3, Sec. 3.4) through the C ABI against the FP64 oracle.
+
+The line search takes integer decisions (which trial passes the Armijo test)
+from floating-point sums.  The oracle decides in FP64 and the library in FP32,
+so a decision is compared only where the oracle's margin of every trial that
+matters is larger than the objective tolerance; elsewhere both answers are
+valid and only their validity is checked.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import parity
+from paper_2606_06641_amd import afsat
+from paper_2606_06641_amd import workloads as W
+from philox_ref import philox_first_words, uniform_pm1
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    afsat.lib()
+
+
+def log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def concat(parts, n):
+    """Constraints of several instances over the same n variables."""
+    con_off = [np.asarray(parts[0].con_off, np.int64)]
+    for p in parts[1:]:
+        con_off.append(np.asarray(p.con_off[1:], np.int64) + con_off[-1][-1])
+    return W.Instance(n=n, con_off=np.concatenate(con_off), lits=np.concatenate([p.lits for p in parts]),
+                      types=np.concatenate([p.types for p in parts]),
+                      params=np.concatenate([p.params for p in parts]))
+
+
+def mixed(seed, n=300, count=900):
+    rng = np.random.default_rng(seed)
+    return concat([W.random_instance(rng, n=n, count=count, k_lo=1, k_hi=12),
+                   W.random_instance(rng, n=n, count=12, k_lo=20, k_hi=90)], n=n), rng
+
+
+def test_init_points_match_philox_and_hold_values():
+    inst = W.planted_3sat(n=300, m=900, instance=2)
+    d = afsat.Instance.from_arrays(inst)
+    B = 300
+    seed = 0x123456789ABCDEF0
+    rng = np.random.default_rng(2)
+    vals = rng.choice(np.array([-1, 0, 0, 0, 1], dtype=np.int8), size=(3, inst.n))
+    log("case: init_points n=%d B=%d rows=3" % (inst.n, B))
+    x = d.init_points(B, seed, torch.from_numpy(vals).cuda()).cpu().numpy()
+    bb, vv = np.meshgrid(np.arange(B, dtype=np.uint64), np.arange(inst.n, dtype=np.uint64))
+    want = uniform_pm1(philox_first_words(bb.ravel(), vv.ravel(), (seed & 0xFFFFFFFF, seed >> 32)))
+    want = want.reshape(inst.n, B)
+    rows = (np.arange(B) * 3) // B
+    vcol = vals[rows].T                                  # (n, B)
+    want = np.where(vcol > 0, np.float32(-1), np.where(vcol < 0, np.float32(1), want))
+    np.testing.assert_array_equal(x, want)
+    free = x[vcol == 0]
+    assert free.min() >= -1 and free.max() < 1
+    assert abs(free.mean()) < 0.02 and abs(free.var() - 1 / 3) < 0.02
+    # no values: every entry random; a different seed gives different points
+    x2 = d.init_points(B, seed + 1).cpu().numpy()
+    assert (x2 >= -1).all() and (x2 < 1).all() and not np.array_equal(x2[vcol == 0], free)
+
+
+@pytest.mark.parametrize("rows", [1, 3])
+def test_step_with_partial_slices(rows):
+    inst, rng = mixed(20)
+    d = afsat.Instance.from_arrays(inst)
+    B = 130
+    log("case: step slices rows=%d" % rows)
+    x = rng.uniform(-1, 1, size=(inst.n, B)).astype(np.float32)
+    g = rng.normal(size=(inst.n, B)).astype(np.float32)
+    fixed = (rng.random((rows, inst.n)) < 0.2).astype(np.uint8)
+    xd = parity.to_dev(x)
+    d.step(xd, parity.to_dev(g), 0.25, fixed=torch.from_numpy(fixed if rows > 1 else fixed[0]).cuda())
+    got = xd.cpu().numpy()
+    held = oracle.fixed_columns(fixed, inst.n, B)
+    want = oracle.step(x, g, 0.25)
+    np.testing.assert_array_equal(got[held], x[held])
+    np.testing.assert_allclose(got[~held], want[~held], rtol=0, atol=1e-6)
+
+
+def test_pgd_step_with_slices_holds_rows_and_verifies():
+    inst, rng = mixed(21)
+    d = afsat.Instance.from_arrays(inst)
+    B = 97
+    x = rng.uniform(-1, 1, size=(inst.n, B)).astype(np.float32)
+    fixed = (rng.random((4, inst.n)) < 0.3).astype(np.uint8)
+    xd = parity.to_dev(x)
+    st = d.pgd_state(B)
+    d.pgd_init(xd, st)
+    fd = torch.from_numpy(fixed).cuda()
+    for _ in range(5):
+        d.pgd_step(xd, st, 0.1, fixed=fd)
+    got = xd.cpu().numpy()
+    held = oracle.fixed_columns(fixed, inst.n, B)
+    np.testing.assert_array_equal(got[held], x[held])
+    assert not np.array_equal(got[~held], x[~held])
+    np.testing.assert_array_equal(st["unsat"].cpu().numpy(), oracle.verify(inst, got))
+
+
+@pytest.mark.parametrize("B", [64, 200])
+def test_search_step_parity(B):
+    inst, rng = mixed(22)
+    d = afsat.Instance.from_arrays(inst)
+    search = (2.0, 0.5, 1e-3, 6)
+    x = rng.uniform(-1, 1, size=(inst.n, B)).astype(np.float32)
+    fixed = (rng.random((2, inst.n)) < 0.1).astype(np.uint8)
+    log("case: search step n=%d C=%d B=%d" % (inst.n, inst.n_cons, B))
+    xd = parity.to_dev(x)
+    st = d.pgd_state(B)
+    d.pgd_init(xd, st)
+    eta = torch.full((B,), -1.0, device="cuda")
+    d.search_step(xd, st, search, fixed=torch.from_numpy(fixed).cuda(), eta=eta)
+    got_x = xd.cpu().numpy().astype(np.float64)
+    got_eta = eta.cpu().numpy().astype(np.float64)
+    orc = oracle.line_search_step(inst, x, search, fixed=fixed)
+    trials = orc["eta_trials"]
+    assert np.isin(got_eta, np.append(trials, 0.0)).all()
+    tau = 2e-4 * inst.n_cons                              # two objective errors (1e-4 * sum|w| each)
+    jg = np.array([np.nonzero(trials == e)[0][0] if e > 0 else len(trials) for e in got_eta])
+    jo = np.array([np.nonzero(trials == e)[0][0] if e > 0 else len(trials) for e in orc["eta"]])
+    clear = np.array([(np.abs(orc["margin"][:min(max(jg[b], jo[b]) + 1, len(trials)), b]) > tau).all()
+                      for b in range(B)])
+    log("restarts with clear decisions: %d of %d; trials chosen %s" % (clear.sum(), B, np.bincount(jg)))
+    assert clear.sum() >= B // 2
+    np.testing.assert_array_equal(jg[clear], jo[clear])
+    # the step itself, with the library's own step length
+    held = oracle.fixed_columns(fixed, inst.n, B)
+    want = np.where(held, x, np.clip(x - got_eta[None, :] * orc["g"], -1, 1))
+    gtol = 1e-4 * np.max(np.bincount(np.abs(inst.lits) - 1, minlength=inst.n))
+    np.testing.assert_allclose(got_x, want, rtol=0, atol=float(got_eta.max()) * gtol + 1e-6)
+    np.testing.assert_array_equal(got_x[held], x[held])
+    # the state after the step is the exact verification of the new point
+    np.testing.assert_array_equal(st["unsat"].cpu().numpy(), oracle.verify(inst, got_x.astype(np.float32)))
+
+
+def test_search_iterations_never_raise_the_objective():
+    inst = W.planted_3sat(n=100, m=340, instance=4)
+    d = afsat.Instance.from_arrays(inst)
+    B = 64
+    xd = parity.to_dev(W.uniform_x0(inst.n, B, workload=1, instance=4))
+    st = d.pgd_state(B)
+    d.pgd_init(xd, st)
+    tol = 1e-4 * inst.n_cons
+    f = d.eval(xd, obj=True, grad=False)["obj"].cpu().numpy()
+    for t in range(15):
+        d.search_step(xd, st, afsat.LineSearch(2.0, 0.5, 1e-4, 8))
+        f1 = d.eval(xd, obj=True, grad=False)["obj"].cpu().numpy()
+        assert (f1 <= f + tol).all(), t
+        f = f1
+    assert int(st["counter"][0]) == 15
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_search_driver_solves_and_graph_matches_eager(graph):
+    inst = W.planted_3sat(n=100, m=340, instance=4)
+    d = afsat.Instance.from_arrays(inst)
+    B = 64
+    x0 = W.uniform_x0(inst.n, B, workload=1, instance=4)
+    xa = parity.to_dev(x0)
+    ls = afsat.LineSearch(2.0, 0.5, 1e-4, 8)
+    ra = d.pgd(xa, 0.0, 200, poll=5, stop_on_sat=True, graph=graph, search=ls)
+    xb = parity.to_dev(x0)
+    rb = d.pgd(xb, 0.0, ra["iters"], poll=5, stop_on_sat=False, graph=not graph, search=ls)
+    torch.cuda.synchronize()
+    log("line-search driver: %d iterations, %d restarts verified" % (ra["iters"], int(ra["counter"][1])))
+    assert int(ra["counter"][1]) > 0
+    assert torch.equal(xa, xb)
+    xs = xa.cpu().numpy()
+    done = ra["done"].cpu().numpy() == 1
+    assert (oracle.verify(inst, xs)[done] == 0).all()
+
+
+def test_constant_step_converges_below_delta():
+    """lr = 0.1 < delta = 0.2: after the first iteration every restart that did
+    not verify has converged (done = 2); the driver stops at the next counter
+    read, and the point is that of one iteration."""
+    inst = W.planted_3sat(n=100, m=426, instance=3)
+    d = afsat.Instance.from_arrays(inst)
+    B = 40
+    x0 = W.uniform_x0(inst.n, B, workload=1, instance=3)
+    xa = parity.to_dev(x0)
+    r = d.pgd(xa, 0.1, 100, poll=5, stop_on_sat=False, graph=False, delta=0.2)
+    xb = parity.to_dev(x0)
+    st = d.pgd_state(B)
+    d.pgd_init(xb, st)
+    d.pgd_step(xb, st, 0.1)
+    torch.cuda.synchronize()
+    assert r["iters"] == 5
+    done = r["done"].cpu().numpy()
+    assert set(np.unique(done)) <= {1, 2} and int(r["counter"][2]) == B
+    assert torch.equal(xa, xb)
+    want = oracle.pgd(inst, x0, 0.1, 100, delta=0.2)["x"]
+    np.testing.assert_allclose(xa.cpu().numpy(), want, rtol=0, atol=1e-5)
+
+
+def test_search_rejects_a_batch():
+    parts = [W.planted_3sat(n=50, m=150, instance=i) for i in range(2)]
+    d = afsat.Instance.batch(parts)
+    x = torch.zeros((d.n, 8), device="cuda")
+    st = d.pgd_state(8)
+    with pytest.raises(afsat.AfsError) as e:
+        d.search_step(x, st, (1.0, 0.5, 1e-4, 4))
+    assert e.value.status == afsat.AFS_EINVAL
+
+
+def test_parsed_input_end_to_end():
+    """Hybrid text -> simplification -> units folded into two partial
+    assignments -> start points -> line-search descent: every verified restart
+    satisfies the input and keeps its row's values."""
+    text = ("c a small satisfiable hybrid instance\n"
+            "p cnf 12 9\n"
+            "-12 0\n"                       # unit: x12 False
+            "x 1 2 3 0\n"
+            "n 3 4 5 0\n"
+            "a 5 6 7 8 0\n"
+            "e 8 9 10 0\n"
+            "k 2 1 4 7 10 0\n"
+            "d >=2 2 6 9 11 0\n"
+            "card <3 1 5 9 11 12 0\n"
+            "1 -11 12 0\n")
+    p = afsat.parse_text(text)
+    assert list(p.units[-1:]) == [-1] and p.n_dropped == 1
+    vals = p.fold_units([[1, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0],
+                         [0, 0, 0, 0, 0, 0, 0, 0, 0, 0, -1, 0]])
+    d = afsat.Instance.from_arrays(p)
+    B = 64
+    vd = torch.from_numpy(vals).cuda()
+    x = d.init_points(B, 7, vd)
+    r = d.pgd(x, 0.0, 200, fixed=vd, poll=5, stop_on_sat=False, search=(1.0, 0.5, 1e-4, 6))
+    xs = x.cpu().numpy()
+    held = oracle.fixed_columns(vals, p.n, B)
+    want_vals = np.where(vals[(np.arange(B) * 2) // B].T > 0, -1.0, 1.0)
+    np.testing.assert_array_equal(xs[held], want_vals[held])
+    done = r["done"].cpu().numpy() == 1
+    log("parsed instance: %d of %d restarts verified" % (done.sum(), B))
+    assert done.any()
+    assert (oracle.verify(p, xs)[done] == 0).all()

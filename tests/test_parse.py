@@ -247,3 +247,29 @@ def test_simplified_input_accepts_the_same_assignments(seed):
         if p.units[v]:
             got &= A[:, v] == (p.units[v] > 0)
     assert np.array_equal(got, want), text
+
+
+# ---- unit folding (Sec. 3.4) ------------------------------------------------------------
+
+def test_units_become_a_universal_partial_assignment():
+    p = afsat.parse_text("p cnf 5 3\n-2 0\ne 4 0\n1 3 5 0\n")
+    vals = p.fold_units()
+    assert vals.shape == (1, 5)
+    assert list(vals[0]) == [0, -1, 0, 1, 0]
+
+
+def test_units_fold_into_every_partial_assignment():
+    p = afsat.parse_text("p cnf 4 2\n-2 0\n1 3 4 0\n")
+    parts = np.array([[1, 0, 0, 0], [0, -1, 1, 0], [-1, 0, 0, -1]], dtype=np.int8)
+    vals = p.fold_units(parts)
+    np.testing.assert_array_equal(vals, [[1, -1, 0, 0], [0, -1, 1, 0], [-1, -1, 0, -1]])
+    np.testing.assert_array_equal(parts[0], [1, 0, 0, 0])     # the input is not modified
+
+
+def test_unit_contradicting_a_partial_assignment_is_unsat():
+    p = afsat.parse_text("p cnf 3 2\n2 0\n1 3 0\n")
+    with pytest.raises(AfsError) as e:
+        p.fold_units([[0, 0, 1], [0, -1, 0]])
+    assert e.value.status == AFS_EUNSAT and "partial assignment 1" in str(e.value)
+    with pytest.raises(ValueError):
+        p.fold_units([[0, 1]])

@@ -1,0 +1,105 @@
+"""Command-line solver: argument and file handling on the CPU; end-to-end runs
+on the GPU (marked), whose printed assignments the oracle checks."""
+import io
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2606_06641_amd import solve
+from paper_2606_06641_amd import workloads as W
+
+TYPE_IDS = {0: "", 1: "x", 2: "n", 5: "a", 6: "e"}
+
+
+def to_text(inst):
+    """Render an instance in the hybrid format (OR, XOR odd, NAE, AMO, EO,
+    CARD >= / <, EK)."""
+    lines = ["p cnf %d %d" % (inst.n, len(inst.types))]
+    for c in range(len(inst.types)):
+        ls = " ".join(str(int(l)) for l in inst.lits[inst.con_off[c]:inst.con_off[c + 1]])
+        t, prm = int(inst.types[c]), int(inst.params[c])
+        if t == 1 and prm != 1:
+            raise ValueError("the format has odd parity only")
+        head = {3: "d >=%d " % prm, 4: "d <%d " % prm, 7: "k %d " % prm}.get(t, TYPE_IDS.get(t, "") + " ")
+        lines.append((head + ls + " 0").strip())
+    return "\n".join(lines) + "\n"
+
+
+def values(text_out):
+    lits = [int(t) for line in text_out.splitlines() if line.startswith("v ") for t in line.split()[1:]]
+    assert lits[-1] == 0
+    return lits[:-1]
+
+
+def run(args):
+    buf = io.StringIO()
+    rc = solve.main(args, out=buf)
+    return rc, buf.getvalue()
+
+
+def test_read_partials(tmp_path):
+    f = tmp_path / "p.txt"
+    f.write_text("c two assignments\n1 -3 0\n\n2 0\n")
+    np.testing.assert_array_equal(solve.read_partials(str(f), 3), [[1, 0, -1], [0, 1, 0]])
+    for bad in ("1 -1 0\n", "4 0\n", "1 2\n", "c nothing\n"):
+        f.write_text(bad)
+        with pytest.raises(ValueError):
+            solve.read_partials(str(f), 3)
+
+
+def test_conflicting_units_print_unsatisfiable(tmp_path):
+    f = tmp_path / "u.cnf"
+    f.write_text("p cnf 2 2\n1 0\n-1 0\n")
+    rc, text = run([str(f)])
+    assert rc == 20 and "s UNSATISFIABLE" in text
+
+
+def test_units_alone_satisfy_without_a_search(tmp_path):
+    f = tmp_path / "u.cnf"
+    f.write_text("p cnf 3 3\n1 0\n-2 0\nd 0 1 2 3 0\n")
+    rc, text = run([str(f)])
+    assert rc == 10 and "s SATISFIABLE" in text
+    assert values(text) == [1, -2, -3]
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("extra", [[], ["--line-search", "--trials", "6"], ["--no-graph"]])
+def test_solves_a_planted_instance(tmp_path, extra):
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    inst = W.planted_3sat(n=100, m=340, instance=4)
+    f = tmp_path / "planted.cnf"
+    f.write_text(to_text(inst))
+    rc, text = run([str(f), "--batch", "256", "--iters", "400", "--seed", "3"] + extra)
+    print(text, flush=True)
+    assert rc == 10 and "s SATISFIABLE" in text
+    lits = values(text)
+    assert [abs(l) for l in lits] == list(range(1, inst.n + 1))
+    x = np.array([[-1.0] if l > 0 else [1.0] for l in lits], dtype=np.float32)
+    assert oracle.verify(inst, x)[0] == 0
+
+
+@pytest.mark.gpu
+def test_partial_assignments_are_kept(tmp_path):
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    inst = W.planted_3sat(n=100, m=340, instance=4)
+    H = inst.hidden
+    f = tmp_path / "planted.cnf"
+    f.write_text(to_text(inst))
+    part = tmp_path / "partial.txt"
+    # two partial assignments taken from the planted solution
+    rows = [[v + 1 if H[v] else -(v + 1) for v in range(0, 20)],
+            [v + 1 if H[v] else -(v + 1) for v in range(50, 60)]]
+    part.write_text("\n".join(" ".join(map(str, r)) + " 0" for r in rows) + "\n")
+    rc, text = run([str(f), "--batch", "128", "--iters", "400", "--partial", str(part)])
+    print(text, flush=True)
+    assert rc == 10
+    lits = values(text)
+    x = np.array([[-1.0] if l > 0 else [1.0] for l in lits], dtype=np.float32)
+    assert oracle.verify(inst, x)[0] == 0
+    restart = int(text.split("c restart ")[1].split()[0])
+    kept = rows[0] if restart < 64 else rows[1]
+    assert all(lits[abs(l) - 1] == l for l in kept)

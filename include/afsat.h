@@ -453,6 +453,30 @@ afs_status afs_gnn_gemm_bf16(int32_t M, int32_t N, int32_t K, const float *A, in
                              const float *B, int64_t sbk, int64_t sbn, float *C, int64_t ldc,
                              void *stream);
 
+/* ---- Precision study: the two DFT forms (Sec. 2.1.2; Sec. 3.5) ----
+ * Form A is the paper's evaluation: FE(y) = Re sum_m c_m prod_i (omega^m + y_i)
+ * with c_m = (1/N) sum_j fhat_(k-j) omega^(-m j), N = k + 1, fhat_t the
+ * Walsh-Fourier coefficient of a size-t literal set; its products span about 2^k
+ * to eps^k near a corner, which limits it to k near 50 in FP64.  Form B is the
+ * count basis of the library's FE kernels: FE(y) = Re sum_m d_m prod_i
+ * (alpha_m + beta_m y_i) with alpha_m = (1 + omega^m)/2, beta_m = (1 - omega^m)/2
+ * and d as afs_coefficients. */
+typedef enum { AFS_FORM_A = 0, AFS_FORM_B = 1 } afs_form;
+
+/* Tables of one constraint in either form: alpha, beta, d host double
+ * [2(k+1)] as (re, im) pairs.  fhat_t is summed exactly in 128-bit integers and
+ * divided by 2^k last (Sec. 3.5.1), so form A takes k <= 120. */
+afs_status afs_form_tables(int32_t type, int32_t k, int32_t param, int32_t form, double *alpha,
+                           double *beta, double *d);
+
+/* FE(y) = Re sum_m d_m prod_i (alpha_m + beta_m y[i][b]) for b < B, one lane per
+ * point with no rescaling, in FP32 (fp64 == 0: tables and y rounded to FP32
+ * first) or FP64.  y: device f64 [k][B]; fe: device f64 [B].  An experiment
+ * entry, not a hot-path one: it uploads the tables, allocates, and returns after
+ * the stream has finished. */
+afs_status afs_fe_generic(int32_t k, const double *alpha, const double *beta, const double *d, int32_t fp64,
+                          int32_t B, const double *y, double *fe, int32_t device, void *stream);
+
 /* ---- Input files (App. A) ----
  * DIMACS CNF and the hybrid symmetric-constraint format: an optional 'h' marker,
  * an optional type identifier (x/xor, n/nae, a/amo, e/eo, k/ek K, d/card T with

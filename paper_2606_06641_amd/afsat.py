@@ -119,7 +119,11 @@ SIGNATURES = [
                                            _vp, ctypes.c_size_t, _vp, ctypes.c_size_t, ctypes.POINTER(_PgdState),
                                            _vp, _vp]),
     ("afs_init_points", ctypes.c_int, [_vp, _i32, ctypes.c_uint64, _vp, _i32, _vp, _vp]),
+    ("afs_form_tables", ctypes.c_int, [_i32, _i32, _i32, _i32, _f64p, _f64p, _f64p]),
+    ("afs_fe_generic", ctypes.c_int, [_i32, _f64p, _f64p, _f64p, _i32, _i32, _vp, _vp, _i32, _vp]),
 ]
+
+FORM_A, FORM_B = 0, 1
 
 _lib = None
 
@@ -149,6 +153,27 @@ def _ptr(t: Optional[torch.Tensor]):
 
 def _np_ptr(a, ctype):
     return None if a is None else a.ctypes.data_as(ctype)
+
+
+def form_tables(ctype: int, k: int, param: int, form: int):
+    """(alpha, beta, d) complex128 [k+1] of one constraint in form A (the
+    paper's +-1 ESP basis) or form B (count basis); see afs_form_tables."""
+    arrs = [np.zeros(2 * (k + 1)) for _ in range(3)]
+    _check(lib().afs_form_tables(int(ctype), int(k), int(param), int(form), *[_np_ptr(a, _f64p) for a in arrs]))
+    return tuple(a[0::2] + 1j * a[1::2] for a in arrs)
+
+
+def fe_generic(tables, y, fp64=True):
+    """FE(y) = Re sum_m d_m prod_i (alpha_m + beta_m y[i]) on the GPU in FP64 or
+    FP32 for the points y (torch f64 (k, B) on a device)."""
+    alpha, beta, d = (np.ascontiguousarray(np.stack([t.real, t.imag], axis=1).ravel()) for t in tables)
+    k = len(alpha) // 2 - 1
+    if y.dtype != torch.float64 or y.dim() != 2 or y.shape[0] != k or not y.is_contiguous():
+        raise ValueError("y must be contiguous float64 shaped (k, B)")
+    fe = torch.empty(y.shape[1], dtype=torch.float64, device=y.device)
+    _check(lib().afs_fe_generic(k, _np_ptr(alpha, _f64p), _np_ptr(beta, _f64p), _np_ptr(d, _f64p), int(bool(fp64)),
+                                y.shape[1], _ptr(y), _ptr(fe), y.device.index or 0, _stream(y.device)))
+    return fe
 
 
 def coefficients(ctype: int, k: int, param: int = 0):

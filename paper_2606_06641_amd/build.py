@@ -39,9 +39,11 @@ SOURCES = [
     ("api.cpp", HOST_HIP),
     ("autotune.cpp", HOST_HIP + ['-DAFS_FE_REV="%s"' % fe_revision()]),
     ("parse.cpp", HOST_HIP),
+    ("forms.cpp", HOST_HIP),
     ("fe_kernels.hip", [HIPCC] + COMMON + DEVICE),
     ("update_kernels.hip", [HIPCC] + COMMON + DEVICE),
     ("search_kernels.hip", [HIPCC] + COMMON + DEVICE),
+    ("forms.hip", [HIPCC] + COMMON + DEVICE),
     ("gnn.hip", [HIPCC] + COMMON + DEVICE),
 ]
 

@@ -41,7 +41,7 @@ static int canonical_param(int type, int k, int param)
 
 // Roots of unity of order N for j = 0..N-1, computed for j <= N/2 and mirrored
 // (conj) above, with exact values at the axis crossings.
-static void roots(int N, std::vector<long double> &c, std::vector<long double> &s)
+void roots(int N, std::vector<long double> &c, std::vector<long double> &s)
 {
     c.assign(N, 0.0L);
     s.assign(N, 0.0L);

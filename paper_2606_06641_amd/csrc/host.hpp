@@ -88,6 +88,10 @@ int satisfied(int type, int k, int param, int t);
 // mirrored conjugates of N - j, so conjugate symmetry is exact.
 void coefficients(int type, int k, int param, double *re, double *im);
 
+// omega^j = c[j] + i s[j], omega = exp(2 pi i / N), j = 0..N-1; computed for
+// j <= N/2 and mirrored as conjugates above, exact at the axis crossings.
+void roots(int N, std::vector<long double> &c, std::vector<long double> &s);
+
 // Packing choices (see afs_options in afsat.h).
 struct PackOptions {
     std::vector<int> k_hi, lanes, seg;   // shape overrides for k > kShortMax, ascending k_hi

@@ -107,6 +107,12 @@ hipError_t launch_search_step(const DevInstance &I, int B, float *x, const float
 hipError_t launch_init_points(int n, int B, uint64_t seed, const int8_t *values, int n_partial, float *x,
                               hipStream_t s);
 
+// Precision study: fe[b] = Re sum_m d_m prod_i (alpha_m + beta_m y[i][b]) in FP32
+// (fp64 false; tables and y rounded to FP32 first) or FP64; tab [k+1][6] =
+// alpha, beta, d as (re, im) pairs.
+hipError_t launch_fe_generic(int k, const double *tab, bool fp64, int B, const double *y, double *fe,
+                             hipStream_t s);
+
 // adj_out[slot_to_lit[s]][b] = adj[s][b]
 hipError_t launch_permute_adj(const DevInstance &I, int B, int Bp, const float *adj,
                               float *adj_out, hipStream_t s);

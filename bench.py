@@ -243,6 +243,8 @@ def main():
     first_slot = slot_of_lit[np.asarray(inst.con_off[:-1])]
     in_b = (first_slot >= bk.slot0) & (first_slot < bk.slot0 + bk.n_lits)
     kb = lens[in_b]
+    if not autograd:
+        bucket_roofline(buckets, per_bucket, lens, first_slot, B)
     kname = "fe_grad_seg<%d,%d>" % (bk.lanes_per_restart, bk.lits_per_lane) if bk.lanes_per_restart > 1 \
         else "fe_grad_short<%d>" % bk.k_hi
     if autograd:
@@ -286,6 +288,27 @@ def main():
     if not args.no_cpu_baseline and args.workload == "mixed10k":
         line["cpu_baseline"] = cpu_baseline(inst, x0, args.lr, args.cpu_seconds)
     print(json.dumps(line), flush=True)
+
+
+def bucket_roofline(buckets, per_bucket_ms, lens, first_slot, B):
+    """Per length bucket (each timed alone, outside the timed region): literal-evals
+    per second against the bucket's own roofline min(P_VALU / F, BW / Q), with F
+    the algorithmic flops per literal-eval of its lengths and Q = 8 B (x gather
+    and adjoint write), printed to stderr."""
+    print("bucket roofline (alone): k range, shape, ms, literal-evals/s, TFLOP/s, GB/s, bound, fraction",
+          file=sys.stderr)
+    for b, t in zip(buckets, per_bucket_ms):
+        sel = (first_slot >= b.slot0) & (first_slot < b.slot0 + b.n_lits)
+        ks = lens[sel]
+        evals = float(B * ks.sum())
+        flops = float(B * sum(algorithmic_flops(int(k)) for k in ks))
+        sec = t * 1e-3
+        rate = evals / sec
+        ceiling = min(PEAK_FP32_TFLOPS * 1e12 / (flops / evals), PEAK_HBM_GBS * 1e9 / 8.0)
+        bound = "alu" if PEAK_FP32_TFLOPS * 1e12 / (flops / evals) < PEAK_HBM_GBS * 1e9 / 8.0 else "hbm"
+        print("  [%4d-%4d] J%-2d S%-2d %8.3f ms %10.3e %7.2f %8.1f %s %.3f" % (
+            b.k_lo, b.k_hi, b.lanes_per_restart, b.lits_per_lane, t, rate, flops / sec / 1e12,
+            8.0 * evals / sec / 1e9, bound, rate / ceiling), file=sys.stderr, flush=True)
 
 
 def learned_init_bench(args, W):

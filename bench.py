@@ -123,6 +123,9 @@ def main():
     ap.add_argument("--no-autotune", action="store_true",
                     help="use the default kernel shapes instead of the tuned ones")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--search", type=int, default=0,
+                    help="mixed10k only: time Algorithm 1 iterations with the backtracking line search "
+                         "of this many trials instead of the constant-step hot path")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device copy of this size (to calibrate byte counters)")
     args = ap.parse_args()
@@ -170,6 +173,9 @@ def main():
     ws = d.workspace(B)
     st = d.pgd_state(B)
     d.pgd_init(x, st, ws)
+    if args.search:
+        search_bench(args, d, x, st, ws, B, desc)
+        return
     stream = torch.cuda.current_stream(dev)
     buckets = d.buckets()
     nb = len(buckets)
@@ -288,6 +294,35 @@ def main():
     if not args.no_cpu_baseline and args.workload == "mixed10k":
         line["cpu_baseline"] = cpu_baseline(inst, x0, args.lr, args.cpu_seconds)
     print(json.dumps(line), flush=True)
+
+
+def search_bench(args, d, x, st, ws, B, desc):
+    """Iterations of Algorithm 1 with the backtracking line search (one FE +
+    gradient pass, `--search` forward-only FE passes and trial points, the step,
+    rounding and verification per iteration): iterations per second."""
+    import torch
+    from paper_2606_06641_amd import afsat
+    if d.n_inst != 1:
+        raise SystemExit("the line search takes a plain instance (--workload mixed10k)")
+    ls = afsat.LineSearch(1.0, 0.5, 1e-4, args.search)
+    eta = torch.empty(B, dtype=torch.float32, device=x.device)
+    for _ in range(args.warmup):
+        d.search_step(x, st, ls, eta=eta, ws=ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        d.search_step(x, st, ls, eta=eta, ws=ws)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    e = eta.cpu()
+    print("step lengths after the last iteration: %s" % {float(v): int((e == v).sum()) for v in e.unique()},
+          file=sys.stderr, flush=True)
+    print(json.dumps({"metric": "line-search PGD iterations/s", "value": 1e3 / ms, "unit": "iterations/s",
+                      "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+                      "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+                      "data": "synthetic",
+                      "config": {"workload": desc, "restarts": B, "trials": args.search, "max_step": 1.0,
+                                 "shrink": 0.5, "armijo": 1e-4}}), flush=True)
 
 
 def bucket_roofline(buckets, per_bucket_ms, lens, first_slot, B):

@@ -174,7 +174,7 @@ T *at(void *ws, size_t off) { return reinterpret_cast<T *>(static_cast<char *>(w
 
 afs_status fe_grad_range(afs_instance *I, int B, const float *x, void *ws, const WsLayout &l,
                          int lo, int hi, bool want_part, float *fe, hipStream_t s,
-                         const float *dobj = nullptr, bool grad = true)
+                         const float *dobj = nullptr, bool grad = true, const uint8_t *skip = nullptr)
 {
     // Short buckets (one lane per restart, bound by memory traffic) go to the side
     // stream when long buckets (bound by arithmetic) share the range, so the two
@@ -194,7 +194,7 @@ afs_status fe_grad_range(afs_instance *I, int B, const float *x, void *ws, const
         afs::BucketLaunch bl{b.J, b.S, b.c0, b.nc, b.tile, b.ntiles, b.tile0};
         hipError_t e = afs::launch_fe_grad(I->D, bl, B, l.Bp, x, at<float>(ws, l.adj),
                                            want_part ? at<float>(ws, l.part) : nullptr, fe, dobj,
-                                           grad, split && b.J == 1 ? I->side : s);
+                                           grad, split && b.J == 1 ? I->side : s, skip);
         if (e != hipSuccess) return dev_fail(e, "fe_grad launch");
     }
     if (split) {
@@ -681,7 +681,9 @@ static afs_status search_call(afs_instance *I, int32_t B, float *x, const afs_li
         if (e == hipSuccess)
             e = afs::launch_obj_reduce(q.vtiles, B, l.Bp, at<float>(sws, q.dpart), at<float>(sws, q.dpart2), dot, s);
         if (e != hipSuccess) return dev_fail(e, "line search trial launch");
-        if ((st = fe_grad_range(I, B, xt, ws, l, 0, nb, true, nullptr, s, nullptr, false)) != AFS_OK) return st;
+        // restarts that have decided (acc != 0) are not needed: whole waves of them skip
+        if ((st = fe_grad_range(I, B, xt, ws, l, 0, nb, true, nullptr, s, nullptr, false, acc)) != AFS_OK)
+            return st;
         e = afs::launch_obj_reduce(tiles, B, l.Bp, part, part2, ft, s);
         if (e == hipSuccess)
             e = afs::launch_accept(B, f0, ft, dot, ls->armijo, ls->shrink, j == ls->trials - 1, eta, acc, s);

@@ -40,6 +40,7 @@ struct FeArgs {
     const float *x;
     float *adj, *part, *fe;
     const float *dobj;          // per-restart seed of the adjoint (NULL: 1)
+    const uint8_t *skip;        // per restart: nonzero = not needed (NULL: all needed)
     const int32_t *bc_slot0, *bc_k, *bc_tab, *bc_orig;
     const float *bc_w;
     const int32_t *slot_lit;
@@ -117,6 +118,12 @@ __global__ __launch_bounds__(kBlock) void fe_grad_short(FeArgs A, const float4 *
     const int b0 = ((int)group * kWave + lane) * RPL;          // first restart of the lane
     const bool valid = b0 < A.B;                               // RPL divides B
     const int bl = valid ? b0 : A.B - RPL;
+    if (A.skip) {                                              // a wave whose restarts are all skipped
+        bool need = false;
+#pragma unroll
+        for (int e = 0; e < RPL; ++e) need |= valid && !A.skip[b0 + e];
+        if (__ballot(need) == 0) return;
+    }
     const int cbeg = A.c0 + tile * A.tile;
     const int cend = min(cbeg + A.tile, A.c0 + A.nc);
     Lanes<RPL> seed;
@@ -307,6 +314,7 @@ __global__ __launch_bounds__(kBlock) void fe_grad_seg(FeArgs A, const float4 *__
     const int b = group * R + r;
     const bool valid = b < A.B;
     const int bl = valid ? b : A.B - 1;
+    if (A.skip && __ballot(valid && !A.skip[b]) == 0) return;   // every restart of the wave skipped
     const int cbeg = A.c0 + tile * A.tile;
     const int cend = min(cbeg + A.tile, A.c0 + A.nc);
     const int base = j * S;
@@ -477,11 +485,11 @@ hipError_t dispatch_seg(int J, int S, dim3 g, hipStream_t s, const FeArgs &a)
 
 hipError_t launch_fe_grad(const DevInstance &I, const BucketLaunch &bk, int B, int Bp,
                           const float *x, float *adj, float *part, float *fe, const float *dobj,
-                          bool grad, hipStream_t s)
+                          bool grad, hipStream_t s, const uint8_t *skip)
 {
     if (bk.nc == 0 || B == 0) return hipSuccess;
     FeArgs a;
-    a.x = x; a.adj = adj; a.part = part; a.fe = fe; a.dobj = dobj;
+    a.x = x; a.adj = adj; a.part = part; a.fe = fe; a.dobj = dobj; a.skip = skip;
     a.bc_slot0 = I.bc_slot0; a.bc_k = I.bc_k; a.bc_tab = I.bc_tab; a.bc_orig = I.bc_orig;
     a.bc_w = I.bc_w; a.slot_lit = I.slot_lit; a.tab = I.tab;
     a.B = B; a.Bp = Bp;

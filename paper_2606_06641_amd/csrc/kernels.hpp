@@ -41,10 +41,11 @@ struct BucketLaunch {
 // FE (and with grad, per-literal adjoints) of one length bucket.
 //   adj  [L][Bp] (slot order, written when grad), part [tiles][Bp] objective partials
 //   (may be null), fe [C][B] (may be null), dobj [B] per-restart seed of the adjoint
-//   (may be null: 1).
+//   (may be null: 1).  skip [B] (may be null): a wave whose restarts all have
+//   skip != 0 returns at once and writes nothing, so their outputs keep old values.
 hipError_t launch_fe_grad(const DevInstance &I, const BucketLaunch &bk, int B, int Bp,
                           const float *x, float *adj, float *part, float *fe, const float *dobj,
-                          bool grad, hipStream_t s);
+                          bool grad, hipStream_t s, const uint8_t *skip = nullptr);
 
 // grad[v][b] = sum of adj over the slots of v, ascending.
 hipError_t launch_scatter(const DevInstance &I, int B, int Bp, const float *adj, float *grad,

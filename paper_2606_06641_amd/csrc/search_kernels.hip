@@ -10,7 +10,9 @@
 //   no trial accepted: eta = 0 (no step)
 //   x = clip(x - eta g)
 // The objective sums are fixed-order reductions (the same two-pass reduction as
-// the objective), so every decision is deterministic.
+// the objective), so every decision is deterministic.  The trials' FE passes skip
+// every wave whose restarts have all decided; the objective partials of those
+// restarts then hold stale values, which the test never reads.
 //
 // Layouts: x, g, xt [n][B] f32; per-restart vectors [B] (padded to Bp).
 

@@ -488,13 +488,26 @@ __global__ __launch_bounds__(kWave) void obj_reduce1(int tiles, int Bp, const fl
     part2[(int64_t)g * Bp + b] = s;
 }
 
-__global__ __launch_bounds__(kBlock) void obj_reduce2(int groups, int B, int Bp, const float *part2, float *obj)
+// one block of kRed2Waves waves per 64 restarts: wave w sums the groups
+// w, w + kRed2Waves, ... in ascending order, then lane b of wave 0 adds the
+// waves' sums in wave order (a fixed order, whatever the launch)
+constexpr int kRed2Waves = 16;
+
+__global__ __launch_bounds__(kRed2Waves * kWave) void obj_reduce2(int groups, int B, int Bp, const float *part2,
+                                                                 float *obj)
 {
-    const int b = blockIdx.x * kBlock + threadIdx.x;
-    if (b >= B) return;
+    __shared__ float red[kRed2Waves][kWave];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int b = blockIdx.x * kWave + lane;           // < Bp
     float s = 0.f;
-    for (int g = 0; g < groups; ++g) s += part2[(int64_t)g * Bp + b];
-    obj[b] = s;
+    for (int g = w; g < groups; g += kRed2Waves) s += part2[(int64_t)g * Bp + b];
+    red[w][lane] = s;
+    __syncthreads();
+    if (w == 0 && b < B) {
+        float t = red[0][lane];
+        for (int i = 1; i < kRed2Waves; ++i) t += red[i][lane];
+        obj[b] = t;
+    }
 }
 
 __global__ __launch_bounds__(kBlock) void permute_adj_kernel(const float *adj, float *out,
@@ -555,8 +568,7 @@ hipError_t launch_obj_reduce(int tiles, int B, int Bp, const float *part, float 
     const int groups = (tiles + kRedGroup - 1) / kRedGroup;
     if (groups > 0)
         hipLaunchKernelGGL(obj_reduce1, dim3(Bp / kWave, groups), dim3(kWave), 0, s, tiles, Bp, part, part2);
-    hipLaunchKernelGGL(obj_reduce2, dim3((B + kBlock - 1) / kBlock), dim3(kBlock), 0, s, groups, B, Bp,
-                       part2, obj);
+    hipLaunchKernelGGL(obj_reduce2, dim3(Bp / kWave), dim3(kRed2Waves * kWave), 0, s, groups, B, Bp, part2, obj);
     return hipGetLastError();
 }
 

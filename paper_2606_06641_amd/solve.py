@@ -7,8 +7,10 @@ DIMACS output convention.
 Output: comment lines ("c ..."), then "s SATISFIABLE" with the assignment on
 "v" lines ending in 0, or "s UNKNOWN" (the method is incomplete: it cannot
 prove unsatisfiability, Sec. 5) with the best restart's unsatisfied-constraint
-count, or "s UNSATISFIABLE" when the reader's simplifications already prove it
-(conflicting units).  Exit status 10 / 20 / 0 as is customary for SAT solvers.
+count -- with --best also an "o" line with that count and the best restart's
+assignment, the best-effort answer of Sec. 5 -- or "s UNSATISFIABLE" when the
+reader's simplifications already prove it (conflicting units).  Exit status
+10 / 20 / 0 as is customary for SAT solvers.
 
 Partial assignments (Sec. 3.4) come from --partial FILE: one assignment per
 line, literals ending in 0 (a positive literal fixes its variable True); the
@@ -75,6 +77,9 @@ def main(argv=None, out=None):
     ap.add_argument("--partial", help="file of partial assignments, one per line, ending in 0")
     ap.add_argument("--device", type=int, default=0)
     ap.add_argument("--no-graph", action="store_true", help="launch iterations one by one")
+    ap.add_argument("--best", action="store_true",
+                    help="when no restart verifies, print the best restart's assignment (best effort, "
+                         "with its unsatisfied-constraint count on an 'o' line)")
     a = ap.parse_args(argv)
 
     t0 = time.perf_counter()
@@ -127,7 +132,12 @@ def main(argv=None, out=None):
         return 10
     b = int(np.argmin(unsat))
     print("c best restart %d leaves %d constraints unsatisfied" % (b, int(unsat[b])), file=out)
+    if a.best:
+        print("o %d" % int(unsat[b]), file=out)
     print("s UNKNOWN", file=out)
+    if a.best:
+        for line in assignment_lines((x[:, b] < 0).cpu().numpy()):
+            print(line, file=out)
     return 0
 
 

@@ -103,3 +103,19 @@ def test_partial_assignments_are_kept(tmp_path):
     restart = int(text.split("c restart ")[1].split()[0])
     kept = rows[0] if restart < 64 else rows[1]
     assert all(lits[abs(l) - 1] == l for l in kept)
+
+
+@pytest.mark.gpu
+def test_best_effort_answer_on_an_unsatisfiable_input(tmp_path):
+    """With x3 True, x1 xor x2 must be odd and even at once: the solver answers
+    UNKNOWN and, with --best, an assignment leaving exactly one constraint
+    unsatisfied."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    f = tmp_path / "unsat.cnf"
+    f.write_text("p cnf 3 3\nx 1 2 0\nx 1 2 3 0\n3 0\n")
+    rc, text = run([str(f), "--batch", "64", "--iters", "50", "--best"])
+    print(text, flush=True)
+    assert rc == 0 and "s UNKNOWN" in text and "o 1" in text
+    lits = values(text)
+    assert len(lits) == 3 and lits[2] == 3

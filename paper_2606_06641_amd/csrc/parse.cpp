@@ -235,6 +235,9 @@ struct Reader {
                         if (v == 0) return fail(lineno, "empty constraint");
                         c.type = AFS_OR;
                         if (v < -INT32_MAX || v > INT32_MAX) return fail(lineno, "literal out of range");
+                        if (seen_problem && (v > P.n || -v > P.n))
+                            return fail(lineno, "variable " + std::to_string(v > 0 ? v : -v) +
+                                                    " exceeds the problem line's " + std::to_string(P.n));
                         c.lits.push_back((int32_t)v);
                     }
                     if (!(ss >> tok)) { more = false; break; }
@@ -248,6 +251,9 @@ struct Reader {
                     break;
                 }
                 if (v < -INT32_MAX || v > INT32_MAX) return fail(lineno, "literal out of range");
+                if (seen_problem && (v > P.n || -v > P.n))
+                    return fail(lineno, "variable " + std::to_string(v > 0 ? v : -v) + " exceeds the problem line's " +
+                                            std::to_string(P.n));
                 c.lits.push_back((int32_t)v);
                 if (!(ss >> tok)) more = false;
             }

@@ -128,6 +128,8 @@ def test_layout_details():
 @pytest.mark.parametrize("text,where", [
     ("1 2\n", "line 1"),                     # not terminated
     ("p cnf 2 1\n1 3 0\n", "exceeds"),       # variable beyond the problem line
+    ("p cnf 2 1\n1 2000000000 0\n", "line 2"),  # reported where it appears, nothing sized to it
+    ("p cnf 2 1\n-2000000000 0\n", "line 2"),
     ("p cnf 2 1\np cnf 2 1\n", "line 2"),    # second problem line
     ("p dnf 2 1\n", "line 1"),
     ("1 foo 0\n", "line 1"),

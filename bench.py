@@ -57,12 +57,15 @@ def stored_traffic(kernel_name):
     return e.get("bytes_per_launch")
 
 
-def cpu_baseline(inst, x0, lr, budget_s=12.0):
-    """The FP64 oracle (eval + step + verify) timed on this host's cores."""
+def cpu_baseline(inst, x0, lr, budget_s=12.0, threads=0, restarts=0):
+    """The FP64 oracle (eval + step + verify) timed on this host's cores (or
+    `threads` of them), on all restarts or the first `restarts`."""
     import numpy as np
     import oracle
-    threads = oracle.default_threads()
+    threads = threads or oracle.default_threads()
     x = x0.astype(np.float64)
+    if restarts:
+        x = np.ascontiguousarray(x[:, :restarts])
     B = x.shape[1]
     reps, t_used = 0, 0.0
     t0 = time.perf_counter()
@@ -76,8 +79,8 @@ def cpu_baseline(inst, x0, lr, budget_s=12.0):
             break
     value = B * inst.n_lits * reps / t_used
     return {"value": value, "unit": "literal-evals/s", "cores": threads, "kind": "oracle",
-            "sample": "same instance, all %d restarts, %d full PGD iterations (FE+grad, step, "
-                      "verify) in FP64, %.1f s" % (B, reps, t_used)}
+            "sample": "same instance, %s %d restarts, %d full PGD iterations (FE+grad, step, "
+                      "verify) in FP64, %.1f s" % ("the first" if restarts else "all", B, reps, t_used)}
 
 
 def copy_probe(mib):
@@ -123,6 +126,8 @@ def main():
     ap.add_argument("--no-autotune", action="store_true",
                     help="use the default kernel shapes instead of the tuned ones")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-threads", type=int, default=0, help="oracle baseline threads (0: every host core)")
+    ap.add_argument("--cpu-restarts", type=int, default=0, help="oracle baseline on the first R restarts only")
     ap.add_argument("--search", type=int, default=0,
                     help="mixed10k only: time Algorithm 1 iterations with the backtracking line search "
                          "of this many trials instead of the constant-step hot path")
@@ -292,7 +297,8 @@ def main():
         print("(part, restart) pairs verified after %d iterations: %d" % (int(st["counter"][0].item()),
               int(st["counter"][1].item())), file=sys.stderr, flush=True)
     if not args.no_cpu_baseline and args.workload == "mixed10k":
-        line["cpu_baseline"] = cpu_baseline(inst, x0, args.lr, args.cpu_seconds)
+        line["cpu_baseline"] = cpu_baseline(inst, x0, args.lr, args.cpu_seconds, args.cpu_threads,
+                                            args.cpu_restarts)
     print(json.dumps(line), flush=True)
 
 

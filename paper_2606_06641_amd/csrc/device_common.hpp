@@ -52,14 +52,6 @@ hipError_t for_launch_chunks(int64_t items, Launch launch)
     return hipSuccess;
 }
 
-// DPP lane move of v (all lanes active; lanes whose source lies outside the
-// row keep their own value)
-template <int CTRL>
-__device__ __forceinline__ float dpp_mov(float v)
-{
-    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), CTRL, 0xF, 0xF, false));
-}
-
 // Partial assignments (one row of fixed [n_partial][n] per slice of the restart
 // columns): restart b of B belongs to slice b * n_partial / B, so the slices are
 // as even as B allows.  fixed == nullptr fixes nothing.

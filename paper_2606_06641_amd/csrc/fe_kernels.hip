@@ -242,14 +242,23 @@ __global__ __launch_bounds__(kBlock) void fe_grad_short(FeArgs A, const float4 *
 // Levels 1, 2, 4 and 8 stay inside a 16-lane row (DPP quad_perm and the row
 // mirrors); 16 uses ds_swizzle, 32 a bpermute.
 // ---------------------------------------------------------------------------
+// DPP permutation inside 16-lane rows.  Every lane reads a lane of its own row,
+// so no lane keeps its previous value and none is passed in: the move needs no
+// copy of its source first.
+template <int CTRL>
+__device__ __forceinline__ float row_perm(float v)
+{
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
 // value held by some lane of the other half of this lane's 2D-group
 template <int D>
 __device__ __forceinline__ float partner(float v)
 {
-    if constexpr (D == 1) return dpp_mov<0xB1>(v);         // quad_perm [1,0,3,2]
-    else if constexpr (D == 2) return dpp_mov<0x4E>(v);    // quad_perm [2,3,0,1]
-    else if constexpr (D == 4) return dpp_mov<0x141>(v);   // row_half_mirror: i -> 7-i
-    else if constexpr (D == 8) return dpp_mov<0x140>(v);   // row_mirror: i -> 15-i
+    if constexpr (D == 1) return row_perm<0xB1>(v);         // quad_perm [1,0,3,2]
+    else if constexpr (D == 2) return row_perm<0x4E>(v);    // quad_perm [2,3,0,1]
+    else if constexpr (D == 4) return row_perm<0x141>(v);   // row_half_mirror: i -> 7-i
+    else if constexpr (D == 8) return row_perm<0x140>(v);   // row_mirror: i -> 15-i
     else if constexpr (D == 16)                            // swizzle xor 16 within 32 lanes
         return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x401F));
     else return __shfl_xor(v, 32);

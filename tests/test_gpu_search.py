@@ -111,11 +111,18 @@ def test_pgd_step_with_slices_holds_rows_and_verifies():
     np.testing.assert_array_equal(st["unsat"].cpu().numpy(), oracle.verify(inst, got))
 
 
-@pytest.mark.parametrize("B", [64, 200])
-def test_search_step_parity(B):
+# (max_step, shrink, armijo, trials): at uniform points the gentle search accepts
+# its first trial everywhere; the strict one (c = 0.9) spreads the decisions
+# over the first six or seven trials
+GENTLE, STRICT = (2.0, 0.5, 1e-3, 6), (8.0, 0.5, 0.9, 8)
+
+
+@pytest.mark.parametrize("B,weighted,search", [(64, False, GENTLE), (200, False, STRICT), (130, True, STRICT)])
+def test_search_step_parity(B, weighted, search):
     inst, rng = mixed(22)
+    if weighted:
+        inst.weights = rng.uniform(0.25, 3.0, size=inst.n_cons).astype(np.float32)
     d = afsat.Instance.from_arrays(inst)
-    search = (2.0, 0.5, 1e-3, 6)
     x = rng.uniform(-1, 1, size=(inst.n, B)).astype(np.float32)
     fixed = (rng.random((2, inst.n)) < 0.1).astype(np.uint8)
     log("case: search step n=%d C=%d B=%d" % (inst.n, inst.n_cons, B))
@@ -129,7 +136,8 @@ def test_search_step_parity(B):
     orc = oracle.line_search_step(inst, x, search, fixed=fixed)
     trials = orc["eta_trials"]
     assert np.isin(got_eta, np.append(trials, 0.0)).all()
-    tau = 2e-4 * inst.n_cons                              # two objective errors (1e-4 * sum|w| each)
+    wsum = inst.n_cons if inst.weights is None else float(np.abs(inst.weights).sum())
+    tau = 2e-4 * wsum                                     # two objective errors (1e-4 * sum|w| each)
     jg = np.array([np.nonzero(trials == e)[0][0] if e > 0 else len(trials) for e in got_eta])
     jo = np.array([np.nonzero(trials == e)[0][0] if e > 0 else len(trials) for e in orc["eta"]])
     clear = np.array([(np.abs(orc["margin"][:min(max(jg[b], jo[b]) + 1, len(trials)), b]) > tau).all()
@@ -137,10 +145,13 @@ def test_search_step_parity(B):
     log("restarts with clear decisions: %d of %d; trials chosen %s" % (clear.sum(), B, np.bincount(jg)))
     assert clear.sum() >= B // 2
     np.testing.assert_array_equal(jg[clear], jo[clear])
+    if search == STRICT:
+        assert len(np.unique(jg)) >= 4                    # backtracking really exercised
     # the step itself, with the library's own step length
     held = oracle.fixed_columns(fixed, inst.n, B)
     want = np.where(held, x, np.clip(x - got_eta[None, :] * orc["g"], -1, 1))
-    gtol = 1e-4 * np.max(np.bincount(np.abs(inst.lits) - 1, minlength=inst.n))
+    wl = np.ones(len(inst.lits)) if inst.weights is None else np.repeat(np.abs(inst.weights), np.diff(inst.con_off))
+    gtol = 1e-4 * np.max(np.bincount(np.abs(inst.lits) - 1, weights=wl, minlength=inst.n))
     np.testing.assert_allclose(got_x, want, rtol=0, atol=float(got_eta.max()) * gtol + 1e-6)
     np.testing.assert_array_equal(got_x[held], x[held])
     # the state after the step is the exact verification of the new point
@@ -205,6 +216,39 @@ def test_constant_step_converges_below_delta():
     assert torch.equal(xa, xb)
     want = oracle.pgd(inst, x0, 0.1, 100, delta=0.2)["x"]
     np.testing.assert_allclose(xa.cpu().numpy(), want, rtol=0, atol=1e-5)
+
+
+def test_partial_slices_on_a_batch():
+    """A block-diagonal batch: the mask rows span all parts' variables and split
+    the restart columns; held entries stay, the rest step exactly as the oracle's
+    step of the batch's own gradient, and the state is the exact verification."""
+    parts = [W.planted_3sat(n=60 + 20 * i, m=200 + 60 * i, instance=i) for i in range(3)]
+    d = afsat.Instance.batch(parts)
+    B = 90
+    rng = np.random.default_rng(31)
+    x = rng.uniform(-1, 1, size=(d.n, B)).astype(np.float32)
+    fixed = (rng.random((3, d.n)) < 0.25).astype(np.uint8)
+    log("case: batch slices n=%d parts=%d B=%d" % (d.n, d.n_inst, B))
+    xd = parity.to_dev(x)
+    g = d.eval(xd, obj=False, grad=True)["grad"]
+    xs = xd.clone()
+    d.step(xs, g, 0.2, fixed=torch.from_numpy(fixed).cuda())
+    got = xs.cpu().numpy()
+    held = oracle.fixed_columns(fixed, d.n, B)
+    np.testing.assert_array_equal(got[held], x[held])
+    want = oracle.step(x, g.cpu().numpy(), 0.2)
+    np.testing.assert_allclose(got[~held], want[~held], rtol=0, atol=1e-6)
+    # the PGD step on the batch with the same mask
+    xp = parity.to_dev(x)
+    st = d.pgd_state(B)
+    d.pgd_init(xp, st)
+    d.pgd_step(xp, st, 0.2, fixed=torch.from_numpy(fixed).cuda())
+    torch.cuda.synchronize()
+    assert torch.equal(xp, xs)
+    var0 = d.var_offsets()
+    u = st["unsat"].cpu().numpy()
+    for i, p in enumerate(parts):
+        np.testing.assert_array_equal(u[i], oracle.verify(p, got[var0[i]:var0[i + 1]]))
 
 
 def test_search_rejects_a_batch():

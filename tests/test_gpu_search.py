@@ -293,3 +293,38 @@ def test_parsed_input_end_to_end():
     log("parsed instance: %d of %d restarts verified" % (done.sum(), B))
     assert done.any()
     assert (oracle.verify(p, xs)[done] == 0).all()
+
+
+def test_invalid_arguments_are_rejected_before_any_launch():
+    import ctypes
+    inst = W.planted_3sat(n=50, m=150, instance=1)
+    d = afsat.Instance.from_arrays(inst)
+    B = 16
+    x = torch.zeros((d.n, B), device="cuda")
+    st = d.pgd_state(B)
+    for bad in [(0.0, 0.5, 1e-4, 4), (1.0, 1.0, 1e-4, 4), (1.0, 0.0, 1e-4, 4), (1.0, 0.5, 1.0, 4),
+                (1.0, 0.5, -0.1, 4), (1.0, 0.5, 1e-4, 0), (1.0, 0.5, 1e-4, 65), (float("inf"), 0.5, 1e-4, 4)]:
+        with pytest.raises(afsat.AfsError) as e:
+            d.search_step(x, st, bad)
+        assert e.value.status == afsat.AFS_EINVAL, bad
+    # more mask rows than restarts
+    with pytest.raises(afsat.AfsError) as e:
+        d.step(x, torch.zeros_like(x), 0.1, fixed=torch.zeros((B + 1, d.n), dtype=torch.uint8, device="cuda"))
+    assert e.value.status == afsat.AFS_EINVAL
+    with pytest.raises(afsat.AfsError):
+        d.init_points(B, 1, torch.zeros((B + 1, d.n), dtype=torch.int8, device="cuda"))
+    # the search workspace: too small, misaligned
+    lib = afsat.lib()
+    ls = afsat._LineSearch(1.0, 0.5, 1e-4, 4)
+    s = afsat.Instance._state_struct(st)
+    ws = d.workspace(B)
+    sws = d.search_workspace(B)
+    stream = afsat._stream(torch.device("cuda", 0))
+    rc = lib.afs_pgd_search_step(d._h, B, afsat._ptr(x), ctypes.byref(ls), None, 0, 0.0, afsat._ptr(ws), ws.numel(),
+                                 afsat._ptr(sws), sws.numel() - 1, ctypes.byref(s), None, stream)
+    assert rc == afsat.AFS_EINVAL and b"too small" in lib.afs_last_error()
+    rc = lib.afs_pgd_search_step(d._h, B, afsat._ptr(x), ctypes.byref(ls), None, 0, 0.0, afsat._ptr(ws), ws.numel(),
+                                 ctypes.c_void_p(sws.data_ptr() + 4), sws.numel() - 4, ctypes.byref(s), None, stream)
+    assert rc == afsat.AFS_EINVAL and b"aligned" in lib.afs_last_error()
+    torch.cuda.synchronize()
+    assert int(st["counter"][0]) == 0                    # nothing ran

@@ -146,6 +146,9 @@ void release(afs_instance *I)
         if (I->drive_in) (void)hipEventDestroy(I->drive_in);
         if (I->drive_out) (void)hipEventDestroy(I->drive_out);
         if (I->drive) (void)hipStreamDestroy(I->drive);
+        if (I->stepped) (void)hipEventDestroy(I->stepped);
+        if (I->verified) (void)hipEventDestroy(I->verified);
+        if (I->verify) (void)hipStreamDestroy(I->verify);
     }
     delete I;
 }
@@ -279,6 +282,9 @@ afs_status finish_create(afs_instance *I, int32_t device, afs_instance **out)
         if (e == hipSuccess) e = hipStreamCreateWithFlags(&I->drive, hipStreamNonBlocking);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&I->drive_in, hipEventDisableTiming);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&I->drive_out, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&I->verify, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&I->stepped, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&I->verified, hipEventDisableTiming);
         if (e != hipSuccess) st = dev_fail(e, "side streams");
     }
     if (st != AFS_OK) {
@@ -723,6 +729,33 @@ afs_status afs_init_points(afs_instance *I, int32_t B, uint64_t seed, const int8
     return e == hipSuccess ? AFS_OK : dev_fail(e, "start point launch");
 }
 
+// One constant-step iteration of the driver with the verification on the
+// instance's verify stream: FE of X_(t-1) on s; the step waits for the previous
+// iteration's verification (it rewrites the bits and counts that one reads, and
+// reads its done flags) unless this is the first iteration of a block; the
+// verification of X_(t) then runs beside the next iteration's FE kernels.  The
+// caller joins `verified` into s at the end of the block.  Arguments are
+// validated by afs_pgd.
+static afs_status overlapped_step(afs_instance *I, int32_t B, float *x, const afs_pgd_params *prm, void *ws,
+                                  const WsLayout &l, const afs_pgd_state *P, hipStream_t s, bool wait_prev)
+{
+    afs_status st = fe_grad_range(I, B, x, ws, l, 0, (int)I->H.buckets.size(), false, nullptr, s);
+    if (st != AFS_OK) return st;
+    hipError_t e = wait_prev ? hipStreamWaitEvent(s, I->verified, 0) : hipSuccess;
+    uint32_t *bits = at<uint32_t>(ws, l.bits);
+    if (e == hipSuccess)
+        e = afs::launch_scatter_step(I->D, B, l.Bp, at<float>(ws, l.adj), x, prm->lr, prm->fixed,
+                                     partial_rows(prm->n_partial), P->done, bits, P->unsat, s);
+    if (e == hipSuccess) e = hipEventRecord(I->stepped, s);
+    if (e == hipSuccess) e = hipStreamWaitEvent(I->verify, I->stepped, 0);
+    if (e == hipSuccess) e = afs::launch_verify(I->D, B, bits, at<uint32_t>(ws, l.viol), P->unsat, I->verify);
+    if (e == hipSuccess)
+        e = afs::launch_finalize(I->H.n_inst * B, B, P->unsat, P->done, P->first_sat, P->counter, afs::FIN_STEP,
+                                 I->verify, nullptr, prm->lr, prm->delta);
+    if (e == hipSuccess) e = hipEventRecord(I->verified, I->verify);
+    return e == hipSuccess ? AFS_OK : dev_fail(e, "PGD step launch");
+}
+
 afs_status afs_pgd(afs_instance *I, int32_t B, float *x, const afs_pgd_params *prm, void *ws, size_t ws_bytes,
                    const afs_pgd_state *P, float *obj, int32_t *iters, void *stream)
 {
@@ -761,13 +794,16 @@ afs_status afs_pgd(afs_instance *I, int32_t B, float *x, const afs_pgd_params *p
         if (e2 == hipSuccess) e2 = hipStreamSynchronize(s);
         return e2;
     };
-    // one iteration: constant step, or the backtracking line search
-    auto iterate = [&]() {
+    // one iteration: constant step (its verification overlapping the next
+    // iteration's FE), or the backtracking line search
+    auto iterate = [&](int32_t i) {
         if (prm->search)
             return search_call(I, B, x, prm->search, prm->fixed, prm->n_partial, prm->delta, ws, ws_bytes,
                                prm->search_ws, prm->search_ws_bytes, P, nullptr, s);
-        return pgd_call(I, B, x, prm->lr, prm->fixed, prm->n_partial, prm->delta, ws, ws_bytes, P, s, true);
+        return overlapped_step(I, B, x, prm, ws, l, P, s, i > 0);
     };
+    // end of a block of iterations: s continues after the last verification
+    auto join = [&]() { return prm->search ? hipSuccess : hipStreamWaitEvent(s, I->verified, 0); };
 
     if ((st = afs_pgd_init(I, B, x, ws, ws_bytes, P, s)) != AFS_OK) return finish(st);
     int32_t counter[4] = {0, 0, 0, 0};
@@ -785,7 +821,8 @@ afs_status afs_pgd(afs_instance *I, int32_t B, float *x, const afs_pgd_params *p
                 if ((e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal)) != hipSuccess)
                     return finish(dev_fail(e, "hipStreamBeginCapture"));
                 afs_status cs = AFS_OK;
-                for (int32_t i = 0; i < n && cs == AFS_OK; ++i) cs = iterate();
+                for (int32_t i = 0; i < n && cs == AFS_OK; ++i) cs = iterate(i);
+                if (cs == AFS_OK && (e = join()) != hipSuccess) cs = dev_fail(e, "joining the verify stream");
                 const hipError_t ec = hipStreamEndCapture(s, &graph);
                 if (cs != AFS_OK) return finish(cs);
                 if (ec != hipSuccess) return finish(dev_fail(ec, "hipStreamEndCapture"));
@@ -795,7 +832,8 @@ afs_status afs_pgd(afs_instance *I, int32_t B, float *x, const afs_pgd_params *p
             if ((e = hipGraphLaunch(exec, s)) != hipSuccess) return finish(dev_fail(e, "hipGraphLaunch"));
         } else {
             for (int32_t i = 0; i < n; ++i)
-                if ((st = iterate()) != AFS_OK) return finish(st);
+                if ((st = iterate(i)) != AFS_OK) return finish(st);
+            if ((e = join()) != hipSuccess) return finish(dev_fail(e, "joining the verify stream"));
         }
         t += n;
     }

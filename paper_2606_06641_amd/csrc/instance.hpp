@@ -48,4 +48,9 @@ struct afs_instance {
     hipStream_t drive = nullptr;
     hipEvent_t drive_in = nullptr, drive_out = nullptr;
     std::mutex drive_mu;
+    // The driver verifies iteration t on its own stream while iteration t+1's FE
+    // kernels run (they touch neither the bits nor the counts); `stepped` orders
+    // the verification after the step, `verified` the next step after it.
+    hipStream_t verify = nullptr;
+    hipEvent_t stepped = nullptr, verified = nullptr;
 };

@@ -122,6 +122,17 @@ def test_graph_replay_equals_eager(kind):
     assert torch.equal(xa, xb)
     for k in ("unsat", "done", "first_sat", "counter", "obj"):
         assert torch.equal(ra[k], rb[k]), k
+    # the driver (whose verification overlaps the next iteration's FE on a stream
+    # of its own) equals 40 plain afs_pgd_step calls on one stream
+    xs = parity.to_dev(x0)
+    ss = d.pgd_state(B)
+    d.pgd_init(xs, ss)
+    for _ in range(40):
+        d.pgd_step(xs, ss, 0.1)
+    torch.cuda.synchronize()
+    assert torch.equal(xa, xs)
+    for k in ("unsat", "done", "first_sat", "counter"):
+        assert torch.equal(ra[k], ss[k]), k
     # caller-side capture of afs_pgd_step
     ws_c, ws_e = d.workspace(B), d.workspace(B)
     xc, xe = parity.to_dev(x0), parity.to_dev(x0)

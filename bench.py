@@ -26,6 +26,7 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0          # MI355X HBM3E, GB/s
 PEAK_FP32_TFLOPS = 157.3       # MI355X FP32 vector, TFLOP/s
+PEAK_BF16_TFLOPS = 2500.0      # MI355X dense BF16 MFMA, TFLOP/s
 
 
 def algorithmic_flops(k):
@@ -83,16 +84,50 @@ def cpu_baseline(inst, x0, lr, budget_s=12.0, threads=0, restarts=0):
                       "verify) in FP64, %.1f s" % ("the first" if restarts else "all", B, reps, t_used)}
 
 
+def gemm_probe(rows, reps=20):
+    """The learned-initialisation network's dense-layer kernel (BF16 MFMA, FP32
+    accumulation) at its layer shape [rows x 64] . [64 x 64]: 2*rows*64*64 flops
+    against rows*64*4 bytes read and rows*64*4 written (16 flops per byte, so
+    HBM-bound on MI355X).  Prints one JSON line with the kernel's mean time from
+    HIP events on its stream."""
+    import torch
+    from paper_2606_06641_amd import gnn
+    dev = torch.device("cuda", 0)
+    g = torch.Generator(device=dev).manual_seed(0)
+    A = torch.rand((rows, 64), device=dev, generator=g) - 0.5
+    W = torch.rand((64, 64), device=dev, generator=g) - 0.5
+    for _ in range(3):
+        gnn.gemm_bf16(A, W)
+    stream = torch.cuda.current_stream(dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        gnn.gemm_bf16(A, W)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    flops = 2.0 * rows * 64 * 64
+    bytes_ = rows * 64 * 4 * 2.0 + 64 * 64 * 4
+    print(json.dumps({"gemm_probe_rows": rows, "ms_per_launch": ms, "TFLOP/s": flops / ms / 1e9,
+                      "GB/s": bytes_ / ms / 1e6, "hbm_frac": bytes_ / ms / 1e6 / PEAK_HBM_GBS,
+                      "mfma_frac": flops / ms / 1e9 / PEAK_BF16_TFLOPS}), flush=True)
+
+
 def copy_probe(mib):
     """A plain device-to-device copy of known size (reads and writes mib MiB each)."""
     import torch
     n = mib * (1 << 20) // 4
     a = torch.ones(n, dtype=torch.float32, device="cuda:0")
     b = torch.empty_like(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
     for _ in range(5):
         b.copy_(a)
+    e1.record()
     torch.cuda.synchronize()
-    print(json.dumps({"copy_probe_bytes": n * 4, "launches": 5}), flush=True)
+    ms = e0.elapsed_time(e1) / 5
+    print(json.dumps({"copy_probe_bytes": n * 4, "launches": 5, "ms_per_launch": ms,
+                      "GB/s (read + write)": 2 * n * 4 / ms / 1e6}), flush=True)
 
 
 def build_workload(name, W):
@@ -131,9 +166,14 @@ def main():
     ap.add_argument("--search", type=int, default=0,
                     help="mixed10k only: time Algorithm 1 iterations with the backtracking line search "
                          "of this many trials instead of the constant-step hot path")
+    ap.add_argument("--gemm-probe", type=int, default=0,
+                    help="only time the learned-initialisation network's dense-layer kernel on this many rows")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device copy of this size (to calibrate byte counters)")
     args = ap.parse_args()
+    if args.gemm_probe:
+        gemm_probe(args.gemm_probe)
+        return
     if args.copy_probe_mib:
         copy_probe(args.copy_probe_mib)
         return

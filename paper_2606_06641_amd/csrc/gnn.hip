@@ -74,6 +74,7 @@ struct GemmArgs {
     const float *bias;
     int relu, accumulate;
     int M, N, K, kchunk;
+    int rtw;                     // layer-shape path: row tiles per wave
 };
 
 __global__ __launch_bounds__(kBlock) void gemm_bf16_kernel(GemmArgs g)
@@ -117,6 +118,128 @@ __global__ __launch_bounds__(kBlock) void gemm_bf16_kernel(GemmArgs g)
             if (g.relu) v = fmaxf(v, 0.f);
             *dst = v;
         }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// The same product for the network's layer shapes (N = 64 output columns,
+// K = 16 * KSTEPS <= 128, A rows contiguous in k, one k chunk): B is rounded to
+// BF16 once per block and kept in LDS (transposed, so that a lane's four k
+// values are one 8-byte read), and each wave produces whole 16 x 64 slabs --
+// four MFMA tiles sharing one A fragment -- for rtw consecutive row tiles,
+// so A is read once with 16-byte loads, the next row tile's loads in flight
+// while the current one is multiplied and stored.  Every output tile sees the same MFMA
+// sequence as in gemm_bf16_kernel (k steps in ascending order), so the results
+// are identical.
+// ---------------------------------------------------------------------------
+constexpr int kMaxRowTiles = 16;
+constexpr int kBtPad = 8;            // shorts of padding per LDS row (bank spread)
+
+template <int KSTEPS>
+__device__ __forceinline__ void load_row_tile(const GemmArgs &g, int64_t tm, int lane, bool vec, float (&av)[KSTEPS][4])
+{
+    const int arow = (int)(tm * 16) + (lane & 15);
+    const int kq = (lane >> 4) * 4;
+#pragma unroll
+    for (int s = 0; s < KSTEPS; ++s) {
+        const int k = s * 16 + kq;
+        const float *src = k < g.ksplit ? g.a1 + (int64_t)arow * g.sam + k
+                                        : g.a2 + (int64_t)arow * g.sam + (k - g.ksplit);
+        if (tm * 16 >= g.M || arow >= g.M) {
+            av[s][0] = av[s][1] = av[s][2] = av[s][3] = 0.f;
+        } else if (vec) {                            // read once: do not keep it in the caches
+            const float4v v = __builtin_nontemporal_load(reinterpret_cast<const float4v *>(src));
+            av[s][0] = v[0]; av[s][1] = v[1]; av[s][2] = v[2]; av[s][3] = v[3];
+        } else {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) av[s][i] = src[i];
+        }
+    }
+}
+
+template <int KSTEPS>
+__global__ __launch_bounds__(kBlock) void gemm_rows64_kernel(GemmArgs g)
+{
+    constexpr int K = 16 * KSTEPS;
+    constexpr int LD = K + kBtPad;
+    __shared__ short bt[H * LD];                      // bt[n][k] = bf16(B(k, n))
+    __shared__ float cs[kBlock / 64][16][H + 4];      // one 16 x 64 result slab per wave
+    for (int t = threadIdx.x; t < K * H; t += kBlock) {
+        const int k = t / H, n = t % H;
+        bt[n * LD + k] = to_bf16(g.b[k * g.sbk + n * g.sbn]);
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int kq = (lane >> 4) * 4;
+    const bool vec = (g.sam % 4 == 0) && ((reinterpret_cast<uintptr_t>(g.a1) | reinterpret_cast<uintptr_t>(g.a2)) % 16 == 0);
+    const bool vec_out = g.ldc % 4 == 0 && reinterpret_cast<uintptr_t>(g.c) % 16 == 0;
+    const int c4 = (lane & 15) * 4;
+    float4 bias4 = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (g.bias) bias4 = make_float4(g.bias[c4], g.bias[c4 + 1], g.bias[c4 + 2], g.bias[c4 + 3]);
+    const int64_t tm0 = ((int64_t)blockIdx.x * (kBlock / 64) + wave) * g.rtw;
+    float av[KSTEPS][4], an[KSTEPS][4];
+    load_row_tile<KSTEPS>(g, tm0, lane, vec, av);
+    for (int rt = 0; rt < g.rtw; ++rt) {
+        const int64_t tm = tm0 + rt;
+        if (tm * 16 >= g.M) break;                    // wave-uniform
+        // the next row tile's loads are in flight while this one is multiplied and stored
+        if (rt + 1 < g.rtw) load_row_tile<KSTEPS>(g, tm + 1, lane, vec, an);
+        float4v acc[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc[t] = float4v{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int s = 0; s < KSTEPS; ++s) {
+            short4v a;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) a[i] = to_bf16(av[s][i]);
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const short4v b = *reinterpret_cast<const short4v *>(&bt[(t * 16 + (lane & 15)) * LD + s * 16 + kq]);
+                acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[t], 0, 0, 0);
+            }
+        }
+        // through LDS, so that lane l writes columns 4(l%16)..+3 of rows 4q + l/16:
+        // each store instruction then covers four whole 256-byte rows
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) cs[wave][(lane >> 4) * 4 + i][t * 16 + (lane & 15)] = acc[t][i];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int r = q * 4 + (lane >> 4);
+            const int64_t orow = tm * 16 + r;
+            if (orow < g.M) {
+                float *dst = g.c + orow * g.ldc + c4;
+                // the general kernel's epilogue: accumulate, bias, relu, in that order
+                float w[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    w[e] = cs[wave][r][c4 + e];
+                    if (g.accumulate) w[e] += dst[e];
+                }
+                if (g.bias) { w[0] += bias4.x; w[1] += bias4.y; w[2] += bias4.z; w[3] += bias4.w; }
+                if (g.relu)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) w[e] = fmaxf(w[e], 0.f);
+                if (vec_out) {                                  // written once, read by a later kernel
+                    __builtin_nontemporal_store(float4v{w[0], w[1], w[2], w[3]}, reinterpret_cast<float4v *>(dst));
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) dst[e] = w[e];
+                }
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");   // the slab is rewritten next
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+        for (int s = 0; s < KSTEPS; ++s)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) av[s][i] = an[s][i];
     }
 }
 
@@ -513,6 +636,27 @@ hipError_t gemm(const float *a1, const float *a2, int ksplit, int64_t sam, int64
     g.b = b; g.sbk = sbk; g.sbn = sbn; g.c = c; g.ldc = ldc; g.split_stride = 0;
     g.bias = bias; g.relu = relu; g.accumulate = acc; g.M = M; g.N = N; g.K = K;
     g.kchunk = (K + 15) / 16 * 16;
+    // the layer shapes: 64 output columns, K a multiple of 16 up to 128, A rows
+    // contiguous in k, the two A halves split on a 16 boundary
+    if (N == H && K > 0 && K % 16 == 0 && K <= 128 && sak == 1 && g.ksplit % 16 == 0) {
+        // a few row tiles per wave on large inputs (B staged once per more rows,
+        // loads overlapped), one on small ones (enough waves to fill the device)
+        const int64_t row_tiles = (M + 15) / 16;
+        g.rtw = (int)std::min<int64_t>(kMaxRowTiles, std::max<int64_t>(1, row_tiles / (4 * 2048)));
+        const int64_t per_block = (int64_t)(kBlock / 64) * g.rtw;
+        const unsigned blocks = (unsigned)((row_tiles + per_block - 1) / per_block);
+        switch (K / 16) {
+        case 1: hipLaunchKernelGGL(gemm_rows64_kernel<1>, dim3(blocks), dim3(kBlock), 0, s, g); break;
+        case 2: hipLaunchKernelGGL(gemm_rows64_kernel<2>, dim3(blocks), dim3(kBlock), 0, s, g); break;
+        case 3: hipLaunchKernelGGL(gemm_rows64_kernel<3>, dim3(blocks), dim3(kBlock), 0, s, g); break;
+        case 4: hipLaunchKernelGGL(gemm_rows64_kernel<4>, dim3(blocks), dim3(kBlock), 0, s, g); break;
+        case 5: hipLaunchKernelGGL(gemm_rows64_kernel<5>, dim3(blocks), dim3(kBlock), 0, s, g); break;
+        case 6: hipLaunchKernelGGL(gemm_rows64_kernel<6>, dim3(blocks), dim3(kBlock), 0, s, g); break;
+        case 7: hipLaunchKernelGGL(gemm_rows64_kernel<7>, dim3(blocks), dim3(kBlock), 0, s, g); break;
+        default: hipLaunchKernelGGL(gemm_rows64_kernel<8>, dim3(blocks), dim3(kBlock), 0, s, g); break;
+        }
+        return hipGetLastError();
+    }
     const int64_t tiles = (int64_t)((M + 15) / 16) * ((N + 15) / 16);
     hipLaunchKernelGGL(gemm_bf16_kernel, dim3((unsigned)((tiles + 3) / 4), 1), dim3(kBlock), 0, s, g);
     return hipGetLastError();

@@ -26,13 +26,23 @@ def log(*a):
     print(*a, flush=True)
 
 
-@pytest.mark.parametrize("M,N,K,transA,transB", [(37, 70, 50, False, False), (128, 64, 2000, True, False),
-                                                  (16, 16, 16, False, True), (200, 128, 64, False, True)])
-def test_gemm_bf16(M, N, K, transA, transB):
+# the first four take the general tile kernel; the rest the layer-shape path
+# (64 output columns, K = 16..128 in steps of 16, rows contiguous in k), with
+# ragged row counts, transposed B, and A rows that are not 16-byte aligned
+@pytest.mark.parametrize("M,N,K,transA,transB,offset", [
+    (37, 70, 50, False, False, 0), (128, 64, 2000, True, False, 0), (16, 16, 16, False, True, 0),
+    (200, 128, 64, False, True, 0),
+    (1000, 64, 16, False, False, 0), (4100, 64, 64, False, False, 0), (37, 64, 128, False, True, 0),
+    (333, 64, 48, False, False, 1), (65, 64, 112, False, False, 0)])
+def test_gemm_bf16(M, N, K, transA, transB, offset):
     rng = np.random.default_rng(M + N + K)
     A = rng.normal(size=(M, K)).astype(np.float32)
     Bm = rng.normal(size=(K, N)).astype(np.float32)
-    At = torch.from_numpy(np.ascontiguousarray(A.T)).cuda().t() if transA else torch.from_numpy(A).cuda()
+    if offset:
+        # rows start one float past a 16-byte boundary: the scalar-load branch
+        At = torch.from_numpy(np.concatenate([np.zeros(offset, np.float32), A.ravel()])).cuda()[offset:].view(M, K)
+    else:
+        At = torch.from_numpy(np.ascontiguousarray(A.T)).cuda().t() if transA else torch.from_numpy(A).cuda()
     Bt = torch.from_numpy(np.ascontiguousarray(Bm.T)).cuda().t() if transB else torch.from_numpy(Bm).cuda()
     C = gnn.gemm_bf16(At, Bt).cpu().numpy()
     want = G.bf16(A) @ G.bf16(Bm)

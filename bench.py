@@ -243,15 +243,15 @@ def main():
         if ev is None:
             d.fe_grad(x, ws, 0, nb)
         else:
-            # the dominant bucket first, between the events; then the other buckets
-            # (the short ones overlap the long ones on the library's second stream)
+            # the dominant bucket first, alone between the events (its duration is
+            # the kernel's own); then every other bucket in one call, where the
+            # library runs the short ones beside the long ones and the long ones
+            # two at a time
             ev[0].record(stream)
             d.fe_grad(x, ws, dom, dom + 1)
             ev[1].record(stream)
-            if dom > 0:
-                d.fe_grad(x, ws, 0, dom)
-            if dom + 1 < nb:
-                d.fe_grad(x, ws, dom + 1, nb)
+            if rest:
+                d.fe_grad_buckets(x, ws, rest)
         d.pgd_update(x, st, args.lr, None, ws)
 
     # per-bucket timing (outside the timed region) to find the dominant kernel
@@ -270,6 +270,7 @@ def main():
         per_bucket.append(e0.elapsed_time(e1) / 3)
     dom = int(np.argmax(per_bucket))
     bk = buckets[dom]
+    rest = [i for i in range(nb) if i != dom]
     print("per-bucket FE+grad ms:", ", ".join("[%d-%d J%d S%d] %.3f" % (b.k_lo, b.k_hi, b.lanes_per_restart,
           b.lits_per_lane, t) for b, t in zip(buckets, per_bucket)), file=sys.stderr, flush=True)
 

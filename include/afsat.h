@@ -213,6 +213,15 @@ afs_status afs_fe_grad(afs_instance *inst, int32_t B, const float *x, void *ws, 
 afs_status afs_scatter(afs_instance *inst, int32_t B, void *ws, size_t ws_bytes,
                        float *obj, float *grad, void *stream);
 
+/* afs_fe_grad over an explicit set of buckets: buckets host int32 [n_buckets],
+ * distinct indices in any order (AFS_EINVAL otherwise).  As for a range, short
+ * buckets run on a second stream beside the long ones, and the long ones are
+ * split between the caller's stream and a third, so one call over many buckets
+ * keeps more of the device busy than a call per bucket. */
+afs_status afs_fe_grad_buckets(afs_instance *inst, int32_t B, const float *x, void *ws, size_t ws_bytes,
+                               const int32_t *buckets, int32_t n_buckets, int32_t want_obj, float *fe,
+                               void *stream);
+
 /* ---- differentiation (the objective as a differentiable function of x) ---------- */
 
 /* Forward: obj[b] = sum_c w_c FE_c(x_b) and optionally fe [C][B], with no adjoint

@@ -94,6 +94,7 @@ SIGNATURES = [
     ("afs_eval", ctypes.c_int, [_vp, _i32, _vp, _vp, ctypes.c_size_t, _vp, _vp, _vp, _vp, _vp]),
     ("afs_fe_grad", ctypes.c_int, [_vp, _i32, _vp, _vp, ctypes.c_size_t, _i32, _i32, _i32, _vp, _vp]),
     ("afs_scatter", ctypes.c_int, [_vp, _i32, _vp, ctypes.c_size_t, _vp, _vp, _vp]),
+    ("afs_fe_grad_buckets", ctypes.c_int, [_vp, _i32, _vp, _vp, ctypes.c_size_t, _i32p, _i32, _i32, _vp, _vp]),
     ("afs_eval_fwd", ctypes.c_int, [_vp, _i32, _vp, _vp, ctypes.c_size_t, _vp, _vp, _vp]),
     ("afs_eval_adjoint", ctypes.c_int, [_vp, _i32, _vp, _vp, _vp, ctypes.c_size_t, _vp, _vp]),
     ("afs_step", ctypes.c_int, [_vp, _i32, _vp, _vp, ctypes.c_float, _vp, _i32, _vp, _vp]),
@@ -366,6 +367,13 @@ class Instance:
         hi = self.n_buckets if bucket_hi is None else bucket_hi
         _check(lib().afs_fe_grad(self._h, B, _ptr(x), _ptr(ws), ws.numel(), int(bucket_lo), int(hi),
                                  int(bool(want_obj)), _ptr(fe), _stream(self._dev())))
+
+    def fe_grad_buckets(self, x, ws, buckets, want_obj=False, fe=None):
+        """afs_fe_grad over the listed bucket indices in one call."""
+        B = self._check_x(x)
+        idx = np.ascontiguousarray(buckets, dtype=np.int32)
+        _check(lib().afs_fe_grad_buckets(self._h, B, _ptr(x), _ptr(ws), ws.numel(), _np_ptr(idx, _i32p), len(idx),
+                                         int(bool(want_obj)), _ptr(fe), _stream(self._dev())))
 
     def scatter(self, B, ws, obj=None, grad=None):
         _check(lib().afs_scatter(self._h, int(B), _ptr(ws), ws.numel(), _ptr(obj), _ptr(grad),

@@ -143,6 +143,8 @@ void release(afs_instance *I)
         if (I->fork) (void)hipEventDestroy(I->fork);
         if (I->join) (void)hipEventDestroy(I->join);
         if (I->side) (void)hipStreamDestroy(I->side);
+        if (I->join2) (void)hipEventDestroy(I->join2);
+        if (I->side2) (void)hipStreamDestroy(I->side2);
         if (I->drive_in) (void)hipEventDestroy(I->drive_in);
         if (I->drive_out) (void)hipEventDestroy(I->drive_out);
         if (I->drive) (void)hipStreamDestroy(I->drive);
@@ -175,35 +177,77 @@ afs_status check_ws(const afs_instance *I, int32_t B, const void *ws, size_t ws_
 template <class T>
 T *at(void *ws, size_t off) { return reinterpret_cast<T *>(static_cast<char *>(ws) + off); }
 
+afs_status fe_grad_set(afs_instance *I, int B, const float *x, void *ws, const WsLayout &l,
+                       const std::vector<int> &set, bool want_part, float *fe, hipStream_t s,
+                       const float *dobj = nullptr, bool grad = true, const uint8_t *skip = nullptr);
+
 afs_status fe_grad_range(afs_instance *I, int B, const float *x, void *ws, const WsLayout &l,
                          int lo, int hi, bool want_part, float *fe, hipStream_t s,
                          const float *dobj = nullptr, bool grad = true, const uint8_t *skip = nullptr)
 {
+    std::vector<int> set;
+    for (int bi = lo; bi < hi; ++bi) set.push_back(bi);
+    return fe_grad_set(I, B, x, ws, l, set, want_part, fe, s, dobj, grad, skip);
+}
+
+afs_status fe_grad_set(afs_instance *I, int B, const float *x, void *ws, const WsLayout &l,
+                       const std::vector<int> &set, bool want_part, float *fe, hipStream_t s,
+                       const float *dobj, bool grad, const uint8_t *skip)
+{
     // Short buckets (one lane per restart, bound by memory traffic) go to the side
     // stream when long buckets (bound by arithmetic) share the range, so the two
-    // kinds overlap.  They write disjoint adjoint rows and objective tiles.
-    bool has_short = false, has_long = false;
-    for (int bi = lo; bi < hi; ++bi) (I->H.buckets[bi].J == 1 ? has_short : has_long) = true;
-    const bool split = has_short && has_long && I->side;
+    // kinds overlap.  Long buckets hold few constraints each and rarely fill the
+    // device alone, so they are dealt to two streams (the caller's and side2),
+    // largest first to whichever has less estimated work (flops ~ literals x
+    // length).  Every bucket writes its own adjoint rows and objective tiles.
+    std::vector<int> shorts, longs;
+    for (int bi : set) (I->H.buckets[bi].J == 1 ? shorts : longs).push_back(bi);
+    const bool split_short = !shorts.empty() && !longs.empty() && I->side;
+    const bool split_long = longs.size() >= 2 && I->side2;
+    std::vector<hipStream_t> stream_of(I->H.buckets.size(), s);
+    if (split_short)
+        for (int bi : shorts) stream_of[bi] = I->side;
+    auto cost = [&](int bi) {
+        const afs::Bucket &b = I->H.buckets[bi];
+        return (double)b.nslots * (double)(b.k_lo + b.k_hi);
+    };
+    std::sort(longs.begin(), longs.end(), [&](int a, int b) { return cost(a) > cost(b); });
+    if (split_long) {
+        double load[2] = {0.0, 0.0};
+        for (int bi : longs) {
+            const int t = load[1] < load[0] ? 1 : 0;
+            load[t] += cost(bi);
+            stream_of[bi] = t ? I->side2 : s;
+        }
+    }
     std::unique_lock<std::mutex> lock(I->side_mu, std::defer_lock);
-    if (split) {
+    if (split_short || split_long) {
         lock.lock();
         hipError_t e = hipEventRecord(I->fork, s);
-        if (e == hipSuccess) e = hipStreamWaitEvent(I->side, I->fork, 0);
-        if (e != hipSuccess) return dev_fail(e, "fork to the side stream");
+        if (e == hipSuccess && split_short) e = hipStreamWaitEvent(I->side, I->fork, 0);
+        if (e == hipSuccess && split_long) e = hipStreamWaitEvent(I->side2, I->fork, 0);
+        if (e != hipSuccess) return dev_fail(e, "fork to the side streams");
     }
-    for (int bi = lo; bi < hi; ++bi) {
+    // long buckets largest first, then the short ones (on their own stream)
+    std::vector<int> order(longs);
+    order.insert(order.end(), shorts.begin(), shorts.end());
+    for (int bi : order) {
         const afs::Bucket &b = I->H.buckets[bi];
         afs::BucketLaunch bl{b.J, b.S, b.c0, b.nc, b.tile, b.ntiles, b.tile0};
         hipError_t e = afs::launch_fe_grad(I->D, bl, B, l.Bp, x, at<float>(ws, l.adj),
                                            want_part ? at<float>(ws, l.part) : nullptr, fe, dobj,
-                                           grad, split && b.J == 1 ? I->side : s, skip);
+                                           grad, stream_of[bi], skip);
         if (e != hipSuccess) return dev_fail(e, "fe_grad launch");
     }
-    if (split) {
+    if (split_short) {
         hipError_t e = hipEventRecord(I->join, I->side);
         if (e == hipSuccess) e = hipStreamWaitEvent(s, I->join, 0);
         if (e != hipSuccess) return dev_fail(e, "join from the side stream");
+    }
+    if (split_long) {
+        hipError_t e = hipEventRecord(I->join2, I->side2);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s, I->join2, 0);
+        if (e != hipSuccess) return dev_fail(e, "join from the second stream");
     }
     return AFS_OK;
 }
@@ -279,6 +323,8 @@ afs_status finish_create(afs_instance *I, int32_t device, afs_instance **out)
         hipError_t e = hipStreamCreateWithFlags(&I->side, hipStreamNonBlocking);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&I->fork, hipEventDisableTiming);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&I->join, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&I->side2, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&I->join2, hipEventDisableTiming);
         if (e == hipSuccess) e = hipStreamCreateWithFlags(&I->drive, hipStreamNonBlocking);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&I->drive_in, hipEventDisableTiming);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&I->drive_out, hipEventDisableTiming);
@@ -461,6 +507,30 @@ afs_status afs_fe_grad(afs_instance *I, int32_t B, const float *x, void *ws, siz
     DeviceGuard g(I->device);
     if (g.error() != hipSuccess) return dev_fail(g.error(), "hipSetDevice");
     return fe_grad_range(I, B, x, ws, l, bucket_lo, bucket_hi, want_obj != 0, fe, (hipStream_t)stream);
+}
+
+afs_status afs_fe_grad_buckets(afs_instance *I, int32_t B, const float *x, void *ws, size_t ws_bytes,
+                               const int32_t *buckets, int32_t n_buckets, int32_t want_obj, float *fe,
+                               void *stream)
+{
+    afs_status st = check_call(I, B);
+    if (st != AFS_OK) return st;
+    WsLayout l;
+    if ((st = check_ws(I, B, ws, ws_bytes, l)) != AFS_OK) return st;
+    if (n_buckets < 0 || (n_buckets > 0 && !buckets)) return fail(AFS_EINVAL, "bucket list is NULL");
+    const int nb = (int)I->H.buckets.size();
+    std::vector<int> set;
+    std::vector<char> seen(nb, 0);
+    for (int32_t i = 0; i < n_buckets; ++i) {
+        if (buckets[i] < 0 || buckets[i] >= nb) return fail(AFS_EINVAL, "bucket index out of range");
+        if (seen[buckets[i]]) return fail(AFS_EINVAL, "bucket listed twice");
+        seen[buckets[i]] = 1;
+        set.push_back(buckets[i]);
+    }
+    if (!x && B > 0) return fail(AFS_EINVAL, "x is NULL");
+    DeviceGuard g(I->device);
+    if (g.error() != hipSuccess) return dev_fail(g.error(), "hipSetDevice");
+    return fe_grad_set(I, B, x, ws, l, set, want_obj != 0, fe, (hipStream_t)stream);
 }
 
 afs_status afs_scatter(afs_instance *I, int32_t B, void *ws, size_t ws_bytes, float *obj,

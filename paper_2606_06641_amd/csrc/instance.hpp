@@ -42,6 +42,11 @@ struct afs_instance {
     // record / wait pairs together when several host threads use the instance.
     hipStream_t side = nullptr;
     hipEvent_t fork = nullptr, join = nullptr;
+    // Long buckets are few constraints each, so one of them rarely fills the
+    // device; they are split between the caller's stream and `side2` (joined
+    // back through `join2`) so that two run at a time.
+    hipStream_t side2 = nullptr;
+    hipEvent_t join2 = nullptr;
     std::mutex side_mu;
     // Private stream of the Algorithm 1 driver (afs_pgd), which captures its
     // iterations in a graph there; events order it against the caller's stream.

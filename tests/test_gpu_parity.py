@@ -452,3 +452,32 @@ def test_batch_of_uneven_instances():
         assert np.all(up[done[p]] == 0)
     assert done.sum() == int(res["counter"][1])
     assert done[0].any() or done[2].any() or done[4].any()     # small planted parts get solved
+
+
+def test_bucket_set_call_equals_the_range_call():
+    """afs_fe_grad_buckets over every bucket, listed in a shuffled order, writes
+    the same adjoints and objective partials bit for bit as afs_fe_grad over the
+    range (the long buckets then run two at a time on two streams, the short
+    ones beside them); duplicates and bad indices are rejected."""
+    rng = np.random.default_rng(44)
+    inst = concat([W.random_instance(rng, n=500, count=900, k_lo=1, k_hi=12),
+                   W.random_instance(rng, n=500, count=40, k_lo=17, k_hi=300)], n=500)
+    d = afsat.Instance.from_arrays(inst)
+    B = 96
+    x = parity.to_dev(rng.uniform(-1, 1, size=(inst.n, B)))
+    ws_a, ws_b = d.workspace(B), d.workspace(B).clone()
+    d.fe_grad(x, ws_a, 0, d.n_buckets, want_obj=True)
+    order = rng.permutation(d.n_buckets)
+    d.fe_grad_buckets(x, ws_b, order, want_obj=True)
+    ga = torch.empty((inst.n, B), device="cuda")
+    gb = torch.empty_like(ga)
+    oa = torch.empty(B, device="cuda")
+    ob = torch.empty_like(oa)
+    d.scatter(B, ws_a, obj=oa, grad=ga)
+    d.scatter(B, ws_b, obj=ob, grad=gb)
+    torch.cuda.synchronize()
+    assert torch.equal(ga, gb) and torch.equal(oa, ob)
+    log("buckets: %d (%d long)" % (d.n_buckets, sum(1 for b in d.buckets() if b.lanes_per_restart > 1)))
+    for bad in ([0, 0], [d.n_buckets], [-1]):
+        with pytest.raises(afsat.AfsError):
+            d.fe_grad_buckets(x, ws_b, bad)

@@ -254,11 +254,14 @@ def main():
                 d.fe_grad_buckets(x, ws, rest)
         d.pgd_update(x, st, args.lr, None, ws)
 
-    # per-bucket timing (outside the timed region) to find the dominant kernel
-    for _ in range(max(1, args.warmup)):
-        step()
-    torch.cuda.synchronize()
+    # per-bucket timing (outside the timed region) to find the dominant kernel;
+    # each bucket is launched alone once first (code loading), and the warm-up
+    # steps come after, in the timed steps' layout, so that every launch of the
+    # dominant kernel in the run is a solo one (as in a profile of the run)
     xd = x.detach()
+    for i in range(nb):
+        d.fe_grad(xd, ws, i, i + 1)
+    torch.cuda.synchronize()
     per_bucket = []
     for i in range(nb):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -273,6 +276,11 @@ def main():
     rest = [i for i in range(nb) if i != dom]
     print("per-bucket FE+grad ms:", ", ".join("[%d-%d J%d S%d] %.3f" % (b.k_lo, b.k_hi, b.lanes_per_restart,
           b.lits_per_lane, t) for b, t in zip(buckets, per_bucket)), file=sys.stderr, flush=True)
+    warm = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+            for _ in range(max(1, args.warmup))]
+    for ev in warm:
+        step(ev, dom)
+    torch.cuda.synchronize()
 
     # timed region: exactly K steps, events around the dominant kernel's launch
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))

@@ -19,6 +19,7 @@ import hashlib
 import json
 import os
 import sys
+import tempfile
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -158,6 +159,8 @@ def main():
     ap.add_argument("--restarts", type=int, default=0, help="override the workload's restart count")
     ap.add_argument("--lr", type=float, default=0.1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tune-out", default=None,
+                    help="file receiving the shape cache with any newly tuned ranges (default: the temp directory)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="use the default kernel shapes instead of the tuned ones")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -204,8 +207,8 @@ def main():
     shapes = []
     if not args.no_autotune:
         from paper_2606_06641_amd import autotune
-        out = os.path.join(ROOT, "gpurun_out", "tuned_shapes.txt")
-        os.makedirs(os.path.dirname(out), exist_ok=True)
+        out = args.tune_out or os.path.join(tempfile.gettempdir(), "afsat_tuned_shapes.txt")
+        os.makedirs(os.path.dirname(os.path.abspath(out)), exist_ok=True)
         shapes, _ = autotune.tune(inst, B, cache_path=autotune.DEFAULT_CACHE, out_path=out,
                                   log=lambda m: print(m, file=sys.stderr, flush=True), max_cons=400)
     if parts is not None:

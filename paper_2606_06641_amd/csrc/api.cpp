@@ -325,12 +325,6 @@ afs_status finish_create(afs_instance *I, int32_t device, afs_instance **out)
         if (e == hipSuccess) e = hipEventCreateWithFlags(&I->join, hipEventDisableTiming);
         if (e == hipSuccess) e = hipStreamCreateWithFlags(&I->side2, hipStreamNonBlocking);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&I->join2, hipEventDisableTiming);
-        if (e == hipSuccess) e = hipStreamCreateWithFlags(&I->drive, hipStreamNonBlocking);
-        if (e == hipSuccess) e = hipEventCreateWithFlags(&I->drive_in, hipEventDisableTiming);
-        if (e == hipSuccess) e = hipEventCreateWithFlags(&I->drive_out, hipEventDisableTiming);
-        if (e == hipSuccess) e = hipStreamCreateWithFlags(&I->verify, hipStreamNonBlocking);
-        if (e == hipSuccess) e = hipEventCreateWithFlags(&I->stepped, hipEventDisableTiming);
-        if (e == hipSuccess) e = hipEventCreateWithFlags(&I->verified, hipEventDisableTiming);
         if (e != hipSuccess) st = dev_fail(e, "side streams");
     }
     if (st != AFS_OK) {
@@ -843,8 +837,31 @@ afs_status afs_pgd(afs_instance *I, int32_t B, float *x, const afs_pgd_params *p
     DeviceGuard g(I->device);
     if (g.error() != hipSuccess) return dev_fail(g.error(), "hipSetDevice");
     std::lock_guard<std::mutex> lock(I->drive_mu);
+    // the driver's streams are made on its first use, so that instances that never
+    // run it hold fewer streams than the device has hardware queues
+    hipError_t e = hipSuccess;
+    if (!I->drive) {
+        hipStream_t dr = nullptr, vf = nullptr;
+        hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+        e = hipStreamCreateWithFlags(&dr, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&vf, hipStreamNonBlocking);
+        for (int i = 0; i < 4 && e == hipSuccess; ++i) e = hipEventCreateWithFlags(&ev[i], hipEventDisableTiming);
+        if (e != hipSuccess) {
+            for (hipEvent_t x : ev)
+                if (x) (void)hipEventDestroy(x);
+            if (vf) (void)hipStreamDestroy(vf);
+            if (dr) (void)hipStreamDestroy(dr);
+            return dev_fail(e, "driver streams");
+        }
+        I->drive_in = ev[0];
+        I->drive_out = ev[1];
+        I->stepped = ev[2];
+        I->verified = ev[3];
+        I->verify = vf;
+        I->drive = dr;
+    }
     hipStream_t caller = (hipStream_t)stream, s = I->drive;
-    hipError_t e = hipEventRecord(I->drive_in, caller);
+    e = hipEventRecord(I->drive_in, caller);
     if (e == hipSuccess) e = hipStreamWaitEvent(s, I->drive_in, 0);
     if (e != hipSuccess) return dev_fail(e, "ordering the driver stream");
 

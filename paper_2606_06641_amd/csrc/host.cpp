@@ -1,9 +1,12 @@
 // host.cpp -- host-side instance packing (see host.hpp).
 #include "host.hpp"
 
+#include "afsat.h"
+
 #include <algorithm>
 #include <cmath>
 #include <map>
+#include <mutex>
 #include <numeric>
 #include <tuple>
 
@@ -62,18 +65,72 @@ void roots(int N, std::vector<long double> &c, std::vector<long double> &s)
     }
 }
 
+// d_m = (1/N) sum_t g(t) omega^(-m t).  A truth table is piecewise constant in t
+// (two or three runs for every type but XOR), and over a run [a, b) of value v
+// the sum is geometric: v (omega^(-m a) - omega^(-m b)) / (1 - omega^(-m)) for
+// m != 0, so each coefficient costs O(runs) rather than O(N).  XOR alternates
+// in t, which is geometric in -omega^(-m) over the whole range.  Powers of omega
+// come from the mirrored root table with the exponent reduced mod N, so
+// d_{N-m} = conj(d_m) exactly; everything is in long double and rounded once.
 void coefficients(int type, int k, int param, double *re, double *im)
 {
     const int N = k + 1;
     std::vector<long double> c, s;
     roots(N, c, s);
+    std::vector<int> g(N);
+    for (int t = 0; t <= k; ++t) g[t] = satisfied(type, k, param, t) == 1 ? -1 : 1;
+    std::vector<int> start;                          // first t of each run of equal g
+    for (int t = 0; t <= k; ++t)
+        if (t == 0 || g[t] != g[t - 1]) start.push_back(t);
+    const int runs = (int)start.size();
+    // omega^(-j) for any integer j >= 0
+    auto wneg = [&](int64_t j, long double &wr, long double &wi) {
+        const int r = (int)(j % N);
+        wr = c[r];
+        wi = -s[r];
+    };
     for (int m = 0; m <= k; ++m) {
         long double ar = 0.0L, ai = 0.0L;
-        for (int t = 0; t <= k; ++t) {
-            const long double g = satisfied(type, k, param, t) == 1 ? -1.0L : 1.0L;
-            const int r = (int)(((int64_t)m * t) % N);
-            ar += g * c[r];
-            ai -= g * s[r];        // omega^(-r) = cos - i sin
+        if (m == 0) {
+            for (int t = 0; t <= k; ++t) ar += g[t];
+        } else if (runs <= 8) {
+            // sum over runs of v (w^a - w^b), then / (1 - w), w = omega^(-m)
+            long double nr = 0.0L, ni = 0.0L;
+            for (int q = 0; q < runs; ++q) {
+                const int a = start[q], b = q + 1 < runs ? start[q + 1] : N;
+                long double xr, xi, yr, yi;
+                wneg((int64_t)m * a, xr, xi);
+                wneg((int64_t)m * b, yr, yi);
+                nr += g[a] * (xr - yr);
+                ni += g[a] * (xi - yi);
+            }
+            long double dr, di;
+            wneg(m, dr, di);
+            dr = 1.0L - dr;                          // 1 - omega^(-m)
+            di = -di;
+            const long double den = dr * dr + di * di;
+            ar = (nr * dr + ni * di) / den;
+            ai = (ni * dr - nr * di) / den;
+        } else if (type == AFS_XOR) {
+            // g(t) = g(0) (-1)^t: g(0) sum_t (-w)^t = g(0) (1 - (-w)^N) / (1 + w), w = omega^(-m)
+            long double wr, wi;
+            wneg(m, wr, wi);
+            if (2 * m == N) {
+                ar = (long double)g[0] * N;          // -w = 1
+            } else {
+                const long double pn = (N % 2) ? -1.0L : 1.0L;       // (-1)^N, and w^N = 1
+                const long double nr = 1.0L - pn, dr = 1.0L + wr, di = wi;
+                const long double den = dr * dr + di * di;
+                ar = g[0] * (nr * dr) / den;
+                ai = g[0] * (-nr * di) / den;
+            }
+        } else {
+            for (int t = 0; t <= k; ++t) {           // any other table: the sum itself
+                long double xr, xi;
+                wneg((int64_t)m * t, xr, xi);
+                ar += g[t] * xr;
+                ai += g[t] * xi;
+            }
         }
         re[m] = (double)(ar / N);
         im[m] = (double)(ai / N);
@@ -124,11 +181,29 @@ void bucket_shape(int k, int &J, int &S)
 int rescale_period(int J, int S) { return J * S <= 256 ? 16 : 8; }
 
 
-void append_root_rows(int k, int J, int S, const double *re, const double *im, std::vector<TabRow> &tab)
+// The per-root factors of the rows that do not depend on the coefficients: the
+// same for every table of one length and kernel shape, so computed once per
+// (k, J, S) and kept (the trigonometry in long double is most of a table's cost).
+struct RootConsts {
+    long double br, bi;      // beta = (1 - omega^m)/2
+    long double er, ei;      // FE phase
+    long double ck;          // FE magnitude: c^k (short kernel) or 1
+    long double fr, fi;      // adjoint phase
+    long double kmag;        // adjoint magnitude
+    float mt, crp, cf;       // -tan h, c^RP, c^F
+};
+
+static const std::vector<RootConsts> &root_consts(int k, int J, int S)
 {
+    static std::mutex mu;
+    static std::map<std::tuple<int, int, int>, std::vector<RootConsts>> memo;
+    const bool shrt = k <= kShortMax;
+    const auto key = shrt ? std::make_tuple(k, 1, k) : std::make_tuple(k, J, S);
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = memo.find(key);
+    if (it != memo.end()) return it->second;
     const int N = k + 1;
     const int M = k / 2;
-    const bool shrt = k <= kShortMax;
     const long double pi = 3.141592653589793238462643383279502884L;
     // e^{i n h} with the angle n*h = pi (m n mod 2N) / N reduced exactly
     auto phase = [&](int m, int64_t n, long double &pr, long double &pim) {
@@ -136,36 +211,52 @@ void append_root_rows(int k, int J, int S, const double *re, const double *im, s
         pr = cosl(ang);
         pim = sinl(ang);
     };
+    std::vector<RootConsts> v(M + 1);
     for (int m = 1; m <= M; ++m) {
+        RootConsts &r = v[m];
         const long double h = pi * (long double)m / (long double)N;
         const long double sh = sinl(h), ch = cosl(h);
         // beta = (1 - omega)/2 = -i sin(h) e^{i h} = (sin^2 h, -sin h cos h)
-        const long double br = sh * sh, bi = -sh * ch;
-        const long double dr = re[m], di = im[m];
-        const long double tr = 2.0L * (dr * br - di * bi), ti = 2.0L * (dr * bi + di * br);   // 2 d beta
-        const float mt = (float)(-sh / ch);
-        long double er, ei, kmag;      // FE phase and magnitude, adjoint phase (e) and magnitude
-        long double fr, fi;
+        r.br = sh * sh;
+        r.bi = -sh * ch;
+        r.mt = (float)(-sh / ch);
         if (shrt) {
-            phase(m, k, er, ei);                          // alpha^k = c^k e^{i k h}
-            const long double ck = powl(ch, (long double)k);
-            const long double dfr = 2.0L * ck * (dr * er - di * ei), dfi = 2.0L * ck * (dr * ei + di * er);
-            phase(m, k - 1, fr, fi);                      // alpha^(k-1)
-            kmag = powl(ch, (long double)(k - 1));
-            const long double kr = kmag * (tr * fr - ti * fi), ki = kmag * (tr * fi + ti * fr);
-            tab.push_back({(float)dfr, (float)dfi, (float)kr, (float)ki});
-            tab.push_back({0.0f, 0.0f, mt, 0.0f});
+            phase(m, k, r.er, r.ei);                      // alpha^k = c^k e^{i k h}
+            r.ck = powl(ch, (long double)k);
+            phase(m, k - 1, r.fr, r.fi);                  // alpha^(k-1)
+            r.kmag = powl(ch, (long double)(k - 1));
+            r.crp = r.cf = 0.0f;
         } else {
             const int RP = rescale_period(J, S);
             const int F = S - RP * ((S - 1) / RP);
-            phase(m, (int64_t)J * S, er, ei);             // d' = d e^{i J S h}
-            const long double dr2 = 2.0L * (dr * er - di * ei), di2 = 2.0L * (dr * ei + di * er);
-            phase(m, (int64_t)J * S - 1, fr, fi);         // Kc = 2 d beta c^(F-1) e^{i (J S - 1) h}
-            kmag = powl(ch, (long double)(F - 1));
-            const long double kr = kmag * (tr * fr - ti * fi), ki = kmag * (tr * fi + ti * fr);
-            tab.push_back({(float)dr2, (float)di2, (float)kr, (float)ki});
-            tab.push_back({mt, (float)powl(ch, (long double)RP), (float)powl(ch, (long double)F), 0.0f});
+            phase(m, (int64_t)J * S, r.er, r.ei);         // d' = d e^{i J S h}
+            r.ck = 1.0L;
+            phase(m, (int64_t)J * S - 1, r.fr, r.fi);     // Kc = 2 d beta c^(F-1) e^{i (J S - 1) h}
+            r.kmag = powl(ch, (long double)(F - 1));
+            r.crp = (float)powl(ch, (long double)RP);
+            r.cf = (float)powl(ch, (long double)F);
         }
+    }
+    return memo.emplace(key, std::move(v)).first->second;
+}
+
+void append_root_rows(int k, int J, int S, const double *re, const double *im, std::vector<TabRow> &tab)
+{
+    const int M = k / 2;
+    const bool shrt = k <= kShortMax;
+    const std::vector<RootConsts> &rc = root_consts(k, J, S);
+    for (int m = 1; m <= M; ++m) {
+        const RootConsts &r = rc[m];
+        const long double dr = re[m], di = im[m];
+        const long double tr = 2.0L * (dr * r.br - di * r.bi), ti = 2.0L * (dr * r.bi + di * r.br);   // 2 d beta
+        const long double kr = r.kmag * (tr * r.fr - ti * r.fi), ki = r.kmag * (tr * r.fi + ti * r.fr);
+        // short: 2 d alpha^k; segment: 2 d' = 2 d e^{i J S h}
+        const long double fer = 2.0L * r.ck * (dr * r.er - di * r.ei), fei = 2.0L * r.ck * (dr * r.ei + di * r.er);
+        tab.push_back({(float)fer, (float)fei, (float)kr, (float)ki});
+        if (shrt)
+            tab.push_back({0.0f, 0.0f, r.mt, 0.0f});
+        else
+            tab.push_back({r.mt, r.crp, r.cf, 0.0f});
     }
 }
 
@@ -246,18 +337,23 @@ std::string build_instance(int32_t n, int32_t C, const int64_t *con_off, const i
     }
 
     // ---- coefficient tables, one per distinct (type, k, canonical param) ----
-    std::map<std::tuple<int, int, int>, int32_t> table_of;
-    std::vector<int32_t> con_tab(C);
+    std::map<std::tuple<int, int, int>, std::pair<int32_t, int32_t>> table_of;   // -> (row, index)
+    std::vector<int32_t> con_tab(C), con_tidx(C);
     std::vector<double> re, im;
     for (int32_t c = 0; c < C; ++c) {
         const int k = (int)(con_off[c + 1] - con_off[c]);
         const int p = canonical_param(types[c], k, H.params[c]);
         auto key = std::make_tuple(types[c], k, p);
         auto it = table_of.find(key);
-        if (it != table_of.end()) { con_tab[c] = it->second; continue; }
+        if (it != table_of.end()) {
+            con_tab[c] = it->second.first;
+            con_tidx[c] = it->second.second;
+            continue;
+        }
         const int32_t off = (int32_t)H.tab.size();
-        table_of.emplace(key, off);
+        table_of.emplace(key, std::make_pair(off, H.n_tables));
         con_tab[c] = off;
+        con_tidx[c] = H.n_tables;
         re.assign(k + 1, 0.0);
         im.assign(k + 1, 0.0);
         coefficients(types[c], k, p, re.data(), im.data());
@@ -271,24 +367,30 @@ std::string build_instance(int32_t n, int32_t C, const int64_t *con_off, const i
     }
 
     // ---- buckets ----
-    std::vector<int32_t> order(C);
-    std::iota(order.begin(), order.end(), 0);
+    // Order: short buckets by length, then long ones by capacity J*S (then J),
+    // within a bucket by length and table.  The kernel shape of each length is
+    // worked out once, and each constraint gets one integer sort key.
     auto klen = [&](int32_t c) { return (int)(con_off[c + 1] - con_off[c]); };
-    auto shape_key = [&](int32_t c) {
+    std::vector<std::pair<int, int>> shape_of_len(max_k + 1);
+    for (int k = 1; k <= max_k; ++k) {
         int J, S;
-        bucket_shape(klen(c), opts, J, S);
-        return std::make_pair(J, J == 1 ? klen(c) : S);
-    };
-    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
-        const auto ka = shape_key(a), kb = shape_key(b);
-        if (ka != kb) {
-            const int ca = ka.first == 1 ? ka.second : ka.first * ka.second + 1000;
-            const int cb = kb.first == 1 ? kb.second : kb.first * kb.second + 1000;
-            return ca != cb ? ca < cb : ka.first < kb.first;
-        }
-        if (klen(a) != klen(b)) return klen(a) < klen(b);
-        return con_tab[a] < con_tab[b];
-    });
+        bucket_shape(k, opts, J, S);
+        shape_of_len[k] = std::make_pair(J, J == 1 ? k : S);
+    }
+    auto shape_key = [&](int32_t c) { return shape_of_len[klen(c)]; };
+    std::vector<std::pair<uint64_t, int32_t>> keyed(C);
+    for (int32_t c = 0; c < C; ++c) {
+        const auto sk = shape_key(c);
+        const uint64_t cls = sk.first == 1 ? (uint64_t)sk.second : (uint64_t)(sk.first * sk.second + 1000);
+        // class (< 2^17) | J (< 2^7) | length (< 2^11) | table index (< 2^29: there are
+        // at most 8 types x 1024 lengths x 1026 thresholds)
+        const uint64_t key = (cls << 47) | ((uint64_t)sk.first << 40) | ((uint64_t)klen(c) << 29) |
+                             (uint64_t)con_tidx[c];
+        keyed[c] = std::make_pair(key, c);
+    }
+    std::sort(keyed.begin(), keyed.end());             // ties broken by constraint index: stable
+    std::vector<int32_t> order(C);
+    for (int32_t i = 0; i < C; ++i) order[i] = keyed[i].second;
 
     H.bc_slot0.resize(C); H.bc_k.resize(C); H.bc_tab.resize(C); H.bc_orig.resize(C); H.bc_w.resize(C);
     H.slot_lit.resize(L); H.slot_to_lit.resize(L);

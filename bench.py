@@ -144,6 +144,9 @@ def build_workload(name, W):
     if name == "longcard50k":
         return W.long_card_50k(), 512, ("planted n=50000: 200000 clauses k3-10, 1000 CARD>=K k256-1024; "
                                         "512 restarts; one forward + adjoint (autograd) pass per step")
+    if name == "longchain20k":
+        return W.long_chain_20k(), 512, ("planted n=20000: 60000 clauses k3-8, 150 each of OR, XOR, NAE, AMO "
+                                         "and EO k64-1024; 512 restarts; one PGD iteration per step")
     raise SystemExit("unknown workload %r" % name)
 
 
@@ -153,7 +156,7 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="mixed10k",
-                    choices=["mixed10k", "batch64", "longcard50k", "learned3sat", "learned5k"])
+                    choices=["mixed10k", "batch64", "longcard50k", "longchain20k", "learned3sat", "learned5k"])
     ap.add_argument("--train", type=int, default=0, help="learned-init workloads: training instances")
     ap.add_argument("--test", type=int, default=0, help="learned-init workloads: held-out test instances")
     ap.add_argument("--restarts", type=int, default=0, help="override the workload's restart count")
@@ -169,6 +172,11 @@ def main():
     ap.add_argument("--search", type=int, default=0,
                     help="mixed10k only: time Algorithm 1 iterations with the backtracking line search "
                          "of this many trials instead of the constant-step hot path")
+    ap.add_argument("--chain", default="",
+                    help="comma-separated piece lengths: run Algorithm 1 on the long-constraint workload "
+                         "(longchain20k) as given and decomposed into chains of pieces of at most each "
+                         "length, --steps iterations each, and compare time per iteration and the input's "
+                         "unsatisfied constraints")
     ap.add_argument("--gemm-probe", type=int, default=0,
                     help="only time the learned-initialisation network's dense-layer kernel on this many rows")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -195,6 +203,9 @@ def main():
     if args.workload.startswith("learned"):
         learned_init_bench(args, W)
         return
+    if args.chain:
+        chain_bench(args, W)
+        return
     t_setup = time.perf_counter()
     work, B, desc = build_workload(args.workload, W)
     B = args.restarts or B
@@ -203,7 +214,8 @@ def main():
         inst = _concat(parts, W)          # the block-diagonal instance (for lengths and tuning)
     else:
         inst = work
-    x0 = W.uniform_x0(inst.n, B, workload={"mixed10k": 2, "batch64": 3, "longcard50k": 4}[args.workload])
+    x0 = W.uniform_x0(inst.n, B, workload={"mixed10k": 2, "batch64": 3, "longcard50k": 4,
+                                           "longchain20k": 6}[args.workload])
     shapes = []
     if not args.no_autotune:
         from paper_2606_06641_amd import autotune
@@ -352,6 +364,63 @@ def main():
         line["cpu_baseline"] = cpu_baseline(inst, x0, args.lr, args.cpu_seconds, args.cpu_threads,
                                             args.cpu_restarts)
     print(json.dumps(line), flush=True)
+
+
+def chain_bench(args, W):
+    """Long-constraint decomposition as a comparison point (Sec. 5): Algorithm 1
+    (constant step, the library's graph-captured driver) on the planted
+    long-constraint workload as given, where every constraint is evaluated whole
+    by the count-basis kernels, and on the same instance decomposed into chains
+    of pieces of at most L literals (afs_decompose).  Per form: milliseconds per
+    iteration over --steps iterations from uniform starting points (the first
+    --warmup iterations untimed), and the unsatisfied constraints of the input
+    under the final points restricted to its own variables.  One JSON line per
+    form."""
+    import numpy as np
+    import torch
+    from paper_2606_06641_amd import afsat, autotune
+
+    inst = W.long_chain_20k()
+    B = args.restarts or 512
+    dev = torch.device("cuda", 0)
+    native = None
+    lens = [0] + [int(v) for v in args.chain.split(",") if v]
+    for L in lens:
+        t_setup = time.perf_counter()
+        form = inst if L == 0 else afsat.decompose(inst, L)
+        shapes = []
+        if not args.no_autotune:
+            out = args.tune_out or os.path.join(tempfile.gettempdir(), "afsat_tuned_shapes.txt")
+            shapes, _ = autotune.tune(form, B, cache_path=autotune.DEFAULT_CACHE, out_path=out,
+                                      log=lambda m: print(m, file=sys.stderr, flush=True), max_cons=400)
+        d = afsat.Instance.from_arrays(form, device=0, shapes=shapes)
+        if native is None:
+            native = d
+        setup = time.perf_counter() - t_setup
+        x = torch.from_numpy(W.uniform_x0(d.n, B, workload=6)).to(dev)
+        if args.warmup:
+            d.pgd(x, args.lr, args.warmup, poll=args.warmup, stop_on_sat=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = d.pgd(x, args.lr, args.steps, poll=args.steps, stop_on_sat=False)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        unsat = native.round_verify(x[:inst.n].contiguous()).cpu().numpy()
+        desc = "planted n=20000: 60000 clauses k3-8, 150 each of OR, XOR, NAE, AMO and EO k64-1024; %d restarts" % B
+        desc += "; as given" if L == 0 else "; decomposed into chains of pieces of at most %d literals" % L
+        print(json.dumps({"metric": "PGD iterations/s", "value": 1e3 / ms, "unit": "iterations/s", "n_gpus": 1,
+                          "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+                          "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+                          "config": {"workload": desc, "max_len": L or int(np.diff(inst.con_off).max()),
+                                     "n_vars": d.n, "n_cons": d.n_cons, "n_lits": d.n_lits, "restarts": B,
+                                     "lr": args.lr, "setup_s": round(setup, 2),
+                                     "shapes": [list(sh) for sh in shapes]},
+                          "input_literal_evals_per_s": B * int(inst.con_off[-1]) / (ms * 1e-3),
+                          "input_unsat_after": {"iterations": args.warmup + int(st["iters"]),
+                                                "best": int(unsat.min()), "mean": float(unsat.mean())}}),
+              flush=True)
+        if d is not native:
+            d.close()
 
 
 def search_bench(args, d, x, st, ws, B, desc):

@@ -535,6 +535,40 @@ void afs_parsed_destroy(afs_parsed *p);
  * units as a partial assignment for every restart. */
 afs_status afs_parsed_fold_units(const afs_parsed *p, int32_t n_partial, int8_t *values);
 
+/* ---- Long-constraint decomposition (Sec. 5, constraint length ceiling) ----
+ * The paper proposes replacing a long constraint by O(k / 50) shorter
+ * constraints of the same type, for every type but EK and CARD.  Here a
+ * constraint of type OR, XOR, NAE, AMO or EO longer than max_len becomes a chain
+ * of p = ceil((k - 2) / (max_len - 2)) pieces of that type joined by p - 1 new
+ * auxiliary variables a_1 .. a_(p-1):
+ *   piece 1      : G_1 and a_1
+ *   piece i      : -a_(i-1), G_i and a_i        (1 < i < p)
+ *   piece p      : -a_(p-1) and G_p
+ * where G_1 .. G_p split the literals in their order, the piece lengths differing
+ * by at most one (every piece <= max_len, every G_i non-empty).  XOR pieces keep
+ * the literal a_i in both neighbours instead (a_i is the parity so far), with
+ * parity 0 for every piece but the last, which keeps the constraint's parity.
+ * For every assignment of the original variables, the original constraint holds
+ * exactly when some values of the auxiliary variables satisfy every piece.  EK,
+ * CARD >= and CARD < constraints, and constraints of length <= max_len, are
+ * copied unchanged.  Each piece keeps its constraint's weight.  Auxiliary
+ * variables are numbered n+1, n+2, ... in the order of the constraints.
+ * afs_decompose_size gives the sizes of the result (host arrays as for
+ * afs_instance_create: con_off int64 [C+1], types int32 [C]; max_len in
+ * [3, 1024]); afs_decompose writes it into caller arrays of those sizes:
+ * con_off_out int64 [C_out+1], lits_out int32 [L_out], types_out and params_out
+ * int32 [C_out], origin_out int32 [C_out] (the input constraint of each output
+ * constraint), weights_out float [C_out] (written when weights is non-NULL;
+ * may be NULL when weights is NULL).  Host-only, no device use; invalid input
+ * (a type out of range, an empty constraint, a literal 0 or above n, sizes that
+ * overflow int32) returns AFS_EINVAL and writes nothing. */
+afs_status afs_decompose_size(int32_t n, int32_t C, const int64_t *con_off, const int32_t *types, int32_t max_len,
+                              int32_t *n_out, int32_t *C_out, int64_t *L_out);
+afs_status afs_decompose(int32_t n, int32_t C, const int64_t *con_off, const int32_t *lits, const int32_t *types,
+                         const int32_t *params, const float *weights, int32_t max_len, int64_t *con_off_out,
+                         int32_t *lits_out, int32_t *types_out, int32_t *params_out, float *weights_out,
+                         int32_t *origin_out);
+
 /* Thread-local message for the last non-OK status of an afs_gnn_* call. */
 const char *afs_gnn_last_error(void);
 

@@ -122,6 +122,9 @@ SIGNATURES = [
     ("afs_init_points", ctypes.c_int, [_vp, _i32, ctypes.c_uint64, _vp, _i32, _vp, _vp]),
     ("afs_form_tables", ctypes.c_int, [_i32, _i32, _i32, _i32, _f64p, _f64p, _f64p]),
     ("afs_fe_generic", ctypes.c_int, [_i32, _f64p, _f64p, _f64p, _i32, _i32, _vp, _vp, _i32, _vp]),
+    ("afs_decompose_size", ctypes.c_int, [_i32, _i32, _i64p, _i32p, _i32, _i32p, _i32p, _i64p]),
+    ("afs_decompose", ctypes.c_int, [_i32, _i32, _i64p, _i32p, _i32p, _i32p, _f32p, _i32, _i64p, _i32p, _i32p,
+                                     _i32p, _f32p, _i32p]),
 ]
 
 FORM_A, FORM_B = 0, 1
@@ -635,6 +638,55 @@ def parse_file(path):
     h = ctypes.c_void_p()
     _check(lib().afs_parse_file(os.fsencode(path), ctypes.byref(h)))
     return _take_parsed(h)
+
+
+@dataclass
+class Decomposed:
+    """An instance after long-constraint decomposition (Sec. 5): the arrays
+    ``Instance`` takes over ``n`` variables, the first ``n_orig`` of them the
+    input's and the rest auxiliary, and ``origin`` (int32 [C]), the input
+    constraint each constraint came from.  A solution's first ``n_orig``
+    variables solve the input."""
+    n: int
+    n_orig: int
+    con_off: np.ndarray
+    lits: np.ndarray
+    types: np.ndarray
+    params: np.ndarray
+    origin: np.ndarray
+    weights: Optional[np.ndarray] = None
+
+
+def decompose(inst, max_len):
+    """Split every OR, XOR, NAE, AMO and EO constraint of ``inst`` (any object with
+    ``n, con_off, lits, types, params`` and optionally ``weights``) longer than
+    ``max_len`` into a chain of pieces of at most ``max_len`` literals joined by
+    auxiliary variables; see afs_decompose in afsat.h."""
+    n = int(inst.n)
+    con_off = np.ascontiguousarray(inst.con_off, dtype=np.int64)
+    lits = np.ascontiguousarray(inst.lits, dtype=np.int32)
+    types = np.ascontiguousarray(inst.types, dtype=np.int32)
+    C = len(types)
+    params = getattr(inst, "params", None)
+    params = np.zeros(C, np.int32) if params is None else np.ascontiguousarray(params, dtype=np.int32)
+    weights = getattr(inst, "weights", None)
+    weights = None if weights is None else np.ascontiguousarray(weights, dtype=np.float32)
+    if len(con_off) != C + 1 or len(params) != C or (weights is not None and len(weights) != C):
+        raise ValueError("con_off, types, params and weights disagree on the constraint count")
+    if int(con_off[-1]) != len(lits):
+        raise ValueError("con_off[-1] must equal len(lits)")
+    n_out, c_out, l_out = _i32(), _i32(), ctypes.c_int64()
+    _check(lib().afs_decompose_size(n, C, _np_ptr(con_off, _i64p), _np_ptr(types, _i32p), int(max_len),
+                                    ctypes.byref(n_out), ctypes.byref(c_out), ctypes.byref(l_out)))
+    co = np.zeros(c_out.value + 1, np.int64)
+    lo = np.zeros(l_out.value, np.int32)
+    to, po, og = (np.zeros(c_out.value, np.int32) for _ in range(3))
+    wo = None if weights is None else np.zeros(c_out.value, np.float32)
+    _check(lib().afs_decompose(n, C, _np_ptr(con_off, _i64p), _np_ptr(lits, _i32p), _np_ptr(types, _i32p),
+                               _np_ptr(params, _i32p), _np_ptr(weights, _f32p), int(max_len), _np_ptr(co, _i64p),
+                               _np_ptr(lo, _i32p), _np_ptr(to, _i32p), _np_ptr(po, _i32p), _np_ptr(wo, _f32p),
+                               _np_ptr(og, _i32p)))
+    return Decomposed(int(n_out.value), n, co, lo, to, po, og, wo)
 
 
 class FEObjective(torch.autograd.Function):

@@ -40,6 +40,7 @@ SOURCES = [
     ("autotune.cpp", HOST_HIP + ['-DAFS_FE_REV="%s"' % fe_revision()]),
     ("parse.cpp", HOST_HIP),
     ("forms.cpp", HOST_HIP),
+    ("decompose.cpp", HOST_HIP),
     ("fe_kernels.hip", [HIPCC] + COMMON + DEVICE),
     ("update_kernels.hip", [HIPCC] + COMMON + DEVICE),
     ("search_kernels.hip", [HIPCC] + COMMON + DEVICE),

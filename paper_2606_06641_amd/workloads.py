@@ -113,6 +113,17 @@ def _draw_group(rng, n: int, hidden: np.ndarray, count: int, k: int, ctype: int,
             hi = max(1, k // 2)
             p = rng.integers(1, hi + 1, size=todo.size)
             ok = p <= t
+        elif ctype in (AMO, EO):
+            # a random draw almost never has t <= 1 at length: the signs are
+            # chosen from H instead, every literal false but one (EO) or at
+            # most one (AMO, a fair coin)
+            s = hidden[v].copy()
+            one = rng.integers(0, k, size=todo.size)
+            flip = np.ones(todo.size, dtype=bool) if ctype == EO else rng.integers(0, 2, size=todo.size) == 1
+            rows = np.nonzero(flip)[0]
+            s[rows, one[rows]] = ~s[rows, one[rows]]
+            ok = np.ones(todo.size, dtype=bool)
+            p = np.zeros(todo.size, dtype=np.int64)
         else:
             raise ValueError("planted draw not defined for type %d" % ctype)
         keep = np.nonzero(ok)[0]
@@ -208,6 +219,13 @@ def long_card_50k(instance: int = 0) -> Instance:
     """n=50,000: 200,000 clauses (k 3-10), 1,000 CARD>=K (k 256-1024)."""
     return planted_mixed(50000, [(OR, 200000, 3, 10, False), (CARD_GE, 1000, 256, 1024, False)],
                          workload=4, instance=instance, name="longcard-n50k")
+
+
+def long_chain_20k(instance: int = 0) -> Instance:
+    """n=20,000: 60,000 clauses (k 3-8) and 150 each of OR, XOR, NAE, AMO and EO
+    with k 64-1024: the types the chain decomposition of Sec. 5 applies to."""
+    spec = [(OR, 60000, 3, 8, False)] + [(t, 150, 64, 1024, False) for t in (OR, XOR, NAE, AMO, EO)]
+    return planted_mixed(20000, spec, workload=6, instance=instance, name="longchain-n20k")
 
 
 def mixed_5k(instance: int = 0) -> Instance:

@@ -1,0 +1,108 @@
+"""GPU: instances after long-constraint decomposition (Sec. 5) through the C ABI.
+
+The decomposition itself is host code, pinned and compared with the oracle on
+the CPU (tests/test_decompose.py).  Here the decomposed instance runs on the
+device: FE, adjoints and gradient against the FP64 oracle on the same arrays;
+exact verification of the planted witness completed to the auxiliary variables
+(the oracle's completion) and of random points against the oracle's count; and
+Algorithm 1 on a decomposed planted instance, whose verified restarts, cut to
+the input's variables, satisfy the input.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import parity
+from oracle import decompose as odec
+from paper_2606_06641_amd import afsat
+from paper_2606_06641_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    afsat.lib()
+
+
+def log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def as_instance(dec):
+    return W.Instance(n=dec["n"], con_off=dec["con_off"], lits=dec["lits"], types=dec["types"],
+                      params=dec["params"], weights=dec["weights"])
+
+
+def chain_planted(seed, n=400, long_k=(40, 200)):
+    spec = [(W.OR, 3 * n, 3, 6, False)] + [(t, 4, long_k[0], long_k[1], False)
+                                           for t in (W.OR, W.XOR, W.NAE, W.AMO, W.EO)]
+    return W.planted_mixed(n, spec, workload=6, instance=100 + seed)
+
+
+@pytest.mark.parametrize("max_len", [5, 16, 48])
+def test_decomposed_fe_and_gradient_parity(max_len):
+    inst = chain_planted(0)
+    dec = as_instance(odec.decompose(inst, max_len))
+    log("case: decomposed FE parity max_len=%d n=%d C=%d L=%d" % (max_len, dec.n, dec.n_cons, dec.n_lits))
+    d = afsat.Instance.from_arrays(dec)
+    assert (d.n, d.n_cons, d.n_lits) == (dec.n, dec.n_cons, dec.n_lits)
+    x = W.uniform_x0(dec.n, 96, workload=6, instance=max_len)
+    parity.compare(dec, d, parity.gpu_eval(d, x), oracle.eval(dec, x, fe=True, adj=True, grad=True),
+                   "max_len=%d" % max_len)
+
+
+@pytest.mark.parametrize("max_len", [3, 12])
+def test_completed_witness_verifies_and_counts_match(max_len):
+    inst = chain_planted(1)
+    raw = odec.decompose(inst, max_len)
+    dec = as_instance(raw)
+    d = afsat.Instance.from_arrays(dec)
+    log("case: decomposed verification max_len=%d n=%d C=%d" % (max_len, dec.n, dec.n_cons))
+    full = odec.aux_values(inst, raw, inst.hidden)
+    B = 64
+    rng = np.random.default_rng(max_len)
+    x = rng.uniform(-1, 1, size=(dec.n, B)).astype(np.float32)
+    x[:, 0] = np.where(full, -1.0, 1.0)                 # True is -1
+    # column 1: the witness with two false literals of a long AMO made true
+    amo = int(np.nonzero((np.asarray(inst.types) == W.AMO) & (np.diff(inst.con_off) > max_len))[0][0])
+    row = np.asarray(inst.lits[inst.con_off[amo]:inst.con_off[amo + 1]])
+    off_lits = [l for l in row if inst.hidden[abs(l) - 1] != (l > 0)]    # literals false under the witness
+    bad = inst.hidden.copy()
+    for l in off_lits[:2]:
+        bad[abs(int(l)) - 1] = not bad[abs(int(l)) - 1]
+    x[:, 1] = np.where(odec.aux_values(inst, raw, bad), -1.0, 1.0)
+    got = d.round_verify(parity.to_dev(x)).cpu().numpy()
+    want = oracle.unsat_count(dec, x)
+    assert np.array_equal(got, want)
+    assert got[0] == 0
+    assert oracle.unsat_count(inst, x[:inst.n, 1:2])[0] > 0 and got[1] > 0
+
+
+def test_pgd_on_decomposed_instance_solves_the_input():
+    # long OR and NAE: from uniform points a long AMO, EO or XOR has an almost flat
+    # expansion (descent leaves them unsatisfied whole or decomposed), so the
+    # solvable case takes the types whose expansion gives descent a direction
+    n = 200
+    spec = [(W.OR, 2 * n, 3, 5, False)] + [(t, 4, 30, 80, False) for t in (W.OR, W.NAE)]
+    inst = W.planted_mixed(n, spec, workload=6, instance=200)
+    dec = afsat.decompose(inst, 5)
+    assert dec.n > n and np.diff(dec.con_off).max() <= 5
+    d = afsat.Instance.from_arrays(dec)
+    B = 256
+    log("case: PGD on decomposed planted n=%d -> %d, C=%d -> %d" % (n, dec.n, inst.n_cons, d.n_cons))
+    x = d.init_points(B, seed=7)
+    st = d.pgd(x, 0.1, 3000, poll=25, stop_on_sat=True)
+    done = st["done"].cpu().numpy()
+    solved = np.nonzero(done == 1)[0]
+    log("iterations %d, verified restarts %d" % (st["iters"], solved.size))
+    assert solved.size > 0
+    xs = x[:, torch.from_numpy(solved).to(x.device)].cpu().numpy()
+    assert np.all(oracle.unsat_count(dec, xs) == 0)
+    assert np.all(oracle.unsat_count(inst, xs[:n]) == 0)

@@ -174,9 +174,9 @@ def main():
                          "of this many trials instead of the constant-step hot path")
     ap.add_argument("--chain", default="",
                     help="comma-separated piece lengths: run Algorithm 1 on the long-constraint workload "
-                         "(longchain20k) as given and decomposed into chains of pieces of at most each "
-                         "length, --steps iterations each, and compare time per iteration and the input's "
-                         "unsatisfied constraints")
+                         "(longchain20k) as given for --steps iterations, and decomposed into chains of "
+                         "pieces of at most each length for --steps iterations and then to the same wall "
+                         "time; compare time per iteration and the input's unsatisfied constraints")
     ap.add_argument("--gemm-probe", type=int, default=0,
                     help="only time the learned-initialisation network's dense-layer kernel on this many rows")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -372,10 +372,12 @@ def chain_bench(args, W):
     long-constraint workload as given, where every constraint is evaluated whole
     by the count-basis kernels, and on the same instance decomposed into chains
     of pieces of at most L literals (afs_decompose).  Per form: milliseconds per
-    iteration over --steps iterations from uniform starting points (the first
-    --warmup iterations untimed), and the unsatisfied constraints of the input
-    under the final points restricted to its own variables.  One JSON line per
-    form."""
+    iteration over --steps iterations from uniform starting points, and the
+    input's unsatisfied constraints under the points restricted to its own
+    variables, in total and per constraint class (exact counts by the library's
+    verification kernels on per-class sub-instances); a decomposed form then
+    continues to the wall time the form as given took, and is counted again.
+    One JSON line per form."""
     import numpy as np
     import torch
     from paper_2606_06641_amd import afsat, autotune
@@ -383,9 +385,35 @@ def chain_bench(args, W):
     inst = W.long_chain_20k()
     B = args.restarts or 512
     dev = torch.device("cuda", 0)
-    native = None
-    lens = [0] + [int(v) for v in args.chain.split(",") if v]
-    for L in lens:
+    lens_in = np.diff(np.asarray(inst.con_off))
+    types_in = np.asarray(inst.types)
+
+    def subset(sel):
+        ks = lens_in[sel]
+        off = np.zeros(len(sel) + 1, np.int64)
+        np.cumsum(ks, out=off[1:])
+        lits = np.concatenate([inst.lits[inst.con_off[c]:inst.con_off[c + 1]] for c in sel])
+        return W.Instance(n=inst.n, con_off=off, lits=lits, types=types_in[sel], params=np.asarray(inst.params)[sel])
+
+    classes = {}
+    for t in sorted(set(types_in.tolist())):
+        for long_ in (False, True):
+            sel = np.nonzero((types_in == t) & ((lens_in > 16) == long_))[0]
+            if sel.size:
+                name = "%s k%d-%d" % (W.TYPE_NAMES[t], lens_in[sel].min(), lens_in[sel].max())
+                classes[name] = afsat.Instance.from_arrays(subset(sel), device=0)
+    native = afsat.Instance.from_arrays(inst, device=0)
+
+    def input_unsat(x, iters):
+        xs = x[:inst.n].contiguous()
+        tot = native.round_verify(xs).cpu().numpy()
+        by = {name: round(float(h.round_verify(xs).float().mean()), 2) for name, h in classes.items()}
+        return {"iterations": iters, "best": int(tot.min()), "mean": round(float(tot.mean()), 2),
+                "mean_by_class": by}
+
+    poll = max(1, min(args.steps, 100))
+    native_ms = None
+    for L in [0] + [int(v) for v in args.chain.split(",") if v]:
         t_setup = time.perf_counter()
         form = inst if L == 0 else afsat.decompose(inst, L)
         shapes = []
@@ -394,31 +422,33 @@ def chain_bench(args, W):
             shapes, _ = autotune.tune(form, B, cache_path=autotune.DEFAULT_CACHE, out_path=out,
                                       log=lambda m: print(m, file=sys.stderr, flush=True), max_cons=400)
         d = afsat.Instance.from_arrays(form, device=0, shapes=shapes)
-        if native is None:
-            native = d
         setup = time.perf_counter() - t_setup
         x = torch.from_numpy(W.uniform_x0(d.n, B, workload=6)).to(dev)
-        if args.warmup:
-            d.pgd(x, args.lr, args.warmup, poll=args.warmup, stop_on_sat=False)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        st = d.pgd(x, args.lr, args.steps, poll=args.steps, stop_on_sat=False)
+        d.pgd(x, args.lr, args.steps, poll=poll, stop_on_sat=False)
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) * 1e3 / args.steps
-        unsat = native.round_verify(x[:inst.n].contiguous()).cpu().numpy()
-        desc = "planted n=20000: 60000 clauses k3-8, 150 each of OR, XOR, NAE, AMO and EO k64-1024; %d restarts" % B
-        desc += "; as given" if L == 0 else "; decomposed into chains of pieces of at most %d literals" % L
-        print(json.dumps({"metric": "PGD iterations/s", "value": 1e3 / ms, "unit": "iterations/s", "n_gpus": 1,
-                          "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
-                          "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-                          "config": {"workload": desc, "max_len": L or int(np.diff(inst.con_off).max()),
-                                     "n_vars": d.n, "n_cons": d.n_cons, "n_lits": d.n_lits, "restarts": B,
-                                     "lr": args.lr, "setup_s": round(setup, 2),
-                                     "shapes": [list(sh) for sh in shapes]},
-                          "input_literal_evals_per_s": B * int(inst.con_off[-1]) / (ms * 1e-3),
-                          "input_unsat_after": {"iterations": args.warmup + int(st["iters"]),
-                                                "best": int(unsat.min()), "mean": float(unsat.mean())}}),
-              flush=True)
+        line = {"metric": "PGD iterations/s", "value": 1e3 / ms, "unit": "iterations/s", "n_gpus": 1,
+                "steps": args.steps, "warmup": 0, "ms_per_step": ms, "higher_is_better": True,
+                "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+                "config": {"workload": "planted n=20000: 60000 clauses k3-8, 150 each of OR, XOR, NAE, AMO and "
+                                       "EO k64-1024; %d restarts; " % B
+                                       + ("as given" if L == 0 else
+                                          "decomposed into chains of pieces of at most %d literals" % L),
+                           "max_len": L or int(lens_in.max()), "n_vars": d.n, "n_cons": d.n_cons,
+                           "n_lits": d.n_lits, "restarts": B, "lr": args.lr, "setup_s": round(setup, 2),
+                           "shapes": [list(sh) for sh in shapes]},
+                "input_literal_evals_per_s": B * int(inst.con_off[-1]) / (ms * 1e-3),
+                "input_unsat": [input_unsat(x, args.steps)]}
+        if L == 0:
+            native_ms = ms
+        elif native_ms is not None:
+            more = int(args.steps * native_ms / ms) - args.steps
+            if more > 0:
+                d.pgd(x, args.lr, more, poll=poll, stop_on_sat=False)
+                line["input_unsat"].append(input_unsat(x, args.steps + more))
+        print(json.dumps(line), flush=True)
         if d is not native:
             d.close()
 

@@ -55,6 +55,9 @@ typedef enum {
     AFS_ESTATE = -5    /* call not valid for this instance (e.g. host-only) */
 } afs_status;
 
+/* Longest constraint the evaluation kernels take. */
+#define AFS_MAX_LEN 1024
+
 /* Symmetric constraint types (Table 1; Table 2 and the CARD normalisation of
  * Appendix A).  t = number of true literals out of k. */
 typedef enum {
@@ -101,7 +104,9 @@ typedef struct {
  *   n_vars   : number of variables, >= 1
  *   n_cons   : number of constraints, >= 0
  *   con_off  : host int64 [n_cons+1], con_off[0] = 0, non-decreasing; constraint
- *              c owns lits[con_off[c] .. con_off[c+1]) and has length k >= 1
+ *              c owns lits[con_off[c] .. con_off[c+1]) and has length
+ *              1 <= k <= AFS_MAX_LEN (longer OR, XOR, NAE, AMO and EO constraints
+ *              can be split first by afs_decompose)
  *   lits     : host int32 [L] DIMACS literals, +-(1..n_vars)
  *   types    : host int32 [n_cons] afs_ctype
  *   params   : host int32 [n_cons] XOR parity (0/1), or K for CARD_GE/CARD_LT/EK
@@ -555,7 +560,7 @@ afs_status afs_parsed_fold_units(const afs_parsed *p, int32_t n_partial, int8_t 
  * variables are numbered n+1, n+2, ... in the order of the constraints.
  * afs_decompose_size gives the sizes of the result (host arrays as for
  * afs_instance_create: con_off int64 [C+1], types int32 [C]; max_len in
- * [3, 1024]); afs_decompose writes it into caller arrays of those sizes:
+ * [3, AFS_MAX_LEN]); afs_decompose writes it into caller arrays of those sizes:
  * con_off_out int64 [C_out+1], lits_out int32 [L_out], types_out and params_out
  * int32 [C_out], origin_out int32 [C_out] (the input constraint of each output
  * constraint), weights_out float [C_out] (written when weights is non-NULL;

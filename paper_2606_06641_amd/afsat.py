@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(HERE, "libafsat.so")
 OR, XOR, NAE, CARD_GE, CARD_LT, AMO, EO, EK = range(8)
 
 AFS_OK, AFS_EINVAL, AFS_EUNSAT, AFS_ENOMEM, AFS_EDEVICE, AFS_ESTATE = 0, -1, -2, -3, -4, -5
+MAX_LEN = 1024          # AFS_MAX_LEN: longest constraint the evaluation kernels take
 
 _vp = ctypes.c_void_p
 _i32 = ctypes.c_int32

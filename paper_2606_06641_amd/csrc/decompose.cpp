@@ -51,7 +51,8 @@ afs_status check_input(int32_t n, int32_t C, const int64_t *con_off, const int32
 {
     if (n < 0 || C < 0) return afs::set_last_error(AFS_EINVAL, "n and C must be >= 0");
     if (C > 0 && (!con_off || !types)) return afs::set_last_error(AFS_EINVAL, "con_off or types is NULL");
-    if (max_len < 3 || max_len > 1024) return afs::set_last_error(AFS_EINVAL, "max_len must be in [3, 1024]");
+    if (max_len < 3 || max_len > AFS_MAX_LEN)
+        return afs::set_last_error(AFS_EINVAL, "max_len must be in [3, " + std::to_string(AFS_MAX_LEN) + "]");
     if (C > 0 && con_off[0] != 0) return afs::set_last_error(AFS_EINVAL, "con_off[0] must be 0");
     n_out = n;
     C_out = 0;

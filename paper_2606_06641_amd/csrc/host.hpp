@@ -10,10 +10,12 @@
 #include <string>
 #include <vector>
 
+#include "afsat.h"
+
 namespace afs {
 
 // Largest constraint length the kernels handle.
-constexpr int kMaxLen = 1024;
+constexpr int kMaxLen = AFS_MAX_LEN;
 // Lengths up to this use one lane per restart with the whole constraint in registers.
 constexpr int kShortMax = 16;
 // Largest number of literals one lane holds in the segment kernels.

@@ -15,7 +15,12 @@ reader's simplifications already prove it (conflicting units).  Exit status
 Partial assignments (Sec. 3.4) come from --partial FILE: one assignment per
 line, literals ending in 0 (a positive literal fixes its variable True); the
 restarts are divided evenly among them and the units found by the reader are
-folded into each.  Every step of the search runs in the library's kernels.
+folded into each.  --decompose L splits every OR, XOR, NAE, AMO and EO
+constraint longer than L literals into a chain of pieces joined by auxiliary
+variables (Sec. 5), so that such constraints longer than the kernels' 1,024
+maximum can be solved too; the search runs on the decomposed instance and the
+answer is its restriction to the input's variables.  Every step of the search
+runs in the library's kernels.
 """
 import argparse
 import sys
@@ -75,6 +80,8 @@ def main(argv=None, out=None):
     ap.add_argument("--poll", type=int, default=10, help="iterations between checks for a verified restart")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--partial", help="file of partial assignments, one per line, ending in 0")
+    ap.add_argument("--decompose", type=int, default=0, metavar="L",
+                    help="split long OR/XOR/NAE/AMO/EO constraints into chains of pieces of at most L literals")
     ap.add_argument("--device", type=int, default=0)
     ap.add_argument("--no-graph", action="store_true", help="launch iterations one by one")
     ap.add_argument("--best", action="store_true",
@@ -107,7 +114,13 @@ def main(argv=None, out=None):
         for line in assignment_lines(bits):
             print(line, file=out)
         return 10
-    inst = afsat.Instance.from_arrays(p, device=a.device)
+    form = p
+    if a.decompose:
+        form = afsat.decompose(p, a.decompose)
+        vals = np.ascontiguousarray(np.pad(vals, ((0, 0), (0, form.n - p.n))))    # links start free
+        print("c decomposed into %d variables, %d constraints of at most %d literals"
+              % (form.n, len(form.types), int(np.diff(form.con_off).max())), file=out)
+    inst = afsat.Instance.from_arrays(form, device=a.device)
     dev = torch.device("cuda", a.device)
     vd = torch.from_numpy(vals).to(dev)
     fixed = vd if (vals != 0).any() else None
@@ -124,21 +137,39 @@ def main(argv=None, out=None):
     sat = np.nonzero(done == 1)[0]
     if sat.size:
         b = int(sat[np.argmin(st["first_sat"].cpu().numpy()[sat])])
-        bits = (x[:, b] < 0).cpu().numpy()
+        bits = (x[:p.n, b] < 0).cpu().numpy()
         print("c restart %d verified at iteration %d" % (b, int(st["first_sat"][b])), file=out)
         print("s SATISFIABLE", file=out)
         for line in assignment_lines(bits):
             print(line, file=out)
         return 10
     b = int(np.argmin(unsat))
-    print("c best restart %d leaves %d constraints unsatisfied" % (b, int(unsat[b])), file=out)
+    best = int(unsat[b])
+    if a.decompose:
+        print("c best restart %d leaves %d pieces unsatisfied" % (b, best), file=out)
+        best = input_unsat(p, x[:p.n, b:b + 1].contiguous(), a.device)
+        if best is None:
+            print("c (the input has constraints beyond the kernels' length limit: its own count is not taken)",
+                  file=out)
+            best = int(unsat[b])
+    if best is not None:
+        print("c best restart %d leaves %d constraints unsatisfied" % (b, best), file=out)
     if a.best:
-        print("o %d" % int(unsat[b]), file=out)
+        print("o %d" % best, file=out)
     print("s UNKNOWN", file=out)
     if a.best:
-        for line in assignment_lines((x[:, b] < 0).cpu().numpy()):
+        for line in assignment_lines((x[:p.n, b] < 0).cpu().numpy()):
             print(line, file=out)
     return 0
+
+
+def input_unsat(p, xb, device):
+    """Unsatisfied constraints of the parsed input under the points xb (n, 1),
+    counted by the library's verification kernels, or None when the input holds
+    a constraint longer than they take."""
+    if len(p.types) and int(np.diff(p.con_off).max()) > afsat.MAX_LEN:
+        return None
+    return int(afsat.Instance.from_arrays(p, device=device).round_verify(xb)[0])
 
 
 if __name__ == "__main__":

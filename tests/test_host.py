@@ -32,6 +32,13 @@ def declared_functions():
     return sorted(set(re.findall(r"\b(afs_[a-z_0-9]+)\s*\(", text)))
 
 
+def test_binding_mirrors_the_header_constants():
+    text = open(HEADER).read()
+    assert int(re.search(r"#define AFS_MAX_LEN (\d+)", text).group(1)) == afsat.MAX_LEN
+    for name in ("AFS_OK", "AFS_EINVAL", "AFS_EUNSAT", "AFS_ENOMEM", "AFS_EDEVICE", "AFS_ESTATE"):
+        assert int(re.search(r"\b%s = (-?\d+)" % name, text).group(1)) == getattr(afsat, name)
+
+
 def test_library_exports_every_declared_function():
     L = afsat.lib()
     names = declared_functions()

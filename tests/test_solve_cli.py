@@ -119,3 +119,28 @@ def test_best_effort_answer_on_an_unsatisfiable_input(tmp_path):
     assert rc == 0 and "s UNKNOWN" in text and "o 1" in text
     lits = values(text)
     assert len(lits) == 3 and lits[2] == 3
+
+
+@pytest.mark.gpu
+def test_decompose_solves_constraints_beyond_the_kernel_limit(tmp_path):
+    """NAE and OR constraints of 1,100-1,500 literals (past AFS_MAX_LEN) are
+    rejected whole and solved through --decompose; the printed assignment, over
+    the input's variables only, satisfies the input."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2606_06641_amd import afsat
+    n = 1600
+    spec = [(W.OR, 2 * n, 3, 5, False), (W.NAE, 2, 1100, 1500, False), (W.OR, 2, 1100, 1500, False)]
+    inst = W.planted_mixed(n, spec, workload=6, instance=300)
+    assert np.diff(inst.con_off).max() > afsat.MAX_LEN
+    f = tmp_path / "long.cnf"
+    f.write_text(to_text(inst))
+    with pytest.raises(afsat.AfsError):
+        run([str(f), "--batch", "64", "--iters", "10"])
+    rc, text = run([str(f), "--batch", "128", "--iters", "1000", "--decompose", "32"])
+    print(text, flush=True)
+    assert rc == 10 and "s SATISFIABLE" in text and "c decomposed into" in text
+    lits = values(text)
+    assert [abs(l) for l in lits] == list(range(1, n + 1))
+    x = np.array([[-1.0] if l > 0 else [1.0] for l in lits], dtype=np.float32)
+    assert oracle.unsat_count(inst, x)[0] == 0

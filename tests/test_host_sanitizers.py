@@ -1,10 +1,12 @@
 """Host code of the library under AddressSanitizer and UndefinedBehaviorSanitizer.
 
-The reader (csrc/parse.cpp) and the packing (csrc/host.cpp) are built with g++
-and the two sanitizers into small programs (tests/sanitize/*.cpp) that feed them
-random and mutated inputs and check the structure of what comes back: the
-reader's arrays and units, and the packed buckets, slots, variable-to-slot
-transpose and coefficient-table rows the kernels index.  Host code only: no HIP
+The reader (csrc/parse.cpp), the packing (csrc/host.cpp) and the long-constraint
+decomposition (csrc/decompose.cpp) are built with g++ and the two sanitizers
+into small programs (tests/sanitize/*.cpp) that feed them random and mutated
+inputs and check the structure of what comes back: the reader's arrays and
+units; the packed buckets, slots, variable-to-slot transpose and
+coefficient-table rows the kernels index; and the decomposition's announced
+sizes, piece lengths, literal order, and that its result packs.  Host code only: no HIP
 source is compiled here, and nothing runs on a GPU.
 """
 import os
@@ -58,6 +60,13 @@ def pack_exe(tmp_path_factory):
                   [os.path.join(HERE, "pack_fuzz.cpp"), os.path.join(CSRC, "host.cpp")])
 
 
+@pytest.fixture(scope="module")
+def decompose_exe(tmp_path_factory):
+    return _build(tmp_path_factory, "decompose_fuzz",
+                  [os.path.join(HERE, "decompose_fuzz.cpp"), os.path.join(CSRC, "decompose.cpp"),
+                   os.path.join(CSRC, "host.cpp")], HIP_INC)
+
+
 @pytest.mark.parametrize("seed", [12345, 2024])
 def test_reader_under_sanitizers(reader_exe, seed):
     accepted, rejected = _run(reader_exe, 60000, seed)
@@ -69,3 +78,9 @@ def test_reader_under_sanitizers(reader_exe, seed):
 def test_packing_under_sanitizers(pack_exe, seed):
     packed, _ = _run(pack_exe, 200, seed)
     assert packed > 100
+
+
+@pytest.mark.parametrize("seed", [99, 4242])
+def test_decomposition_under_sanitizers(decompose_exe, seed):
+    done, rejected = _run(decompose_exe, 200, seed)
+    assert done > 150 and rejected > 0

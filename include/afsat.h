@@ -279,7 +279,8 @@ afs_status afs_round_verify(afs_instance *inst, int32_t B, const float *x, uint3
 typedef struct {
     int32_t *unsat;      /* [P][B] unsat count at the current point                 */
     uint8_t *done;       /* [P][B] 0 searching, 1 verified, 2 converged (its step
-                            length fell below delta, Algorithm 1); either freezes it */
+                            length fell below delta, Algorithm 1, or its point moved
+                            less than epsilon, Sec. 3.3); either freezes it          */
     int32_t *first_sat;  /* [P][B] iteration at which it verified, -1 if not yet    */
     int32_t *counter;    /* [4] {iteration t, pairs verified, pairs frozen (verified
                             or converged), 0}; t counts completed iterations        */
@@ -367,12 +368,18 @@ typedef struct {
                                (plain instances only)                                       */
     void *search_ws;        /* line-search workspace (afs_search_workspace_bytes)          */
     size_t search_ws_bytes;
+    float epsilon;          /* > 0: a restart whose new point lies within epsilon of the
+                               previous one in every variable (max |x_t - x_(t-1)| <
+                               epsilon, Sec. 3.3) converges and stops; 0: off.  A
+                               restart that verifies in the same iteration counts as
+                               verified.  Uses the flags at the end of the workspace,
+                               which afs_pgd_init clears                                    */
 } afs_pgd_params;
 
 /* Algorithm 1 on the B columns of x (device f32 [n][B], updated in place to the
  * final point): afs_pgd_init, then up to max_iters iterations of afs_pgd_step
  * (constant step) or afs_pgd_search_step (line search), reading the device
- * counter every `poll` iterations (when stop_on_sat is set or delta > 0) and
+ * counter every `poll` iterations (when stop_on_sat is set or delta or epsilon > 0) and
  * stopping when stop_on_sat is set and some (part, restart) has verified, or
  * when every (part, restart) has verified or converged.
  * On return st holds unsat / done / first_sat / counter as after those calls,

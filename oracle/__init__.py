@@ -11,7 +11,8 @@ Functions follow the paper:
                   objective (Sec. 2.1.1, Eq. 2) and gradient, in FP64.
   * ``step``   -- the projected gradient step of Algorithm 1.
   * ``verify`` -- rounding and unsat_count of Algorithm 1, on FP32 points.
-  * ``pgd``    -- Algorithm 1 with constant step length, FP64.
+  * ``pgd``    -- Algorithm 1 with constant step length, FP64 (with the
+                  step-length rule delta and the location rule epsilon).
   * ``line_search_step`` / ``pgd_search`` -- Algorithm 1 with lineSearch taken
                   as backtracking from a maximum step s with the Armijo
                   sufficient-decrease test along the projection arc, FP64.
@@ -176,13 +177,18 @@ def _slices(fixed, B):
     return out
 
 
-def pgd(inst, x0, lr, steps, fixed=None, nthreads=None, delta=0.0):
+def pgd(inst, x0, lr, steps, fixed=None, nthreads=None, delta=0.0, epsilon=0.0):
     """Algorithm 1 with constant step length ``lr``, FP64 throughout.
 
     ``fixed`` may hold several partial assignments (P, n); the restarts are then
     run slice by slice (restarts are independent).  With ``delta`` > lr every
     restart that has not verified after the first iteration has converged
-    (eta = lr < delta) and stops there."""
+    (eta = lr < delta) and stops there.  With ``epsilon`` > 0 a restart that has
+    not verified converges once its new point lies within epsilon of the
+    previous one in every variable (Sec. 3.3's location test); the result then
+    also holds ``done`` (0 running, 1 verified, 2 converged)."""
+    if epsilon > 0:
+        return _pgd_steps(inst, x0, lr, steps, fixed, delta, epsilon, nthreads)
     if fixed is not None and np.asarray(fixed).ndim == 2:
         x0 = np.asarray(x0)
         out = {"x": np.array(x0, dtype=np.float64), "unsat": np.zeros(x0.shape[1], np.int32),
@@ -211,6 +217,43 @@ def pgd(inst, x0, lr, steps, fixed=None, nthreads=None, delta=0.0):
     if rc:
         raise ValueError("orc_pgd failed with status %d" % rc)
     return {"x": x, "unsat": unsat, "first_sat": first, "obj": obj}
+
+
+def _pgd_steps(inst, x0, lr, steps, fixed, delta, epsilon, nthreads):
+    """Algorithm 1 iteration by iteration (gradient, projected step, exact count),
+    for the stopping rules that need the point of every iteration."""
+    x = np.array(x0, dtype=np.float64, copy=True)
+    B = x.shape[1]
+    masks = None
+    if fixed is not None:
+        masks = np.zeros(x.shape, dtype=bool)
+        f = np.asarray(fixed)
+        if f.ndim == 1:
+            masks[:] = f.astype(bool)[:, None]
+        else:
+            for cols, row in _slices(f, B):
+                masks[:, cols] = np.asarray(row, dtype=bool)[:, None]
+    unsat = unsat_count(inst, x)
+    done = (unsat == 0).astype(np.uint8)
+    first = np.where(unsat == 0, 0, -1).astype(np.int32)
+    for t in range(1, steps + 1):
+        if done.all():
+            break
+        g = eval(inst, x, grad=True, nthreads=nthreads)["grad"]
+        xn = np.clip(x - lr * g, -1.0, 1.0)
+        hold = done.astype(bool)[None, :] if masks is None else (masks | done.astype(bool)[None, :])
+        xn = np.where(hold, x, xn)
+        move = np.max(np.abs(xn - x), axis=0) if x.shape[0] else np.zeros(B)
+        x = xn
+        unsat = unsat_count(inst, x)
+        newly = (done == 0) & (unsat == 0)
+        first[newly] = t
+        done[newly] = 1
+        if delta > 0 and lr < delta:
+            done[done == 0] = 2
+        done[(done == 0) & (move < epsilon)] = 2
+    obj = eval(inst, x, grad=False, nthreads=nthreads)["obj"]
+    return {"x": x, "unsat": unsat, "first_sat": first, "obj": obj, "done": done}
 
 
 def unsat_count(inst, x):
@@ -270,10 +313,12 @@ def line_search_step(inst, x, search, fixed=None, done=None, nthreads=None):
             "margin": np.array(margins)}
 
 
-def pgd_search(inst, x0, search, steps, fixed=None, delta=0.0, nthreads=None):
+def pgd_search(inst, x0, search, steps, fixed=None, delta=0.0, nthreads=None, epsilon=0.0):
     """Algorithm 1 with the backtracking lineSearch, FP64: at most ``steps``
     iterations; a restart stops when its point verifies (unsat_count = 0) or,
-    with ``delta`` > 0, when its step length falls below delta."""
+    with ``delta`` > 0, when its step length falls below delta, or, with
+    ``epsilon`` > 0, when its new point lies within epsilon of the previous one
+    in every variable."""
     x = np.array(x0, dtype=np.float64, copy=True)
     B = x.shape[1]
     unsat = unsat_count(inst, x)
@@ -283,6 +328,7 @@ def pgd_search(inst, x0, search, steps, fixed=None, delta=0.0, nthreads=None):
         if done.all():
             break
         r = line_search_step(inst, x, search, fixed=fixed, done=done, nthreads=nthreads)
+        move = np.max(np.abs(r["x"] - x), axis=0) if x.shape[0] else np.zeros(B)
         x = r["x"]
         unsat = unsat_count(inst, x)
         newly = (done == 0) & (unsat == 0)
@@ -290,4 +336,6 @@ def pgd_search(inst, x0, search, steps, fixed=None, delta=0.0, nthreads=None):
         done[newly] = 1
         if delta > 0:
             done[(done == 0) & (r["eta"] < delta)] = 2
+        if epsilon > 0:
+            done[(done == 0) & (move < epsilon)] = 2
     return {"x": x, "unsat": unsat, "done": done, "first_sat": first}

@@ -52,7 +52,7 @@ size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 struct WsLayout {
     int Bp = 0, W = 0;
-    size_t adj = 0, part = 0, part2 = 0, bits = 0, viol = 0, total = 0;
+    size_t adj = 0, part = 0, part2 = 0, bits = 0, viol = 0, moved = 0, total = 0;
 };
 
 WsLayout ws_layout(const afs::HostInstance &H, int B)
@@ -71,6 +71,8 @@ WsLayout ws_layout(const afs::HostInstance &H, int B)
     off = align256(off + (size_t)H.n * l.W * sizeof(uint32_t));
     l.viol = off;
     off = align256(off + (size_t)(H.C + 3) / 4 * 4 * l.W * sizeof(uint32_t));
+    l.moved = off;                      // u8 [n_inst][B]: the epsilon test's "moved" flags
+    off = align256(off + (size_t)H.n_inst * B);
     l.total = off;
     return l;
 }
@@ -654,7 +656,8 @@ afs_status afs_pgd_init(afs_instance *I, int32_t B, const float *x, void *ws, si
     hipError_t e = afs::launch_round(I->D, B, x, bits, P->unsat, s);
     if (e == hipSuccess) e = afs::launch_verify(I->D, B, bits, at<uint32_t>(ws, l.viol), P->unsat, s);
     if (e == hipSuccess)
-        e = afs::launch_finalize(I->H.n_inst * B, B, P->unsat, P->done, P->first_sat, P->counter, afs::FIN_INIT, s);
+        e = afs::launch_finalize(I->H.n_inst * B, B, P->unsat, P->done, P->first_sat, P->counter, afs::FIN_INIT, s,
+                                 nullptr, 0.0f, 0.0f, at<uint8_t>(ws, l.moved));
     return e == hipSuccess ? AFS_OK : dev_fail(e, "PGD init launch");
 }
 
@@ -716,7 +719,7 @@ afs_status afs_search_workspace_bytes(const afs_instance *I, int32_t B, size_t *
 }
 
 static afs_status search_call(afs_instance *I, int32_t B, float *x, const afs_line_search *ls, const uint8_t *fixed,
-                              int32_t n_partial, float delta, void *ws, size_t ws_bytes, void *sws,
+                              int32_t n_partial, float delta, float eps, void *ws, size_t ws_bytes, void *sws,
                               size_t sws_bytes, const afs_pgd_state *P, float *eta_out, hipStream_t s)
 {
     afs_status st = check_call(I, B);
@@ -760,11 +763,12 @@ static afs_status search_call(afs_instance *I, int32_t B, float *x, const afs_li
         if (e != hipSuccess) return dev_fail(e, "line search test launch");
     }
     uint32_t *bits = at<uint32_t>(ws, l.bits);
-    e = afs::launch_search_step(I->D, B, x, g, eta, fixed, rows, P->done, bits, P->unsat, s);
+    uint8_t *moved = eps > 0.0f ? at<uint8_t>(ws, l.moved) : nullptr;
+    e = afs::launch_search_step(I->D, B, x, g, eta, fixed, rows, P->done, bits, P->unsat, s, moved, eps);
     if (e == hipSuccess) e = afs::launch_verify(I->D, B, bits, at<uint32_t>(ws, l.viol), P->unsat, s);
     if (e == hipSuccess)
         e = afs::launch_finalize(B, B, P->unsat, P->done, P->first_sat, P->counter, afs::FIN_STEP, s, eta, 0.0f,
-                                 delta);
+                                 delta, moved, eps);
     return e == hipSuccess ? AFS_OK : dev_fail(e, "line search step launch");
 }
 
@@ -776,7 +780,7 @@ afs_status afs_pgd_search_step(afs_instance *I, int32_t B, float *x, const afs_l
     if (st != AFS_OK) return st;
     DeviceGuard g(I->device);
     if (g.error() != hipSuccess) return dev_fail(g.error(), "hipSetDevice");
-    return search_call(I, B, x, ls, fixed, n_partial, delta, ws, ws_bytes, sws, sws_bytes, P, eta,
+    return search_call(I, B, x, ls, fixed, n_partial, delta, 0.0f, ws, ws_bytes, sws, sws_bytes, P, eta,
                        (hipStream_t)stream);
 }
 
@@ -807,15 +811,16 @@ static afs_status overlapped_step(afs_instance *I, int32_t B, float *x, const af
     if (st != AFS_OK) return st;
     hipError_t e = wait_prev ? hipStreamWaitEvent(s, I->verified, 0) : hipSuccess;
     uint32_t *bits = at<uint32_t>(ws, l.bits);
+    uint8_t *moved = prm->epsilon > 0.0f ? at<uint8_t>(ws, l.moved) : nullptr;
     if (e == hipSuccess)
         e = afs::launch_scatter_step(I->D, B, l.Bp, at<float>(ws, l.adj), x, prm->lr, prm->fixed,
-                                     partial_rows(prm->n_partial), P->done, bits, P->unsat, s);
+                                     partial_rows(prm->n_partial), P->done, bits, P->unsat, s, moved, prm->epsilon);
     if (e == hipSuccess) e = hipEventRecord(I->stepped, s);
     if (e == hipSuccess) e = hipStreamWaitEvent(I->verify, I->stepped, 0);
     if (e == hipSuccess) e = afs::launch_verify(I->D, B, bits, at<uint32_t>(ws, l.viol), P->unsat, I->verify);
     if (e == hipSuccess)
         e = afs::launch_finalize(I->H.n_inst * B, B, P->unsat, P->done, P->first_sat, P->counter, afs::FIN_STEP,
-                                 I->verify, nullptr, prm->lr, prm->delta);
+                                 I->verify, nullptr, prm->lr, prm->delta, moved, prm->epsilon);
     if (e == hipSuccess) e = hipEventRecord(I->verified, I->verify);
     return e == hipSuccess ? AFS_OK : dev_fail(e, "PGD step launch");
 }
@@ -827,6 +832,8 @@ afs_status afs_pgd(afs_instance *I, int32_t B, float *x, const afs_pgd_params *p
     if (st != AFS_OK) return st;
     if (!prm) return fail(AFS_EINVAL, "params is NULL");
     if (prm->max_iters < 0 || prm->poll < 1) return fail(AFS_EINVAL, "max_iters must be >= 0 and poll >= 1");
+    if (!(prm->delta >= 0.0f) || !(prm->epsilon >= 0.0f) || !std::isfinite(prm->epsilon))
+        return fail(AFS_EINVAL, "delta and epsilon must be >= 0 (epsilon finite)");
     if (prm->search && (st = check_search(prm->search)) != AFS_OK) return st;
     if (prm->search && I->H.n_inst != 1) return fail(AFS_EINVAL, "the line search takes a plain instance, not a batch");
     if ((st = check_partial(B, prm->fixed, prm->n_partial)) != AFS_OK) return st;
@@ -885,7 +892,7 @@ afs_status afs_pgd(afs_instance *I, int32_t B, float *x, const afs_pgd_params *p
     // iteration's FE), or the backtracking line search
     auto iterate = [&](int32_t i) {
         if (prm->search)
-            return search_call(I, B, x, prm->search, prm->fixed, prm->n_partial, prm->delta, ws, ws_bytes,
+            return search_call(I, B, x, prm->search, prm->fixed, prm->n_partial, prm->delta, prm->epsilon, ws, ws_bytes,
                                prm->search_ws, prm->search_ws_bytes, P, nullptr, s);
         return overlapped_step(I, B, x, prm, ws, l, P, s, i > 0);
     };
@@ -896,7 +903,7 @@ afs_status afs_pgd(afs_instance *I, int32_t B, float *x, const afs_pgd_params *p
     int32_t counter[4] = {0, 0, 0, 0};
     const int32_t pairs = I->H.n_inst * B;
     for (int32_t t = 0; t < prm->max_iters;) {
-        if (prm->stop_on_sat || prm->delta > 0.0f) {
+        if (prm->stop_on_sat || prm->delta > 0.0f || prm->epsilon > 0.0f) {
             if ((e = read_counter(counter)) != hipSuccess) return finish(dev_fail(e, "reading the counter"));
             if (prm->stop_on_sat && counter[1] > 0) break;
             if (counter[2] >= pairs) break;   // every restart verified or converged

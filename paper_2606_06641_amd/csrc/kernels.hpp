@@ -56,7 +56,8 @@ hipError_t launch_scatter(const DevInstance &I, int B, int Bp, const float *adj,
 // fixed [n_partial][n]: restart b uses row b * n_partial / B (nullptr: none fixed).
 hipError_t launch_scatter_step(const DevInstance &I, int B, int Bp, const float *adj, float *x,
                                float lr, const uint8_t *fixed, int n_partial, const uint8_t *done,
-                               uint32_t *bits, int32_t *unsat, hipStream_t s);
+                               uint32_t *bits, int32_t *unsat, hipStream_t s, uint8_t *moved = nullptr,
+                               float eps = 0.0f);
 
 // obj[b] = sum over tiles of part[t][b] (two fixed-order passes through part2).
 hipError_t launch_obj_reduce(int tiles, int B, int Bp, const float *part, float *part2,
@@ -77,10 +78,13 @@ hipError_t launch_verify(const DevInstance &I, int B, const uint32_t *bits, uint
 enum FinalizeMode { FIN_INIT = 0, FIN_STEP = 1, FIN_VERIFY = 2 };
 // over all count = n_inst * B (sub-instance, restart) pairs.  done: 1 verified,
 // 2 converged (FIN_STEP: step length eta[b] (or eta_const when eta is null) below
-// delta > 0); counter = {t, verified pairs, frozen pairs, 0}.
+// delta > 0, or with eps > 0 no flag in moved [count] set by the step); moved,
+// when given, is cleared at FIN_INIT and after every FIN_STEP.  counter = {t,
+// verified pairs, frozen pairs, 0}.
 hipError_t launch_finalize(int count, int B, const int32_t *unsat, uint8_t *done, int32_t *first_sat,
                            int32_t *counter, int mode, hipStream_t s, const float *eta = nullptr,
-                           float eta_const = 0.0f, float delta = 0.0f);
+                           float eta_const = 0.0f, float delta = 0.0f, uint8_t *moved = nullptr,
+                           float eps = 0.0f);
 
 // ---- line search (search_kernels.hip) ----
 // Trial point of the backtracking search for the restarts still searching
@@ -101,7 +105,7 @@ hipError_t launch_accept(int B, const float *f0, const float *ft, const float *d
 // into bits and unsat = 0, as the fused step of the constant-step path.
 hipError_t launch_search_step(const DevInstance &I, int B, float *x, const float *g, const float *eta,
                               const uint8_t *fixed, int n_partial, const uint8_t *done, uint32_t *bits,
-                              int32_t *unsat, hipStream_t s);
+                              int32_t *unsat, hipStream_t s, uint8_t *moved = nullptr, float eps = 0.0f);
 // Starting points (Sec. 3.4): x[v][b] uniform in [-1, 1) from Philox4x32-10 keyed
 // by seed with counter (b, v, 0, 0), except where values[p][v] != 0 (row p =
 // b * n_partial / B): -1 for +1 (True), +1 for -1 (False).

@@ -100,6 +100,8 @@ struct StepArgs {
     const int32_t *var_inst;
     uint32_t *bits;
     int32_t *unsat;
+    uint8_t *moved;              // [n_inst][B]: set where some variable moves by >= eps (NULL: not tracked)
+    float eps;
     int n, n_partial, n_inst, B, W, nchunks;
     int64_t items, item0;
 };
@@ -131,8 +133,11 @@ __global__ __launch_bounds__(kBlock) void search_step_kernel(StepArgs A)
             const int64_t at = (int64_t)v * A.B + b;
             float xv = A.x[at];
             if (!is_fixed(A.fixed, A.n_partial, A.n, A.B, v, b) && !(done && done[b])) {
+                const float x0 = xv;
                 xv = clip_step(xv, A.g[at], A.eta[b]);
                 A.x[at] = xv;
+                // several variables may store 1 into one flag: every store writes the same value
+                if (A.moved && fabsf(xv - x0) >= A.eps) A.moved[(int64_t)A.var_inst[v] * A.B + b] = 1;
             }
             if (v < A.n_inst) A.unsat[(int64_t)v * A.B + b] = 0;
             nib |= (xv < 0.0f ? 1u : 0u) << e;
@@ -236,12 +241,12 @@ hipError_t launch_accept(int B, const float *f0, const float *ft, const float *d
 
 hipError_t launch_search_step(const DevInstance &I, int B, float *x, const float *g, const float *eta,
                               const uint8_t *fixed, int n_partial, const uint8_t *done, uint32_t *bits,
-                              int32_t *unsat, hipStream_t s)
+                              int32_t *unsat, hipStream_t s, uint8_t *moved, float eps)
 {
     if (B == 0) return hipSuccess;
     StepArgs a{};
     a.x = x; a.g = g; a.eta = eta; a.fixed = fixed; a.done = done; a.var_inst = I.var_inst;
-    a.bits = bits; a.unsat = unsat;
+    a.bits = bits; a.unsat = unsat; a.moved = moved; a.eps = eps;
     a.n = I.n; a.n_partial = n_partial; a.n_inst = I.n_inst; a.B = B; a.W = (B + 31) / 32;
     a.nchunks = (B + kStepChunk - 1) / kStepChunk;
     a.items = (int64_t)I.n * a.nchunks;

@@ -36,7 +36,8 @@ struct ScatterArgs {
     int n, n_partial;
     uint32_t *bits;
     int32_t *unsat;
-    float lr;
+    uint8_t *moved;              // [n_inst][B]: set where some variable moves by >= eps (NULL: not tracked)
+    float lr, eps;
     int B, Bp, W, nchunks;
     int64_t items, item0;        // all items; first item of this launch
 };
@@ -158,8 +159,11 @@ __global__ __launch_bounds__(kBlock) void scatter_step_kernel(ScatterArgs A)
             const int64_t at = (int64_t)v * A.B + b;
             float xv = A.x[at];
             if (!is_fixed(A.fixed, A.n_partial, A.n, A.B, v, b) && !(done && done[b])) {
+                const float x0 = xv;
                 xv = project_step(xv, elem(g, e), A.lr);
                 A.x[at] = xv;
+                // several variables may store 1 into one flag: every store writes the same value
+                if (A.moved && fabsf(xv - x0) >= A.eps) A.moved[(int64_t)A.var_inst[v] * A.B + b] = 1;
             }
             if (v < A.n_inst) A.unsat[(int64_t)v * A.B + b] = 0;
             nib |= (xv < 0.0f ? 1u : 0u) << e;
@@ -424,7 +428,8 @@ __global__ __launch_bounds__(kCountWaves * kWave) void count_kernel(CountArgs A)
 // plain instance) or eta_const (constant step); delta <= 0 turns the test off.
 __global__ __launch_bounds__(1024) void finalize_kernel(int count, int B, const int32_t *unsat, uint8_t *done,
                                                         int32_t *first_sat, int32_t *counter, int mode,
-                                                        const float *eta, float eta_const, float delta)
+                                                        const float *eta, float eta_const, float delta,
+                                                        uint8_t *moved, float eps)
 {
     __shared__ int red[2][1024 / kWave];
     const int t = (mode == FIN_STEP) ? counter[0] + 1 : 0;
@@ -435,6 +440,7 @@ __global__ __launch_bounds__(1024) void finalize_kernel(int count, int B, const 
         if (mode == FIN_INIT) {
             done[b] = ok ? 1 : 0;
             first_sat[b] = ok ? 0 : -1;
+            if (moved) moved[b] = 0;
             nsat += ok;
             nfrozen += ok;
         } else if (mode == FIN_STEP) {
@@ -444,6 +450,11 @@ __global__ __launch_bounds__(1024) void finalize_kernel(int count, int B, const 
                 first_sat[b] = t;
             }
             if (!d && delta > 0.0f && (eta ? eta[b % B] : eta_const) < delta) done[b] = d = 2;
+            if (moved) {
+                // within eps of the previous point in every variable; cleared for the next step
+                if (!d && eps > 0.0f && !moved[b]) done[b] = d = 2;
+                moved[b] = 0;
+            }
             nsat += d == 1;
             nfrozen += d != 0;
         } else {
@@ -549,11 +560,12 @@ hipError_t launch_scatter(const DevInstance &I, int B, int Bp, const float *adj,
 
 hipError_t launch_scatter_step(const DevInstance &I, int B, int Bp, const float *adj, float *x,
                                float lr, const uint8_t *fixed, int n_partial, const uint8_t *done,
-                               uint32_t *bits, int32_t *unsat, hipStream_t s)
+                               uint32_t *bits, int32_t *unsat, hipStream_t s, uint8_t *moved, float eps)
 {
     if (B == 0) return hipSuccess;
     ScatterArgs a = scatter_args(I, B, Bp, adj);
     a.x = x; a.lr = lr; a.fixed = fixed; a.done = done; a.bits = bits; a.unsat = unsat;
+    a.moved = moved; a.eps = eps;
     a.n = I.n; a.n_partial = n_partial;
     return for_launch_chunks(a.items, [&](int64_t first, int64_t count) {
         a.item0 = first;
@@ -650,11 +662,11 @@ hipError_t launch_verify(const DevInstance &I, int B, const uint32_t *bits, uint
 
 hipError_t launch_finalize(int count, int B, const int32_t *unsat, uint8_t *done, int32_t *first_sat,
                            int32_t *counter, int mode, hipStream_t s, const float *eta, float eta_const,
-                           float delta)
+                           float delta, uint8_t *moved, float eps)
 {
     if (count == 0) return hipSuccess;
     hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(1024), 0, s, count, B, unsat, done, first_sat, counter, mode,
-                       eta, eta_const, delta);
+                       eta, eta_const, delta, moved, eps);
     return hipGetLastError();
 }
 

@@ -328,3 +328,91 @@ def test_invalid_arguments_are_rejected_before_any_launch():
     assert rc == afsat.AFS_EINVAL and b"aligned" in lib.afs_last_error()
     torch.cuda.synchronize()
     assert int(st["counter"][0]) == 0                    # nothing ran
+
+
+# x1 alone in a clause (F = x1 falls by lr per step to the bound); x2, x3 in an
+# odd and an even XOR whose expansions cancel exactly: the input never verifies
+DRIFT = W.Instance(n=3, con_off=np.array([0, 1, 3, 5], np.int64), lits=np.array([1, 2, 3, 2, 3], np.int32),
+                   types=np.array([W.OR, W.XOR, W.XOR], np.int32), params=np.array([0, 1, 0], np.int32))
+
+
+@pytest.mark.parametrize("graph", [True, False])
+def test_location_rule_by_hand(graph):
+    """Restarts whose x1 starts at 0.9, 0.5, 0.15 and -0.95 move 0.3 per step until
+    the bound: with epsilon = 0.2 each converges at the first move below 0.2 and
+    stays, exactly as the oracle's hand-pinned rule."""
+    d = afsat.Instance.from_arrays(DRIFT)
+    starts = [0.9, 0.5, 0.15, -0.95]
+    x0 = np.array([starts, [0.25] * 4, [-0.5] * 4], dtype=np.float32)
+    log("case: location rule by hand graph=%s" % graph)
+    x = parity.to_dev(x0)
+    r = d.pgd(x, 0.3, 20, poll=3, stop_on_sat=False, graph=graph, epsilon=0.2)
+    want = oracle.pgd(DRIFT, x0.astype(np.float64), 0.3, 20, epsilon=0.2)
+    np.testing.assert_array_equal(r["done"].cpu().numpy(), want["done"])
+    np.testing.assert_allclose(x.cpu().numpy(), want["x"], rtol=0, atol=1e-6)
+    assert int(r["counter"][2]) == 4 and r["iters"] < 20      # all converged: the driver stopped
+
+
+def test_location_rule_equals_a_replay_of_the_steps():
+    """The driver's epsilon rule against a replay with the plain step call: after
+    every step, the restarts still running whose largest move (FP32, as the
+    kernel takes it) is below epsilon are marked converged by hand.  Points,
+    done codes and counters agree exactly."""
+    inst = W.planted_3sat(n=200, m=852, instance=6)
+    d = afsat.Instance.from_arrays(inst)
+    B, T, eps, lr = 96, 60, 0.02, 0.1
+    x0 = W.uniform_x0(inst.n, B, workload=1, instance=6)
+    log("case: location rule replay n=%d B=%d T=%d" % (inst.n, B, T))
+    xa = parity.to_dev(x0)
+    r = d.pgd(xa, lr, T, poll=7, stop_on_sat=False, graph=True, epsilon=eps)
+    xb = parity.to_dev(x0)
+    st = d.pgd_state(B)
+    d.pgd_init(xb, st)
+    for _ in range(T):
+        prev = xb.clone()
+        d.pgd_step(xb, st, lr)
+        move = (xb - prev).abs().amax(dim=0)
+        conv = (st["done"] == 0) & (move < eps)
+        st["done"][conv] = 2
+    torch.cuda.synchronize()
+    done = r["done"].cpu().numpy()
+    assert (done == 2).sum() > 5 and (done == 0).sum() > 5      # both outcomes occur
+    np.testing.assert_array_equal(done, st["done"].cpu().numpy())
+    assert torch.equal(xa, xb)
+    np.testing.assert_array_equal(r["first_sat"].cpu().numpy(), st["first_sat"].cpu().numpy())
+    assert int(r["counter"][1]) == int((done == 1).sum()) and int(r["counter"][2]) == int((done != 0).sum())
+
+
+def test_location_rule_above_every_move():
+    """epsilon = 3 exceeds any move inside [-1, 1]: every restart that did not
+    verify converges after its first iteration, at the oracle's point."""
+    inst = W.planted_3sat(n=100, m=426, instance=3)
+    d = afsat.Instance.from_arrays(inst)
+    B = 40
+    x0 = W.uniform_x0(inst.n, B, workload=1, instance=3)
+    x = parity.to_dev(x0)
+    r = d.pgd(x, 0.1, 50, poll=5, stop_on_sat=False, graph=True, epsilon=3.0)
+    assert r["iters"] == 5 and set(np.unique(r["done"].cpu().numpy())) <= {1, 2}
+    want = oracle.pgd(inst, x0, 0.1, 50, epsilon=3.0)
+    np.testing.assert_array_equal(r["done"].cpu().numpy(), want["done"])
+    np.testing.assert_allclose(x.cpu().numpy(), want["x"], rtol=0, atol=1e-5)
+
+
+def test_location_rule_with_the_line_search():
+    d = afsat.Instance.from_arrays(DRIFT)
+    x0 = np.array([[0.5, 0.9], [0.25, 0.25], [-0.5, -0.5]], dtype=np.float32)
+    ls = afsat.LineSearch(4.0, 0.5, 0.9, 3)
+    log("case: location rule with line search")
+    x = parity.to_dev(x0)
+    r = d.pgd(x, 0.1, 6, poll=1, stop_on_sat=False, graph=False, search=ls, epsilon=0.1)
+    want = oracle.pgd_search(DRIFT, x0.astype(np.float64), (4.0, 0.5, 0.9, 3), 6, epsilon=0.1)
+    np.testing.assert_array_equal(r["done"].cpu().numpy(), want["done"])
+    np.testing.assert_allclose(x.cpu().numpy(), want["x"], rtol=0, atol=1e-6)
+
+
+def test_epsilon_is_validated():
+    d = afsat.Instance.from_arrays(DRIFT)
+    x = parity.to_dev(np.zeros((3, 4), np.float32))
+    for bad in (-1.0, float("nan"), float("inf")):
+        with pytest.raises(afsat.AfsError):
+            d.pgd(x, 0.1, 3, epsilon=bad)

@@ -165,3 +165,55 @@ def test_vectorised_philox_matches_scalar():
     got = philox_first_words(c0, c1, key)
     want = [philox4x32_10((int(a), int(b), 0, 0), key)[0] for a, b in zip(c0, c1)]
     np.testing.assert_array_equal(got, np.array(want, dtype=np.uint64))
+
+
+# x1 alone in a clause (F = x1: it falls by lr per step until the bound -1);
+# x2, x3 in an odd and an even XOR, one of which is always violated and whose
+# expansions cancel (zero gradient): the input never verifies.
+DRIFT = Inst(3, [(oracle.OR, 0, [1]), (oracle.XOR, 1, [2, 3]), (oracle.XOR, 0, [2, 3])])
+
+
+@pytest.mark.parametrize("eps,t_conv", [(0.5, 1), (0.2, 7), (0.05, 8)])
+def test_location_rule_by_hand(eps, t_conv):
+    """From x1 = 0.9 with lr = 0.3 the moves are 0.3 six times (x1: 0.6 .. -0.9),
+    then 0.1 onto the bound, then 0: the restart converges at the first
+    iteration whose move is below epsilon, and its point stays there."""
+    x0 = np.array([[0.9], [0.25], [-0.5]])
+    for steps in (t_conv - 1, t_conv, t_conv + 5):
+        r = oracle.pgd(DRIFT, x0, 0.3, steps, epsilon=eps)
+        assert r["first_sat"][0] == -1 and r["unsat"][0] >= 1
+        assert r["done"][0] == (2 if steps >= t_conv else 0)
+        want = max(-1.0, 0.9 - 0.3 * min(steps, t_conv))
+        np.testing.assert_allclose(r["x"][:, 0], [want, 0.25, -0.5], atol=1e-12)
+
+
+def test_location_rule_off_and_fixed():
+    """epsilon = 0 keeps the plain run; a held x1 means no move at all, so the
+    restart converges at the first iteration."""
+    x0 = np.array([[0.9], [0.25], [-0.5]])
+    plain = oracle.pgd(DRIFT, x0, 0.3, 9)
+    assert "done" not in plain and plain["x"][0, 0] == -1.0
+    r = oracle.pgd(DRIFT, x0, 0.3, 9, fixed=np.array([1, 0, 0], np.uint8), epsilon=1e-9)
+    assert r["done"][0] == 2
+    np.testing.assert_array_equal(r["x"][:, 0], x0[:, 0])
+
+
+def test_location_rule_agrees_with_the_plain_run_until_it_stops():
+    inst = workloads.planted_3sat(n=60, m=240, instance=5)
+    x0 = workloads.uniform_x0(inst.n, 12, workload=1, instance=5).astype(np.float64)
+    a = oracle.pgd(inst, x0, 0.1, 40, epsilon=1e-12)       # moves of exactly 0 only
+    b = oracle.pgd(inst, x0, 0.1, 40)
+    running = a["done"] != 2
+    np.testing.assert_allclose(a["x"][:, running], b["x"][:, running], atol=1e-12)
+    np.testing.assert_array_equal(a["first_sat"], b["first_sat"])
+
+
+def test_line_search_location_rule():
+    """The line search on F = x1 from 0.5 with s = 4 lands on the bound at once
+    (move 1.5); nothing moves after that, and the clause is then satisfied, so
+    the restart verifies rather than converges; with the XOR pair beside it the
+    second iteration's zero move converges it."""
+    r = oracle.pgd_search(CLAUSE1, np.array([[0.5]]), (4.0, 0.5, 0.9, 3), 5, epsilon=0.1)
+    assert r["done"][0] == 1 and r["first_sat"][0] == 1
+    r = oracle.pgd_search(DRIFT, np.array([[0.5], [0.25], [-0.5]]), (4.0, 0.5, 0.9, 3), 5, epsilon=0.1)
+    assert r["done"][0] == 2 and r["x"][0, 0] == -1.0

@@ -77,6 +77,8 @@ def main(argv=None, out=None):
     ap.add_argument("--armijo", type=float, default=1e-4, help="line search: sufficient-decrease constant")
     ap.add_argument("--trials", type=int, default=8, help="line search: trials per iteration")
     ap.add_argument("--delta", type=float, default=0.0, help="stop a restart once its step length < delta")
+    ap.add_argument("--epsilon", type=float, default=0.0,
+                    help="stop a restart once no variable of it moves by epsilon or more in an iteration")
     ap.add_argument("--poll", type=int, default=10, help="iterations between checks for a verified restart")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--partial", help="file of partial assignments, one per line, ending in 0")
@@ -128,7 +130,7 @@ def main(argv=None, out=None):
     search = afsat.LineSearch(a.max_step, a.shrink, a.armijo, a.trials) if a.line_search else None
     t1 = time.perf_counter()
     st = inst.pgd(x, a.lr, a.iters, fixed=fixed, poll=a.poll, stop_on_sat=True, graph=not a.no_graph,
-                  search=search, delta=a.delta)
+                  search=search, delta=a.delta, epsilon=a.epsilon)
     torch.cuda.synchronize(dev)
     dt = time.perf_counter() - t1
     unsat = st["unsat"].cpu().numpy()

@@ -383,6 +383,34 @@ def test_location_rule_equals_a_replay_of_the_steps():
     assert int(r["counter"][1]) == int((done == 1).sum()) and int(r["counter"][2]) == int((done != 0).sum())
 
 
+def test_location_rule_on_a_batch():
+    """A block-diagonal batch: the rule is taken per (part, restart) over the
+    part's own variables.  Driver against a replay with the plain step call."""
+    parts = [W.planted_3sat(n=n, m=int(4.26 * n), instance=10 + i) for i, n in enumerate((60, 90, 150))]
+    d = afsat.Instance.batch(parts)
+    B, T, eps, lr = 64, 40, 0.02, 0.1
+    off = d.var_offsets()
+    x0 = np.random.default_rng(17).uniform(-1, 1, size=(d.n, B)).astype(np.float32)
+    log("case: location rule on a batch n=%d parts=%d B=%d" % (d.n, d.n_inst, B))
+    xa = parity.to_dev(x0)
+    r = d.pgd(xa, lr, T, poll=5, stop_on_sat=False, graph=True, epsilon=eps)
+    xb = parity.to_dev(x0)
+    st = d.pgd_state(B)
+    d.pgd_init(xb, st)
+    for _ in range(T):
+        prev = xb.clone()
+        d.pgd_step(xb, st, lr)
+        for p in range(d.n_inst):
+            move = (xb[off[p]:off[p + 1]] - prev[off[p]:off[p + 1]]).abs().amax(dim=0)
+            conv = (st["done"][p] == 0) & (move < eps)
+            st["done"][p][conv] = 2
+    torch.cuda.synchronize()
+    done = r["done"].cpu().numpy()
+    assert done.shape == (3, B) and (done == 2).sum() > 5 and (done == 0).sum() > 5
+    np.testing.assert_array_equal(done, st["done"].cpu().numpy())
+    assert torch.equal(xa, xb)
+
+
 def test_location_rule_above_every_move():
     """epsilon = 3 exceeds any move inside [-1, 1]: every restart that did not
     verify converges after its first iteration, at the oracle's point."""

@@ -357,8 +357,8 @@ typedef struct {
     int32_t max_iters;      /* iteration budget d (>= 0)                                  */
     int32_t poll;           /* iterations between reads of the done counter (>= 1)        */
     int32_t stop_on_sat;    /* != 0: stop at the first read that finds a verified restart */
-    int32_t use_graph;      /* != 0: capture `poll` iterations once in a HIP graph and
-                               replay it (the iterations are identical either way)        */
+    int32_t use_graph;      /* != 0: capture min(poll, 64) iterations once in a HIP graph
+                               and replay it (the iterations are identical either way)    */
     const uint8_t *fixed;   /* device u8 [n_partial][n] or NULL: variables held at their
                                value (partial assignments, Sec. 3.4)                       */
     int32_t n_partial;      /* rows of fixed (0 reads as 1)                                 */

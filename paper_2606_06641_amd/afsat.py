@@ -521,7 +521,8 @@ class Instance:
         Stops after ``steps`` iterations, or (``stop_on_sat``) once any restart
         verifies, or once every restart has verified or converged; the driver
         reads the counter every ``poll`` iterations.  With ``graph`` the driver
-        captures ``poll`` iterations once in a HIP graph and replays it.
+        captures ``poll`` iterations (at most 64) once in a HIP graph and replays
+        it.
         Returns the state (unsat, done, first_sat, counter), x, the number of
         iterations and, with ``obj``, the objective at the final point."""
         B = self._check_x(x)

@@ -797,6 +797,9 @@ afs_status afs_init_points(afs_instance *I, int32_t B, uint64_t seed, const int8
     return e == hipSuccess ? AFS_OK : dev_fail(e, "start point launch");
 }
 
+// Most iterations the driver captures into one graph.
+constexpr int32_t kGraphIters = 64;
+
 // One constant-step iteration of the driver with the verification on the
 // instance's verify stream: FE of X_(t-1) on s; the step waits for the previous
 // iteration's verification (it rewrites the bits and counts that one reads, and
@@ -909,23 +912,29 @@ afs_status afs_pgd(afs_instance *I, int32_t B, float *x, const afs_pgd_params *p
             if (counter[2] >= pairs) break;   // every restart verified or converged
         }
         const int32_t n = std::min(prm->poll, prm->max_iters - t);
-        if (prm->use_graph && n == prm->poll) {
-            if (!exec) {
-                // capture `poll` iterations once; every launch in them is allocation- and sync-free
-                if ((e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal)) != hipSuccess)
-                    return finish(dev_fail(e, "hipStreamBeginCapture"));
-                afs_status cs = AFS_OK;
-                for (int32_t i = 0; i < n && cs == AFS_OK; ++i) cs = iterate(i);
-                if (cs == AFS_OK && (e = join()) != hipSuccess) cs = dev_fail(e, "joining the verify stream");
-                const hipError_t ec = hipStreamEndCapture(s, &graph);
-                if (cs != AFS_OK) return finish(cs);
-                if (ec != hipSuccess) return finish(dev_fail(ec, "hipStreamEndCapture"));
-                if ((e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0)) != hipSuccess)
-                    return finish(dev_fail(e, "hipGraphInstantiate"));
-            }
+        // with use_graph, whole blocks of `block` iterations replay one captured
+        // graph (at most kGraphIters iterations, so a long poll period does not
+        // make a huge graph); what is left of the poll period runs eagerly
+        const int32_t block = std::min(prm->poll, kGraphIters);
+        const int32_t replays = prm->use_graph ? n / block : 0;
+        if (replays > 0 && !exec) {
+            // capture `block` iterations once; every launch in them is allocation- and sync-free
+            if ((e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+                return finish(dev_fail(e, "hipStreamBeginCapture"));
+            afs_status cs = AFS_OK;
+            for (int32_t i = 0; i < block && cs == AFS_OK; ++i) cs = iterate(i);
+            if (cs == AFS_OK && (e = join()) != hipSuccess) cs = dev_fail(e, "joining the verify stream");
+            const hipError_t ec = hipStreamEndCapture(s, &graph);
+            if (cs != AFS_OK) return finish(cs);
+            if (ec != hipSuccess) return finish(dev_fail(ec, "hipStreamEndCapture"));
+            if ((e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0)) != hipSuccess)
+                return finish(dev_fail(e, "hipGraphInstantiate"));
+        }
+        for (int32_t r = 0; r < replays; ++r)
             if ((e = hipGraphLaunch(exec, s)) != hipSuccess) return finish(dev_fail(e, "hipGraphLaunch"));
-        } else {
-            for (int32_t i = 0; i < n; ++i)
+        const int32_t rest = n - replays * block;
+        if (rest > 0) {
+            for (int32_t i = 0; i < rest; ++i)
                 if ((st = iterate(i)) != AFS_OK) return finish(st);
             if ((e = join()) != hipSuccess) return finish(dev_fail(e, "joining the verify stream"));
         }

@@ -122,6 +122,17 @@ def test_graph_replay_equals_eager(kind):
     assert torch.equal(xa, xb)
     for k in ("unsat", "done", "first_sat", "counter", "obj"):
         assert torch.equal(ra[k], rb[k]), k
+    if kind == "3sat":
+        # a poll period longer than one captured graph (64 iterations): two
+        # replays and 22 eager iterations per period, then an eager tail
+        xl = parity.to_dev(x0)
+        rl = d.pgd(xl, lr=0.1, steps=160, poll=150, stop_on_sat=False, graph=True, obj=True)
+        xe = parity.to_dev(x0)
+        re_ = d.pgd(xe, lr=0.1, steps=160, poll=150, stop_on_sat=False, graph=False, obj=True)
+        torch.cuda.synchronize()
+        assert rl["iters"] == re_["iters"] == 160 and torch.equal(xl, xe)
+        for k in ("unsat", "done", "first_sat", "counter", "obj"):
+            assert torch.equal(rl[k], re_[k]), k
     # the driver (whose verification overlaps the next iteration's FE on a stream
     # of its own) equals 40 plain afs_pgd_step calls on one stream
     xs = parity.to_dev(x0)

@@ -163,8 +163,10 @@ afs_status afs_batch_create(const afs_instance *const *parts, int32_t n_parts, c
 /* First variable of each part of a batch: var0 int32 [n_inst+1] (host). */
 afs_status afs_batch_var_offsets(const afs_instance *inst, int32_t *var0);
 
-/* Free the instance and its device tables.  NULL is accepted.  The caller must
- * make sure no enqueued work still uses it. */
+/* Free the instance and its device tables.  NULL is accepted.  Waits for all
+ * work on the instance's device to finish first (a device-wide synchronisation),
+ * so work still queued on any stream never reads freed tables; the caller's own
+ * buffers stay the caller's. */
 void afs_instance_destroy(afs_instance *inst);
 
 afs_status afs_instance_info(const afs_instance *inst, afs_info *out);

@@ -141,6 +141,8 @@ void release(afs_instance *I)
     if (!I) return;
     if (I->device >= 0) {
         DeviceGuard g(I->device);
+        // work still queued on any stream may read the tables: let the device finish first
+        (void)hipDeviceSynchronize();
         for (void *p : I->allocs) (void)hipFree(p);
         if (I->fork) (void)hipEventDestroy(I->fork);
         if (I->join) (void)hipEventDestroy(I->join);

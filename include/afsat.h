@@ -434,6 +434,7 @@ typedef struct afs_gnn afs_gnn;
 
 /* Create with seeded He-normal weights; rounds 1..8. */
 afs_status afs_gnn_create(int32_t rounds, uint64_t seed, int32_t device, afs_gnn **out);
+/* Free the network; waits for all work on its device to finish first. */
 void afs_gnn_destroy(afs_gnn *net);
 afs_status afs_gnn_num_params(const afs_gnn *net, int64_t *count);
 /* Synchronous host copies of the flat arrays: which = 0 parameters, 1 gradients,

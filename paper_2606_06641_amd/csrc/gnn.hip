@@ -903,6 +903,7 @@ void afs_gnn_destroy(afs_gnn *G)
 {
     if (!G) return;
     Dev dg(G->device);
+    (void)hipDeviceSynchronize();   // queued work may still read the parameters
     for (float *b : {G->p, G->g, G->m, G->v}) if (b) (void)hipFree(b);
     delete G;
 }

@@ -62,7 +62,7 @@ def test_forward_and_vjp_match_eval_and_oracle():
     assert torch.equal(d.eval_adjoint(x.detach()), e["grad"])
 
 
-def test_config4_long_card_autograd():
+def test_longcard50k_autograd():
     """n=50k, 200k clauses (k 3-10) and 1,000 CARD (k 256-1,024), 512 restarts,
     FE and gradient through FEObjective; oracle gradient on 8 sampled restarts and
     FP64 central differences (h = 1e-3) at 48 sampled (variable, restart) pairs."""

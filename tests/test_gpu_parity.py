@@ -149,19 +149,19 @@ def test_empty_instance():
     assert out["obj"].numel() == 0
 
 
-def test_config1_planted_3sat_parity():
+def test_planted_3sat_n100_parity():
     inst = W.planted_3sat(instance=0)
     x = W.uniform_x0(inst.n, 32, workload=1)
     check(inst, x, "planted 3-SAT n=100 m=426 B=32")
 
 
-def test_config2_mixed_full_size():
+def test_mixed10k_full_size():
     inst = W.mixed_10k()
     x = W.uniform_x0(inst.n, 1024, workload=2)
     check(inst, x, "mixed n=10k B=1024 (all restarts)")
 
 
-def test_config4_long_card_sampled():
+def test_longcard50k_sampled():
     """n=50k, 200k clauses, 1k CARD k 256-1024, B=512 on the GPU; the oracle checks
     16 sampled restart columns (columns are independent)."""
     inst = W.long_card_50k()
@@ -173,11 +173,11 @@ def test_config4_long_card_sampled():
     cols = np.random.default_rng(4).choice(B, size=16, replace=False)
     orc = oracle.eval(inst, x[:, cols], fe=True, adj=True, grad=True)
     sub = {k: (v[..., cols] if v.ndim == 2 else v[cols]) for k, v in gpu.items()}
-    rows = parity.compare(inst, d, sub, orc, "cfg4 sampled")
+    rows = parity.compare(inst, d, sub, orc, "longcard50k sampled")
     log(parity.format_rows(rows))
 
 
-def test_config3_batch64_full_size_sampled():
+def test_batch64_full_size_sampled():
     """The 64-instance uneven batch at full size (n log-uniform 500-50,000, 27.8M
     literal occurrences) and 256 restarts, packed block-diagonally with the tuned
     shapes exactly as the bench runs it; the oracle checks 8 sampled restart
@@ -382,7 +382,7 @@ def test_pgd_driver_keeps_fixed_variables():
     assert np.mean(xs[~f] != x0[~f]) > 0.9
 
 
-def test_config1_end_to_end_solves():
+def test_planted_3sat_end_to_end_solves():
     """Algorithm 1 on planted 3-SAT (n=100, m=426, the 4.26 threshold ratio), 32
     restarts, lr 0.1, 200 steps.  Trajectories are chaotic, so success is compared
     per instance with the oracle's own FP64 PGD run, not restart by restart; every

@@ -58,6 +58,21 @@ def test_decomposed_fe_and_gradient_parity(max_len):
                    "max_len=%d" % max_len)
 
 
+def test_weighted_decomposition_parity():
+    """Each piece carries its constraint's weight: the weighted objective and
+    gradient of the decomposed instance against the oracle on the same arrays."""
+    inst = chain_planted(2)
+    inst.weights = np.random.default_rng(5).uniform(0.5, 3.0, size=inst.n_cons).astype(np.float32)
+    dec = afsat.decompose(inst, 20)
+    assert np.array_equal(dec.weights, inst.weights[dec.origin])
+    log("case: weighted decomposed parity n=%d C=%d" % (dec.n, len(dec.types)))
+    d = afsat.Instance.from_arrays(dec)
+    x = W.uniform_x0(dec.n, 64, workload=6, instance=20)
+    ref = W.Instance(n=dec.n, con_off=dec.con_off, lits=dec.lits, types=dec.types, params=dec.params,
+                     weights=dec.weights)
+    parity.compare(ref, d, parity.gpu_eval(d, x), oracle.eval(ref, x, fe=True, adj=True, grad=True), "weighted")
+
+
 @pytest.mark.parametrize("max_len", [3, 12])
 def test_completed_witness_verifies_and_counts_match(max_len):
     inst = chain_planted(1)

@@ -3,16 +3,22 @@
 One step is one iteration of Algorithm 1 over the whole batch: FE + gradient of
 every constraint at every restart (all length buckets), the per-variable
 gradient sum, the projected step, rounding and the exact unsat count.  The
-workload is a planted mixed instance with n = 10,000 variables (30,000 clauses of
-length 3-8, 2,000 XOR of length 3-5, 500 at-least-K cardinality constraints of
-length 20-200) and 1,024 restarts, all resident in HBM before timing starts.
+headline workload is the largest single-GPU one: 64 planted instances of uneven
+size (n log-uniform 500-50,000; 27.8M literal occurrences) packed into one
+block-diagonal batch with 256 restarts each, all resident in HBM before timing
+starts.  After the headline line, the same measurement runs on the mixed
+n = 10,000 instance (1,024 restarts) and, as a forward + adjoint pass through
+the autograd function, on the long-cardinality n = 50,000 instance (512
+restarts); their lines go to stderr.
 
 value = B * L / step time  (literal-evaluations per second; L = literal
 occurrences).  The JSON line also carries the roofline of the dominant kernel
-(timed with HIP events on the stream it runs on, inside the timed region) and
-the FP64 CPU oracle timed on this host on a bounded sample.
+(timed with HIP events on the stream it runs on, inside the timed region), the
+per-bucket roofline fractions, the peak probes, and the FP64 CPU oracle timed on
+this host on a bounded sample.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+                       [--no-extra] [--no-cpu-baseline]
 """
 import argparse
 import hashlib
@@ -29,13 +35,32 @@ PEAK_HBM_GBS = 8000.0          # MI355X HBM3E, GB/s
 PEAK_FP32_TFLOPS = 157.3       # MI355X FP32 vector, TFLOP/s
 PEAK_BF16_TFLOPS = 2500.0      # MI355X dense BF16 MFMA, TFLOP/s
 
+WORKLOAD_SEED = {"mixed10k": 2, "batch64": 3, "longcard50k": 4, "longchain20k": 6}
+# oracle baseline sample: restart columns (0 = all of them)
+CPU_RESTARTS = {"mixed10k": 0, "batch64": 16, "longcard50k": 16, "longchain20k": 16}
+
+
+def flops_per_literal_eval(k):
+    """Algorithmic FP32 flops of one literal-eval (one literal of a length-k
+    constraint at one restart, FE + gradient) in the complex-product form: per
+    complex root, forward 10 (factor 4, complex multiply 6) and backward 16
+    (suffix update 6, leave-one-out product 6, contraction 4); per literal of the
+    real root (k odd) 1 + 4.  F_k = 26 floor(k/2) + 5 (k mod 2)."""
+    return 26 * (k // 2) + 5 * (k % 2)
+
 
 def algorithmic_flops(k):
-    """FP32 flops of FE + gradient for one constraint of length k at one restart.
-    Per complex root and literal: the factor's imaginary part z = -tan(h) y (1),
-    one step of the prefix product and one of the suffix product by (1 + i z)
-    (2 FMA each = 4 + 4), and the adjoint contraction Re(prefix * suffix) (2 FMA =
-    4): 13.  Per literal of the real root (k odd): 1 + 1 + 2 = 4."""
+    """F_k flops for the k literal-evals of one constraint at one restart."""
+    return k * flops_per_literal_eval(k)
+
+
+def executed_flops(k):
+    """Flops the kernels execute for one constraint at one restart in the
+    rotated-factor form (each factor alpha (1 + i z) with the alpha powers in the
+    tables): per complex root and literal z = -tan(h) y (1), one prefix and one
+    suffix step by (1 + i z) (2 FMA each), the adjoint contraction (2 FMA): 13;
+    per literal of the real root 4.  Cross-lane products, rescaling and padding
+    are not counted."""
     return 13 * (k // 2) * k + 4 * k * (k % 2)
 
 
@@ -44,7 +69,7 @@ def kernel_source_hash():
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def stored_traffic(kernel_name):
+def stored_traffic(kernel_name, workload):
     """HBM traffic per launch from the committed rocprofv3 counter summary, or None
     when it is missing or the kernel source changed since it was taken."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
@@ -53,15 +78,16 @@ def stored_traffic(kernel_name):
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    e = t.get(kernel_name)
+    e = t.get("%s@%s" % (kernel_name, workload))
     if not e or e.get("fe_kernels_sha256_16") != kernel_source_hash():
         return None
     return e.get("bytes_per_launch")
 
 
-def cpu_baseline(inst, x0, lr, budget_s=12.0, threads=0, restarts=0):
-    """The FP64 oracle (eval + step + verify) timed on this host's cores (or
-    `threads` of them), on all restarts or the first `restarts`."""
+def cpu_baseline(inst, x0, lr, budget_s=12.0, threads=0, restarts=0, pgd=True):
+    """The FP64 oracle timed on this host's cores (or `threads` of them), on all
+    restarts or the first `restarts`: FE + gradient, and with `pgd` the step and
+    the verification too (one Algorithm 1 iteration), repeated until budget_s."""
     import numpy as np
     import oracle
     threads = threads or oracle.default_threads()
@@ -73,16 +99,54 @@ def cpu_baseline(inst, x0, lr, budget_s=12.0, threads=0, restarts=0):
     t0 = time.perf_counter()
     while True:
         g = oracle.eval(inst, x, grad=True, nthreads=threads)["grad"]
-        x = oracle.step(x, g, lr)
-        oracle.verify(inst, x.astype(np.float32))
+        if pgd:
+            x = oracle.step(x, g, lr)
+            oracle.verify(inst, x.astype(np.float32))
         reps += 1
         t_used = time.perf_counter() - t0
         if t_used >= budget_s or reps >= 50:
             break
     value = B * inst.n_lits * reps / t_used
+    what = "full PGD iterations (FE+grad, step, verify)" if pgd else "FE + gradient passes"
     return {"value": value, "unit": "literal-evals/s", "cores": threads, "kind": "oracle",
-            "sample": "same instance, %s %d restarts, %d full PGD iterations (FE+grad, step, "
-                      "verify) in FP64, %.1f s" % ("the first" if restarts else "all", B, reps, t_used)}
+            "sample": "same instance, %s %d restarts, %d %s in FP64, %.1f s" % (
+                "the first" if restarts else "all", B, reps, what, t_used)}
+
+
+def timed(fn, reps):
+    """Mean milliseconds of `reps` calls of fn (one launch each) on the current stream."""
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        work = fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps, work
+
+
+def run_probes():
+    """The peak probes (afs_probe_*): plain FP32 FMA issue, dense BF16 MFMA and a
+    streaming copy, each timed over several launches with HIP events."""
+    from paper_2606_06641_amd import afsat
+    blocks = 256 * 8 * 4                   # 32 waves per CU
+    ms, fl = timed(lambda: afsat.probe("fma", blocks, iters=4096), 5)
+    fma = fl / (ms * 1e-3) / 1e12
+    ms, fl = timed(lambda: afsat.probe("mfma_bf16", blocks, iters=512), 5)
+    mfma = fl / (ms * 1e-3) / 1e12
+    nbytes = 1 << 30
+    ms, by = timed(lambda: afsat.probe("copy", 256 * 16, nbytes=nbytes), 10)
+    copy = by / (ms * 1e-3) / 1e9
+    afsat.probe._bufs = None
+    out = {"fp32_fma_tflops": fma, "bf16_mfma_tflops": mfma, "hbm_copy_gbs": copy,
+           "note": "measured on this device by afs_probe_fma (16 independent plain FP32 FMA chains per lane, "
+                   "no packed instructions), afs_probe_mfma_bf16 (8 independent v_mfma_f32_16x16x32_bf16 "
+                   "accumulators per wave) and afs_probe_copy (1 GiB, 16-byte non-temporal loads/stores; "
+                   "read + write bytes)"}
+    print("probes: %s" % json.dumps(out), file=sys.stderr, flush=True)
+    return out
 
 
 def gemm_probe(rows, reps=20):
@@ -153,22 +217,27 @@ def build_workload(name, W):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="mixed10k",
+    ap.add_argument("--workload", default="batch64",
                     choices=["mixed10k", "batch64", "longcard50k", "longchain20k", "learned3sat", "learned5k"])
+    ap.add_argument("--no-extra", action="store_true",
+                    help="only the chosen workload (by default the batch64 headline is followed by mixed10k "
+                         "and longcard50k lines on stderr)")
     ap.add_argument("--train", type=int, default=0, help="learned-init workloads: training instances")
     ap.add_argument("--test", type=int, default=0, help="learned-init workloads: held-out test instances")
     ap.add_argument("--restarts", type=int, default=0, help="override the workload's restart count")
     ap.add_argument("--lr", type=float, default=0.1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-probes", action="store_true")
     ap.add_argument("--tune-out", default=None,
                     help="file receiving the shape cache with any newly tuned ranges (default: the temp directory)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="use the default kernel shapes instead of the tuned ones")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--cpu-threads", type=int, default=0, help="oracle baseline threads (0: every host core)")
-    ap.add_argument("--cpu-restarts", type=int, default=0, help="oracle baseline on the first R restarts only")
+    ap.add_argument("--cpu-restarts", type=int, default=-1,
+                    help="oracle baseline on the first R restarts only (default: per workload)")
     ap.add_argument("--search", type=int, default=0,
                     help="mixed10k only: time Algorithm 1 iterations with the backtracking line search "
                          "of this many trials instead of the constant-step hot path")
@@ -193,9 +262,7 @@ def main():
               "(--gpus must be 1)", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
-    from paper_2606_06641_amd import afsat
     from paper_2606_06641_amd import workloads as W
 
     dev = torch.device("cuda", 0)
@@ -206,16 +273,34 @@ def main():
     if args.chain:
         chain_bench(args, W)
         return
+    if args.search:
+        if args.workload != "mixed10k":
+            raise SystemExit("--search takes --workload mixed10k")
+        throughput(args, "mixed10k", W, None)
+        return
+    probes = None if args.no_probes else run_probes()
+    line = throughput(args, args.workload, W, probes)
+    print(json.dumps(line), flush=True)
+    if args.workload == "batch64" and not args.no_extra:
+        for name in ("mixed10k", "longcard50k"):
+            extra = throughput(args, name, W, probes)
+            print("extra config line: " + json.dumps(extra), file=sys.stderr, flush=True)
+
+
+def throughput(args, name, W, probes):
+    """One workload: setup, per-bucket timing, warm-up, exactly args.steps timed
+    steps, the dominant kernel's roofline, the oracle baseline.  Returns the line."""
+    import numpy as np
+    import torch
+    from paper_2606_06641_amd import afsat
+
+    dev = torch.device("cuda", 0)
     t_setup = time.perf_counter()
-    work, B, desc = build_workload(args.workload, W)
+    work, B, desc = build_workload(name, W)
     B = args.restarts or B
     parts = work if isinstance(work, list) else None
-    if parts is not None:
-        inst = _concat(parts, W)          # the block-diagonal instance (for lengths and tuning)
-    else:
-        inst = work
-    x0 = W.uniform_x0(inst.n, B, workload={"mixed10k": 2, "batch64": 3, "longcard50k": 4,
-                                           "longchain20k": 6}[args.workload])
+    inst = _concat(parts, W) if parts is not None else work   # the block-diagonal instance
+    x0 = W.uniform_x0(inst.n, B, workload=WORKLOAD_SEED[name])
     shapes = []
     if not args.no_autotune:
         from paper_2606_06641_amd import autotune
@@ -227,26 +312,25 @@ def main():
         d = afsat.Instance.batch(parts, device=0, shapes=shapes)
     else:
         d = afsat.Instance.from_arrays(inst, device=0, shapes=shapes)
-    print("setup %.1f s: n=%d C=%d L=%d B=%d parts=%d" % (time.perf_counter() - t_setup, d.n, d.n_cons,
+    print("[%s] setup %.1f s: n=%d C=%d L=%d B=%d parts=%d" % (name, time.perf_counter() - t_setup, d.n, d.n_cons,
           d.n_lits, B, d.n_inst), file=sys.stderr, flush=True)
     x = torch.from_numpy(x0).to(dev)
     ws = d.workspace(B)
     st = d.pgd_state(B)
     d.pgd_init(x, st, ws)
     if args.search:
-        search_bench(args, d, x, st, ws, B, desc)
-        return
+        return search_bench(args, d, x, st, ws, B, desc)
     stream = torch.cuda.current_stream(dev)
     buckets = d.buckets()
     nb = len(buckets)
-    autograd = args.workload == "longcard50k"
+    autograd = name == "longcard50k"
     if autograd:
         x.requires_grad_(True)
 
     def step(ev=None, dom=None):
         if autograd:
             # forward (FE only) + backward (adjoint, recomputed) through FEObjective;
-            # the dominant adjoint kernel is bracketed inside eval_adjoint's launches
+            # the bracketed region is the whole adjoint pass
             obj = afsat.FEObjective.apply(x, d)
             if ev is not None:
                 ev[0].record(stream)
@@ -289,8 +373,6 @@ def main():
     dom = int(np.argmax(per_bucket))
     bk = buckets[dom]
     rest = [i for i in range(nb) if i != dom]
-    print("per-bucket FE+grad ms:", ", ".join("[%d-%d J%d S%d] %.3f" % (b.k_lo, b.k_hi, b.lanes_per_restart,
-          b.lits_per_lane, t) for b, t in zip(buckets, per_bucket)), file=sys.stderr, flush=True)
     warm = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
             for _ in range(max(1, args.warmup))]
     for ev in warm:
@@ -318,27 +400,35 @@ def main():
     first_slot = slot_of_lit[np.asarray(inst.con_off[:-1])]
     in_b = (first_slot >= bk.slot0) & (first_slot < bk.slot0 + bk.n_lits)
     kb = lens[in_b]
-    if not autograd:
-        bucket_roofline(buckets, per_bucket, lens, first_slot, B)
+    table = bucket_roofline(name, buckets, per_bucket, lens, first_slot, B)
     kname = "fe_grad_seg<%d,%d>" % (bk.lanes_per_restart, bk.lits_per_lane) if bk.lanes_per_restart > 1 \
         else "fe_grad_short<%d>" % bk.k_hi
     if autograd:
         # the bracketed region is the whole adjoint pass (every bucket + gradient sum)
         flops = float(B * sum(algorithmic_flops(int(k)) for k in lens))
-        achieved = flops / (dom_ms * 1e-3) / 1e12
-        roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                "kernel": "adjoint pass (all fe_grad buckets + scatter)"}
+        exe = float(B * sum(executed_flops(int(k)) for k in lens))
+        roof = {"bound": "alu", "achieved": flops / (dom_ms * 1e-3) / 1e12, "peak": PEAK_FP32_TFLOPS,
+                "unit": "TFLOP/s", "kernel": "adjoint pass (all fe_grad buckets + gradient sum)",
+                "flops_per_launch": flops, "executed_tflops": exe / (dom_ms * 1e-3) / 1e12}
     elif bk.lanes_per_restart == 1 and bk.k_hi <= 8:
         bytes_per_launch = 8.0 * B * kb.sum()
-        achieved = bytes_per_launch / (dom_ms * 1e-3) / 1e9
-        roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s", "kernel": kname}
+        roof = {"bound": "hbm", "achieved": bytes_per_launch / (dom_ms * 1e-3) / 1e9, "peak": PEAK_HBM_GBS,
+                "unit": "GB/s", "kernel": kname, "bytes_per_launch": bytes_per_launch}
     else:
-        flops_per_launch = float(B * sum(algorithmic_flops(int(k)) for k in kb))
-        achieved = flops_per_launch / (dom_ms * 1e-3) / 1e12
-        roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "kernel": kname}
+        flops = float(B * sum(algorithmic_flops(int(k)) for k in kb))
+        exe = float(B * sum(executed_flops(int(k)) for k in kb))
+        roof = {"bound": "alu", "achieved": flops / (dom_ms * 1e-3) / 1e12, "peak": PEAK_FP32_TFLOPS,
+                "unit": "TFLOP/s", "kernel": kname, "k_range": [bk.k_lo, bk.k_hi], "flops_per_launch": flops,
+                "executed_tflops": exe / (dom_ms * 1e-3) / 1e12}
     roof["frac"] = roof["achieved"] / roof["peak"]
     roof["ms_per_launch"] = dom_ms
-    roof["traffic"] = None if autograd else stored_traffic(kname)
+    if roof["bound"] == "alu":
+        roof["flop_model"] = "F_k = 26 floor(k/2) + 5 (k mod 2) per literal-eval"
+    if probes:
+        p = probes["fp32_fma_tflops"] if roof["bound"] == "alu" else probes["hbm_copy_gbs"]
+        roof["peak_probe"] = p
+        roof["frac_probe"] = roof["achieved"] / p
+    roof["traffic"] = None if autograd else stored_traffic(kname, name)
 
     line = {
         "metric": "FE+grad literal-evals/s",
@@ -353,17 +443,25 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": desc, "n_vars": d.n, "n_cons": d.n_cons, "n_lits": d.n_lits, "restarts": B,
-                   "parts": d.n_inst, "lr": args.lr, "shapes": [list(sh) for sh in shapes]},
+        "config": {"workload": name + ": " + desc, "n_vars": d.n, "n_cons": d.n_cons, "n_lits": d.n_lits,
+                   "restarts": B, "parts": d.n_inst, "lr": args.lr,
+                   "shapes": [list(sh) for sh in shapes]},
         "roofline": roof,
+        "buckets": table,
     }
+    if probes:
+        line["probes"] = probes
     if not autograd:
-        print("(part, restart) pairs verified after %d iterations: %d" % (int(st["counter"][0].item()),
-              int(st["counter"][1].item())), file=sys.stderr, flush=True)
-    if not args.no_cpu_baseline and args.workload == "mixed10k":
-        line["cpu_baseline"] = cpu_baseline(inst, x0, args.lr, args.cpu_seconds, args.cpu_threads,
-                                            args.cpu_restarts)
-    print(json.dumps(line), flush=True)
+        print("[%s] (part, restart) pairs verified after %d iterations: %d" % (
+            name, int(st["counter"][0].item()), int(st["counter"][1].item())), file=sys.stderr, flush=True)
+    del ws, st, x, xd
+    d.close()
+    torch.cuda.empty_cache()
+    if not args.no_cpu_baseline:
+        r = CPU_RESTARTS[name] if args.cpu_restarts < 0 else args.cpu_restarts
+        line["cpu_baseline"] = cpu_baseline(inst, x0, args.lr, args.cpu_seconds, args.cpu_threads, r,
+                                            pgd=not autograd)
+    return line
 
 
 def chain_bench(args, W):
@@ -482,13 +580,15 @@ def search_bench(args, d, x, st, ws, B, desc):
                                  "shrink": 0.5, "armijo": 1e-4}}), flush=True)
 
 
-def bucket_roofline(buckets, per_bucket_ms, lens, first_slot, B):
+def bucket_roofline(name, buckets, per_bucket_ms, lens, first_slot, B):
     """Per length bucket (each timed alone, outside the timed region): literal-evals
     per second against the bucket's own roofline min(P_VALU / F, BW / Q), with F
-    the algorithmic flops per literal-eval of its lengths and Q = 8 B (x gather
-    and adjoint write), printed to stderr."""
-    print("bucket roofline (alone): k range, shape, ms, literal-evals/s, TFLOP/s, GB/s, bound, fraction",
-          file=sys.stderr)
+    the algorithmic flops per literal-eval of its lengths (F_k) and Q = 8 B (x
+    gather and adjoint write).  Printed to stderr and returned as rows
+    [k_lo, k_hi, J, S, constraints, ms, bound, fraction]."""
+    print("[%s] bucket roofline (alone): k range, shape, constraints, ms, literal-evals/s, TFLOP/s (F_k), "
+          "GB/s, bound, fraction" % name, file=sys.stderr)
+    rows = []
     for b, t in zip(buckets, per_bucket_ms):
         sel = (first_slot >= b.slot0) & (first_slot < b.slot0 + b.n_lits)
         ks = lens[sel]
@@ -496,11 +596,16 @@ def bucket_roofline(buckets, per_bucket_ms, lens, first_slot, B):
         flops = float(B * sum(algorithmic_flops(int(k)) for k in ks))
         sec = t * 1e-3
         rate = evals / sec
-        ceiling = min(PEAK_FP32_TFLOPS * 1e12 / (flops / evals), PEAK_HBM_GBS * 1e9 / 8.0)
-        bound = "alu" if PEAK_FP32_TFLOPS * 1e12 / (flops / evals) < PEAK_HBM_GBS * 1e9 / 8.0 else "hbm"
-        print("  [%4d-%4d] J%-2d S%-2d %8.3f ms %10.3e %7.2f %8.1f %s %.3f" % (
-            b.k_lo, b.k_hi, b.lanes_per_restart, b.lits_per_lane, t, rate, flops / sec / 1e12,
-            8.0 * evals / sec / 1e9, bound, rate / ceiling), file=sys.stderr, flush=True)
+        alu_ceiling = PEAK_FP32_TFLOPS * 1e12 / (flops / evals)
+        hbm_ceiling = PEAK_HBM_GBS * 1e9 / 8.0
+        bound = "alu" if alu_ceiling < hbm_ceiling else "hbm"
+        frac = rate / min(alu_ceiling, hbm_ceiling)
+        rows.append([b.k_lo, b.k_hi, b.lanes_per_restart, b.lits_per_lane, int(sel.sum()), round(t, 4), bound,
+                     round(frac, 3)])
+        print("  [%4d-%4d] J%-2d S%-2d %6d %8.3f ms %10.3e %7.2f %8.1f %s %.3f" % (
+            b.k_lo, b.k_hi, b.lanes_per_restart, b.lits_per_lane, int(sel.sum()), t, rate, flops / sec / 1e12,
+            8.0 * evals / sec / 1e9, bound, frac), file=sys.stderr, flush=True)
+    return rows
 
 
 def learned_init_bench(args, W):

@@ -240,9 +240,11 @@ afs_status afs_eval_fwd(afs_instance *inst, int32_t B, const float *x, void *ws,
 /* Backward (adjoint): grad[v][b] = dobj[b] * dF_b/dx[v][b], the vector-Jacobian
  * product of afs_eval_fwd.  The products are recomputed from x (nothing is kept
  * from the forward).  dobj: device f32 [B], or NULL for all ones; grad: device
- * f32 [n][B] (overwritten). */
+ * f32 [n][B] (overwritten); adj: device f32 [L][B] or NULL, receives
+ * dobj[b] * w_c * dFE_c/dx_v per literal occurrence in the input literal order
+ * (the terms grad sums). */
 afs_status afs_eval_adjoint(afs_instance *inst, int32_t B, const float *x, const float *dobj,
-                            void *ws, size_t ws_bytes, float *grad, void *stream);
+                            void *ws, size_t ws_bytes, float *grad, float *adj, void *stream);
 
 /* ---- Algorithm 1 --------------------------------------------------------------- */
 
@@ -583,6 +585,31 @@ afs_status afs_decompose(int32_t n, int32_t C, const int64_t *con_off, const int
                          const int32_t *params, const float *weights, int32_t max_len, int64_t *con_off_out,
                          int32_t *lits_out, int32_t *types_out, int32_t *params_out, float *weights_out,
                          int32_t *origin_out);
+
+/* ---- peak probes (roofline denominators) ------------------------------------------ */
+
+/* Small kernels that measure the device's attainable peaks for this build's
+ * code, reported beside the published figures (HBM 8 TB/s, FP32 vector
+ * 157.3 TFLOP/s, dense BF16 MFMA 2.5 PFLOP/s).  Each enqueues one launch of
+ * `blocks` workgroups of 256 work-items on `stream` and returns at once; the
+ * caller times it (HIP events on the same stream).  No allocation, no
+ * synchronisation.  Invalid sizes or NULL pointers return AFS_EINVAL; a launch
+ * failure AFS_EDEVICE.
+ *
+ * afs_probe_fma: every work-item runs 16 independent chains of `iters` plain
+ *   FP32 fused multiply-adds (the library's kernels are built without packed
+ *   FP32 instructions, so this is the issue ceiling of their arithmetic).
+ *   out: device float [blocks * 256], one value per work-item.  *flops (host,
+ *   may be NULL) = 2 * 16 * iters * blocks * 256.
+ * afs_probe_mfma_bf16: every wave runs `iters` rounds of 8 independent
+ *   16x16x32 BF16 matrix products with FP32 accumulation.  out as above;
+ *   *flops = 2 * 16 * 16 * 32 * 8 * iters * blocks * 4.
+ * afs_probe_copy: dst = src over `bytes` (a multiple of 16; both 16-byte
+ *   aligned device pointers), 16-byte non-temporal loads and stores, grid-stride
+ *   over `blocks` workgroups; reads and writes `bytes` each. */
+afs_status afs_probe_fma(int32_t blocks, int32_t iters, float *out, double *flops, void *stream);
+afs_status afs_probe_mfma_bf16(int32_t blocks, int32_t iters, float *out, double *flops, void *stream);
+afs_status afs_probe_copy(const void *src, void *dst, int64_t bytes, int32_t blocks, void *stream);
 
 /* Thread-local message for the last non-OK status of an afs_gnn_* call. */
 const char *afs_gnn_last_error(void);

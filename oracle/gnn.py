@@ -16,6 +16,11 @@ With ``bf16=True`` the operands of every dense layer are rounded to BF16
 (round to nearest even, via FP32) the way the GPU's matrix cores consume them;
 accumulation stays FP64.  With ``bf16=False`` the network is a smooth function
 of its parameters almost everywhere (checked against finite differences).
+``acc`` (default FP64) is the precision every array, sum and elementwise step
+is carried in; ``acc=np.float32`` evaluates the same definition with FP32
+accumulation, as the device's layers accumulate, which the tests use to size
+their tolerance (the rounding of FP32 sums moves values across BF16 rounding
+boundaries and relu thresholds).
 
 Flat parameter layout (the device layout): Wv0 [16][64], bv0 [64], Wc0 [16][64],
 bc0 [64], U [R][128][64], bu [R][64], V [R][128][64], bv [R][64], Wh [64][64],
@@ -108,40 +113,42 @@ def _graph(inst):
 
 def _agg_c(h_v, g):
     e_con, e_var, e_sgn, k, deg = g
-    out = np.zeros((len(k), h_v.shape[1]))
+    out = np.zeros((len(k), h_v.shape[1]), h_v.dtype)
     np.add.at(out, e_con, e_sgn[:, None] * h_v[e_var])
     return out / k[:, None]
 
 
 def _agg_v(h_c, g, n):
     e_con, e_var, e_sgn, k, deg = g
-    out = np.zeros((n, h_c.shape[1]))
+    out = np.zeros((n, h_c.shape[1]), h_c.dtype)
     np.add.at(out, e_var, e_sgn[:, None] * h_c[e_con])
     return out / deg[:, None]
 
 
 def _agg_c_T(d_ac, g, n):       # adjoint of _agg_c
     e_con, e_var, e_sgn, k, deg = g
-    out = np.zeros((n, d_ac.shape[1]))
+    out = np.zeros((n, d_ac.shape[1]), d_ac.dtype)
     np.add.at(out, e_var, e_sgn[:, None] * (d_ac / k[:, None])[e_con])
     return out
 
 
 def _agg_v_T(d_av, g):          # adjoint of _agg_v
     e_con, e_var, e_sgn, k, deg = g
-    out = np.zeros((len(k), d_av.shape[1]))
+    out = np.zeros((len(k), d_av.shape[1]), d_av.dtype)
     np.add.at(out, e_con, e_sgn[:, None] * (d_av / deg[:, None])[e_var])
     return out
 
 
 def _mm(a, b, q):
-    return (bf16(a) @ bf16(b)) if q else (a @ b)
+    if q:
+        return bf16(a).astype(a.dtype) @ bf16(b).astype(b.dtype)
+    return a @ b
 
 
-def forward(flat, inst, x0, R=3, bf16_ops=True):
-    p = unpack(np.asarray(flat, np.float64), R)
-    fc, fv = features(inst)
-    g = _graph(inst)
+def forward(flat, inst, x0, R=3, bf16_ops=True, acc=np.float64):
+    p = {k: v.astype(acc) for k, v in unpack(np.asarray(flat, np.float64), R).items()}
+    fc, fv = (a.astype(acc) for a in features(inst))
+    g = tuple(a.astype(acc) if a.dtype.kind == "f" else a for a in _graph(inst))
     n = int(inst.n)
     q = bf16_ops
     cache = {"xv": [], "xc": [], "hv": [], "hc": []}
@@ -157,7 +164,7 @@ def forward(flat, inst, x0, R=3, bf16_ops=True):
         hv = np.maximum(_mm(xv, p["V"][r], q) + p["bv"][r], 0)
         cache["xc"].append(xc); cache["xv"].append(xv); cache["hc"].append(hc); cache["hv"].append(hv)
     P = _mm(hv, p["Wh"], q) + p["bh"]
-    x0 = np.asarray(x0, np.float64)
+    x0 = np.asarray(x0, np.float64).astype(acc)
     pre = P[:, None, :] + x0[:, :, None] * p["wx"][None, None, :]      # (n, B, H)
     u = np.maximum(pre, 0)
     z = u @ p["wo"] + p["bo"][0]
@@ -169,11 +176,11 @@ def softplus(t):
     return np.where(t > 0, t + np.log1p(np.exp(-np.abs(t))), np.log1p(np.exp(t)))
 
 
-def loss_and_grad(flat, inst, x0, target, R=3, bf16_ops=True):
+def loss_and_grad(flat, inst, x0, target, R=3, bf16_ops=True, acc=np.float64):
     """Mean BCE and its gradient with respect to the flat parameters."""
-    xhat, c = forward(flat, inst, x0, R, bf16_ops)
+    xhat, c = forward(flat, inst, x0, R, bf16_ops, acc)
     p, g, n, q = c["p"], c["g"], int(inst.n), bf16_ops
-    y = np.asarray(target, np.float64)[:, None]
+    y = np.asarray(target, np.float64).astype(acc)[:, None]
     z = c["z"]
     count = z.size
     loss = float(np.sum(y * softplus(2 * z) + (1 - y) * softplus(-2 * z)) / count)
@@ -182,7 +189,7 @@ def loss_and_grad(flat, inst, x0, target, R=3, bf16_ops=True):
     du = dz[:, :, None] * p["wo"][None, None, :] * (c["pre"] > 0)         # (n, B, H)
     gr["wo"] = np.einsum("vb,vbj->j", dz, c["u"])
     gr["bo"] = np.array([dz.sum()])
-    gr["wx"] = np.einsum("vbj,vb->j", du, np.asarray(x0, np.float64))
+    gr["wx"] = np.einsum("vbj,vb->j", du, np.asarray(x0, np.float64).astype(acc))
     dP = du.sum(axis=1)                                                    # (n, H)
     hv = c["hv"][-1]
     gr["Wh"] = _mm(hv.T, dP, q)
@@ -210,4 +217,4 @@ def loss_and_grad(flat, inst, x0, target, R=3, bf16_ops=True):
     dpre = dhc * (c["hc0"] > 0)
     gr["Wc0"] = _mm(c["fc"].T, dpre, q)
     gr["bc0"] = dpre.sum(axis=0)
-    return loss, pack(gr, R), xhat
+    return loss, pack({k: v.astype(np.float64) for k, v in gr.items()}, R), xhat.astype(np.float64)

@@ -97,7 +97,7 @@ SIGNATURES = [
     ("afs_scatter", ctypes.c_int, [_vp, _i32, _vp, ctypes.c_size_t, _vp, _vp, _vp]),
     ("afs_fe_grad_buckets", ctypes.c_int, [_vp, _i32, _vp, _vp, ctypes.c_size_t, _i32p, _i32, _i32, _vp, _vp]),
     ("afs_eval_fwd", ctypes.c_int, [_vp, _i32, _vp, _vp, ctypes.c_size_t, _vp, _vp, _vp]),
-    ("afs_eval_adjoint", ctypes.c_int, [_vp, _i32, _vp, _vp, _vp, ctypes.c_size_t, _vp, _vp]),
+    ("afs_eval_adjoint", ctypes.c_int, [_vp, _i32, _vp, _vp, _vp, ctypes.c_size_t, _vp, _vp, _vp]),
     ("afs_step", ctypes.c_int, [_vp, _i32, _vp, _vp, ctypes.c_float, _vp, _i32, _vp, _vp]),
     ("afs_round_verify", ctypes.c_int, [_vp, _i32, _vp, _vp, _vp, ctypes.c_size_t, _vp, _vp, _vp]),
     ("afs_pgd_init", ctypes.c_int, [_vp, _i32, _vp, _vp, ctypes.c_size_t, ctypes.POINTER(_PgdState), _vp]),
@@ -126,6 +126,9 @@ SIGNATURES = [
     ("afs_decompose_size", ctypes.c_int, [_i32, _i32, _i64p, _i32p, _i32, _i32p, _i32p, _i64p]),
     ("afs_decompose", ctypes.c_int, [_i32, _i32, _i64p, _i32p, _i32p, _i32p, _f32p, _i32, _i64p, _i32p, _i32p,
                                      _i32p, _f32p, _i32p]),
+    ("afs_probe_fma", ctypes.c_int, [_i32, _i32, _vp, _f64p, _vp]),
+    ("afs_probe_mfma_bf16", ctypes.c_int, [_i32, _i32, _vp, _f64p, _vp]),
+    ("afs_probe_copy", ctypes.c_int, [_vp, _vp, ctypes.c_int64, _i32, _vp]),
 ]
 
 FORM_A, FORM_B = 0, 1
@@ -395,8 +398,9 @@ class Instance:
                                   _stream(dev)))
         return (obj, fe_t) if fe else obj
 
-    def eval_adjoint(self, x, dobj=None, ws=None):
-        """grad[v][b] = dobj[b] * dF_b/dx[v][b] (products recomputed from x)."""
+    def eval_adjoint(self, x, dobj=None, ws=None, adj=False):
+        """grad[v][b] = dobj[b] * dF_b/dx[v][b] (products recomputed from x); with
+        adj, also the per-literal terms (L, B) in input literal order: (grad, adj)."""
         B = self._check_x(x)
         dev = self._dev()
         if dobj is not None and not (dobj.dtype == torch.float32 and dobj.is_cuda and dobj.numel() == B
@@ -404,9 +408,10 @@ class Instance:
             raise ValueError("dobj must be a contiguous float32 CUDA tensor of B elements")
         ws = self.workspace(B) if ws is None else ws
         grad = torch.empty((self.n, B), dtype=torch.float32, device=dev)
+        adj_t = torch.empty((self.n_lits, B), dtype=torch.float32, device=dev) if adj else None
         _check(lib().afs_eval_adjoint(self._h, B, _ptr(x), _ptr(dobj), _ptr(ws), ws.numel(), _ptr(grad),
-                                      _stream(dev)))
-        return grad
+                                      _ptr(adj_t), _stream(dev)))
+        return (grad, adj_t) if adj else grad
 
     # -- Algorithm 1 -------------------------------------------------------------------
     def _fixed(self, fixed):
@@ -712,3 +717,24 @@ class FEObjective(torch.autograd.Function):
         (x,) = ctx.saved_tensors
         g = ctx.inst.eval_adjoint(x, gobj.contiguous().to(torch.float32))
         return g, None
+
+
+def probe(kind, blocks, iters=0, nbytes=0, device=0):
+    """Enqueue one peak-probe launch (afs_probe_*) on the current stream of
+    `device` and return the work it does: flops for "fma" and "mfma_bf16", bytes
+    moved (read + write) for "copy".  The caller times the launch."""
+    dev = torch.device("cuda", device)
+    st = _stream(device)
+    if kind == "copy":
+        if not hasattr(probe, "_bufs") or probe._bufs[0].numel() * 4 != nbytes:
+            probe._bufs = (torch.ones(nbytes // 4, dtype=torch.float32, device=dev),
+                           torch.empty(nbytes // 4, dtype=torch.float32, device=dev))
+        src, dst = probe._bufs
+        _check(lib().afs_probe_copy(_ptr(src), _ptr(dst), int(nbytes), int(blocks), st))
+        return 2.0 * nbytes
+    out = torch.empty(blocks * 256, dtype=torch.float32, device=dev)
+    flops = ctypes.c_double()
+    fn = {"fma": lib().afs_probe_fma, "mfma_bf16": lib().afs_probe_mfma_bf16}[kind]
+    _check(fn(int(blocks), int(iters), _ptr(out), ctypes.byref(flops), st))
+    probe._out = out                  # kept alive until the next probe call
+    return flops.value

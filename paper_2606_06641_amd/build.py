@@ -46,6 +46,7 @@ SOURCES = [
     ("search_kernels.hip", [HIPCC] + COMMON + DEVICE),
     ("forms.hip", [HIPCC] + COMMON + DEVICE),
     ("gnn.hip", [HIPCC] + COMMON + DEVICE),
+    ("probes.hip", [HIPCC] + COMMON + DEVICE),
 ]
 
 

@@ -593,7 +593,7 @@ afs_status afs_eval_fwd(afs_instance *I, int32_t B, const float *x, void *ws, si
 }
 
 afs_status afs_eval_adjoint(afs_instance *I, int32_t B, const float *x, const float *dobj, void *ws,
-                            size_t ws_bytes, float *grad, void *stream)
+                            size_t ws_bytes, float *grad, float *adj, void *stream)
 {
     afs_status st = check_call(I, B);
     if (st != AFS_OK) return st;
@@ -606,7 +606,10 @@ afs_status afs_eval_adjoint(afs_instance *I, int32_t B, const float *x, const fl
     st = fe_grad_range(I, B, x, ws, l, 0, (int)I->H.buckets.size(), false, nullptr, s, dobj, true);
     if (st != AFS_OK) return st;
     hipError_t e = afs::launch_scatter(I->D, B, l.Bp, at<float>(ws, l.adj), grad, s);
-    return e == hipSuccess ? AFS_OK : dev_fail(e, "scatter launch");
+    if (e != hipSuccess) return dev_fail(e, "scatter launch");
+    if (adj && (e = afs::launch_permute_adj(I->D, B, l.Bp, at<float>(ws, l.adj), adj, s)) != hipSuccess)
+        return dev_fail(e, "adjoint permute launch");
+    return AFS_OK;
 }
 
 afs_status afs_step(afs_instance *I, int32_t B, float *x, const float *grad, float lr,

@@ -1,19 +1,27 @@
 """Helpers for GPU-vs-oracle parity (tolerances per length bucket).
 
-Tolerances, per bucket (FE and every per-literal adjoint lie in [-1, 1] times the
-constraint weight, and both may be arbitrarily close to 0, so errors are taken
-relative to that range, with a relative-L2 test on top):
-  FE      : max |FE_gpu - FE_orc|                         <= 1e-4
-  adjoint : max |adj_gpu - adj_orc|                       <= 1e-4 * max|w|
-            ||adj_gpu - adj_orc||_2                       <= 1e-4 * ||adj_orc||_2 + 1e-6 * sqrt(count)
-  obj     : |F_gpu - F_orc| per restart                   <= 1e-4 * sum_c |w_c|
-  grad    : max |grad_gpu - grad_orc| over (v, b)         <= 1e-4 * max_v sum_{occ of v} |w|
+Both FE and the gradient can be arbitrarily close to 0 (a satisfied long
+cardinality constraint has FE = -1 + 1e-30 and a gradient of that order), so a
+per-element relative error is meaningless; the bars are relative to the largest
+oracle value of the bucket, plus a relative-L2 bar over the bucket:
+
+  FE      : max |FE_gpu - FE_orc|        <= 1e-4 * max |FE_orc|         (per bucket)
+  adjoint : max |adj_gpu - adj_orc|      <= 1e-4 * max |adj_orc|        (per bucket)
+            ||adj_gpu - adj_orc||_2      <= 1e-4 * ||adj_orc||_2        (per bucket)
+  obj     : max |F_gpu - F_orc|          <= 1e-4 * max |F_orc|
+  grad    : max |grad_gpu - grad_orc|    <= 1e-4 * max |grad_orc|
+            ||grad_gpu - grad_orc||_2    <= 1e-4 * ||grad_orc||_2
+
+A bucket (or array) whose oracle values are all exactly zero is held to the
+absolute bar ABS_FLOOR instead (a constant constraint has FE = -1 exactly and a
+zero gradient; the kernels must return zeros to within FP32 rounding of the
+table entries).
 """
 import numpy as np
 import torch
 
-FE_TOL = 1e-4
-ADJ_TOL = 1e-4
+REL_TOL = 1e-4
+ABS_FLOOR = 1e-6
 
 
 def to_dev(a, device=0):
@@ -40,37 +48,72 @@ def bucket_of_constraints(inst, lit_bucket):
     return lit_bucket[np.asarray(inst.con_off[:-1], dtype=np.int64)]
 
 
+def rel_max(got, want):
+    """(max |got - want|, the bar it is held to, the error relative to max |want|
+    or, when want is all zero, absolute)."""
+    if got.size == 0:
+        return 0.0, ABS_FLOOR, 0.0
+    err = float(np.max(np.abs(got - want)))
+    scale = float(np.max(np.abs(want)))
+    if scale > 0:
+        return err, REL_TOL * scale, err / scale
+    return err, ABS_FLOOR, err
+
+
+def rel_l2(got, want):
+    """(||got - want||_2, the bar it is held to, the relative error)."""
+    if got.size == 0:
+        return 0.0, ABS_FLOOR, 0.0
+    err = float(np.linalg.norm(got - want))
+    ref = float(np.linalg.norm(want))
+    if ref > 0:
+        return err, REL_TOL * ref, err / ref
+    return err, ABS_FLOOR * np.sqrt(got.size), err / np.sqrt(got.size)
+
+
+def check_adjoints(adj_gpu, adj_orc, lit_bucket, buckets, label=""):
+    """Per bucket: the adjoint bars.  Returns [(max err / max|orc|, L2 err / ||orc||)]."""
+    out = []
+    for i, b in enumerate(buckets):
+        lm = lit_bucket == i
+        g, w = adj_gpu[lm], adj_orc[lm]
+        e, bar, r = rel_max(g, w)
+        assert e <= bar, (label, "adj max", b, e, bar)
+        e2, bar2, r2 = rel_l2(g, w)
+        assert e2 <= bar2, (label, "adj l2", b, e2, bar2)
+        out.append((r, r2))
+    return out
+
+
 def compare(inst, dinst, gpu, orc, label=""):
-    """Assert parity per bucket; return a per-bucket error table."""
-    w = np.ones(inst.n_cons) if inst.weights is None else np.asarray(inst.weights, np.float64)
+    """Assert parity per bucket; return a per-bucket error table with errors
+    relative to the bucket's largest oracle value (FE, adjoint) and its norm."""
     lb = bucket_of_literals(dinst)
     cb = bucket_of_constraints(inst, lb)
-    lit_w = np.repeat(np.abs(w), np.diff(inst.con_off))
+    buckets = dinst.buckets()
+    adj_rel = check_adjoints(gpu["adj"], orc["adj"], lb, buckets, label)
     rows = []
-    for i, b in enumerate(dinst.buckets()):
+    for i, b in enumerate(buckets):
         cm = cb == i
-        lm = lb == i
-        fe_err = np.max(np.abs(gpu["fe"][cm] - orc["fe"][cm])) if cm.any() else 0.0
-        d = gpu["adj"][lm] - orc["adj"][lm]
-        adj_max = np.max(np.abs(d)) if d.size else 0.0
-        adj_l2 = np.linalg.norm(d)
-        ref_l2 = np.linalg.norm(orc["adj"][lm])
-        wmax = np.max(lit_w[lm]) if lm.any() else 1.0
-        rows.append((b.k_lo, b.k_hi, b.lanes_per_restart, b.lits_per_lane, fe_err, adj_max,
-                     adj_l2 / max(ref_l2, 1e-30)))
-        assert fe_err <= FE_TOL, (label, "FE", b, fe_err)
-        assert adj_max <= ADJ_TOL * wmax, (label, "adj max", b, adj_max)
-        assert adj_l2 <= ADJ_TOL * ref_l2 + 1e-6 * np.sqrt(d.size), (label, "adj l2", b, adj_l2, ref_l2)
-    obj_tol = FE_TOL * max(np.sum(np.abs(w)), 1.0)
-    assert np.max(np.abs(gpu["obj"] - orc["obj"])) <= obj_tol, (label, "obj")
-    deg_w = np.zeros(inst.n)
-    np.add.at(deg_w, np.abs(inst.lits) - 1, lit_w)
-    assert np.max(np.abs(gpu["grad"] - orc["grad"])) <= ADJ_TOL * max(deg_w.max(), 1.0), (label, "grad")
+        e, bar, r = rel_max(gpu["fe"][cm], orc["fe"][cm])
+        assert e <= bar, (label, "FE", b, e, bar)
+        rows.append((b.k_lo, b.k_hi, b.lanes_per_restart, b.lits_per_lane, r) + adj_rel[i])
+    e, bar, _ = rel_max(gpu["obj"], orc["obj"])
+    assert e <= bar, (label, "obj", e, bar)
+    check_grad(gpu["grad"], orc["grad"], label)
     return rows
 
 
+def check_grad(got, want, label=""):
+    e, bar, r = rel_max(got, want)
+    assert e <= bar, (label, "grad max", e, bar)
+    e2, bar2, r2 = rel_l2(got, want)
+    assert e2 <= bar2, (label, "grad l2", e2, bar2)
+    return r, r2
+
+
 def format_rows(rows):
-    lines = ["k_lo k_hi  J  S   max|dFE|   max|dadj|  rel-L2(adj)"]
+    lines = ["k_lo k_hi  J  S  max|dFE|/max|FE|  max|dadj|/max|adj|  rel-L2(adj)"]
     for r in rows:
-        lines.append("%4d %4d %2d %2d  %9.2e  %9.2e  %9.2e" % r)
+        lines.append("%4d %4d %2d %2d  %14.2e  %18.2e  %11.2e" % r)
     return "\n".join(lines)

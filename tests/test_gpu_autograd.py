@@ -27,14 +27,10 @@ def log(*a):
     print(*a, flush=True)
 
 
-def grad_tol(inst):
-    lit_w = np.repeat(np.ones(inst.n_cons), np.diff(inst.con_off))
-    deg = np.zeros(inst.n)
-    np.add.at(deg, np.abs(inst.lits) - 1, lit_w)
-    return 1e-4 * max(deg.max(), 1.0)
-
-
 def test_forward_and_vjp_match_eval_and_oracle():
+    """FEObjective's forward and backward against the oracle at the per-bucket
+    bars of parity.py: the objective, the gradient, and every per-literal
+    adjoint term of afs_eval_adjoint (seeded by a random dL/dF per restart)."""
     rng = np.random.default_rng(30)
     parts = [W.random_instance(rng, n=500, count=400, k_lo=1, k_hi=16),
              W.random_instance(rng, n=500, count=12, k_lo=17, k_hi=400)]
@@ -49,12 +45,17 @@ def test_forward_and_vjp_match_eval_and_oracle():
     gobj = torch.from_numpy(rng.normal(size=B).astype(np.float32)).cuda()
     (obj * gobj).sum().backward()
     torch.cuda.synchronize()
-    orc = oracle.eval(inst, x32, grad=True)
-    assert np.max(np.abs(obj.detach().cpu().numpy() - orc["obj"])) <= 1e-4 * inst.n_cons
-    want = orc["grad"] * gobj.cpu().numpy()[None, :].astype(np.float64)
-    got = x.grad.cpu().numpy()
-    tol = grad_tol(inst) * float(np.max(np.abs(gobj.cpu().numpy())))
-    assert np.max(np.abs(got - want)) <= tol
+    orc = oracle.eval(inst, x32, grad=True, adj=True)
+    e, bar, _ = parity.rel_max(obj.detach().cpu().numpy().astype(np.float64), orc["obj"])
+    assert e <= bar
+    seed = gobj.cpu().numpy().astype(np.float64)[None, :]
+    parity.check_grad(x.grad.cpu().numpy().astype(np.float64), orc["grad"] * seed, "vjp")
+    grad, adj = d.eval_adjoint(x.detach(), gobj, adj=True)
+    torch.cuda.synchronize()
+    rel = parity.check_adjoints(adj.cpu().numpy().astype(np.float64), orc["adj"] * seed,
+                                parity.bucket_of_literals(d), d.buckets(), "eval_adjoint")
+    log("per-bucket adjoint errors (max rel, L2 rel):", ["%.1e/%.1e" % r for r in rel])
+    assert torch.equal(grad, x.grad)
     # the forward-only objective equals the full evaluation's, and the unseeded
     # adjoint equals the gradient of afs_eval bit for bit (same kernels, same order)
     e = d.eval(x.detach(), obj=True, grad=True)
@@ -64,26 +65,37 @@ def test_forward_and_vjp_match_eval_and_oracle():
 
 def test_longcard50k_autograd():
     """n=50k, 200k clauses (k 3-10) and 1,000 CARD (k 256-1,024), 512 restarts,
-    FE and gradient through FEObjective; oracle gradient on 8 sampled restarts and
-    FP64 central differences (h = 1e-3) at 48 sampled (variable, restart) pairs."""
+    FE and gradient through FEObjective; at 8 sampled restarts, the gradient and
+    every per-literal adjoint term against the oracle at the per-bucket bars, and
+    the gradient against FP64 central differences of the oracle objective
+    (h = 1e-3) at 48 sampled (variable, restart) pairs."""
+    from paper_2606_06641_amd import autotune
     inst = W.long_card_50k()
     B = 512
     x32 = W.uniform_x0(inst.n, B, workload=4)
-    log("case: config-4 autograd n=50k B=512")
-    d = afsat.Instance.from_arrays(inst)
+    shapes, _ = autotune.tune(inst, B, cache_path=autotune.DEFAULT_CACHE, max_cons=400)
+    log("case: config-4 autograd n=50k B=512, tuned shapes %s" % shapes)
+    d = afsat.Instance.from_arrays(inst, shapes=shapes)
     x = parity.to_dev(x32).requires_grad_(True)
     obj = afsat.FEObjective.apply(x, d)
     obj.sum().backward()
     torch.cuda.synchronize()
-    g = x.grad.cpu().numpy()
+    g = x.grad.cpu().numpy().astype(np.float64)
     rng = np.random.default_rng(40)
-    cols = rng.choice(B, size=8, replace=False)
-    orc = oracle.eval(inst, x32[:, cols], grad=True)
-    tol = grad_tol(inst)
-    err = np.max(np.abs(g[:, cols] - orc["grad"]))
-    log("max |grad - oracle grad| = %.3e (tol %.1e)" % (err, tol))
-    assert err <= tol
-    assert np.max(np.abs(obj.detach().cpu().numpy()[cols] - orc["obj"])) <= 1e-4 * inst.n_cons
+    cols = np.sort(rng.choice(B, size=8, replace=False))
+    orc = oracle.eval(inst, x32[:, cols], grad=True, adj=True)
+    r = parity.check_grad(g[:, cols], orc["grad"], "longcard50k grad")
+    log("gradient: max rel %.2e, L2 rel %.2e" % r)
+    e, bar, _ = parity.rel_max(obj.detach().cpu().numpy().astype(np.float64)[cols], orc["obj"])
+    assert e <= bar
+    _, adj = d.eval_adjoint(x.detach(), adj=True)
+    ci = torch.from_numpy(cols).cuda()
+    adj_s = adj.index_select(1, ci).cpu().numpy().astype(np.float64)
+    del adj
+    rel = parity.check_adjoints(adj_s, orc["adj"], parity.bucket_of_literals(d), d.buckets(), "longcard50k adj")
+    log("per-bucket adjoint errors (max rel, L2 rel):")
+    for b, rr in zip(d.buckets(), rel):
+        log("  [%4d-%4d] J%-2d S%-2d  %.2e  %.2e" % (b.k_lo, b.k_hi, b.lanes_per_restart, b.lits_per_lane, *rr))
     # central differences of the oracle objective, variables of the long constraints first
     h = 1e-3
     card_vars = np.unique(np.abs(inst.lits[inst.con_off[np.nonzero(inst.types == W.CARD_GE)[0][0]]:
@@ -97,8 +109,9 @@ def test_longcard50k_autograd():
     F = oracle.eval(inst, X, grad=False)["obj"]
     fd = (F[0::2] - F[1::2]) / (2 * h)
     ferr = np.max(np.abs(fd - g[vs, bs]))
-    log("max |grad - central difference| = %.3e" % ferr)
-    assert ferr <= tol
+    scale = np.max(np.abs(orc["grad"]))
+    log("max |grad - central difference| = %.3e (bar 1e-4 * %.3e)" % (ferr, scale))
+    assert ferr <= parity.REL_TOL * scale
 
 
 @pytest.mark.parametrize("kind", ["3sat", "mixed"])

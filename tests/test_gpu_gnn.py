@@ -60,7 +60,43 @@ def mixed_small(seed):
                       params=np.concatenate([a.params, b.params]))
 
 
+def host_params(R, seed):
+    """A seeded parameter vector drawn on the host (He-normal weights by fan-in,
+    small random biases), so that both sides take the same input."""
+    lay, total = G.layout(R)
+    rng = np.random.default_rng(seed)
+    p = np.zeros(total)
+    fan = {"Wv0": 3, "Wc0": 4, "U": 128, "V": 128, "Wh": 64, "wx": 1, "wo": 64}
+    for name, (o, shp) in lay.items():
+        size = int(np.prod(shp))
+        sd = (0.1 if name == "wo" else 1.0) * np.sqrt(2.0 / fan[name]) if name in fan else 0.05
+        p[o:o + size] = rng.normal(0, sd, size)
+    return p.astype(np.float32)
+
+
+def rel_l2_by_group(g, ref, R=3):
+    lay, _ = G.layout(R)
+    out = {}
+    for name, (o, shp) in lay.items():
+        sl = slice(o, o + int(np.prod(shp)))
+        out[name] = np.linalg.norm(g[sl] - ref[sl]) / max(np.linalg.norm(ref[sl]), 1e-30)
+    return out
+
+
 def test_forward_backward_match_reference():
+    """Forward (xhat), loss and every parameter gradient of the device network
+    against the FP64 reference with BF16 operands, under an error model.
+
+    The device accumulates in FP32.  An FP32 sum lands on the other side of a
+    BF16 rounding midpoint, or of a relu threshold, than the FP64 sum now and
+    then; each such event moves one operand by a BF16 ulp (2^-8) and its effect
+    runs through every later layer, so the difference is a rare discrete
+    event, not a small uniform rounding.  The model is the reference itself
+    evaluated in FP32 (acc=np.float32) over 32 parameter draws: per parameter
+    group, the mean and the worst rel-L2 distance between the FP32 and FP64
+    evaluations.  The device, on 8 of those draws, must stay within 3x the
+    model's mean (+1e-6) and 1.5x its worst (+1e-5); xhat likewise by max |.|;
+    the loss within 1e-5 relative."""
     inst = mixed_small(3)
     d = afsat.Instance.from_arrays(inst)
     net = gnn.GNN(rounds=3, seed=7)
@@ -69,25 +105,39 @@ def test_forward_backward_match_reference():
     x0 = rng.uniform(-1, 1, size=(inst.n, B)).astype(np.float32)
     target = rng.integers(0, 2, size=inst.n).astype(np.uint8)
     xd = parity.to_dev(x0)
-    xhat = net.forward(d, xd).cpu().numpy()
-    net.zero_grad()
-    loss = float(net.loss_backward(d, xd, torch.from_numpy(target).cuda()).item())
-    grads = net.get(1).astype(np.float64)
-    params = net.get(0).astype(np.float64)
-    rl, rg, rx = G.loss_and_grad(params, inst, x0, target, R=3, bf16_ops=True)
-    xerr = np.max(np.abs(xhat - rx))
-    log("xhat max err %.2e  loss %.6f vs %.6f" % (xerr, loss, rl))
-    assert xerr <= 2e-3
-    assert abs(loss - rl) <= 1e-4 * max(1.0, abs(rl))
-    lay, _ = G.layout(3)
-    for name, (o, shp) in lay.items():
-        g1 = grads[o:o + int(np.prod(shp))]
-        g2 = rg[o:o + int(np.prod(shp))]
-        rel = np.linalg.norm(g1 - g2) / max(np.linalg.norm(g2), 1e-12)
-        log("grad %-4s rel-L2 %.2e  |g| %.2e" % (name, rel, np.linalg.norm(g2)))
-        assert rel <= 2e-2, name
+    tg = torch.from_numpy(target).cuda()
+    model = {}
+    dev_err = {}
+    for draw in range(32):
+        params = host_params(3, 1000 + draw)
+        l64, g64, x64 = G.loss_and_grad(params, inst, x0, target, R=3, bf16_ops=True)
+        _, g32, x32 = G.loss_and_grad(params, inst, x0, target, R=3, bf16_ops=True, acc=np.float32)
+        for k, v in rel_l2_by_group(g32, g64).items():
+            model.setdefault(k, []).append(v)
+        model.setdefault("xhat", []).append(float(np.max(np.abs(x32 - x64))))
+        if draw >= 8:
+            continue
+        net.set(params, 0)
+        xhat = net.forward(d, xd).cpu().numpy()
+        net.zero_grad()
+        loss = float(net.loss_backward(d, xd, tg).item())
+        grads = net.get(1).astype(np.float64)
+        assert abs(loss - l64) <= 1e-5 * max(1.0, abs(l64)), (draw, loss, l64)
+        for k, v in rel_l2_by_group(grads, g64).items():
+            dev_err.setdefault(k, []).append(v)
+        dev_err.setdefault("xhat", []).append(float(np.max(np.abs(xhat - x64))))
+    for k in dev_err:
+        mean_bar = 3 * np.mean(model[k]) + 1e-6
+        worst_bar = 1.5 * np.max(model[k]) + 1e-5
+        log("%-4s device mean %.2e worst %.2e | model mean %.2e worst %.2e" % (
+            k, np.mean(dev_err[k]), np.max(dev_err[k]), np.mean(model[k]), np.max(model[k])))
+        assert np.mean(dev_err[k]) <= mean_bar, k
+        assert np.max(dev_err[k]) <= worst_bar, k
     # gradients accumulate across calls; zero_grad clears them
-    net.loss_backward(d, xd, torch.from_numpy(target).cuda())
+    net.zero_grad()
+    net.loss_backward(d, xd, tg)
+    grads = net.get(1)
+    net.loss_backward(d, xd, tg)
     assert np.allclose(net.get(1), 2 * grads, rtol=1e-5, atol=1e-9)
     net.zero_grad()
     assert np.all(net.get(1) == 0)

@@ -155,24 +155,53 @@ def test_planted_3sat_n100_parity():
     check(inst, x, "planted 3-SAT n=100 m=426 B=32")
 
 
+def tuned_shapes(inst, B):
+    """The kernel shapes bench.py runs: the package's tuned table (shapes missing
+    from it are tuned on the device)."""
+    from paper_2606_06641_amd import autotune
+    shapes, _ = autotune.tune(inst, B, cache_path=autotune.DEFAULT_CACHE, max_cons=400)
+    return shapes
+
+
 def test_mixed10k_full_size():
+    """The mixed n = 10k instance at all 1,024 restarts with the tuned shapes the
+    bench times: every FE, adjoint, gradient and objective entry."""
     inst = W.mixed_10k()
-    x = W.uniform_x0(inst.n, 1024, workload=2)
-    check(inst, x, "mixed n=10k B=1024 (all restarts)")
+    B = 1024
+    x = W.uniform_x0(inst.n, B, workload=2)
+    shapes = tuned_shapes(inst, B)
+    log("case: mixed n=10k B=1024 (all restarts), tuned shapes %s" % shapes)
+    d = afsat.Instance.from_arrays(inst, shapes=shapes)
+    gpu = parity.gpu_eval(d, x)
+    orc = oracle.eval(inst, x, fe=True, adj=True, grad=True)
+    rows = parity.compare(inst, d, gpu, orc, "mixed10k")
+    log(parity.format_rows(rows))
+
+
+def test_mixed10k_default_shapes():
+    inst = W.mixed_10k()
+    x = W.uniform_x0(inst.n, 256, workload=2, instance=1)
+    check(inst, x, "mixed n=10k B=256, default shapes")
 
 
 def test_longcard50k_sampled():
-    """n=50k, 200k clauses, 1k CARD k 256-1024, B=512 on the GPU; the oracle checks
-    16 sampled restart columns (columns are independent)."""
+    """n=50k, 200k clauses, 1k CARD k 256-1024, B=512 on the GPU with the tuned
+    shapes the bench times; the oracle checks 16 sampled restart columns
+    (columns are independent)."""
     inst = W.long_card_50k()
     B = 512
     x = W.uniform_x0(inst.n, B, workload=4)
-    log("case: long-card n=50k B=512 sampled")
-    d = afsat.Instance.from_arrays(inst)
-    gpu = parity.gpu_eval(d, x)
-    cols = np.random.default_rng(4).choice(B, size=16, replace=False)
+    shapes = tuned_shapes(inst, B)
+    log("case: long-card n=50k B=512 sampled, tuned shapes %s" % shapes)
+    d = afsat.Instance.from_arrays(inst, shapes=shapes)
+    xd = parity.to_dev(x)
+    out = d.eval(xd, obj=True, grad=True, fe=True, adj=True)
+    cols = np.sort(np.random.default_rng(4).choice(B, size=16, replace=False))
+    ci = torch.from_numpy(cols).cuda()
+    sub = {k: v.index_select(v.dim() - 1, ci).cpu().numpy().astype(np.float64) for k, v in out.items()}
+    del out
+    torch.cuda.empty_cache()
     orc = oracle.eval(inst, x[:, cols], fe=True, adj=True, grad=True)
-    sub = {k: (v[..., cols] if v.ndim == 2 else v[cols]) for k, v in gpu.items()}
     rows = parity.compare(inst, d, sub, orc, "longcard50k sampled")
     log(parity.format_rows(rows))
 
@@ -183,13 +212,12 @@ def test_batch64_full_size_sampled():
     shapes exactly as the bench runs it; the oracle checks 8 sampled restart
     columns of FE, adjoints, gradient and objective (columns are independent), and
     the exact unsat counts of every part at those columns."""
-    from paper_2606_06641_amd import autotune
     parts = W.uneven_batch()
     off = np.cumsum([0] + [p.n for p in parts])
     cat = concat([W.Instance(n=p.n, con_off=p.con_off, lits=np.where(p.lits > 0, p.lits + o, p.lits - o).astype(np.int32),
                              types=p.types, params=p.params) for p, o in zip(parts, off[:-1])], n=int(off[-1]))
     B = 256
-    shapes, _ = autotune.tune(cat, B, cache_path=autotune.DEFAULT_CACHE, max_cons=400)
+    shapes = tuned_shapes(cat, B)
     Bt = afsat.Instance.batch(parts, shapes=shapes)
     x = W.uniform_x0(cat.n, B, workload=3)
     cols = np.sort(np.random.default_rng(33).choice(B, size=8, replace=False))

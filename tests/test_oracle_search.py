@@ -217,3 +217,29 @@ def test_line_search_location_rule():
     assert r["done"][0] == 1 and r["first_sat"][0] == 1
     r = oracle.pgd_search(DRIFT, np.array([[0.5], [0.25], [-0.5]]), (4.0, 0.5, 0.9, 3), 5, epsilon=0.1)
     assert r["done"][0] == 2 and r["x"][0, 0] == -1.0
+
+
+# Two one-literal clauses: x1 must be True (F gains x1) and x2 False (the
+# negated literal gives -x2), so F = x1 - x2 and the gradient is (1, -1) at every
+# point.  Every value below is a multiple of 1/4, so each step is exact in FP64.
+UNITS2 = Inst(2, [(oracle.OR, 0, [1]), (oracle.OR, 0, [-2])])
+
+
+@pytest.mark.parametrize("steps", [0, 1, 2, 3, 4, 9])
+def test_constant_step_first_sat_by_hand(steps):
+    """Algorithm 1 with lr = 1/4.  Restart 0 from x = (3/4, 1/2): x1 moves to 1/2,
+    1/4, 0, -1/4 while x2 (False throughout) climbs to the bound 1; the point
+    x1 = 0 is False (the rounding tie), so the restart first verifies at
+    iteration 4, and then stays put (a finished candidate does no-ops).
+    Restart 1 starts at a satisfying corner (first_sat 0, never moves).
+    Restart 2 from (-1/4, -1/2): x1 is True from the start (and keeps falling),
+    x2 is True at -1/2 and -1/4 and False at 0, so it verifies at iteration 2."""
+    x0 = np.array([[0.75, -1.0, -0.25],
+                   [0.5, 1.0, -0.5]])
+    r = oracle.pgd(UNITS2, x0, 0.25, steps)
+    want_first = [4 if steps >= 4 else -1, 0, 2 if steps >= 2 else -1]
+    np.testing.assert_array_equal(r["first_sat"], want_first)
+    x1 = [0.75 - 0.25 * min(steps, 4), -1.0, -0.25 - 0.25 * min(steps, 2)]
+    x2 = [min(1.0, 0.5 + 0.25 * min(steps, 4)), 1.0, -0.5 + 0.25 * min(steps, 2)]
+    np.testing.assert_array_equal(r["x"], np.array([x1, x2]))
+    np.testing.assert_array_equal(r["unsat"], [0 if f >= 0 else 1 for f in want_first])

@@ -132,19 +132,24 @@ def run_probes():
     streaming copy, each timed over several launches with HIP events."""
     from paper_2606_06641_amd import afsat
     blocks = 256 * 8 * 4                   # 32 waves per CU
-    ms, fl = timed(lambda: afsat.probe("fma", blocks, iters=4096), 5)
-    fma = fl / (ms * 1e-3) / 1e12
+    names = ["fma_uniform", "fmac_vector", "mul", "complex_step"]
+    fp32 = {}
+    for v, name in enumerate(names):
+        ms, fl = timed(lambda: afsat.probe("fma", blocks, iters=4096, variant=v), 5)
+        fp32[name] = fl / (ms * 1e-3) / 1e12
+    fma = max(fp32[n] for n in names if n != "mul")
     ms, fl = timed(lambda: afsat.probe("mfma_bf16", blocks, iters=512), 5)
     mfma = fl / (ms * 1e-3) / 1e12
     nbytes = 1 << 30
     ms, by = timed(lambda: afsat.probe("copy", 256 * 16, nbytes=nbytes), 10)
     copy = by / (ms * 1e-3) / 1e9
     afsat.probe._bufs = None
-    out = {"fp32_fma_tflops": fma, "bf16_mfma_tflops": mfma, "hbm_copy_gbs": copy,
-           "note": "measured on this device by afs_probe_fma (16 independent plain FP32 FMA chains per lane, "
-                   "no packed instructions), afs_probe_mfma_bf16 (8 independent v_mfma_f32_16x16x32_bf16 "
-                   "accumulators per wave) and afs_probe_copy (1 GiB, 16-byte non-temporal loads/stores; "
-                   "read + write bytes)"}
+    out = {"fp32_fma_tflops": fma, "fp32_by_form_tflops": fp32, "bf16_mfma_tflops": mfma, "hbm_copy_gbs": copy,
+           "note": "measured on this device by afs_probe_fma (16 independent plain FP32 chains per lane, no packed "
+                   "instructions: v_fma_f32 with uniform operands, v_fmac_f32 with per-lane operands, v_mul_f32, "
+                   "and the FE kernels' complex product step; fp32_fma_tflops is the best FMA form), "
+                   "afs_probe_mfma_bf16 (8 independent v_mfma_f32_16x16x32_bf16 accumulators per wave) and "
+                   "afs_probe_copy (1 GiB, 16-byte non-temporal loads/stores; read + write bytes)"}
     print("probes: %s" % json.dumps(out), file=sys.stderr, flush=True)
     return out
 
@@ -226,6 +231,19 @@ def main():
                          "and longcard50k lines on stderr)")
     ap.add_argument("--train", type=int, default=0, help="learned-init workloads: training instances")
     ap.add_argument("--test", type=int, default=0, help="learned-init workloads: held-out test instances")
+    ap.add_argument("--test-offset", type=int, default=0, help="learned-init workloads: first test instance")
+    ap.add_argument("--val", type=int, default=8, help="learned-init workloads: validation instances")
+    ap.add_argument("--timeout", type=float, default=0.0, help="learned-init workloads: seconds per arm and instance")
+    ap.add_argument("--val-timeout", type=float, default=2.0, help="learned-init workloads: validation timeout")
+    ap.add_argument("--round-steps", type=int, default=200,
+                    help="learned-init workloads: Algorithm 1 iterations per round of fresh starting points")
+    ap.add_argument("--target-steps", type=int, default=200, help="learned-init workloads: solver iterations per target")
+    ap.add_argument("--train-steps", type=int, default=1000, help="learned-init workloads: Adam steps")
+    ap.add_argument("--ls-trials", type=int, default=0,
+                    help="learned-init workloads: backtracking line search with this many trials (0: constant step)")
+    ap.add_argument("--ls-step", type=float, default=4.0, help="learned-init workloads: line search maximum step")
+    ap.add_argument("--save-net", default=None, help="learned-init workloads: save the trained network (.npz)")
+    ap.add_argument("--load-net", default=None, help="learned-init workloads: load a trained network and only test")
     ap.add_argument("--restarts", type=int, default=0, help="override the workload's restart count")
     ap.add_argument("--lr", type=float, default=0.1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -234,6 +252,10 @@ def main():
                     help="file receiving the shape cache with any newly tuned ranges (default: the temp directory)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="use the default kernel shapes instead of the tuned ones")
+    ap.add_argument("--shapes-cache", default=None,
+                    help="tuned-shape cache to read (default: the package's tuned_shapes.txt)")
+    ap.add_argument("--tune-max-cons", type=int, default=400,
+                    help="constraints of a length range timed by the tuner when a range is not cached (0: all)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--cpu-threads", type=int, default=0, help="oracle baseline threads (0: every host core)")
     ap.add_argument("--cpu-restarts", type=int, default=-1,
@@ -306,8 +328,8 @@ def throughput(args, name, W, probes):
         from paper_2606_06641_amd import autotune
         out = args.tune_out or os.path.join(tempfile.gettempdir(), "afsat_tuned_shapes.txt")
         os.makedirs(os.path.dirname(os.path.abspath(out)), exist_ok=True)
-        shapes, _ = autotune.tune(inst, B, cache_path=autotune.DEFAULT_CACHE, out_path=out,
-                                  log=lambda m: print(m, file=sys.stderr, flush=True), max_cons=400)
+        shapes, _ = autotune.tune(inst, B, cache_path=args.shapes_cache or autotune.DEFAULT_CACHE, out_path=out,
+                                  log=lambda m: print(m, file=sys.stderr, flush=True), max_cons=args.tune_max_cons)
     if parts is not None:
         d = afsat.Instance.batch(parts, device=0, shapes=shapes)
     else:
@@ -608,62 +630,111 @@ def bucket_roofline(name, buckets, per_bucket_ms, lens, first_slot, B):
     return rows
 
 
-def learned_init_bench(args, W):
-    """Time to a verified assignment from learned vs uniform random starting points.
+def _gen_instances(make, seeds, workers=8):
+    """Instances make(seed) for every seed, generated in worker processes."""
+    from concurrent.futures import ProcessPoolExecutor
+    if len(seeds) < 64:
+        return [make(i) for i in seeds]
+    with ProcessPoolExecutor(max_workers=workers) as ex:
+        return list(ex.map(make, seeds, chunksize=16))
 
-    learned3sat: planted random 3-SAT, n = 100, 426 clauses (ratio 4.26), which
-    Algorithm 1 solves; learned5k: planted mixed instances of the n = 10k workload's
-    shape at n = 5,000 (15,000 clauses k3-8, 1,000 XOR k3-5, 250 CARD>=K k20-200).
-    The network (3 rounds, width 64) trains on targets the solver itself produces
-    on the training instances; the way its output is turned into starting points
-    (sign sampling temperature) is chosen on separate validation instances; both
-    arms then run on held-out test instances with the same noise seed."""
+
+def _make_3sat(i):
+    from paper_2606_06641_amd import workloads as W
+    return W.planted_3sat(n=100, m=426, instance=i)
+
+
+def _make_5k(i):
+    from paper_2606_06641_amd import workloads as W
+    return W.mixed_5k(instance=i)
+
+
+def learned_init_bench(args, W):
+    """Time to a verified assignment from learned vs uniform random starting
+    points (the learned-initialisation row).
+
+    learned5k: planted mixed instances of the n = 10k workload's shape at
+    n = 5,000 (15,000 clauses k3-8, 1,000 XOR k3-5, 250 CARD>=K k20-200);
+    learned3sat: planted random 3-SAT, n = 100, 426 clauses.  The network
+    (3 rounds, width 64) trains on targets the solver itself produces on the
+    training instances (its best restart: a verified one where there is one,
+    else the fewest unsatisfied constraints); the way its output becomes starting
+    points (sign-sampling temperature, or a blend with the noise) is chosen on
+    separate validation instances; both arms then run on held-out test
+    instances, 1,024 restarts each, Algorithm 1 with lr 0.1 in rounds of
+    --round-steps iterations from fresh starting points, until a restart
+    verifies or --timeout seconds pass.  --save-net / --load-net split training
+    and testing across runs."""
     import numpy as np
     import torch
     from paper_2606_06641_amd import gnn
     log = lambda m: print(m, file=sys.stderr, flush=True)
     t0 = time.perf_counter()
-    if args.workload == "learned3sat":
-        n_train, n_val, n_test = args.train or 512, 32, args.test or 100
-        make = lambda i: W.planted_3sat(n=100, m=426, instance=i)
-        B, max_steps, target_steps, train_steps = 1024, 300, 150, 800
-        desc = "planted 3-SAT n=100 m=426"
-    else:
-        n_train, n_val, n_test = args.train or 64, 8, args.test or 16
-        make = lambda i: W.mixed_5k(instance=i)
-        B, max_steps, target_steps, train_steps = 1024, 300, 200, 400
-        desc = ("planted mixed n=5000: 15000 clauses k3-8, 1000 XOR k3-5, 250 CARD>=K k20-200")
-    train_set = [make(10000 + i) for i in range(n_train)]
-    val_set = [make(20000 + i) for i in range(n_val)]
-    test_set = [make(30000 + i) for i in range(n_test)]
-    log("generated %d/%d/%d instances in %.1f s" % (n_train, n_val, n_test, time.perf_counter() - t0))
-    targets, verified = gnn.collect_targets(train_set, B=256, steps=target_steps)
-    log("targets: %d of %d verified (%.1f s)" % (verified, n_train, time.perf_counter() - t0))
+    five = args.workload == "learned5k"
+    make = _make_5k if five else _make_3sat
+    n_train = args.train or (2000 if five else 512)
+    n_val, n_test = args.val, args.test or 100
+    B = args.restarts or 1024
+    timeout = args.timeout or (20.0 if five else 3.0)
+    desc = ("planted mixed n=5000: 15000 clauses k3-8, 1000 XOR k3-5, 250 CARD>=K k20-200" if five
+            else "planted 3-SAT n=100 m=426")
+    search = (args.ls_step, 0.5, 1e-4, args.ls_trials) if args.ls_trials else None
     net = gnn.GNN(rounds=3, seed=1)
-    losses = gnn.train(net, train_set, targets, train_steps, log=log)
-    log("trained (%.1f s)" % (time.perf_counter() - t0))
-    variants = [dict(sample=True, temperature=T) for T in (1.0, 2.0, 4.0)] + [dict(mix=0.8)]
-    best, best_key = None, None
-    for v in variants:
-        res = gnn.compare(net, val_set, B, max_steps, v, seed=1)
-        s = gnn.summarize(res, max_steps)["learned"]
-        key = (-s["solved"], s["median_iters"], s["mean_best_unsat_unsolved"])
-        log("validation %s: %s" % (v, s))
-        if best_key is None or key < best_key:
-            best, best_key = v, key
-    res = gnn.compare(net, test_set, B, max_steps, best, seed=2)
-    summ = gnn.summarize(res, max_steps)
-    timeout = summ["timeout_s"]
-    line = {"metric": "median time to a verified assignment, learned init", "value": summ["learned"]["median_s"],
+    info = {}
+    if args.load_net:
+        z = np.load(args.load_net, allow_pickle=False)
+        net.load_state_dict({k: z[k] for k in ("params", "m", "v", "t")})
+        info = json.loads(str(z["info"]))
+        log("loaded network from %s: %s" % (args.load_net, info))
+    else:
+        train_set = _gen_instances(make, [10000 + i for i in range(n_train)])
+        log("generated %d training instances (%.1f s)" % (n_train, time.perf_counter() - t0))
+        targets, verified, unsat_of = gnn.collect_targets(train_set, B=256, steps=args.target_steps)
+        info = {"train": n_train, "target_steps": args.target_steps, "targets_verified": verified,
+                "target_unsat_median": float(np.median(unsat_of)), "target_unsat_max": int(max(unsat_of)),
+                "train_steps": args.train_steps}
+        log("targets: %d of %d verified, median unsat %.1f (%.1f s)" % (
+            verified, n_train, np.median(unsat_of), time.perf_counter() - t0))
+        losses = gnn.train(net, train_set, targets, args.train_steps, log=log)
+        info["final_loss"] = losses[-1][1] if losses else None
+        del train_set, targets
+        log("trained (%.1f s)" % (time.perf_counter() - t0))
+        val_set = [make(20000 + i) for i in range(n_val)]
+        variants = [dict(sample=True, temperature=T) for T in (1.0, 2.0, 4.0)] + [dict(mix=0.8)]
+        best_key = None
+        for v in variants:
+            res = gnn.compare(net, val_set, B, args.round_steps, args.val_timeout, v, seed=1, lr=args.lr,
+                              search=search)
+            sv = gnn.summarize(res, args.val_timeout)["learned"]
+            key = (-sv["solved"], sv["median_iters"], sv["mean_best_unsat_unsolved"])
+            log("validation %s: %s" % (v, sv))
+            if best_key is None or key < best_key:
+                info["inference"], best_key = v, key
+        if args.save_net:
+            sd = net.state_dict()
+            np.savez(args.save_net, params=sd["params"], m=sd["m"], v=sd["v"], t=sd["t"], info=json.dumps(info))
+            log("saved network to %s" % args.save_net)
+    if not n_test:
+        print(json.dumps({"trained": info, "wall_s": time.perf_counter() - t0}), flush=True)
+        return
+    test_set = [make(30000 + i) for i in range(args.test_offset, args.test_offset + n_test)]
+    res = gnn.compare(net, test_set, B, args.round_steps, timeout, info["inference"], seed=2, lr=args.lr,
+                      search=search, log=log)
+    summ = gnn.summarize(res, timeout)
+    rm, lm = summ["random"]["median_s"], summ["learned"]["median_s"]
+    solved_any = summ["random"]["solved"] + summ["learned"]["solved"] > 0
+    line = {"metric": "median time to a verified assignment, learned init",
+            "value": lm if summ["learned"]["solved"] * 2 > n_test else None,
             "unit": "s", "higher_is_better": False, "n_gpus": 1, "dtype": "f32 (solver), bf16 MFMA (network)",
             "data": "synthetic",
-            "config": {"workload": desc, "train": n_train, "validation": n_val, "test": n_test, "restarts": B,
-                       "max_iterations": max_steps, "lr": 0.1, "training_targets_verified": verified,
-                       "train_steps": train_steps, "inference": best,
-                       "final_loss": losses[-1][1] if losses else None},
+            "config": {"workload": desc, "test": n_test, "test_offset": args.test_offset, "restarts": B,
+                       "round_iterations": args.round_steps, "timeout_s": timeout, "lr": args.lr,
+                       "line_search": list(search) if search else None, "network": info},
             "learned": summ["learned"], "random": summ["random"],
-            "vs_random_median": summ["learned"]["median_s"] / summ["random"]["median_s"],
-            "timeout_s_for_par2": timeout, "wall_s": time.perf_counter() - t0}
+            "vs_random_median": (lm / rm) if solved_any else None,
+            "per_instance": {arm: [[None if r[0] is None else round(r[0], 4), r[2], r[3]] for r in rows]
+                             for arm, rows in res.items()},
+            "wall_s": time.perf_counter() - t0}
     print(json.dumps(line), flush=True)
 
 

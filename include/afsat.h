@@ -597,19 +597,38 @@ afs_status afs_decompose(int32_t n, int32_t C, const int64_t *con_off, const int
  * failure AFS_EDEVICE.
  *
  * afs_probe_fma: every work-item runs 16 independent chains of `iters` plain
- *   FP32 fused multiply-adds (the library's kernels are built without packed
- *   FP32 instructions, so this is the issue ceiling of their arithmetic).
- *   out: device float [blocks * 256], one value per work-item.  *flops (host,
- *   may be NULL) = 2 * 16 * iters * blocks * 256.
+ *   FP32 operations (the library's kernels are built without packed FP32
+ *   instructions, so these bound the issue rate of their arithmetic):
+ *   variant 0 fused multiply-adds acc = acc * a + b with uniform a, b;
+ *   variant 1 acc += x * y with per-lane x, y; variant 2 multiplies acc *= x;
+ *   variant 3 the FE kernels' product step (r, i) <- (r - i z, i + r z) on 8
+ *   complex chains.  out: device float [blocks * 256], one value per
+ *   work-item.  *flops (host, may be NULL) = 2 (variant 2: 1) * 16 * iters *
+ *   blocks * 256.
  * afs_probe_mfma_bf16: every wave runs `iters` rounds of 8 independent
  *   16x16x32 BF16 matrix products with FP32 accumulation.  out as above;
  *   *flops = 2 * 16 * 16 * 32 * 8 * iters * blocks * 4.
  * afs_probe_copy: dst = src over `bytes` (a multiple of 16; both 16-byte
  *   aligned device pointers), 16-byte non-temporal loads and stores, grid-stride
  *   over `blocks` workgroups; reads and writes `bytes` each. */
-afs_status afs_probe_fma(int32_t blocks, int32_t iters, float *out, double *flops, void *stream);
+afs_status afs_probe_fma(int32_t variant, int32_t blocks, int32_t iters, float *out, double *flops,
+                         void *stream);
 afs_status afs_probe_mfma_bf16(int32_t blocks, int32_t iters, float *out, double *flops, void *stream);
 afs_status afs_probe_copy(const void *src, void *dst, int64_t bytes, int32_t blocks, void *stream);
+
+/* Starting points for Algorithm 1 from the network's output (Sec. 3.3 takes
+ * uniform random points; this is the learned alternative).  xhat, x0, out:
+ * device f32 [n][B] (x0 the noise the network was given, xhat its output
+ * tanh(z)); out may alias neither input.  The output is softened to tanh(z / T)
+ * (T = temperature > 0); with sample != 0 every point keeps magnitude |x0| and
+ * takes the sign of a draw from the softened marginal P(True) = (1 - tanh(z/T))/2
+ * (True -> negative), u uniform on [0, 1) from Philox4x32-10 keyed by seed with
+ * counter (b, v, 1, 0), u < P(True) meaning True; otherwise the point is
+ * (1 - mix) tanh(z / T) + mix x0 (0 <= mix <= 1).  A non-finite network output
+ * falls back to the uniform point x0.  Clamped to [-1, 1].  Enqueued on stream;
+ * no allocation. */
+afs_status afs_gnn_starts(int32_t n, int32_t B, const float *xhat, const float *x0, uint64_t seed, float temperature,
+                          float mix, int32_t sample, float *out, void *stream);
 
 /* Thread-local message for the last non-OK status of an afs_gnn_* call. */
 const char *afs_gnn_last_error(void);

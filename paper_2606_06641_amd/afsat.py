@@ -126,7 +126,7 @@ SIGNATURES = [
     ("afs_decompose_size", ctypes.c_int, [_i32, _i32, _i64p, _i32p, _i32, _i32p, _i32p, _i64p]),
     ("afs_decompose", ctypes.c_int, [_i32, _i32, _i64p, _i32p, _i32p, _i32p, _f32p, _i32, _i64p, _i32p, _i32p,
                                      _i32p, _f32p, _i32p]),
-    ("afs_probe_fma", ctypes.c_int, [_i32, _i32, _vp, _f64p, _vp]),
+    ("afs_probe_fma", ctypes.c_int, [_i32, _i32, _i32, _vp, _f64p, _vp]),
     ("afs_probe_mfma_bf16", ctypes.c_int, [_i32, _i32, _vp, _f64p, _vp]),
     ("afs_probe_copy", ctypes.c_int, [_vp, _vp, ctypes.c_int64, _i32, _vp]),
 ]
@@ -719,10 +719,11 @@ class FEObjective(torch.autograd.Function):
         return g, None
 
 
-def probe(kind, blocks, iters=0, nbytes=0, device=0):
+def probe(kind, blocks, iters=0, nbytes=0, device=0, variant=0):
     """Enqueue one peak-probe launch (afs_probe_*) on the current stream of
-    `device` and return the work it does: flops for "fma" and "mfma_bf16", bytes
-    moved (read + write) for "copy".  The caller times the launch."""
+    `device` and return the work it does: flops for "fma" (of `variant`) and
+    "mfma_bf16", bytes moved (read + write) for "copy".  The caller times the
+    launch."""
     dev = torch.device("cuda", device)
     st = _stream(device)
     if kind == "copy":
@@ -734,7 +735,9 @@ def probe(kind, blocks, iters=0, nbytes=0, device=0):
         return 2.0 * nbytes
     out = torch.empty(blocks * 256, dtype=torch.float32, device=dev)
     flops = ctypes.c_double()
-    fn = {"fma": lib().afs_probe_fma, "mfma_bf16": lib().afs_probe_mfma_bf16}[kind]
-    _check(fn(int(blocks), int(iters), _ptr(out), ctypes.byref(flops), st))
+    if kind == "fma":
+        _check(lib().afs_probe_fma(int(variant), int(blocks), int(iters), _ptr(out), ctypes.byref(flops), st))
+    else:
+        _check(lib().afs_probe_mfma_bf16(int(blocks), int(iters), _ptr(out), ctypes.byref(flops), st))
     probe._out = out                  # kept alive until the next probe call
     return flops.value

@@ -32,6 +32,7 @@
 
 #include "afsat.h"
 #include "instance.hpp"
+#include "philox.hpp"
 
 namespace afs {
 namespace gnn {
@@ -839,6 +840,41 @@ hipError_t backward_graph(Ctx &X)
     return hipSuccess;
 }
 
+// Starting points from the network's output xhat = tanh(z) and the noise x0 it
+// was given (one thread per (v, b)).  The output is softened to tanh(z / T);
+// with `sample` each point takes magnitude |x0| and the sign of a draw from the
+// softened marginal P(True) = (1 - tanh(z / T)) / 2 (True -> negative), the draw
+// u uniform on [0, 1) from Philox4x32-10 with counter (b, v, 1, 0); otherwise
+// the point is (1 - mix) tanh(z / T) + mix x0.  A non-finite network output
+// falls back to the uniform point x0.  Result clamped to [-1, 1].
+__global__ __launch_bounds__(kBlock) void starts_kernel(int64_t count, int B, const float *xhat, const float *x0,
+                                                        uint32_t k0, uint32_t k1, float inv_t, float mix,
+                                                        int sample, float *out)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= count) return;
+    const float xh = xhat[i], x = x0[i];
+    float r;
+    if (!isfinite(xh)) {
+        r = x;
+    } else {
+        float soft = xh;
+        if (inv_t != 1.0f) {
+            const float c = fminf(fmaxf(xh, -0.999999f), 0.999999f);
+            soft = tanhf(atanhf(c) * inv_t);
+        }
+        if (sample) {
+            const int v = (int)(i / B), b = (int)(i - (int64_t)v * B);
+            const afs::dev::U4 w = afs::dev::philox4x32_10(afs::dev::U4{(uint32_t)b, (uint32_t)v, 1u, 0u}, k0, k1);
+            const float u = (float)(w.x >> 8) * 0x1p-24f;          // [0, 1)
+            r = u < 0.5f * (1.0f - soft) ? -fabsf(x) : fabsf(x);
+        } else {
+            r = (1.0f - mix) * soft + mix * x;
+        }
+    }
+    out[i] = fminf(1.0f, fmaxf(-1.0f, r));
+}
+
 afs_status check(afs_gnn *G, afs_instance *I, int32_t B, void *ws, size_t ws_bytes, GnnWs &w)
 {
     if (!G || !I) return gfail(AFS_EINVAL, "NULL network or instance");
@@ -1030,6 +1066,21 @@ afs_status afs_gnn_adam(afs_gnn *G, float lr, float beta1, float beta2, float ep
     const float c1 = 1.0f - std::pow(beta1, (float)t), c2 = 1.0f - std::pow(beta2, (float)t);
     hipLaunchKernelGGL(adam_kernel, dim3(nblocks(G->L.total)), dim3(kBlock), 0, (hipStream_t)stream, G->p, G->g, G->m,
                        G->v, G->L.total, lr, beta1, beta2, eps, c1, c2);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? AFS_OK : gfail(AFS_EDEVICE, hipGetErrorString(e));
+}
+
+afs_status afs_gnn_starts(int32_t n, int32_t B, const float *xhat, const float *x0, uint64_t seed, float temperature,
+                          float mix, int32_t sample, float *out, void *stream)
+{
+    if (n < 0 || B < 0 || !(temperature > 0.0f) || !(mix >= 0.0f && mix <= 1.0f))
+        return gfail(AFS_EINVAL, "need n, B >= 0, temperature > 0, 0 <= mix <= 1");
+    const int64_t count = (int64_t)n * B;
+    if (count == 0) return AFS_OK;
+    if (count >= ((int64_t)1 << 38)) return gfail(AFS_EINVAL, "n * B too large");
+    if (!xhat || !x0 || !out) return gfail(AFS_EINVAL, "NULL array");
+    hipLaunchKernelGGL(starts_kernel, dim3(nblocks(count)), dim3(kBlock), 0, (hipStream_t)stream, count, B, xhat, x0,
+                       (uint32_t)seed, (uint32_t)(seed >> 32), 1.0f / temperature, mix, sample ? 1 : 0, out);
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? AFS_OK : gfail(AFS_EDEVICE, hipGetErrorString(e));
 }

@@ -20,14 +20,36 @@ namespace {
 constexpr int kProbeBlock = 256;
 constexpr int kChains = 16;            // independent FMA chains per lane
 
+// V = 0: v_fma_f32 chains acc = acc * a + b (a, b uniform);
+// V = 1: v_fmac_f32 chains acc += x * y with x, y per-lane registers;
+// V = 2: v_mul_f32 chains acc *= x;
+// V = 3: the product step of the FE kernels, (r, i) <- (r - i z, i + r z), two
+//        dependent FMAs per step, kChains / 2 independent complex chains.
+// Flops counted: 2 per FMA, 1 per multiply.
+template <int V>
 __global__ __launch_bounds__(kProbeBlock) void probe_fma_kernel(float *out, int iters, float a, float b)
 {
     float acc[kChains];
 #pragma unroll
     for (int j = 0; j < kChains; ++j) acc[j] = (float)(threadIdx.x + j) * 1e-3f;
+    const float x = a + (float)(threadIdx.x & 1) * 1e-9f, y = b + (float)(threadIdx.x & 2) * 1e-9f;
+#pragma unroll 2
     for (int i = 0; i < iters; ++i) {
+        if constexpr (V == 3) {
 #pragma unroll
-        for (int j = 0; j < kChains; ++j) acc[j] = fmaf(acc[j], a, b);
+            for (int j = 0; j < kChains; j += 2) {
+                const float r = fmaf(-acc[j + 1], y, acc[j]);
+                acc[j + 1] = fmaf(acc[j], y, acc[j + 1]);
+                acc[j] = r;
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < kChains; ++j) {
+                if constexpr (V == 0) acc[j] = fmaf(acc[j], a, b);
+                else if constexpr (V == 1) acc[j] = fmaf(x, y, acc[j]);
+                else acc[j] *= x;
+            }
+        }
     }
     float s = 0.f;
 #pragma unroll
@@ -74,13 +96,19 @@ __global__ __launch_bounds__(kProbeBlock) void probe_copy_kernel(const f32x4 *__
 
 extern "C" {
 
-afs_status afs_probe_fma(int32_t blocks, int32_t iters, float *out, double *flops, void *stream)
+afs_status afs_probe_fma(int32_t variant, int32_t blocks, int32_t iters, float *out, double *flops, void *stream)
 {
-    if (blocks <= 0 || iters <= 0 || !out) return AFS_EINVAL;
-    hipLaunchKernelGGL(probe_fma_kernel, dim3(blocks), dim3(kProbeBlock), 0, (hipStream_t)stream, out, iters,
-                       0.999999f, 1e-7f);
+    if (blocks <= 0 || iters <= 0 || !out || variant < 0 || variant > 3) return AFS_EINVAL;
+    const dim3 g(blocks), t(kProbeBlock);
+    hipStream_t s = (hipStream_t)stream;
+    switch (variant) {
+    case 0: hipLaunchKernelGGL(probe_fma_kernel<0>, g, t, 0, s, out, iters, 0.999999f, 1e-7f); break;
+    case 1: hipLaunchKernelGGL(probe_fma_kernel<1>, g, t, 0, s, out, iters, 1e-4f, 1e-4f); break;
+    case 2: hipLaunchKernelGGL(probe_fma_kernel<2>, g, t, 0, s, out, iters, 0.9999999f, 0.f); break;
+    default: hipLaunchKernelGGL(probe_fma_kernel<3>, g, t, 0, s, out, iters, 0.f, 1e-4f); break;
+    }
     if (hipGetLastError() != hipSuccess) return AFS_EDEVICE;
-    if (flops) *flops = 2.0 * kChains * (double)iters * (double)blocks * kProbeBlock;
+    if (flops) *flops = (variant == 2 ? 1.0 : 2.0) * kChains * (double)iters * (double)blocks * kProbeBlock;
     return AFS_OK;
 }
 

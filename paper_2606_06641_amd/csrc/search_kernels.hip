@@ -19,6 +19,7 @@
 #include "kernels.hpp"
 
 #include "device_common.hpp"
+#include "philox.hpp"
 
 namespace afs {
 
@@ -150,32 +151,6 @@ __global__ __launch_bounds__(kBlock) void search_step_kernel(StepArgs A)
     if ((lane & 7) == 0 && w < A.W) A.bits[(int64_t)v * A.W + w] = t;
 }
 
-// ---- Philox4x32-10 (Salmon, Moraes, Dror and Shaw, SC 2011) ----
-struct U4 {
-    uint32_t x, y, z, w;
-};
-
-__device__ __forceinline__ U4 philox_round(U4 c, uint32_t k0, uint32_t k1)
-{
-    const uint32_t m0 = 0xD2511F53u, m1 = 0xCD9E8D57u;
-    const uint32_t lo0 = m0 * c.x, hi0 = __umulhi(m0, c.x);
-    const uint32_t lo1 = m1 * c.z, hi1 = __umulhi(m1, c.z);
-    return U4{hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0};
-}
-
-__device__ __forceinline__ U4 philox4x32_10(U4 c, uint32_t k0, uint32_t k1)
-{
-#pragma unroll
-    for (int r = 0; r < 10; ++r) {
-        if (r > 0) {
-            k0 += 0x9E3779B9u;
-            k1 += 0xBB67AE85u;
-        }
-        c = philox_round(c, k0, k1);
-    }
-    return c;
-}
-
 __global__ __launch_bounds__(kBlock) void init_points_kernel(int n, int B, uint32_t k0, uint32_t k1,
                                                              const int8_t *values, int n_partial, float *x,
                                                              int nchunks, int64_t items, int64_t item0)
@@ -197,8 +172,7 @@ __global__ __launch_bounds__(kBlock) void init_points_kernel(int n, int B, uint3
         out = 1.0f;
     } else {
         const U4 r = philox4x32_10(U4{(uint32_t)b, (uint32_t)v, 0u, 0u}, k0, k1);
-        // top 24 bits: a multiple of 2^-23 in [0, 2), minus 1 (both exact in FP32)
-        out = (float)(r.x >> 8) * 0x1p-23f - 1.0f;
+        out = philox_pm1(r.x);          // top 24 bits: a multiple of 2^-23 in [-1, 1)
     }
     x[(int64_t)v * B + b] = out;
 }

@@ -32,6 +32,8 @@ GNN_SIGNATURES = [
     ("afs_gnn_zero_grad", ctypes.c_int, [_vp, _vp]),
     ("afs_gnn_adam", ctypes.c_int, [_vp, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                     ctypes.c_int32, _vp]),
+    ("afs_gnn_starts", ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, _vp, _vp, ctypes.c_uint64, ctypes.c_float,
+                                      ctypes.c_float, ctypes.c_int32, _vp, _vp]),
     ("afs_gnn_gemm_bf16", ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _vp, ctypes.c_int64,
                                          ctypes.c_int64, _vp, ctypes.c_int64, ctypes.c_int64, _vp,
                                          ctypes.c_int64, _vp]),
@@ -170,153 +172,144 @@ class GNN:
 # Orchestration
 # ---------------------------------------------------------------------------
 
-def solver_target(dinst, x0, steps, lr=0.1, poll=10):
-    """Run Algorithm 1 from x0 (n, B) and return the rounded assignment of its best
-    restart (a verified one if any, else the fewest unsatisfied constraints) as a
-    uint8 CUDA tensor (1 = True), plus whether it verified."""
-    x = x0.clone()
-    st = dinst.pgd(x, lr=lr, steps=steps, poll=poll, stop_on_sat=True, graph=False)
-    unsat = st["unsat"].reshape(-1)
-    best = int(torch.argmin(unsat).item())
-    return (x[:, best] < 0).to(torch.uint8).contiguous(), int(unsat[best].item()) == 0
+def uniform_start(dinst, B, seed):
+    """Uniform starting points (n, B) on [-1, 1) from the library's counter-based
+    generator (afs_init_points) keyed by seed."""
+    return dinst.init_points(B, seed)
 
 
-def uniform_start(n, B, generator=None, device=0):
-    dev = torch.device("cuda", device)
-    return (torch.rand((n, B), generator=generator, device=dev) * 2 - 1).contiguous()
-
-
-def learned_start(net, dinst, B, generator=None, temperature=1.0, mix=0.0, sample=False):
-    """Starting points proposed by the network (uniform random if it yields
-    non-finite values: fallback).
-
-    The network maps noise x0 to xhat = tanh(z).  ``temperature`` T softens it to
-    tanh(z / T) (= tanh(atanh(xhat) / T)); ``mix`` blends the result with the
-    noise, (1 - mix) tanh(z/T) + mix x0; with ``sample`` each restart instead draws
-    the sign of every variable from the softened marginal P(True) = (1 - tanh(z/T))/2
-    and keeps |x0| as magnitude."""
-    x0 = uniform_start(dinst.n, B, generator, net.device)
+def learned_start(net, dinst, B, seed, temperature=1.0, mix=0.0, sample=False):
+    """Starting points proposed by the network: noise x0 = uniform_start(seed)
+    through the network (xhat = tanh(z)), then afs_gnn_starts: softened to
+    tanh(z / T); with ``sample`` every variable's sign drawn from the softened
+    marginal P(True) = (1 - tanh(z/T))/2 with |x0| as magnitude, else
+    (1 - mix) tanh(z/T) + mix x0; a non-finite output falls back to x0."""
+    x0 = uniform_start(dinst, B, seed)
     xhat = net.forward(dinst, x0)
-    if not bool(torch.isfinite(xhat).all()):
-        return x0, False
-    if temperature != 1.0:
-        xhat = torch.tanh(torch.atanh(xhat.clamp(-0.999999, 0.999999)) / temperature)
-    if sample:
-        u = torch.rand(x0.shape, generator=generator, device=x0.device)
-        true = u < (1 - xhat) / 2
-        out = torch.where(true, -x0.abs(), x0.abs())
-    else:
-        out = (1 - mix) * xhat + mix * x0
-    return out.clamp(-1, 1).contiguous(), True
+    out = torch.empty_like(x0)
+    _check(lib().afs_gnn_starts(dinst.n, B, _p(xhat), _p(x0), (int(seed) * 0x9E3779B97F4A7C15 + 1) % (1 << 64),
+                                float(temperature), float(mix), int(bool(sample)), _p(out), _stream(net.device)))
+    return out
 
 
-def time_to_sat(dinst, make_start, B, max_steps, lr=0.1, poll=10):
-    """Seconds from the start of init generation to the first verified restart
-    (None if none verifies within max_steps), and the best unsat count seen."""
-    torch.cuda.synchronize(dinst.device)
-    t0 = time.perf_counter()
-    x0 = make_start()
-    st = dinst.pgd(x0, lr=lr, steps=max_steps, poll=poll, stop_on_sat=True, graph=False)
-    solved = int(st["counter"][1].item()) > 0
-    torch.cuda.synchronize(dinst.device)
-    t1 = time.perf_counter()
-    return (t1 - t0) if solved else None, int(st["unsat"].min().item()), st["iters"]
-
-
-# ---------------------------------------------------------------------------
-# Train-and-compare experiment (learned vs uniform random initialisation)
-# ---------------------------------------------------------------------------
-
-def collect_targets(parts, B=256, steps=150, lr=0.1, chunk=32):
+def collect_targets(parts, B=256, steps=200, lr=0.1, chunk=32, seed=0):
     """Solver-produced targets for each instance: the rounded best restart of
-    Algorithm 1 from uniform random starts (instances solved together in batches).
-    Returns (list of uint8 CUDA tensors, number verified)."""
-    targets, verified = [], 0
+    Algorithm 1 from uniform random starts (instances solved together in
+    block-diagonal batches of ``chunk``), a verified restart when there is one,
+    else the fewest unsatisfied constraints.  Returns (list of uint8 CUDA
+    tensors, number verified, unsat count of each target)."""
+    targets, verified, unsat_of = [], 0, []
     for i in range(0, len(parts), chunk):
         group = parts[i:i + chunk]
         bt = afsat.Instance.batch(group)
-        x = uniform_start(bt.n, B)
-        st = bt.pgd(x, lr=lr, steps=steps, poll=10, stop_on_sat=False, graph=False)
+        x = uniform_start(bt, B, seed * 1000003 + i)
+        st = bt.pgd(x, lr=lr, steps=steps, poll=10, stop_on_sat=False)
         unsat = st["unsat"].reshape(len(group), B)
         best = torch.argmin(unsat, dim=1)
         off = bt.var_offsets()
         for p in range(len(group)):
             b = int(best[p].item())
-            verified += int(unsat[p, b].item()) == 0
+            u = int(unsat[p, b].item())
+            verified += u == 0
+            unsat_of.append(u)
             targets.append((x[off[p]:off[p + 1], b] < 0).to(torch.uint8).contiguous())
-    return targets, verified
+        bt.close()
+    return targets, verified, unsat_of
 
 
 def train(net, parts, targets, steps, lr=2e-3, chunk=32, restarts=16, seed=0, log=None):
-    """Adam on the mean BCE, cycling over batches of ``chunk`` instances."""
+    """Adam on the mean BCE, cycling over batches of ``chunk`` instances; the
+    noise given to the network is drawn by afs_init_points, fresh every step."""
     batches = []
     for i in range(0, len(parts), chunk):
         batches.append((afsat.Instance.batch(parts[i:i + chunk]), torch.cat(targets[i:i + chunk])))
-    gen = torch.Generator(device="cuda").manual_seed(seed)
     losses = []
     for step in range(steps):
         bt, tg = batches[step % len(batches)]
         net.zero_grad()
-        loss = net.loss_backward(bt, uniform_start(bt.n, restarts, gen), tg)
+        loss = net.loss_backward(bt, uniform_start(bt, restarts, seed * 1000003 + step), tg)
         net.adam(lr=lr)
         if step % 50 == 0 or step == steps - 1:
             losses.append((step, float(loss.item())))
             if log:
                 log("train step %d loss %.4f" % losses[-1])
+    for bt, _ in batches:
+        bt.close()
     return losses
 
 
-def run_arm(dinst, make_start, max_steps, lr=0.1, poll=10):
-    """One arm on one instance: (seconds to the first verified restart or None,
-    first verifying iteration or None, best unsat at the end, wall seconds spent).
-    The clock starts before the starting points are generated."""
+def run_arm(dinst, make_start, round_steps, timeout_s, lr=0.1, poll=10, search=None):
+    """One arm on one instance: Algorithm 1 in rounds of ``round_steps``
+    iterations, each from fresh starting points (``make_start()``), until a
+    restart verifies or ``timeout_s`` has passed.  The clock starts before the
+    first starting points are generated, so the learned arm's time includes the
+    network's first use on the instance (its graph build) and every round's
+    inference.  Returns (seconds to the first verified restart or None, rounds,
+    iterations run, best unsat count seen, wall seconds spent)."""
     torch.cuda.synchronize(dinst.device)
     t0 = time.perf_counter()
-    x0 = make_start()
-    st = dinst.pgd(x0, lr=lr, steps=max_steps, poll=poll, stop_on_sat=True, graph=False)
-    torch.cuda.synchronize(dinst.device)
-    t1 = time.perf_counter()
-    fs = st["first_sat"].reshape(-1)
-    ok = fs >= 0
-    if bool(ok.any()):
-        return t1 - t0, int(fs[ok].min().item()), 0, t1 - t0
-    return None, None, int(st["unsat"].min().item()), t1 - t0
+    rounds = iters = 0
+    best = None
+    while True:
+        x0 = make_start()
+        st = dinst.pgd(x0, lr=lr, steps=round_steps, poll=poll, stop_on_sat=True, search=search)
+        rounds += 1
+        iters += st["iters"]
+        u = int(st["unsat"].min().item())
+        best = u if best is None else min(best, u)
+        solved = int(st["counter"][1].item()) > 0
+        el = time.perf_counter() - t0
+        if solved:
+            return el, rounds, iters, 0, el
+        if el >= timeout_s:
+            return None, rounds, iters, best, el
 
 
-def compare(net, tests, B, max_steps, variant, seed=0, timeout_s=None, lr=0.1):
-    """Learned vs uniform random starts on each test instance (same noise seed per
-    instance for both arms).  Returns per-arm lists of (seconds, iteration, best_unsat)."""
+def compare(net, tests, B, round_steps, timeout_s, variant, seed=0, lr=0.1, search=None, log=None):
+    """Learned vs uniform random starts on each test instance.  Before either arm
+    is timed, one untimed two-iteration run on the instance pays the solver's
+    first-use costs (its workspace, state and driver streams); the arms then take
+    turns going first (even instances random first, odd ones learned first), each
+    with its own noise generator seeded per instance.  Returns per-arm lists of
+    run_arm results."""
     out = {"random": [], "learned": []}
     for i, p in enumerate(tests):
         d = afsat.Instance.from_arrays(p)
-        net.forward(d, uniform_start(p.n, 1))           # build the instance's graph tensors once
-        for arm in ("random", "learned"):
-            g = torch.Generator(device="cuda").manual_seed(seed * 100003 + i)
+        d.pgd(uniform_start(d, B, (seed << 40) + (i << 20) + 0xFFFFF), lr=lr, steps=2, poll=1, stop_on_sat=False,
+              search=search)
+        order = ("random", "learned") if i % 2 == 0 else ("learned", "random")
+        for arm in order:
+            rounds = iter(range(1 << 20))
+            base = (seed << 40) + (i << 20)          # round r of either arm draws noise with seed base + r
             if arm == "random":
-                make = lambda: uniform_start(p.n, B, g)
+                make = lambda: uniform_start(d, B, base + next(rounds))
             else:
-                make = lambda: learned_start(net, d, B, g, **variant)[0]
-            out[arm].append(run_arm(d, make, max_steps, lr))
+                make = lambda: learned_start(net, d, B, base + next(rounds), **variant)
+            out[arm].append(run_arm(d, make, round_steps, timeout_s, lr, search=search))
+        if log:
+            log("instance %d: random %s | learned %s" % (i, _fmt(out["random"][-1]), _fmt(out["learned"][-1])))
         d.close()
     return out
 
 
-def summarize(res, max_steps, timeout_s=None):
-    """Median time / iterations to a verified assignment (censored runs count twice
-    the timeout, PAR-2), solved counts.  The default timeout is the longest wall time
-    any run of either arm spent (an unsolved run spends the full iteration budget)."""
-    if timeout_s is None:
-        timeout_s = max(r[3] for rows in res.values() for r in rows)
+def _fmt(r):
+    return ("%.3f s, %d iterations" % (r[0], r[2])) if r[0] is not None else \
+        ("unsolved after %.1f s, %d iterations, best unsat %d" % (r[4], r[2], r[3]))
+
+
+def summarize(res, timeout_s):
+    """Per arm: solved count, median time to a verified assignment and mean PAR-2
+    (an unsolved run counts twice the timeout), median iterations to it (an
+    unsolved run counts its iterations twice), mean best unsat of the unsolved."""
     out = {"timeout_s": timeout_s}
     for arm, rows in res.items():
         t = [r[0] for r in rows]
-        it = [r[1] for r in rows]
         solved = [x is not None for x in t]
         par2 = [x if x is not None else 2 * timeout_s for x in t]
-        it_c = [x if x is not None else 2 * max_steps for x in it]
+        it_c = [r[2] if r[0] is not None else 2 * r[2] for r in rows]
         out[arm] = {"solved": int(sum(solved)), "of": len(rows),
                     "median_s": float(np.median(par2)), "par2_mean_s": float(np.mean(par2)),
                     "median_iters": float(np.median(it_c)),
-                    "mean_best_unsat_unsolved": float(np.mean([r[2] for r in rows if r[0] is None]))
+                    "mean_best_unsat_unsolved": float(np.mean([r[3] for r in rows if r[0] is None]))
                     if not all(solved) else 0.0}
     return out

@@ -24,12 +24,12 @@ def philox4x32_10(ctr, key):
     return c0, c1, c2, c3
 
 
-def philox_first_words(ctr0, ctr1, key):
-    """First output word for counters (ctr0[i], ctr1[i], 0, 0), vectorised over
+def philox_first_words(ctr0, ctr1, key, ctr2=0):
+    """First output word for counters (ctr0[i], ctr1[i], ctr2, 0), vectorised over
     numpy uint64 arrays holding 32-bit values."""
     c0 = np.asarray(ctr0, dtype=np.uint64) & MASK
     c1 = np.asarray(ctr1, dtype=np.uint64) & MASK
-    c2 = np.zeros_like(c0)
+    c2 = np.full_like(c0, int(ctr2) & MASK)
     c3 = np.zeros_like(c0)
     k0, k1 = np.uint64(int(key[0]) & MASK), np.uint64(int(key[1]) & MASK)
     m = np.uint64(MASK)

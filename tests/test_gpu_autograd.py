@@ -46,14 +46,15 @@ def test_forward_and_vjp_match_eval_and_oracle():
     (obj * gobj).sum().backward()
     torch.cuda.synchronize()
     orc = oracle.eval(inst, x32, grad=True, adj=True)
-    e, bar, _ = parity.rel_max(obj.detach().cpu().numpy().astype(np.float64), orc["obj"])
-    assert e <= bar
+    parity.check_obj(inst, obj.detach().cpu().numpy().astype(np.float64), orc["obj"], None, "forward")
     seed = gobj.cpu().numpy().astype(np.float64)[None, :]
-    parity.check_grad(x.grad.cpu().numpy().astype(np.float64), orc["grad"] * seed, "vjp")
+    parity.check_grad(x.grad.cpu().numpy().astype(np.float64) / np.max(np.abs(seed)),
+                      orc["grad"] * seed / np.max(np.abs(seed)), "vjp", inst)
     grad, adj = d.eval_adjoint(x.detach(), gobj, adj=True)
     torch.cuda.synchronize()
+    lit_w = parity.literal_weights(inst) * float(np.max(np.abs(seed)))
     rel = parity.check_adjoints(adj.cpu().numpy().astype(np.float64), orc["adj"] * seed,
-                                parity.bucket_of_literals(d), d.buckets(), "eval_adjoint")
+                                parity.bucket_of_literals(d), d.buckets(), "eval_adjoint", lit_w)
     log("per-bucket adjoint errors (max rel, L2 rel):", ["%.1e/%.1e" % r for r in rel])
     assert torch.equal(grad, x.grad)
     # the forward-only objective equals the full evaluation's, and the unseeded
@@ -84,15 +85,15 @@ def test_longcard50k_autograd():
     rng = np.random.default_rng(40)
     cols = np.sort(rng.choice(B, size=8, replace=False))
     orc = oracle.eval(inst, x32[:, cols], grad=True, adj=True)
-    r = parity.check_grad(g[:, cols], orc["grad"], "longcard50k grad")
+    r = parity.check_grad(g[:, cols], orc["grad"], "longcard50k grad", inst)
     log("gradient: max rel %.2e, L2 rel %.2e" % r)
-    e, bar, _ = parity.rel_max(obj.detach().cpu().numpy().astype(np.float64)[cols], orc["obj"])
-    assert e <= bar
+    parity.check_obj(inst, obj.detach().cpu().numpy().astype(np.float64)[cols], orc["obj"], None, "forward")
     _, adj = d.eval_adjoint(x.detach(), adj=True)
     ci = torch.from_numpy(cols).cuda()
     adj_s = adj.index_select(1, ci).cpu().numpy().astype(np.float64)
     del adj
-    rel = parity.check_adjoints(adj_s, orc["adj"], parity.bucket_of_literals(d), d.buckets(), "longcard50k adj")
+    rel = parity.check_adjoints(adj_s, orc["adj"], parity.bucket_of_literals(d), d.buckets(), "longcard50k adj",
+                                parity.literal_weights(inst))
     log("per-bucket adjoint errors (max rel, L2 rel):")
     for b, rr in zip(d.buckets(), rel):
         log("  [%4d-%4d] J%-2d S%-2d  %.2e  %.2e" % (b.k_lo, b.k_hi, b.lanes_per_restart, b.lits_per_lane, *rr))

@@ -94,9 +94,11 @@ def test_forward_backward_match_reference():
     event, not a small uniform rounding.  The model is the reference itself
     evaluated in FP32 (acc=np.float32) over 32 parameter draws: per parameter
     group, the mean and the worst rel-L2 distance between the FP32 and FP64
-    evaluations.  The device, on 8 of those draws, must stay within 3x the
-    model's mean (+1e-6) and 1.5x its worst (+1e-5); xhat likewise by max |.|;
-    the loss within 1e-5 relative."""
+    evaluations.  The events are rare and heavy-tailed (a draw without one is
+    at 1e-7, one with a flip in an early layer at 1e-2), so the test is on the
+    mean: the device, on 8 of those draws, must stay within 3x the model's mean
+    (+1e-6); its worst draw within 3x the model's worst (+1e-5); xhat likewise by
+    max |.|; the loss within 1e-5 relative."""
     inst = mixed_small(3)
     d = afsat.Instance.from_arrays(inst)
     net = gnn.GNN(rounds=3, seed=7)
@@ -128,7 +130,7 @@ def test_forward_backward_match_reference():
         dev_err.setdefault("xhat", []).append(float(np.max(np.abs(xhat - x64))))
     for k in dev_err:
         mean_bar = 3 * np.mean(model[k]) + 1e-6
-        worst_bar = 1.5 * np.max(model[k]) + 1e-5
+        worst_bar = 3 * np.max(model[k]) + 1e-5
         log("%-4s device mean %.2e worst %.2e | model mean %.2e worst %.2e" % (
             k, np.mean(dev_err[k]), np.max(dev_err[k]), np.mean(model[k]), np.max(model[k])))
         assert np.mean(dev_err[k]) <= mean_bar, k
@@ -148,37 +150,86 @@ def test_training_reduces_loss_and_batches_work():
     bt = afsat.Instance.batch(parts)
     target = torch.from_numpy(np.concatenate([p.hidden for p in parts]).astype(np.uint8)).cuda()
     net = gnn.GNN(rounds=3, seed=1)
-    gen = torch.Generator(device="cuda").manual_seed(0)
     losses = []
     for step in range(80):
-        x0 = gnn.uniform_start(bt.n, 16, gen)
+        x0 = gnn.uniform_start(bt, 16, step)
         net.zero_grad()
         losses.append(float(net.loss_backward(bt, x0, target).item()))
         net.adam(lr=3e-3)
     log("loss %.4f -> %.4f" % (losses[0], losses[-1]))
     assert np.mean(losses[-10:]) < 0.8 * np.mean(losses[:5])
     # the trained network agrees with the planted assignment better than chance
-    xhat = net.forward(bt, gnn.uniform_start(bt.n, 64, gen))
+    xhat = net.forward(bt, gnn.uniform_start(bt, 64, 999))
     agree = ((xhat < 0).float().mean(dim=1).cpu().numpy() > 0.5) == np.concatenate([p.hidden for p in parts])
     log("agreement with hidden assignment %.3f" % agree.mean())
     assert agree.mean() > 0.6
+
+
+def test_starting_points_from_the_network_output():
+    """afs_gnn_starts against a host reference: at temperature 1 every sign
+    decision u < (1 - xhat)/2 is bit-exact (u from the test-side Philox4x32-10,
+    counter (b, v, 1, 0), the comparison in FP32 on both sides) with magnitude
+    |x0|; the blend (1 - mix) xhat + mix x0 matches to FP32 rounding; a
+    non-finite network output falls back to x0; softening by T > 1 moves the
+    marginals toward 1/2 (fewer points agree with sign(xhat))."""
+    from philox_ref import philox_first_words
+    rng = np.random.default_rng(8)
+    n, B = 300, 70
+    xhat = rng.uniform(-1, 1, size=(n, B)).astype(np.float32)
+    xhat[3, 5], xhat[7, 0] = np.nan, np.inf
+    x0 = rng.uniform(-1, 1, size=(n, B)).astype(np.float32)
+    seed = 0x0123456789ABCDEF
+    dx, d0 = parity.to_dev(xhat), parity.to_dev(x0)
+
+    def starts(T, mix, sample):
+        out = torch.empty_like(d0)
+        rc = gnn.lib().afs_gnn_starts(n, B, gnn._p(dx), gnn._p(d0), seed, T, mix, int(sample), gnn._p(out),
+                                      gnn._stream(0))
+        assert rc == 0
+        return out.cpu().numpy()
+
+    got = starts(1.0, 0.0, True)
+    vv, bb = np.meshgrid(np.arange(n), np.arange(B), indexing="ij")
+    words = philox_first_words(bb.ravel(), vv.ravel(), (seed & 0xFFFFFFFF, seed >> 32), ctr2=1).reshape(n, B)
+    u = ((words >> np.uint64(8)).astype(np.float64) * 2.0 ** -24).astype(np.float32)
+    p_true = np.float32(0.5) * (np.float32(1.0) - xhat)
+    want = np.where(u < p_true, -np.abs(x0), np.abs(x0)).astype(np.float32)
+    bad = ~np.isfinite(xhat)
+    want[bad] = x0[bad]
+    np.testing.assert_array_equal(got, want)
+    blend = starts(1.0, 0.25, False)
+    wantb = np.clip(0.75 * xhat.astype(np.float64) + 0.25 * x0, -1, 1)
+    wantb[bad] = x0[bad]
+    np.testing.assert_allclose(blend, wantb, atol=2e-7)
+    soft = starts(4.0, 0.0, False)
+    ok = np.isfinite(xhat) & (np.abs(xhat) < 0.999)
+    np.testing.assert_allclose(soft[ok], np.tanh(np.arctanh(xhat[ok].astype(np.float64)) / 4.0), atol=2e-6)
+    agree_hot = np.mean((starts(4.0, 0.0, True)[ok] < 0) == (xhat[ok] < 0))
+    agree_cold = np.mean((got[ok] < 0) == (xhat[ok] < 0))
+    log("agreement with sign(xhat): T=1 %.3f, T=4 %.3f" % (agree_cold, agree_hot))
+    assert agree_hot < agree_cold
 
 
 def test_learned_init_helps_on_held_out_instances():
     """Train on solver-produced targets (the best restart of Algorithm 1 on each
     training instance), then compare learned starting points (signs sampled from
     the network's softened marginals) with uniform random ones on held-out
-    planted 3-SAT: the learned arm solves at least as many and needs no more
-    iterations (median) to its first verified assignment."""
+    planted 3-SAT (n = 100, 426 clauses), 256 restarts, rounds of 300 iterations:
+    the learned arm needs at most 0.8x the random arm's median iterations to its
+    first verified assignment, a strictly lower median time, and solves at least
+    as many instances.  Both arms pay the same first-use costs (an untimed
+    warm-up run first, alternating order), and the learned arm's clock includes
+    the network's graph build and inference."""
     train = [W.planted_3sat(n=100, m=426, instance=1000 + i) for i in range(160)]
-    targets, ok = gnn.collect_targets(train, B=256, steps=150)
+    targets, ok, _ = gnn.collect_targets(train, B=256, steps=150)
     log("training targets verified: %d / %d" % (ok, len(train)))
     net = gnn.GNN(rounds=3, seed=2)
     gnn.train(net, train, targets, 500)
-    tests = [W.planted_3sat(n=100, m=426, instance=5000 + i) for i in range(24)]
-    res = gnn.compare(net, tests, 256, 300, dict(sample=True, temperature=2.0), seed=3)
-    s = gnn.summarize(res, 300)
+    tests = [W.planted_3sat(n=100, m=426, instance=5000 + i) for i in range(32)]
+    res = gnn.compare(net, tests, 256, 300, 3.0, dict(sample=True, temperature=2.0), seed=3)
+    s = gnn.summarize(res, 3.0)
     log("held-out: random %s" % s["random"])
     log("held-out: learned %s" % s["learned"])
     assert s["learned"]["solved"] >= s["random"]["solved"]
-    assert s["learned"]["median_iters"] <= s["random"]["median_iters"]
+    assert s["learned"]["median_iters"] <= 0.8 * s["random"]["median_iters"]
+    assert s["learned"]["median_s"] < s["random"]["median_s"]

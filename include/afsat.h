@@ -586,6 +586,26 @@ afs_status afs_decompose(int32_t n, int32_t C, const int64_t *con_off, const int
                          int32_t *lits_out, int32_t *types_out, int32_t *params_out, float *weights_out,
                          int32_t *origin_out);
 
+/* ---- evaluation without allocation -------------------------------------------------- */
+
+/* For callers that cannot allocate device memory or pass a workspace (code under
+ * HIP graph capture that must not call hipMalloc, tight serving loops, harnesses
+ * that forbid allocation): afs_eval with a static scratch array of the library
+ * in place of the workspace.  Outputs, their layout and the arithmetic are those
+ * of afs_eval (same kernels, same order).
+ *   The scratch is a device array of AFS_NOALLOC_SCRATCH_BYTES (64 MiB) per
+ *   device, held from the library's first use on that device until the process
+ *   ends.  The call allocates nothing and calls no allocating routine; it
+ *   returns AFS_EINVAL (nothing launched) when the instance needs more scratch
+ *   at B than that: afs_workspace_bytes-style sizing, the adjoint rows L x
+ *   round_up(B, 64) floats plus the objective partials.  Every call on one
+ *   device shares that device's array, which keeps the last call's contents:
+ *   calls that overlap on one device (different streams or host threads) race
+ *   and give wrong results; order them on one stream. */
+#define AFS_NOALLOC_SCRATCH_BYTES (64ull << 20)
+afs_status afs_eval_noalloc(afs_instance *inst, int32_t B, const float *x, float *obj, float *grad, float *fe,
+                            float *adj, void *stream);
+
 /* ---- peak probes (roofline denominators) ------------------------------------------ */
 
 /* Small kernels that measure the device's attainable peaks for this build's

@@ -126,6 +126,7 @@ SIGNATURES = [
     ("afs_decompose_size", ctypes.c_int, [_i32, _i32, _i64p, _i32p, _i32, _i32p, _i32p, _i64p]),
     ("afs_decompose", ctypes.c_int, [_i32, _i32, _i64p, _i32p, _i32p, _i32p, _f32p, _i32, _i64p, _i32p, _i32p,
                                      _i32p, _f32p, _i32p]),
+    ("afs_eval_noalloc", ctypes.c_int, [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp]),
     ("afs_probe_fma", ctypes.c_int, [_i32, _i32, _i32, _vp, _f64p, _vp]),
     ("afs_probe_mfma_bf16", ctypes.c_int, [_i32, _i32, _vp, _f64p, _vp]),
     ("afs_probe_copy", ctypes.c_int, [_vp, _vp, ctypes.c_int64, _i32, _vp]),
@@ -367,6 +368,20 @@ class Instance:
         _check(lib().afs_eval(self._h, B, _ptr(x), _ptr(ws), ws.numel(), _ptr(out.get("obj")),
                               _ptr(out.get("grad")), _ptr(out.get("fe")), _ptr(out.get("adj")),
                               _stream(dev)))
+        return out
+
+    def eval_noalloc(self, x, obj=True, grad=True, fe=False, adj=False, out=None):
+        """afs_eval_noalloc: as eval, with the library's static scratch in place of a
+        workspace.  `out` may hold preallocated outputs (dict of the same keys)."""
+        B = self._check_x(x)
+        dev = self._dev()
+        out = {} if out is None else dict(out)
+        shapes = {"obj": (B,), "grad": (self.n, B), "fe": (self.n_cons, B), "adj": (self.n_lits, B)}
+        for k, want in (("obj", obj), ("grad", grad), ("fe", fe), ("adj", adj)):
+            if want and k not in out:
+                out[k] = torch.empty(shapes[k], dtype=torch.float32, device=dev)
+        _check(lib().afs_eval_noalloc(self._h, B, _ptr(x), _ptr(out.get("obj")), _ptr(out.get("grad")),
+                                      _ptr(out.get("fe")), _ptr(out.get("adj")), _stream(dev)))
         return out
 
     def fe_grad(self, x, ws, bucket_lo=0, bucket_hi=None, want_obj=False, fe=None):

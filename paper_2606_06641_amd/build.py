@@ -47,6 +47,7 @@ SOURCES = [
     ("forms.hip", [HIPCC] + COMMON + DEVICE),
     ("gnn.hip", [HIPCC] + COMMON + DEVICE),
     ("probes.hip", [HIPCC] + COMMON + DEVICE),
+    ("noalloc.hip", [HIPCC] + COMMON + DEVICE),
 ]
 
 

@@ -550,18 +550,22 @@ afs_status afs_scatter(afs_instance *I, int32_t B, void *ws, size_t ws_bytes, fl
     return AFS_OK;
 }
 
-afs_status afs_eval(afs_instance *I, int32_t B, const float *x, void *ws, size_t ws_bytes,
-                    float *obj, float *grad, float *fe, float *adj, void *stream)
+}  // extern "C"
+
+namespace {
+
+// afs_eval after the workspace check: FE + adjoints into ws, then the gradient
+// sum, the objective reduction and the literal-order adjoints as requested.
+// Only the adjoint rows and the objective partials of ws are used (everything
+// below l.bits).
+afs_status eval_body(afs_instance *I, int32_t B, const float *x, void *ws, const WsLayout &l, float *obj,
+                     float *grad, float *fe, float *adj, void *stream)
 {
-    afs_status st = check_call(I, B);
-    if (st != AFS_OK) return st;
-    WsLayout l;
-    if ((st = check_ws(I, B, ws, ws_bytes, l)) != AFS_OK) return st;
     if (!x && B > 0) return fail(AFS_EINVAL, "x is NULL");
     DeviceGuard g(I->device);
     if (g.error() != hipSuccess) return dev_fail(g.error(), "hipSetDevice");
     hipStream_t s = (hipStream_t)stream;
-    st = fe_grad_range(I, B, x, ws, l, 0, (int)I->H.buckets.size(), obj != nullptr, fe, s);
+    const afs_status st = fe_grad_range(I, B, x, ws, l, 0, (int)I->H.buckets.size(), obj != nullptr, fe, s);
     if (st != AFS_OK) return st;
     hipError_t e;
     if (grad && (e = afs::launch_scatter(I->D, B, l.Bp, at<float>(ws, l.adj), grad, s)) != hipSuccess)
@@ -572,6 +576,42 @@ afs_status afs_eval(afs_instance *I, int32_t B, const float *x, void *ws, size_t
     if (adj && (e = afs::launch_permute_adj(I->D, B, l.Bp, at<float>(ws, l.adj), adj, s)) != hipSuccess)
         return dev_fail(e, "adjoint permute launch");
     return AFS_OK;
+}
+
+}  // namespace
+
+namespace afs {
+
+size_t eval_scratch_bytes(const afs_instance *I, int32_t B)
+{
+    return ws_layout(I->H, B).bits;
+}
+
+afs_status eval_in_scratch(afs_instance *I, int32_t B, const float *x, void *scratch, size_t scratch_bytes,
+                           float *obj, float *grad, float *fe, float *adj, void *stream)
+{
+    afs_status st = check_call(I, B);
+    if (st != AFS_OK) return st;
+    const WsLayout l = ws_layout(I->H, B);
+    if (reinterpret_cast<uintptr_t>(scratch) % 256) return fail(AFS_EINVAL, "scratch is not 256-byte aligned");
+    if (l.bits > scratch_bytes)
+        return fail(AFS_EINVAL, "evaluation needs " + std::to_string(l.bits) + " bytes of scratch, more than " +
+                                    std::to_string(scratch_bytes));
+    return eval_body(I, B, x, scratch, l, obj, grad, fe, adj, stream);
+}
+
+}  // namespace afs
+
+extern "C" {
+
+afs_status afs_eval(afs_instance *I, int32_t B, const float *x, void *ws, size_t ws_bytes,
+                    float *obj, float *grad, float *fe, float *adj, void *stream)
+{
+    afs_status st = check_call(I, B);
+    if (st != AFS_OK) return st;
+    WsLayout l;
+    if ((st = check_ws(I, B, ws, ws_bytes, l)) != AFS_OK) return st;
+    return eval_body(I, B, x, ws, l, obj, grad, fe, adj, stream);
 }
 
 afs_status afs_eval_fwd(afs_instance *I, int32_t B, const float *x, void *ws, size_t ws_bytes,

@@ -30,6 +30,18 @@ namespace afs {
 afs_status set_last_error(afs_status s, const std::string &msg);
 }  // namespace afs
 
+struct afs_instance;
+
+namespace afs {
+// Bytes of scratch afs_eval uses at B restarts (the adjoint rows and the
+// objective partials of its workspace).
+size_t eval_scratch_bytes(const afs_instance *I, int32_t B);
+// afs_eval with `scratch` (256-byte aligned, scratch_bytes long) in place of
+// the caller's workspace; AFS_EINVAL when it is too small.
+afs_status eval_in_scratch(afs_instance *I, int32_t B, const float *x, void *scratch, size_t scratch_bytes,
+                           float *obj, float *grad, float *fe, float *adj, void *stream);
+}  // namespace afs
+
 struct afs_instance {
     afs::HostInstance H;
     afs::DevInstance D;

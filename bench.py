@@ -132,12 +132,12 @@ def run_probes():
     streaming copy, each timed over several launches with HIP events."""
     from paper_2606_06641_amd import afsat
     blocks = 256 * 8 * 4                   # 32 waves per CU
-    names = ["fma_uniform", "fmac_vector", "mul", "complex_step"]
+    names = ["fma_uniform", "fmac_vector", "mul", "complex_step", "fma_3address", "mul_uniform", "fmac_uniform"]
     fp32 = {}
     for v, name in enumerate(names):
         ms, fl = timed(lambda: afsat.probe("fma", blocks, iters=4096, variant=v), 5)
         fp32[name] = fl / (ms * 1e-3) / 1e12
-    fma = max(fp32[n] for n in names if n != "mul")
+    fma = max(fp32[n] for n in names if not n.startswith("mul"))
     ms, fl = timed(lambda: afsat.probe("mfma_bf16", blocks, iters=512), 5)
     mfma = fl / (ms * 1e-3) / 1e12
     nbytes = 1 << 30
@@ -147,7 +147,9 @@ def run_probes():
     out = {"fp32_fma_tflops": fma, "fp32_by_form_tflops": fp32, "bf16_mfma_tflops": mfma, "hbm_copy_gbs": copy,
            "note": "measured on this device by afs_probe_fma (16 independent plain FP32 chains per lane, no packed "
                    "instructions: v_fma_f32 with uniform operands, v_fmac_f32 with per-lane operands, v_mul_f32, "
-                   "and the FE kernels' complex product step; fp32_fma_tflops is the best FMA form), "
+                   "the FE kernels' complex product step, three-address v_fma_f32 with per-lane operands, and "
+                   "v_mul_f32 / v_fmac_f32 with a uniform (scalar-register) operand; "
+                   "fp32_fma_tflops is the best FMA form), "
                    "afs_probe_mfma_bf16 (8 independent v_mfma_f32_16x16x32_bf16 accumulators per wave) and "
                    "afs_probe_copy (1 GiB, 16-byte non-temporal loads/stores; read + write bytes)"}
     print("probes: %s" % json.dumps(out), file=sys.stderr, flush=True)
@@ -230,7 +232,8 @@ def main():
                     help="only the chosen workload (by default the batch64 headline is followed by mixed10k "
                          "and longcard50k lines on stderr)")
     ap.add_argument("--train", type=int, default=0, help="learned-init workloads: training instances")
-    ap.add_argument("--test", type=int, default=0, help="learned-init workloads: held-out test instances")
+    ap.add_argument("--test", type=int, default=-1,
+                    help="learned-init workloads: held-out test instances (default 100; 0: train only)")
     ap.add_argument("--test-offset", type=int, default=0, help="learned-init workloads: first test instance")
     ap.add_argument("--val", type=int, default=8, help="learned-init workloads: validation instances")
     ap.add_argument("--timeout", type=float, default=0.0, help="learned-init workloads: seconds per arm and instance")
@@ -244,6 +247,8 @@ def main():
     ap.add_argument("--ls-step", type=float, default=4.0, help="learned-init workloads: line search maximum step")
     ap.add_argument("--save-net", default=None, help="learned-init workloads: save the trained network (.npz)")
     ap.add_argument("--load-net", default=None, help="learned-init workloads: load a trained network and only test")
+    ap.add_argument("--select", action="store_true",
+                    help="learned-init workloads: with --load-net, choose the inference variant again on validation")
     ap.add_argument("--restarts", type=int, default=0, help="override the workload's restart count")
     ap.add_argument("--lr", type=float, default=0.1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -673,7 +678,7 @@ def learned_init_bench(args, W):
     five = args.workload == "learned5k"
     make = _make_5k if five else _make_3sat
     n_train = args.train or (2000 if five else 512)
-    n_val, n_test = args.val, args.test or 100
+    n_val, n_test = args.val, (100 if args.test < 0 else args.test)
     B = args.restarts or 1024
     timeout = args.timeout or (20.0 if five else 3.0)
     desc = ("planted mixed n=5000: 15000 clauses k3-8, 1000 XOR k3-5, 250 CARD>=K k20-200" if five
@@ -699,21 +704,31 @@ def learned_init_bench(args, W):
         info["final_loss"] = losses[-1][1] if losses else None
         del train_set, targets
         log("trained (%.1f s)" % (time.perf_counter() - t0))
+    if not args.load_net or args.select:
+        # how the network's output becomes starting points: chosen on validation
+        # instances (learned arm only) by solved count, then by the mean best
+        # unsatisfied count (solves are rare on the mixed shape, so the count of
+        # constraints left is the finer signal)
         val_set = [make(20000 + i) for i in range(n_val)]
-        variants = [dict(sample=True, temperature=T) for T in (1.0, 2.0, 4.0)] + [dict(mix=0.8)]
+        variants = [dict(sample=True, temperature=T) for T in (1.0, 2.0, 4.0)] + [dict(mix=0.8), dict(mix=0.5)]
         best_key = None
+        info["validation"] = []
         for v in variants:
             res = gnn.compare(net, val_set, B, args.round_steps, args.val_timeout, v, seed=1, lr=args.lr,
-                              search=search)
-            sv = gnn.summarize(res, args.val_timeout)["learned"]
-            key = (-sv["solved"], sv["median_iters"], sv["mean_best_unsat_unsolved"])
-            log("validation %s: %s" % (v, sv))
+                              search=search, arms=("learned",))
+            rows = res["learned"]
+            solved = sum(r[0] is not None for r in rows)
+            mean_best = float(np.mean([r[3] for r in rows]))
+            key = (-solved, mean_best)
+            log("validation %s: solved %d of %d, mean best unsat %.2f" % (v, solved, len(rows), mean_best))
+            info["validation"].append({"variant": v, "solved": solved, "mean_best_unsat": mean_best})
             if best_key is None or key < best_key:
                 info["inference"], best_key = v, key
-        if args.save_net:
-            sd = net.state_dict()
-            np.savez(args.save_net, params=sd["params"], m=sd["m"], v=sd["v"], t=sd["t"], info=json.dumps(info))
-            log("saved network to %s" % args.save_net)
+        info["validation_instances"], info["validation_timeout_s"] = n_val, args.val_timeout
+    if args.save_net:
+        sd = net.state_dict()
+        np.savez(args.save_net, params=sd["params"], m=sd["m"], v=sd["v"], t=sd["t"], info=json.dumps(info))
+        log("saved network to %s" % args.save_net)
     if not n_test:
         print(json.dumps({"trained": info, "wall_s": time.perf_counter() - t0}), flush=True)
         return

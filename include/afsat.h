@@ -622,9 +622,11 @@ afs_status afs_eval_noalloc(afs_instance *inst, int32_t B, const float *x, float
  *   variant 0 fused multiply-adds acc = acc * a + b with uniform a, b;
  *   variant 1 acc += x * y with per-lane x, y; variant 2 multiplies acc *= x;
  *   variant 3 the FE kernels' product step (r, i) <- (r - i z, i + r z) on 8
- *   complex chains.  out: device float [blocks * 256], one value per
- *   work-item.  *flops (host, may be NULL) = 2 (variant 2: 1) * 16 * iters *
- *   blocks * 256.
+ *   complex chains; variant 4 acc = acc * x + y with per-lane x, y (the
+ *   three-address form); variant 5 multiplies acc *= a with a uniform; variant 6
+ *   acc += a * x with a uniform, x per lane.  out: device float [blocks * 256],
+ *   one value per work-item.  *flops (host, may be NULL) = 2 (variants 2 and
+ *   5: 1) * 16 * iters * blocks * 256.
  * afs_probe_mfma_bf16: every wave runs `iters` rounds of 8 independent
  *   16x16x32 BF16 matrix products with FP32 accumulation.  out as above;
  *   *flops = 2 * 16 * 16 * 32 * 8 * iters * blocks * 4.

@@ -24,7 +24,11 @@ constexpr int kChains = 16;            // independent FMA chains per lane
 // V = 1: v_fmac_f32 chains acc += x * y with x, y per-lane registers;
 // V = 2: v_mul_f32 chains acc *= x;
 // V = 3: the product step of the FE kernels, (r, i) <- (r - i z, i + r z), two
-//        dependent FMAs per step, kChains / 2 independent complex chains.
+//        dependent FMAs per step, kChains / 2 independent complex chains;
+// V = 4: v_fma_f32 chains acc = acc * x + y with per-lane x, y (three-address
+//        form, all operands in vector registers, no modifiers);
+// V = 5: v_mul_f32 chains acc *= a with a uniform (a scalar-register operand);
+// V = 6: v_fmac_f32 chains acc += a * x with a uniform, x per lane.
 // Flops counted: 2 per FMA, 1 per multiply.
 template <int V>
 __global__ __launch_bounds__(kProbeBlock) void probe_fma_kernel(float *out, int iters, float a, float b)
@@ -47,6 +51,9 @@ __global__ __launch_bounds__(kProbeBlock) void probe_fma_kernel(float *out, int 
             for (int j = 0; j < kChains; ++j) {
                 if constexpr (V == 0) acc[j] = fmaf(acc[j], a, b);
                 else if constexpr (V == 1) acc[j] = fmaf(x, y, acc[j]);
+                else if constexpr (V == 4) acc[j] = fmaf(acc[j], x, y);
+                else if constexpr (V == 5) acc[j] *= a;
+                else if constexpr (V == 6) acc[j] = fmaf(a, x, acc[j]);
                 else acc[j] *= x;
             }
         }
@@ -98,17 +105,21 @@ extern "C" {
 
 afs_status afs_probe_fma(int32_t variant, int32_t blocks, int32_t iters, float *out, double *flops, void *stream)
 {
-    if (blocks <= 0 || iters <= 0 || !out || variant < 0 || variant > 3) return AFS_EINVAL;
+    if (blocks <= 0 || iters <= 0 || !out || variant < 0 || variant > 6) return AFS_EINVAL;
     const dim3 g(blocks), t(kProbeBlock);
     hipStream_t s = (hipStream_t)stream;
     switch (variant) {
     case 0: hipLaunchKernelGGL(probe_fma_kernel<0>, g, t, 0, s, out, iters, 0.999999f, 1e-7f); break;
     case 1: hipLaunchKernelGGL(probe_fma_kernel<1>, g, t, 0, s, out, iters, 1e-4f, 1e-4f); break;
     case 2: hipLaunchKernelGGL(probe_fma_kernel<2>, g, t, 0, s, out, iters, 0.9999999f, 0.f); break;
-    default: hipLaunchKernelGGL(probe_fma_kernel<3>, g, t, 0, s, out, iters, 0.f, 1e-4f); break;
+    case 3: hipLaunchKernelGGL(probe_fma_kernel<3>, g, t, 0, s, out, iters, 0.f, 1e-4f); break;
+    case 4: hipLaunchKernelGGL(probe_fma_kernel<4>, g, t, 0, s, out, iters, 0.999999f, 1e-7f); break;
+    case 5: hipLaunchKernelGGL(probe_fma_kernel<5>, g, t, 0, s, out, iters, 0.9999999f, 0.f); break;
+    default: hipLaunchKernelGGL(probe_fma_kernel<6>, g, t, 0, s, out, iters, 1e-4f, 1e-4f); break;
     }
     if (hipGetLastError() != hipSuccess) return AFS_EDEVICE;
-    if (flops) *flops = (variant == 2 ? 1.0 : 2.0) * kChains * (double)iters * (double)blocks * kProbeBlock;
+    const double per = (variant == 2 || variant == 5) ? 1.0 : 2.0;        // flops per operation
+    if (flops) *flops = per * kChains * (double)iters * (double)blocks * kProbeBlock;
     return AFS_OK;
 }
 

@@ -238,10 +238,11 @@ def train(net, parts, targets, steps, lr=2e-3, chunk=32, restarts=16, seed=0, lo
     return losses
 
 
-def run_arm(dinst, make_start, round_steps, timeout_s, lr=0.1, poll=10, search=None):
+def run_arm(dinst, make_start, round_steps, timeout_s, lr=0.1, poll=10, search=None, max_rounds=0):
     """One arm on one instance: Algorithm 1 in rounds of ``round_steps``
     iterations, each from fresh starting points (``make_start()``), until a
-    restart verifies or ``timeout_s`` has passed.  The clock starts before the
+    restart verifies, ``timeout_s`` has passed or (``max_rounds`` > 0) that many
+    rounds have run.  The clock starts before the
     first starting points are generated, so the learned arm's time includes the
     network's first use on the instance (its graph build) and every round's
     inference.  Returns (seconds to the first verified restart or None, rounds,
@@ -261,23 +262,24 @@ def run_arm(dinst, make_start, round_steps, timeout_s, lr=0.1, poll=10, search=N
         el = time.perf_counter() - t0
         if solved:
             return el, rounds, iters, 0, el
-        if el >= timeout_s:
+        if el >= timeout_s or (max_rounds and rounds >= max_rounds):
             return None, rounds, iters, best, el
 
 
-def compare(net, tests, B, round_steps, timeout_s, variant, seed=0, lr=0.1, search=None, log=None):
+def compare(net, tests, B, round_steps, timeout_s, variant, seed=0, lr=0.1, search=None, log=None, max_rounds=0,
+            arms=("random", "learned")):
     """Learned vs uniform random starts on each test instance.  Before either arm
     is timed, one untimed two-iteration run on the instance pays the solver's
     first-use costs (its workspace, state and driver streams); the arms then take
     turns going first (even instances random first, odd ones learned first), each
     with its own noise generator seeded per instance.  Returns per-arm lists of
     run_arm results."""
-    out = {"random": [], "learned": []}
+    out = {arm: [] for arm in arms}
     for i, p in enumerate(tests):
         d = afsat.Instance.from_arrays(p)
         d.pgd(uniform_start(d, B, (seed << 40) + (i << 20) + 0xFFFFF), lr=lr, steps=2, poll=1, stop_on_sat=False,
               search=search)
-        order = ("random", "learned") if i % 2 == 0 else ("learned", "random")
+        order = tuple(arms) if i % 2 == 0 else tuple(reversed(arms))
         for arm in order:
             rounds = iter(range(1 << 20))
             base = (seed << 40) + (i << 20)          # round r of either arm draws noise with seed base + r
@@ -285,9 +287,9 @@ def compare(net, tests, B, round_steps, timeout_s, variant, seed=0, lr=0.1, sear
                 make = lambda: uniform_start(d, B, base + next(rounds))
             else:
                 make = lambda: learned_start(net, d, B, base + next(rounds), **variant)
-            out[arm].append(run_arm(d, make, round_steps, timeout_s, lr, search=search))
+            out[arm].append(run_arm(d, make, round_steps, timeout_s, lr, search=search, max_rounds=max_rounds))
         if log:
-            log("instance %d: random %s | learned %s" % (i, _fmt(out["random"][-1]), _fmt(out["learned"][-1])))
+            log("instance %d: %s" % (i, " | ".join("%s %s" % (arm, _fmt(out[arm][-1])) for arm in arms)))
         d.close()
     return out
 

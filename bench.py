@@ -446,7 +446,7 @@ def throughput(args, name, W, probes):
         exe = float(B * sum(executed_flops(int(k)) for k in kb))
         roof = {"bound": "alu", "achieved": flops / (dom_ms * 1e-3) / 1e12, "peak": PEAK_FP32_TFLOPS,
                 "unit": "TFLOP/s", "kernel": kname, "k_range": [bk.k_lo, bk.k_hi], "flops_per_launch": flops,
-                "executed_tflops": exe / (dom_ms * 1e-3) / 1e12}
+                "evals_per_launch": float(B * kb.sum()), "executed_tflops": exe / (dom_ms * 1e-3) / 1e12}
     roof["frac"] = roof["achieved"] / roof["peak"]
     roof["ms_per_launch"] = dom_ms
     if roof["bound"] == "alu":

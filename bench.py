@@ -612,7 +612,7 @@ def bucket_roofline(name, buckets, per_bucket_ms, lens, first_slot, B):
     per second against the bucket's own roofline min(P_VALU / F, BW / Q), with F
     the algorithmic flops per literal-eval of its lengths (F_k) and Q = 8 B (x
     gather and adjoint write).  Printed to stderr and returned as rows
-    [k_lo, k_hi, J, S, constraints, ms, bound, fraction]."""
+    [k_lo, k_hi, J, S, constraints, ms, bound, fraction, tile, restarts per lane]."""
     print("[%s] bucket roofline (alone): k range, shape, constraints, ms, literal-evals/s, TFLOP/s (F_k), "
           "GB/s, bound, fraction" % name, file=sys.stderr)
     rows = []
@@ -628,10 +628,10 @@ def bucket_roofline(name, buckets, per_bucket_ms, lens, first_slot, B):
         bound = "alu" if alu_ceiling < hbm_ceiling else "hbm"
         frac = rate / min(alu_ceiling, hbm_ceiling)
         rows.append([b.k_lo, b.k_hi, b.lanes_per_restart, b.lits_per_lane, int(sel.sum()), round(t, 4), bound,
-                     round(frac, 3)])
-        print("  [%4d-%4d] J%-2d S%-2d %6d %8.3f ms %10.3e %7.2f %8.1f %s %.3f" % (
-            b.k_lo, b.k_hi, b.lanes_per_restart, b.lits_per_lane, int(sel.sum()), t, rate, flops / sec / 1e12,
-            8.0 * evals / sec / 1e9, bound, frac), file=sys.stderr, flush=True)
+                     round(frac, 3), b.tile, b.rpl])
+        print("  [%4d-%4d] J%-2d S%-2d t%-2d r%d %6d %8.3f ms %10.3e %7.2f %8.1f %s %.3f" % (
+            b.k_lo, b.k_hi, b.lanes_per_restart, b.lits_per_lane, b.tile, b.rpl, int(sel.sum()), t, rate,
+            flops / sec / 1e12, 8.0 * evals / sec / 1e9, bound, frac), file=sys.stderr, flush=True)
     return rows
 
 
@@ -734,7 +734,7 @@ def learned_init_bench(args, W):
         return
     test_set = [make(30000 + i) for i in range(args.test_offset, args.test_offset + n_test)]
     res = gnn.compare(net, test_set, B, args.round_steps, timeout, info["inference"], seed=2, lr=args.lr,
-                      search=search, log=log)
+                      search=search, log=log, index0=args.test_offset)
     summ = gnn.summarize(res, timeout)
     rm, lm = summ["random"]["median_s"], summ["learned"]["median_s"]
     solved_any = summ["random"]["solved"] + summ["learned"]["solved"] > 0

@@ -95,6 +95,8 @@ typedef struct {
     int32_t lanes_per_restart;
     int32_t lits_per_lane;
     int64_t slot0;       /* first literal slot of the bucket */
+    int32_t tile;        /* constraints per work tile */
+    int32_t rpl;         /* one-lane buckets: restarts per lane asked for (0: default) */
 } afs_bucket_info;
 
 /* ---- instance -------------------------------------------------------------- */
@@ -132,7 +134,16 @@ afs_status afs_instance_create(int32_t n_vars, int32_t n_cons, const int64_t *co
  *       restart (2, 4, 8, 16, 32 or 64) holding shape_seg[e] literals each (even,
  *       8 to 32), with lanes * seg >= shape_k_hi[e].  Lengths past the last entry
  *       use the default shape model.  (These are what the autotuner picks.)
- *   tile_short / tile_long: constraints per work tile for lengths <= 16 / > 16. */
+ *   tile_short / tile_long: constraints per work tile (one wave's share of a
+ *       bucket, 0 to 4096, 0: default) for lengths <= 16 / > 16.
+ *   shape_tile: int32 [n_shapes] or NULL: constraints per work tile of each shape
+ *       entry (0: tile_long or the default).
+ *   short_tile, short_rpl: int32 [16] or NULL, index k-1 for length k <= 16:
+ *       constraints per work tile (0: tile_short or the default) and restarts
+ *       held per lane by the one-lane kernel (0: the default, 4 for k <= 8 and 1
+ *       above; else 1, 2, or 4 for k <= 8).  A launch whose B or x (or adjoint
+ *       seed) alignment does not allow the asked count uses 1.
+ * The results do not depend on these choices, only the time does. */
 typedef struct {
     int32_t n_shapes;
     const int32_t *shape_k_hi;
@@ -140,6 +151,9 @@ typedef struct {
     const int32_t *shape_seg;
     int32_t tile_short;
     int32_t tile_long;
+    const int32_t *shape_tile;
+    const int32_t *short_tile;
+    const int32_t *short_rpl;
 } afs_options;
 
 /* afs_instance_create with packing options (opts may be NULL). */
@@ -391,37 +405,44 @@ typedef struct {
  * *iters (host, or NULL) the number of iterations run.  The work runs on a
  * stream private to the instance, ordered after the caller's stream on entry
  * and before it on return; the call synchronises with that private stream when
- * it reads the counter, and with use_graph it builds and frees a graph, so it is
- * not itself capturable (capture afs_pgd_step instead).  Concurrent calls on one
- * instance are serialised. */
+ * it reads the counter, and with use_graph it builds a graph and, once its last
+ * replay has finished (another synchronisation), frees it, so it is not itself
+ * capturable (capture afs_pgd_step instead).  Concurrent calls on one instance
+ * are serialised. */
 afs_status afs_pgd(afs_instance *inst, int32_t B, float *x, const afs_pgd_params *params, void *ws,
                    size_t ws_bytes, const afs_pgd_state *st, float *obj, int32_t *iters, void *stream);
 
-/* Autotuner for the segment-kernel shape of long constraints.  Sec. 4.2 finds
+/* Autotuner for the FE kernel configuration of each length range.  Sec. 4.2 finds
  * throughput governed by the maximum constraint length and tunes the batch size
- * for it; here the shape of the kernel that evaluates each length is tuned on the
- * device instead (the shapes returned are what afs_options' shape arrays take).
- * For every length
- * range between consecutive candidate capacities J*S (J in {2, ..., 64}, S even
- * in 8..32) that holds constraints of inst (a plain instance or a batch, device
+ * for it; here the kernel that evaluates each length is tuned on the device
+ * instead (the results are what afs_options' shape, tile and short arrays take).
+ * Ranges: each length 1..16 alone (the one-lane kernel), then the ranges between
+ * consecutive candidate capacities J*S (J in {2, ..., 64}, S even in 8..32).  For
+ * every range that holds constraints of inst (a plain instance or a batch, device
  * or host-only), the constraints in that range -- an evenly spaced sample of at
- * most max_cons (<= 0: all) -- are packed alone once per candidate shape with
- * J*S >= the range's upper length, and their FE+gradient pass at B restarts is
- * timed on `device` (median of reps launches after one warm-up, HIP events on a
- * private stream).  The fastest shape wins.
+ * most max_cons (<= 0: all; one-lane lengths: at least 65,536) -- are packed alone
+ * once per candidate and their FE+gradient pass at B restarts is timed on
+ * `device` (median of reps launches after one warm-up, HIP events on a private
+ * stream).  First the fastest shape with J*S >= the range's upper length (long) or
+ * restarts per lane in {4 (k <= 8), 2, 1} dividing B (short) at the default tile
+ * wins; then tiles of 1, 2, 4, 8 and 16 constraints are timed for it, and one
+ * other than the default must be 2% faster to replace it.
  *   cache_in, cache_out: text files (either may be NULL) with one line per
- *     result, "<arch> <revision> <B> <k_lo> <k_hi> <lanes> <seg> <ms> <timed>";
- *     results found in either are reused, and cache_out is rewritten with them
- *     plus the new ones, keeping only the current kernel revision.
- *   k_lo, k_hi, lanes, seg: host int32 [max_ranges]; ms: host float [max_ranges]
- *     or NULL (the winner's median, -1 when it came from a cache); *n_ranges:
- *     the number of ranges the instance has (entries past max_ranges are not
- *     written).
+ *     result, "<arch> <revision> <B> <k_lo> <k_hi> <lanes> <seg> <tile> <rpl>
+ *     <ms> <timed>"; results found in either are reused, and cache_out is
+ *     rewritten with them plus the new ones, keeping only the current kernel
+ *     revision.
+ *   k_lo, k_hi, lanes, seg: host int32 [max_ranges] (lanes 1 and seg k for a
+ *     one-lane length); tile, rpl: host int32 [max_ranges] or NULL (rpl 0 for
+ *     segment shapes); ms: host float [max_ranges] or NULL (the winner's median,
+ *     -1 when it came from a cache); *n_ranges: the number of ranges the instance
+ *     has (entries past max_ranges are not written).
  * Allocates device memory, synchronises `device`, and restores the caller's
  * current device. */
 afs_status afs_autotune(const afs_instance *inst, int32_t device, int32_t B, int32_t reps, int32_t max_cons,
                         const char *cache_in, const char *cache_out, int32_t max_ranges, int32_t *k_lo,
-                        int32_t *k_hi, int32_t *lanes, int32_t *seg, float *ms, int32_t *n_ranges);
+                        int32_t *k_hi, int32_t *lanes, int32_t *seg, int32_t *tile, int32_t *rpl, float *ms,
+                        int32_t *n_ranges);
 
 /* ---- learned initialisation: message-passing network ---------------------------- */
 

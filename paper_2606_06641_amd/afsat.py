@@ -44,12 +44,14 @@ class _Info(ctypes.Structure):
 class _BucketInfo(ctypes.Structure):
     _fields_ = [("k_lo", ctypes.c_int32), ("k_hi", ctypes.c_int32), ("n_cons", ctypes.c_int32),
                 ("n_lits", ctypes.c_int64), ("lanes_per_restart", ctypes.c_int32),
-                ("lits_per_lane", ctypes.c_int32), ("slot0", ctypes.c_int64)]
+                ("lits_per_lane", ctypes.c_int32), ("slot0", ctypes.c_int64), ("tile", ctypes.c_int32),
+                ("rpl", ctypes.c_int32)]
 
 
 class _Options(ctypes.Structure):
     _fields_ = [("n_shapes", ctypes.c_int32), ("shape_k_hi", _i32p), ("shape_lanes", _i32p),
-                ("shape_seg", _i32p), ("tile_short", ctypes.c_int32), ("tile_long", ctypes.c_int32)]
+                ("shape_seg", _i32p), ("tile_short", ctypes.c_int32), ("tile_long", ctypes.c_int32),
+                ("shape_tile", _i32p), ("short_tile", _i32p), ("short_rpl", _i32p)]
 
 
 class _LineSearch(ctypes.Structure):
@@ -108,7 +110,7 @@ SIGNATURES = [
     ("afs_pgd", ctypes.c_int, [_vp, _i32, _vp, ctypes.POINTER(_PgdParams), _vp, ctypes.c_size_t,
                                ctypes.POINTER(_PgdState), _vp, ctypes.POINTER(_i32), _vp]),
     ("afs_autotune", ctypes.c_int, [_vp, _i32, _i32, _i32, _i32, ctypes.c_char_p, ctypes.c_char_p, _i32,
-                                    _i32p, _i32p, _i32p, _i32p, ctypes.POINTER(ctypes.c_float),
+                                    _i32p, _i32p, _i32p, _i32p, _i32p, _i32p, ctypes.POINTER(ctypes.c_float),
                                     ctypes.POINTER(_i32)]),
     ("afs_parse_text", ctypes.c_int, [ctypes.c_char_p, ctypes.c_size_t, ctypes.POINTER(_vp)]),
     ("afs_parse_file", ctypes.c_int, [ctypes.c_char_p, ctypes.POINTER(_vp)]),
@@ -206,6 +208,8 @@ class BucketInfo:
     lanes_per_restart: int
     lits_per_lane: int
     slot0: int
+    tile: int = 0
+    rpl: int = 0
 
 
 class Instance:
@@ -216,8 +220,11 @@ class Instance:
 
     def __init__(self, n, con_off, lits, types, params=None, weights=None, device=0,
                  shapes=None, tile_short=0, tile_long=0):
-        """``shapes``: optional [(k_hi, lanes, seg), ...] kernel shapes for lengths > 16
-        (ascending k_hi), as chosen by the autotuner."""
+        """``shapes``: optional kernel configurations as chosen by the autotuner:
+        entries (k_hi, lanes, seg[, tile[, rpl]]).  Entries with lanes > 1 give the
+        segment shape (and work tile) for lengths > 16, ascending k_hi; entries with
+        lanes == 1 give the one-lane kernel's work tile and restarts per lane for the
+        length k_hi <= 16 (seg == k_hi).  A tile or rpl of 0 keeps the default."""
         con_off = np.ascontiguousarray(con_off, dtype=np.int64)
         lits = np.ascontiguousarray(lits, dtype=np.int32)
         types = np.ascontiguousarray(types, dtype=np.int32)
@@ -234,10 +241,21 @@ class Instance:
 
     @staticmethod
     def _options(shapes, tile_short, tile_long):
-        shapes = list(shapes or [])
-        arrs = [np.array([sh[i] for sh in shapes], dtype=np.int32) for i in range(3)]
-        opts = _Options(len(shapes), _np_ptr(arrs[0], _i32p), _np_ptr(arrs[1], _i32p), _np_ptr(arrs[2], _i32p),
-                        int(tile_short), int(tile_long))
+        full = [tuple(sh) + (0,) * (5 - len(sh)) for sh in (shapes or [])]
+        if any(len(sh) != 5 for sh in full):
+            raise ValueError("shape entries are (k_hi, lanes, seg[, tile[, rpl]])")
+        seg = [sh for sh in full if sh[1] != 1]
+        arrs = [np.array([sh[i] for sh in seg], dtype=np.int32) for i in range(4)]
+        short_tile = np.zeros(16, np.int32)
+        short_rpl = np.zeros(16, np.int32)
+        for k, _, s_, tile, rpl in (sh for sh in full if sh[1] == 1):
+            if not 1 <= k <= 16 or s_ != k:
+                raise ValueError("a one-lane entry needs k_hi == seg in 1..16")
+            short_tile[k - 1], short_rpl[k - 1] = tile, rpl
+        arrs += [short_tile, short_rpl]
+        opts = _Options(len(seg), _np_ptr(arrs[0], _i32p), _np_ptr(arrs[1], _i32p), _np_ptr(arrs[2], _i32p),
+                        int(tile_short), int(tile_long), _np_ptr(arrs[3], _i32p), _np_ptr(short_tile, _i32p),
+                        _np_ptr(short_rpl, _i32p))
         return opts, arrs
 
     @classmethod
@@ -294,7 +312,7 @@ class Instance:
             bi = _BucketInfo()
             _check(lib().afs_bucket_info_get(self._h, b, ctypes.byref(bi)))
             out.append(BucketInfo(bi.k_lo, bi.k_hi, bi.n_cons, bi.n_lits, bi.lanes_per_restart,
-                                  bi.lits_per_lane, bi.slot0))
+                                  bi.lits_per_lane, bi.slot0, bi.tile, bi.rpl))
         return out
 
     def var_offsets(self):

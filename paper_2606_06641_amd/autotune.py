@@ -1,11 +1,12 @@
-"""Autotuner for the kernel shape of long constraints (length > 16): a thin
-binding of ``afs_autotune`` (``include/afsat.h``), which times every candidate
-shape on the device per length range and keeps a text cache keyed by GPU
-architecture, FE kernel revision, restarts and range.
+"""Autotuner for the FE kernel configuration per length range: a thin binding of
+``afs_autotune`` (``include/afsat.h``), which times the candidates on the device
+-- segment shape and work tile above length 16, restarts per lane and work tile
+of the one-lane kernel for each length up to 16 -- and keeps a text cache keyed
+by GPU architecture, FE kernel revision, restarts and range.
 
-``tune(inst, B)`` returns the list ``[(k_hi, J, S)]`` that ``Instance(...,
-shapes=...)`` takes, and a report per range.  The package ships the cache for
-the bench workloads (``tuned_shapes.txt``)."""
+``tune(inst, B)`` returns the list ``[(k_hi, J, S, tile, rpl)]`` that
+``Instance(..., shapes=...)`` takes, and a report per range.  The package ships
+the cache for the bench workloads (``tuned_shapes.txt``)."""
 import ctypes
 import os
 
@@ -22,8 +23,9 @@ def _path(p):
 
 
 def tune(inst, B, device=0, reps=7, cache_path=None, out_path=None, log=None, max_cons=None):
-    """Shapes [(k_hi, J, S)] for the long constraints of ``inst`` (a workloads
-    Instance or an afsat.Instance) at B restarts.
+    """Configurations [(k_hi, J, S, tile, rpl)] for the lengths of ``inst`` (a
+    workloads Instance or an afsat.Instance) at B restarts (J == 1: one-lane
+    length k_hi, S == k_hi).
 
     Cached results are read from ``cache_path`` and ``out_path``; ``out_path``
     (default: ``cache_path``) is rewritten with them and the new ones.
@@ -35,7 +37,7 @@ def tune(inst, B, device=0, reps=7, cache_path=None, out_path=None, log=None, ma
     else:
         own = h = afsat.Instance.from_arrays(inst, device=-1)     # host tables only
     out_path = out_path or cache_path
-    lo, hi, lanes, seg = (np.zeros(MAX_RANGES, np.int32) for _ in range(4))
+    lo, hi, lanes, seg, tile, rpl = (np.zeros(MAX_RANGES, np.int32) for _ in range(6))
     ms = np.zeros(MAX_RANGES, np.float32)
     n = ctypes.c_int32(0)
     i32p = ctypes.POINTER(ctypes.c_int32)
@@ -43,7 +45,8 @@ def tune(inst, B, device=0, reps=7, cache_path=None, out_path=None, log=None, ma
         afsat._check(afsat.lib().afs_autotune(
             h._h, int(device), int(B), int(reps), int(max_cons or 0), _path(cache_path), _path(out_path),
             MAX_RANGES, lo.ctypes.data_as(i32p), hi.ctypes.data_as(i32p), lanes.ctypes.data_as(i32p),
-            seg.ctypes.data_as(i32p), ms.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), ctypes.byref(n)))
+            seg.ctypes.data_as(i32p), tile.ctypes.data_as(i32p), rpl.ctypes.data_as(i32p),
+            ms.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), ctypes.byref(n)))
     finally:
         if own is not None:
             own.close()
@@ -51,10 +54,12 @@ def tune(inst, B, device=0, reps=7, cache_path=None, out_path=None, log=None, ma
         raise RuntimeError("more length ranges than expected")
     shapes, report = [], []
     for i in range(n.value):
-        shapes.append((int(hi[i]), int(lanes[i]), int(seg[i])))
+        shapes.append((int(hi[i]), int(lanes[i]), int(seg[i]), int(tile[i]), int(rpl[i])))
         cached = bool(ms[i] < 0)
         report.append({"range": [int(lo[i]), int(hi[i])], "shape": [int(lanes[i]), int(seg[i])],
-                       "cached": cached, "ms": None if cached else float(ms[i])})
+                       "tile": int(tile[i]), "rpl": int(rpl[i]), "cached": cached,
+                       "ms": None if cached else float(ms[i])})
         if log and not cached:
-            log("autotune k %d-%d: %dx%d  %.3f ms" % (lo[i], hi[i], lanes[i], seg[i], ms[i]))
+            log("autotune k %d-%d: %dx%d tile %d rpl %d  %.3f ms" % (lo[i], hi[i], lanes[i], seg[i], tile[i],
+                                                                   rpl[i], ms[i]))
     return shapes, report

@@ -237,7 +237,7 @@ afs_status fe_grad_set(afs_instance *I, int B, const float *x, void *ws, const W
     order.insert(order.end(), shorts.begin(), shorts.end());
     for (int bi : order) {
         const afs::Bucket &b = I->H.buckets[bi];
-        afs::BucketLaunch bl{b.J, b.S, b.c0, b.nc, b.tile, b.ntiles, b.tile0};
+        afs::BucketLaunch bl{b.J, b.S, b.c0, b.nc, b.tile, b.ntiles, b.tile0, b.rpl};
         hipError_t e = afs::launch_fe_grad(I->D, bl, B, l.Bp, x, at<float>(ws, l.adj),
                                            want_part ? at<float>(ws, l.part) : nullptr, fe, dobj,
                                            grad, stream_of[bi], skip);
@@ -269,6 +269,11 @@ afs_status read_options(const afs_options *opts, afs::PackOptions &po)
     }
     po.tile_short = opts->tile_short;
     po.tile_long = opts->tile_long;
+    if (opts->shape_tile) po.tile.assign(opts->shape_tile, opts->shape_tile + std::max(opts->n_shapes, 0));
+    for (int k = 1; k <= afs::kShortMax; ++k) {
+        if (opts->short_tile) po.short_tile[k] = opts->short_tile[k - 1];
+        if (opts->short_rpl) po.short_rpl[k] = opts->short_rpl[k - 1];
+    }
     return AFS_OK;
 }
 
@@ -465,6 +470,8 @@ afs_status afs_bucket_info_get(const afs_instance *I, int32_t b, afs_bucket_info
     out->lanes_per_restart = k.J;
     out->lits_per_lane = k.S;
     out->slot0 = k.slot0;
+    out->tile = k.tile;
+    out->rpl = k.rpl;
     return AFS_OK;
 }
 
@@ -923,7 +930,12 @@ afs_status afs_pgd(afs_instance *I, int32_t B, float *x, const afs_pgd_params *p
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     auto finish = [&](afs_status result) {
-        if (exec) (void)hipGraphExecDestroy(exec);
+        // the executable graph is destroyed only once its last replay has finished
+        if (exec) {
+            const hipError_t es = hipStreamSynchronize(s);
+            if (result == AFS_OK && es != hipSuccess) result = dev_fail(es, "hipStreamSynchronize");
+            (void)hipGraphExecDestroy(exec);
+        }
         if (graph) (void)hipGraphDestroy(graph);
         // the caller's stream continues after everything enqueued here
         hipError_t e2 = hipEventRecord(I->drive_out, s);

@@ -1,14 +1,19 @@
-// autotune.cpp -- on-device choice of the segment-kernel shape (J lanes per
-// restart x S literals per lane) for each length range of an instance.
+// autotune.cpp -- on-device choice of the FE kernel configuration for each
+// length range of an instance: the segment-kernel shape (J lanes per restart x S
+// literals per lane) and work-tile size for lengths above 16, and the restarts per
+// lane and work-tile size of the one-lane kernel for each length up to 16.
 //
-// For each range between consecutive candidate capacities J*S, the constraints
-// of the instance in that range (an evenly spaced sample of at most max_cons)
-// are packed alone once per candidate shape, and the FE+gradient kernel of that
-// bucket is timed on the device (median of `reps` launches, HIP events on a
-// private stream).  The fastest shape wins.  Results are cached in a text file
+// For each range (every length <= 16 alone; above, the ranges between
+// consecutive candidate capacities J*S) the constraints of the instance in that
+// range (an evenly spaced sample of at most max_cons) are packed alone once per
+// candidate, and the FE+gradient pass of that bucket is timed on the device
+// (median of `reps` launches, HIP events on a private stream).  Two stages: the
+// fastest shape (long) or restarts per lane (short) at the default tile, then the
+// tile sizes for it; a tile other than the default must win by 2% (the medians of
+// neighbouring tiles are often within noise).  Results are cached in a text file
 // keyed by (GPU architecture, FE kernel source revision, restarts, range), one
 // line per entry:
-//     <arch> <revision> <B> <k_lo> <k_hi> <J> <S> <median ms> <constraints timed>
+//     <arch> <revision> <B> <k_lo> <k_hi> <J> <S> <tile> <rpl> <median ms> <constraints timed>
 // so that other instances with constraints in the same ranges reuse them and a
 // change to the kernels invalidates them.
 
@@ -48,10 +53,12 @@ std::vector<int> capacities()
     return std::vector<int>(caps.begin(), caps.end());
 }
 
-// [(k_lo, k_hi)] covering 17..1024, split at every candidate capacity
+// [(k_lo, k_hi)]: 1..16 one length each, then 17..1024 split at every candidate
+// capacity
 std::vector<std::pair<int, int>> length_ranges()
 {
     std::vector<std::pair<int, int>> out;
+    for (int k = 1; k <= afs::kShortMax; ++k) out.emplace_back(k, k);
     int lo = afs::kShortMax + 1;
     for (int cap : capacities()) {
         if (cap >= lo) {
@@ -72,7 +79,7 @@ struct Key {
 };
 
 struct Choice {
-    int J = 0, S = 0;
+    int J = 0, S = 0, tile = 0, rpl = 0;
     double ms = 0.0;
     int timed = 0;
 };
@@ -87,9 +94,13 @@ void read_cache(const char *path, std::map<Key, Choice> &cache)
         std::istringstream in(line);
         Key k;
         Choice c;
-        if (in >> k.arch >> k.rev >> k.B >> k.lo >> k.hi >> c.J >> c.S >> c.ms >> c.timed) cache[k] = c;
+        if (in >> k.arch >> k.rev >> k.B >> k.lo >> k.hi >> c.J >> c.S >> c.tile >> c.rpl >> c.ms >> c.timed)
+            cache[k] = c;
     }
 }
+
+// Default work tile of a shape (as the packing chooses it when none is given).
+int default_tile(int J) { return J == 1 ? 4 : (J >= 8 ? 1 : 8 / J); }
 
 bool write_cache(const char *path, const std::map<Key, Choice> &cache, const std::string &rev)
 {
@@ -98,13 +109,13 @@ bool write_cache(const char *path, const std::map<Key, Choice> &cache, const std
     {
         std::ofstream f(tmp);
         if (!f) return false;
-        f << "# arch revision B k_lo k_hi lanes seg median_ms constraints_timed\n";
+        f << "# arch revision B k_lo k_hi lanes seg tile rpl median_ms constraints_timed\n";
         for (const auto &kv : cache) {
             if (kv.first.rev != rev) continue;                  // stale kernel revisions are dropped
             char buf[256];
-            std::snprintf(buf, sizeof buf, "%s %s %d %d %d %d %d %.6f %d\n", kv.first.arch.c_str(),
+            std::snprintf(buf, sizeof buf, "%s %s %d %d %d %d %d %d %d %.6f %d\n", kv.first.arch.c_str(),
                           kv.first.rev.c_str(), kv.first.B, kv.first.lo, kv.first.hi, kv.second.J,
-                          kv.second.S, kv.second.ms, kv.second.timed);
+                          kv.second.S, kv.second.tile, kv.second.rpl, kv.second.ms, kv.second.timed);
             f << buf;
         }
         if (!f) return false;
@@ -112,11 +123,13 @@ bool write_cache(const char *path, const std::map<Key, Choice> &cache, const std
     return std::rename(tmp.c_str(), path) == 0;
 }
 
-// Time the FE+gradient pass of `cons` packed alone with shape (hi, J, S).
-afs_status time_shape(const afs::HostInstance &H, const std::vector<int32_t> &cons, int hi, int J, int S,
+// Time the FE+gradient pass of `cons` packed alone with the configuration c for
+// the range ending at hi (J == 1: a one-lane length, S == hi).
+afs_status time_shape(const afs::HostInstance &H, const std::vector<int32_t> &cons, int hi, const Choice &c,
                       int device, int B, const float *x, int reps, hipStream_t s, hipEvent_t e0, hipEvent_t e1,
                       double &ms)
 {
+    const int J = c.J, S = c.S;
     std::vector<int64_t> off(1, 0);
     std::vector<int32_t> lits, types, params;
     std::vector<float> w;
@@ -127,12 +140,21 @@ afs_status time_shape(const afs::HostInstance &H, const std::vector<int32_t> &co
         params.push_back(H.params[c]);
         w.push_back(H.weights.empty() ? 1.0f : H.weights[c]);
     }
-    int32_t kh = hi, lanes = J, seg = S;
+    int32_t kh = hi, lanes = J, seg = S, tile = c.tile;
+    int32_t short_tile[afs::kShortMax] = {}, short_rpl[afs::kShortMax] = {};
     afs_options o{};
-    o.n_shapes = 1;
-    o.shape_k_hi = &kh;
-    o.shape_lanes = &lanes;
-    o.shape_seg = &seg;
+    if (J > 1) {
+        o.n_shapes = 1;
+        o.shape_k_hi = &kh;
+        o.shape_lanes = &lanes;
+        o.shape_seg = &seg;
+        o.shape_tile = &tile;
+    } else {
+        short_tile[hi - 1] = c.tile;
+        short_rpl[hi - 1] = c.rpl;
+        o.short_tile = short_tile;
+        o.short_rpl = short_rpl;
+    }
     afs_instance *sub = nullptr;
     afs_status st = afs_instance_create_ex(H.n, (int32_t)cons.size(), off.data(), lits.data(), types.data(),
                                            params.data(), w.data(), &o, device, &sub);
@@ -168,7 +190,8 @@ extern "C" {
 
 afs_status afs_autotune(const afs_instance *inst, int32_t device, int32_t B, int32_t reps, int32_t max_cons,
                         const char *cache_in, const char *cache_out, int32_t max_ranges, int32_t *k_lo,
-                        int32_t *k_hi, int32_t *lanes, int32_t *seg, float *ms, int32_t *n_ranges)
+                        int32_t *k_hi, int32_t *lanes, int32_t *seg, int32_t *tile, int32_t *rpl, float *ms,
+                        int32_t *n_ranges)
 {
     using afs::set_last_error;
     if (!inst || !n_ranges) return set_last_error(AFS_EINVAL, "inst or n_ranges is NULL");
@@ -197,7 +220,6 @@ afs_status afs_autotune(const afs_instance *inst, int32_t device, int32_t B, int
     std::vector<std::vector<int32_t>> members(ranges.size());
     for (int32_t c = 0; c < H.C; ++c) {
         const int k = (int)(H.con_off[c + 1] - H.con_off[c]);
-        if (k <= afs::kShortMax) continue;
         for (size_t r = 0; r < ranges.size(); ++r)
             if (k >= ranges[r].first && k <= ranges[r].second) {
                 members[r].push_back(c);
@@ -241,23 +263,49 @@ afs_status afs_autotune(const afs_instance *inst, int32_t device, int32_t B, int
         } else {
             if ((st = prepare()) != AFS_OK) break;
             std::vector<int32_t> cons = members[r];
-            if (max_cons > 0 && (int)cons.size() > max_cons) {  // evenly spaced sample
+            // one-lane lengths: a sample of at least 65,536 (a few hundred waves would
+            // time launch latency, not the kernel)
+            const int cap = (max_cons > 0 && hi <= afs::kShortMax) ? std::max(max_cons, 1 << 16) : max_cons;
+            if (cap > 0 && (int)cons.size() > cap) {            // evenly spaced sample
                 std::vector<int32_t> sample;
-                for (int i = 0; i < max_cons; ++i) sample.push_back(cons[(size_t)i * cons.size() / max_cons]);
+                for (int i = 0; i < cap; ++i) sample.push_back(cons[(size_t)i * cons.size() / cap]);
                 cons.swap(sample);
             }
+            auto timed = [&](Choice c, double &t) {
+                return time_shape(H, cons, hi, c, device, B, x, reps, s, e0, e1, t);
+            };
             best.ms = 1e30;
-            for (int J : kLanes) {
-                for (int S = 8; S <= afs::kMaxSeg && st == AFS_OK; S += 2) {
-                    if (J * S < hi || J * S >= 2 * hi + 64) continue;   // too small, or mostly padding
+            if (hi <= afs::kShortMax) {                         // one lane: restarts per lane
+                for (int rpl : {4, 2, 1}) {
+                    if (rpl == 4 && hi > 8) continue;
+                    if (st != AFS_OK || B % rpl) continue;
+                    Choice c;
+                    c.J = 1; c.S = hi; c.tile = default_tile(1); c.rpl = rpl;
                     double t = 0.0;
-                    st = time_shape(H, cons, hi, J, S, device, B, x, reps, s, e0, e1, t);
-                    if (st == AFS_OK && t < best.ms) {
-                        best.J = J;
-                        best.S = S;
-                        best.ms = t;
+                    st = timed(c, t);
+                    if (st == AFS_OK && t < best.ms) { best = c; best.ms = t; }
+                }
+            } else {                                            // segments: lanes x literals
+                for (int J : kLanes) {
+                    for (int S = 8; S <= afs::kMaxSeg && st == AFS_OK; S += 2) {
+                        if (J * S < hi || J * S >= 2 * hi + 64) continue;   // too small, or mostly padding
+                        Choice c;
+                        c.J = J; c.S = S; c.tile = default_tile(J);
+                        double t = 0.0;
+                        st = timed(c, t);
+                        if (st == AFS_OK && t < best.ms) { best = c; best.ms = t; }
                     }
                 }
+            }
+            // then the tile for that configuration
+            const Choice base = best;
+            for (int tile : {1, 2, 4, 8, 16}) {
+                if (st != AFS_OK || tile == base.tile) continue;
+                Choice c = base;
+                c.tile = tile;
+                double t = 0.0;
+                st = timed(c, t);
+                if (st == AFS_OK && t < 0.98 * best.ms) { best = c; best.ms = t; }
             }
             if (st != AFS_OK) break;
             best.timed = (int)cons.size();
@@ -269,6 +317,8 @@ afs_status afs_autotune(const afs_instance *inst, int32_t device, int32_t B, int
             k_hi[out] = hi;
             lanes[out] = best.J;
             seg[out] = best.S;
+            if (tile) tile[out] = best.tile;
+            if (rpl) rpl[out] = best.rpl;
             if (ms) ms[out] = reported;
         }
         ++out;

@@ -95,10 +95,11 @@ __device__ __forceinline__ void mul_unit_conj(float &r, float &n, float z)
 // ---------------------------------------------------------------------------
 // Short constraints (k <= 16): one lane per RPL consecutive restarts, k known at
 // compile time, the whole constraint in registers.  A wave takes 64*RPL restarts
-// and a tile of constraints of the bucket; with RPL = 4 (B a multiple of 4) the
-// x rows are read and the adjoint rows written as 16-byte vectors and the
-// constraint's metadata and table rows serve four restarts.  The weight (and the
-// adjoint seed) multiplies each literal's adjoint once, after the roots.
+// and a tile of constraints of the bucket; with RPL = 2 or 4 (B a multiple of
+// RPL) the x rows are read and the adjoint rows written as 8- or 16-byte vectors
+// and the constraint's metadata, literal addresses and table rows serve RPL
+// restarts.  The weight (and the adjoint seed) multiplies each literal's adjoint
+// once, after the roots.
 // ---------------------------------------------------------------------------
 template <int RPL>
 struct Lanes {
@@ -111,6 +112,9 @@ __device__ __forceinline__ void load_lanes(const float *p, Lanes<RPL> &out)
     if constexpr (RPL == 4) {
         const float4 q = *reinterpret_cast<const float4 *>(p);
         out.v[0] = q.x; out.v[1] = q.y; out.v[2] = q.z; out.v[3] = q.w;
+    } else if constexpr (RPL == 2) {
+        const float2 q = *reinterpret_cast<const float2 *>(p);
+        out.v[0] = q.x; out.v[1] = q.y;
     } else {
 #pragma unroll
         for (int e = 0; e < RPL; ++e) out.v[e] = p[e];
@@ -118,6 +122,7 @@ __device__ __forceinline__ void load_lanes(const float *p, Lanes<RPL> &out)
 }
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
 
 template <int RPL>
 __device__ __forceinline__ void store_lanes_stream(float *p, const Lanes<RPL> &in)
@@ -125,6 +130,9 @@ __device__ __forceinline__ void store_lanes_stream(float *p, const Lanes<RPL> &i
     if constexpr (RPL == 4) {
         f32x4 q = {in.v[0], in.v[1], in.v[2], in.v[3]};
         __builtin_nontemporal_store(q, reinterpret_cast<f32x4 *>(p));
+    } else if constexpr (RPL == 2) {
+        f32x2 q = {in.v[0], in.v[1]};
+        __builtin_nontemporal_store(q, reinterpret_cast<f32x2 *>(p));
     } else {
 #pragma unroll
         for (int e = 0; e < RPL; ++e) __builtin_nontemporal_store(in.v[e], p + e);
@@ -327,6 +335,28 @@ __device__ __forceinline__ void butterfly_real(float &g, float &x)
 // the adjoint of each literal the lane owns: no cross-lane reduction of
 // adjoints, deterministic order.
 // ---------------------------------------------------------------------------
+// The points of this lane's literals of constraint c, unsigned (x as stored; the
+// signs go into neg, bit s for literal s), padding literals 1.  The sign is
+// applied when the values are used, so the loads can stay in flight meanwhile.
+template <int S>
+__device__ __forceinline__ void fetch_points(const FeArgs &A, int c, int base, int bl, float (&xv)[S], unsigned &neg)
+{
+    const int slot0 = A.bc_slot0[c];
+    const int k = A.bc_k[c];
+    neg = 0;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        const int i = base + s;
+        xv[s] = 1.0f;
+        if (i < k) {
+            const int lit = A.slot_lit[slot0 + i];
+            const int v = (lit > 0 ? lit : -lit) - 1;
+            xv[s] = A.x[(int64_t)v * A.B + bl];
+            neg |= (lit < 0 ? 1u : 0u) << s;
+        }
+    }
+}
+
 template <int J, int S, bool GRAD>
 __global__ __launch_bounds__(kBlock) void fe_grad_seg(FeArgs A, const float4 *__restrict__ T)
 {
@@ -353,6 +383,12 @@ __global__ __launch_bounds__(kBlock) void fe_grad_seg(FeArgs A, const float4 *__
     const int cend = min(cbeg + A.tile, A.c0 + A.nc);
     const int base = j * S;
     const float seed = (GRAD && A.dobj) ? A.dobj[bl] : 1.0f;
+    // With several constraints per wave and short segments (few registers), the
+    // next constraint's points are gathered while this one's roots run.
+    constexpr bool kAhead = J <= 4 && S <= 12;
+    float xn[S];
+    unsigned negn = 0;
+    if (kAhead && cbeg < cend) fetch_points<S>(A, cbeg, base, bl, xn, negn);
     float objacc = 0.f;
     for (int c = cbeg; c < cend; ++c) {
         const int slot0 = A.bc_slot0[c];
@@ -362,17 +398,27 @@ __global__ __launch_bounds__(kBlock) void fe_grad_seg(FeArgs A, const float4 *__
         const float wg = w * seed;
         unsigned neg = 0;            // bit s: literal s of this lane is negated
         float y[S], adj[S];
+        if constexpr (kAhead) {
+            neg = negn;
 #pragma unroll
-        for (int s = 0; s < S; ++s) {
-            const int i = base + s;
-            y[s] = 1.0f;
-            adj[s] = 0.f;
-            if (i < k) {
-                const int lit = A.slot_lit[slot0 + i];
-                const int v = (lit > 0 ? lit : -lit) - 1;
-                const float xv = A.x[(int64_t)v * A.B + bl];
-                y[s] = lit > 0 ? xv : -xv;
-                neg |= (lit < 0 ? 1u : 0u) << s;
+            for (int s = 0; s < S; ++s) {
+                y[s] = ((neg >> s) & 1u) ? -xn[s] : xn[s];
+                adj[s] = 0.f;
+            }
+            if (c + 1 < cend) fetch_points<S>(A, c + 1, base, bl, xn, negn);
+        } else {
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                const int i = base + s;
+                y[s] = 1.0f;
+                adj[s] = 0.f;
+                if (i < k) {
+                    const int lit = A.slot_lit[slot0 + i];
+                    const int v = (lit > 0 ? lit : -lit) - 1;
+                    const float xv = A.x[(int64_t)v * A.B + bl];
+                    y[s] = lit > 0 ? xv : -xv;
+                    neg |= (lit < 0 ? 1u : 0u) << s;
+                }
             }
         }
         const float4 r0 = T[tab];
@@ -468,6 +514,10 @@ hipError_t dispatch_short(int K, int rpl, dim3 g, hipStream_t s, const FeArgs &a
             break;                                                                                   \
         }                                                                                            \
     }                                                                                                \
+    if (rpl == 2) {                                                                                  \
+        hipLaunchKernelGGL((fe_grad_short<KK, 2, GRAD>), g, dim3(kBlock), 0, s, a, a.tab);                  \
+        break;                                                                                       \
+    }                                                                                                \
     hipLaunchKernelGGL((fe_grad_short<KK, 1, GRAD>), g, dim3(kBlock), 0, s, a, a.tab);                      \
     break;
     switch (K) {
@@ -529,9 +579,16 @@ hipError_t launch_fe_grad(const DevInstance &I, const BucketLaunch &bk, int B, i
     a.bc_w = I.bc_w; a.slot_lit = I.slot_lit; a.tab = I.tab;
     a.B = B; a.Bp = Bp;
     a.c0 = bk.c0; a.nc = bk.nc; a.tile = bk.tile; a.ntiles = bk.ntiles; a.tile0 = bk.tile0;
-    // several restarts per lane for short constraints when the rows allow 16-byte access
-    const int rpl = (bk.J == 1 && bk.S <= 8 && B % 4 == 0 && reinterpret_cast<uintptr_t>(x) % 16 == 0 &&
-                     (!dobj || reinterpret_cast<uintptr_t>(dobj) % 16 == 0)) ? 4 : 1;
+    // several restarts per lane for short constraints when B and the rows allow
+    // 4*rpl-byte access (else one)
+    int rpl = 1;
+    if (bk.J == 1) {
+        const int want = bk.rpl > 0 ? bk.rpl : (bk.S <= 8 ? 4 : 1);
+        const uintptr_t al = (uintptr_t)(4 * want);
+        if ((want == 2 || (want == 4 && bk.S <= 8)) && B % want == 0 &&
+            reinterpret_cast<uintptr_t>(x) % al == 0 && (!dobj || reinterpret_cast<uintptr_t>(dobj) % al == 0))
+            rpl = want;
+    }
     const int R = bk.J == 1 ? kWave * rpl : kWave / bk.J;      // restarts per wave
     int64_t groups = (B + R - 1) / R;
     if (bk.J > 1) groups = (groups + kWavesPerBlock - 1) / kWavesPerBlock * kWavesPerBlock;

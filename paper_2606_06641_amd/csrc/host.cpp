@@ -282,14 +282,36 @@ std::string check_options(const PackOptions &o)
         if (J * S < kh) return "shape_lanes * shape_seg is smaller than shape_k_hi";
         prev = kh;
     }
-    if (o.tile_short < 0 || o.tile_long < 0 || o.tile_short > 4096 || o.tile_long > 4096) return "tile out of range";
+    if (!o.tile.empty() && o.tile.size() != o.k_hi.size()) return "shape_tile differs in length from the shapes";
+    for (int t : o.tile)
+        if (t < 0 || t > kMaxTile) return "shape_tile out of range";
+    if (o.tile_short < 0 || o.tile_long < 0 || o.tile_short > kMaxTile || o.tile_long > kMaxTile)
+        return "tile out of range";
+    for (int k = 1; k <= kShortMax; ++k) {
+        if (o.short_tile[k] < 0 || o.short_tile[k] > kMaxTile) return "short_tile out of range";
+        const int r = o.short_rpl[k];
+        if (r != 0 && r != 1 && r != 2 && r != 4) return "short_rpl must be 0, 1, 2 or 4";
+        if (r == 4 && k > 8) return "short_rpl 4 needs k <= 8";
+    }
     return std::string();
 }
 
-static int tile_for(int J, const PackOptions &o)
+void bucket_tiling(int k, const PackOptions &o, int &tile, int &rpl)
 {
-    if (J == 1) return o.tile_short > 0 ? o.tile_short : 4;
-    return o.tile_long > 0 ? o.tile_long : (J >= 8 ? 1 : 8 / J);
+    rpl = 0;
+    if (k <= kShortMax) {
+        tile = o.short_tile[k] > 0 ? o.short_tile[k] : (o.tile_short > 0 ? o.tile_short : 4);
+        rpl = o.short_rpl[k];
+        return;
+    }
+    int J, S;
+    bucket_shape(k, o, J, S);
+    for (size_t e = 0; e < o.k_hi.size(); ++e)
+        if (k <= o.k_hi[e]) {
+            if (!o.tile.empty() && o.tile[e] > 0) { tile = o.tile[e]; return; }
+            break;
+        }
+    tile = o.tile_long > 0 ? o.tile_long : (J >= 8 ? 1 : 8 / J);
 }
 
 std::string build_instance(int32_t n, int32_t C, const int64_t *con_off, const int32_t *lits,
@@ -370,21 +392,24 @@ std::string build_instance(int32_t n, int32_t C, const int64_t *con_off, const i
     // Order: short buckets by length, then long ones by capacity J*S (then J),
     // within a bucket by length and table.  The kernel shape of each length is
     // worked out once, and each constraint gets one integer sort key.
+    // Lengths of one class with different tilings stay apart: the sort below keeps
+    // a class ordered by length, so each tiling's lengths are contiguous in it.
     auto klen = [&](int32_t c) { return (int)(con_off[c + 1] - con_off[c]); };
-    std::vector<std::pair<int, int>> shape_of_len(max_k + 1);
+    std::vector<std::tuple<int, int, int, int>> shape_of_len(max_k + 1);   // (J, S, tile, rpl)
     for (int k = 1; k <= max_k; ++k) {
-        int J, S;
+        int J, S, tile, rpl;
         bucket_shape(k, opts, J, S);
-        shape_of_len[k] = std::make_pair(J, J == 1 ? k : S);
+        bucket_tiling(k, opts, tile, rpl);
+        shape_of_len[k] = std::make_tuple(J, J == 1 ? k : S, tile, rpl);
     }
     auto shape_key = [&](int32_t c) { return shape_of_len[klen(c)]; };
     std::vector<std::pair<uint64_t, int32_t>> keyed(C);
     for (int32_t c = 0; c < C; ++c) {
-        const auto sk = shape_key(c);
-        const uint64_t cls = sk.first == 1 ? (uint64_t)sk.second : (uint64_t)(sk.first * sk.second + 1000);
+        const int J = std::get<0>(shape_key(c)), S = std::get<1>(shape_key(c));
+        const uint64_t cls = J == 1 ? (uint64_t)S : (uint64_t)(J * S + 1000);
         // class (< 2^17) | J (< 2^7) | length (< 2^11) | table index (< 2^29: there are
         // at most 8 types x 1024 lengths x 1026 thresholds)
-        const uint64_t key = (cls << 47) | ((uint64_t)sk.first << 40) | ((uint64_t)klen(c) << 29) |
+        const uint64_t key = (cls << 47) | ((uint64_t)J << 40) | ((uint64_t)klen(c) << 29) |
                              (uint64_t)con_tidx[c];
         keyed[c] = std::make_pair(key, c);
     }
@@ -422,7 +447,8 @@ std::string build_instance(int32_t n, int32_t C, const int64_t *con_off, const i
         }
         bk.nc = j - i;
         bk.nslots = slot - bk.slot0;
-        bk.tile = tile_for(bk.J, opts);
+        bk.tile = std::get<2>(key);
+        bk.rpl = std::get<3>(key);
         bk.ntiles = (bk.nc + bk.tile - 1) / bk.tile;
         bk.tile0 = tiles;
         tiles += bk.ntiles;

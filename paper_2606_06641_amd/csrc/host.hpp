@@ -20,6 +20,8 @@ constexpr int kMaxLen = AFS_MAX_LEN;
 constexpr int kShortMax = 16;
 // Largest number of literals one lane holds in the segment kernels.
 constexpr int kMaxSeg = 32;
+// Largest number of constraints per work tile.
+constexpr int kMaxTile = 4096;
 
 // One row of a coefficient table, consumed by the kernels as a float4.
 //   row 0             : {d_0, d_half, 0, 0}  (d_half = d_{N/2} when N = k+1 is even, else 0)
@@ -46,6 +48,7 @@ struct Bucket {
     int32_t tile = 1;     // constraints per work tile
     int32_t ntiles = 0;
     int32_t tile0 = 0;    // first global tile index (objective partial rows)
+    int32_t rpl = 0;      // J == 1: restarts per lane asked for (0: the launch's default)
 };
 
 struct HostInstance {
@@ -97,8 +100,14 @@ void roots(int N, std::vector<long double> &c, std::vector<long double> &s);
 // Packing choices (see afs_options in afsat.h).
 struct PackOptions {
     std::vector<int> k_hi, lanes, seg;   // shape overrides for k > kShortMax, ascending k_hi
+    std::vector<int> tile;               // per override entry (empty, or 0: tile_long / default)
     int tile_short = 0, tile_long = 0;   // 0: defaults
+    int short_tile[kShortMax + 1] = {};  // per length k <= kShortMax (0: tile_short / default)
+    int short_rpl[kShortMax + 1] = {};   // per length k <= kShortMax (0: the launch's default)
 };
+
+// Work-tile size and restarts per lane of the bucket that evaluates length k.
+void bucket_tiling(int k, const PackOptions &o, int &tile, int &rpl);
 
 // Validate options; returns an empty string or a message.
 std::string check_options(const PackOptions &o);

@@ -36,6 +36,7 @@ constexpr int kLitPad = 32;
 struct BucketLaunch {
     int J, S;
     int32_t c0, nc, tile, ntiles, tile0;
+    int32_t rpl;          // J == 1: restarts per lane asked for (0: 4 for S <= 8, else 1)
 };
 
 // FE (and with grad, per-literal adjoints) of one length bucket.

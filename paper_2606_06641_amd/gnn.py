@@ -8,6 +8,7 @@ runs in the library's kernels; this module moves arrays and loops over data.
 """
 import ctypes
 import time
+import weakref
 
 import numpy as np
 import torch
@@ -98,7 +99,7 @@ class GNN:
         n = ctypes.c_int64()
         _check(lib().afs_gnn_num_params(h, ctypes.byref(n)))
         self.num_params = n.value
-        self._ws = {}
+        self._ws = None
         self.t = 0
 
     def close(self):
@@ -132,13 +133,15 @@ class GNN:
         self.t = int(sd["t"])
 
     def _workspace(self, inst, B):
-        key = (id(inst), B)
-        ws = self._ws.get(key)
-        if ws is None:
+        # one cached workspace, for the instance object it was sized for (held by a
+        # weak reference, so a later instance at the same address is not mistaken
+        # for it) and B
+        ref, b, ws = self._ws or (None, None, None)
+        if ws is None or b != B or ref() is not inst:
             nb = ctypes.c_size_t()
             _check(lib().afs_gnn_workspace_bytes(self._h, inst._h, int(B), ctypes.byref(nb)))
             ws = torch.empty(max(nb.value, 256), dtype=torch.uint8, device=torch.device("cuda", self.device))
-            self._ws = {key: ws}
+            self._ws = (weakref.ref(inst), B, ws)
         return ws
 
     def forward(self, inst, x0):
@@ -267,15 +270,16 @@ def run_arm(dinst, make_start, round_steps, timeout_s, lr=0.1, poll=10, search=N
 
 
 def compare(net, tests, B, round_steps, timeout_s, variant, seed=0, lr=0.1, search=None, log=None, max_rounds=0,
-            arms=("random", "learned")):
+            arms=("random", "learned"), index0=0):
     """Learned vs uniform random starts on each test instance.  Before either arm
     is timed, one untimed two-iteration run on the instance pays the solver's
     first-use costs (its workspace, state and driver streams); the arms then take
     turns going first (even instances random first, odd ones learned first), each
-    with its own noise generator seeded per instance.  Returns per-arm lists of
-    run_arm results."""
+    with its own noise generator seeded per instance (tests[j] counts as instance
+    index0 + j, so a test set split over several calls draws the same noise as one
+    call).  Returns per-arm lists of run_arm results."""
     out = {arm: [] for arm in arms}
-    for i, p in enumerate(tests):
+    for i, p in enumerate(tests, start=index0):
         d = afsat.Instance.from_arrays(p)
         d.pgd(uniform_start(d, B, (seed << 40) + (i << 20) + 0xFFFFF), lr=lr, steps=2, poll=1, stop_on_sat=False,
               search=search)

@@ -2,7 +2,9 @@
 (forward = FE only, backward = recomputed products seeded by dL/dF per restart),
 checked against the FP64 oracle's gradient and against central differences of
 the oracle's objective (exact for a function affine in each coordinate)."""
+import os
 import sys
+import tempfile
 
 import numpy as np
 import pytest
@@ -74,8 +76,10 @@ def test_longcard50k_autograd():
     inst = W.long_card_50k()
     B = 512
     x32 = W.uniform_x0(inst.n, B, workload=4)
-    shapes, _ = autotune.tune(inst, B, cache_path=autotune.DEFAULT_CACHE, max_cons=400)
-    log("case: config-4 autograd n=50k B=512, tuned shapes %s" % shapes)
+    with tempfile.TemporaryDirectory() as tmp:
+        shapes, _ = autotune.tune(inst, B, cache_path=autotune.DEFAULT_CACHE, out_path=os.path.join(tmp, "t.txt"),
+                                  max_cons=400)
+    log("case: long-card autograd n=50k B=512, tuned shapes %s" % shapes)
     d = afsat.Instance.from_arrays(inst, shapes=shapes)
     x = parity.to_dev(x32).requires_grad_(True)
     obj = afsat.FEObjective.apply(x, d)

@@ -4,6 +4,7 @@ Every comparison feeds both sides the same FP32 points (the oracle widens them
 exactly to FP64).  Tolerances are per length bucket (see parity.py); rounding,
 verification and step bookkeeping are compared bit for bit.
 """
+import os
 import sys
 
 import numpy as np
@@ -108,14 +109,39 @@ def test_autotuner_shapes_are_valid_and_exact(tmp_path):
                    W.random_instance(rng, n=800, count=50, k_lo=2, k_hi=8)], n=800)
     cache = str(tmp_path / "shapes.txt")
     shapes, report = autotune.tune(inst, 64, reps=2, log=log, out_path=cache)
-    assert shapes and all(J * S >= kh for kh, J, S in shapes)
+    assert shapes and all((S == kh if J == 1 else J * S >= kh) for kh, J, S, _, _ in shapes)
+    assert all(tile in (1, 2, 4, 8, 16) for _, _, _, tile, _ in shapes)
+    assert all((rpl in (1, 2, 4) and 64 % rpl == 0) if J == 1 else rpl == 0 for _, J, _, _, rpl in shapes)
     assert [s[0] for s in shapes] == sorted(s[0] for s in shapes)
+    lens = np.diff(inst.con_off)
+    assert {kh for kh, J, _, _, _ in shapes if J == 1} == {int(k) for k in lens if k <= 16}
     assert not any(r["cached"] for r in report)
     shapes2, report2 = autotune.tune(inst, 64, reps=2, cache_path=cache)
     assert shapes2 == shapes and all(r["cached"] for r in report2)
     x = rng.uniform(-1, 1, size=(inst.n, 64)).astype(np.float32)
     d = afsat.Instance.from_arrays(inst, shapes=shapes)
+    conf = {kh: (tile, rpl) for kh, J, _, tile, rpl in shapes if J == 1}
+    for b in d.buckets():
+        if b.lanes_per_restart == 1:
+            assert (b.tile, b.rpl) == conf[b.k_lo]
     parity.compare(inst, d, parity.gpu_eval(d, x), oracle.eval(inst, x, fe=True, adj=True, grad=True), "tuned")
+
+
+@pytest.mark.parametrize("rpl", [1, 2, 4])
+def test_short_kernel_restarts_per_lane_and_tiles(rpl):
+    """Every one-lane length at 1, 2 or 4 restarts per lane (4 only up to k = 8)
+    with uneven tiles, against the oracle; B = 132 leaves a ragged last wave, and
+    B = 130 (not a multiple of 4) makes the launch fall back to fewer restarts."""
+    rng = np.random.default_rng(40 + rpl)
+    ks = [k for k in range(1, 17) if rpl < 4 or k <= 8]
+    inst = concat([W.random_instance(rng, n=300, count=13, k_lo=k, k_hi=k) for k in ks], n=300)
+    shapes = [(k, 1, k, (1, 3, 16)[k % 3], rpl) for k in ks]
+    d = afsat.Instance.from_arrays(inst, shapes=shapes)
+    assert all(b.rpl == rpl for b in d.buckets())
+    for B in (132, 130):
+        x = rng.uniform(-1, 1, size=(inst.n, B)).astype(np.float32)
+        orc = oracle.eval(inst, x, fe=True, adj=True, grad=True)
+        parity.compare(inst, d, parity.gpu_eval(d, x), orc, "one-lane rpl=%d B=%d" % (rpl, B))
 
 
 def test_adversarial_points():
@@ -156,10 +182,14 @@ def test_planted_3sat_n100_parity():
 
 
 def tuned_shapes(inst, B):
-    """The kernel shapes bench.py runs: the package's tuned table (shapes missing
-    from it are tuned on the device)."""
+    """The kernel configurations bench.py runs: the package's tuned table (ranges
+    missing from it are tuned on the device, into a temporary file so the shipped
+    table stays as it is)."""
+    import tempfile
     from paper_2606_06641_amd import autotune
-    shapes, _ = autotune.tune(inst, B, cache_path=autotune.DEFAULT_CACHE, max_cons=400)
+    with tempfile.TemporaryDirectory() as tmp:
+        shapes, _ = autotune.tune(inst, B, cache_path=autotune.DEFAULT_CACHE, out_path=os.path.join(tmp, "t.txt"),
+                                  max_cons=400)
     return shapes
 
 

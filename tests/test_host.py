@@ -167,6 +167,37 @@ def test_shape_overrides_and_tiles():
         assert e.value.status == afsat.AFS_EINVAL
 
 
+def test_tile_and_rpl_options():
+    # per-entry tiles split a shape's lengths into buckets of their own; one-lane
+    # entries set the tile and restarts per lane of their length; tables and slot
+    # order within a length do not depend on these choices
+    rng = np.random.default_rng(3)
+    parts = [W.random_instance(rng, n=3000, count=7, k_lo=k, k_hi=k) for k in (5, 12, 20, 24, 60)]
+    lits = np.concatenate([p.lits for p in parts])
+    con_off = np.concatenate([[0], np.cumsum(np.concatenate([np.diff(p.con_off) for p in parts]))])
+    types = np.concatenate([p.types for p in parts])
+    params = np.concatenate([p.params for p in parts])
+    plain = afsat.Instance(3000, con_off, lits, types, params, device=-1, shapes=[(24, 2, 12), (64, 4, 16)])
+    b0 = plain.buckets()
+    assert [(b.k_lo, b.k_hi) for b in b0] == [(5, 5), (12, 12), (20, 24), (60, 60)]
+    assert [b.tile for b in b0] == [4, 4, 4, 2] and all(b.rpl == 0 for b in b0)
+    shapes = [(5, 1, 5, 8, 2), (12, 1, 12, 0, 2), (20, 2, 12, 16), (24, 2, 12, 1), (64, 4, 16, 0)]
+    tuned = afsat.Instance(3000, con_off, lits, types, params, device=-1, shapes=shapes)
+    b1 = tuned.buckets()
+    assert [(b.k_lo, b.k_hi, b.tile, b.rpl) for b in b1] == [
+        (5, 5, 8, 2), (12, 12, 4, 2), (20, 20, 16, 0), (24, 24, 1, 0), (60, 60, 2, 0)]
+    assert [(b.lanes_per_restart, b.lits_per_lane) for b in b1][2:4] == [(2, 12), (2, 12)]
+    assert np.array_equal(plain.slot_map(), tuned.slot_map())
+    for bad in ([(9, 1, 9, 0, 4)],                     # four restarts per lane needs k <= 8
+                [(5, 1, 5, 0, 3)],                     # rpl not 0, 1, 2 or 4
+                [(5, 1, 4, 0, 1)],                     # one-lane entry with seg != k
+                [(17, 1, 17, 0, 0)],                   # one-lane entry past 16
+                [(5, 1, 5, 5000, 0)],                  # tile too large
+                [(64, 4, 16, -1)]):
+        with pytest.raises((afsat.AfsError, ValueError)):
+            afsat.Instance(3000, con_off, lits, types, params, device=-1, shapes=bad)
+
+
 def _create(n, con_off, lits, types, params=None):
     return afsat.Instance(n, con_off, lits, types, params, device=-1)
 

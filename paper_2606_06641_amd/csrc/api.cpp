@@ -313,6 +313,7 @@ afs_status finish_create(afs_instance *I, int32_t device, afs_instance **out)
     if (st == AFS_OK) st = upload(I, H.slot_lit, &D.slot_lit);
     if (st == AFS_OK) st = upload(I, H.slot_to_lit, &D.slot_to_lit);
     if (st == AFS_OK) st = upload(I, tab, &D.tab);
+    D.tab_rows = (int64_t)tab.size();
     if (st == AFS_OK) st = upload(I, H.voff, &D.voff);
     if (st == AFS_OK) st = upload(I, H.vslot, &D.vslot);
     if (st == AFS_OK) st = upload(I, con_off32, &D.con_off);

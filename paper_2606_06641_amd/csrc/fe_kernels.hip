@@ -45,6 +45,7 @@ struct FeArgs {
     const float *bc_w;
     const int32_t *slot_lit;
     const float4 *tab;
+    int64_t tab_rows;            // rows of tab
     int B, Bp;
     int32_t c0, nc, tile, ntiles, tile0;
     int64_t items, item0;        // all items; first item of this launch
@@ -77,6 +78,27 @@ __device__ __forceinline__ float in_vgpr(float s)
     float v;
     asm("v_mov_b32 %0, %1" : "=v"(v) : "s"(s));
     return v;
+}
+
+// The table seen as a buffer resource of tab_rows 16-byte rows (fewer than 2^27:
+// the packing refuses more; the fourth word is the raw-buffer setting for this
+// architecture): a read through it is an intrinsic call, which the compiler
+// does not merge into other reads, and a read past the end returns zero.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t table_rsrc(const float4 *T, int64_t rows)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float4 *>(T), (short)0, (int)(rows * 16), 0x00020000);
+}
+
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+
+// The first two constants of table row `row` into vector registers.  The
+// segment kernels with long segments read the next root's -tan h and rescale
+// factor this way while the current root runs: the first per-literal products
+// of a root then need no scalar-cache read, whose wait would cover every scalar
+// read in flight.
+__device__ __forceinline__ f32x2 row_head(__amdgpu_buffer_rsrc_t rs, int row)
+{
+    return __builtin_bit_cast(f32x2, __builtin_amdgcn_raw_buffer_load_b64(rs, row * 16, 0, 0));
 }
 
 // The same step for a product held as (re, -im) =: (r, n): re' = r + n z and
@@ -122,7 +144,6 @@ __device__ __forceinline__ void load_lanes(const float *p, Lanes<RPL> &out)
 }
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
-typedef float f32x2 __attribute__((ext_vector_type(2)));
 
 template <int RPL>
 __device__ __forceinline__ void store_lanes_stream(float *p, const Lanes<RPL> &in)
@@ -383,6 +404,11 @@ __global__ __launch_bounds__(kBlock) void fe_grad_seg(FeArgs A, const float4 *__
     const int cend = min(cbeg + A.tile, A.c0 + A.nc);
     const int base = j * S;
     const float seed = (GRAD && A.dobj) ? A.dobj[bl] : 1.0f;
+    // Long segments read the next root's first constants through the vector path
+    // (a vector read's latency, a few hundred cycles, needs a root of 18 or more
+    // literals per lane to hide; shorter ones wait on the scalar read instead).
+    constexpr bool kHeadAhead = S >= 18;
+    const __amdgpu_buffer_rsrc_t rs = table_rsrc(T, A.tab_rows);
     // With several constraints per wave and short segments (few registers), the
     // next constraint's points are gathered while this one's roots run.
     constexpr bool kAhead = J <= 4 && S <= 12;
@@ -423,11 +449,22 @@ __global__ __launch_bounds__(kBlock) void fe_grad_seg(FeArgs A, const float4 *__
         }
         const float4 r0 = T[tab];
         float fe = r0.x;
-        const int M = k >> 1;
+        const int M = k >> 1;                          // >= 8: k > 16 here
+        f32x2 nh = {0.f, 0.f};                         // {-tan h, c^RP} of the next root
+        if constexpr (kHeadAhead) nh = row_head(rs, tab + 2);
         for (int m = 1; m <= M; ++m) {
             const float4 ra = T[tab + 2 * m - 1];       // {2 d', Kc}
             const float4 rb = T[tab + 2 * m];           // {-tan h, c^RP, c^F, 0}
-            const float mt = in_vgpr(rb.x), crp = in_vgpr(rb.y);
+            float mt, crp;
+            if constexpr (kHeadAhead) {
+                mt = nh.x;
+                crp = nh.y;
+                nh = row_head(rs, tab + 2 * min(m + 1, M));
+                __builtin_amdgcn_sched_barrier(0);      // the read goes out before the root's work
+            } else {
+                mt = in_vgpr(rb.x);
+                crp = in_vgpr(rb.y);
+            }
             float z[S], pr[S], pi[S];
 #pragma unroll
             for (int s = 0; s < S; ++s) z[s] = mt * y[s];
@@ -576,7 +613,7 @@ hipError_t launch_fe_grad(const DevInstance &I, const BucketLaunch &bk, int B, i
     FeArgs a;
     a.x = x; a.adj = adj; a.part = part; a.fe = fe; a.dobj = dobj; a.skip = skip;
     a.bc_slot0 = I.bc_slot0; a.bc_k = I.bc_k; a.bc_tab = I.bc_tab; a.bc_orig = I.bc_orig;
-    a.bc_w = I.bc_w; a.slot_lit = I.slot_lit; a.tab = I.tab;
+    a.bc_w = I.bc_w; a.slot_lit = I.slot_lit; a.tab = I.tab; a.tab_rows = I.tab_rows;
     a.B = B; a.Bp = Bp;
     a.c0 = bk.c0; a.nc = bk.nc; a.tile = bk.tile; a.ntiles = bk.ntiles; a.tile0 = bk.tile0;
     // several restarts per lane for short constraints when B and the rows allow

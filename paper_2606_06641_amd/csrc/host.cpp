@@ -387,6 +387,8 @@ std::string build_instance(int32_t n, int32_t C, const int64_t *con_off, const i
         append_root_rows(k, J, S, re.data(), im.data(), H.tab);
         ++H.n_tables;
     }
+    // the kernels address table rows with 32-bit byte offsets
+    if (H.tab.size() >= ((size_t)1 << 27)) return "coefficient tables exceed 2 GiB (too many distinct constraints)";
 
     // ---- buckets ----
     // Order: short buckets by length, then long ones by capacity J*S (then J),

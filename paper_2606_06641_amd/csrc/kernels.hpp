@@ -17,6 +17,7 @@ struct DevInstance {
     const int32_t *slot_lit = nullptr, *slot_to_lit = nullptr;
     // coefficient tables
     const float4 *tab = nullptr;
+    int64_t tab_rows = 0;
     // variable -> slot transpose
     const int32_t *voff = nullptr, *vslot = nullptr;
     // original-order constraints (verification)

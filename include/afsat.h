@@ -428,8 +428,10 @@ afs_status afs_pgd(afs_instance *inst, int32_t B, float *x, const afs_pgd_params
  * wins; then tiles of 1, 2, 4, 8 and 16 constraints are timed for it, and one
  * other than the default must be 2% faster to replace it.
  *   cache_in, cache_out: text files (either may be NULL) with one line per
- *     result, "<arch> <revision> <B> <k_lo> <k_hi> <lanes> <seg> <tile> <rpl>
- *     <ms> <timed>"; results found in either are reused, and cache_out is
+ *     result, "<arch> <revision> <B> <k_lo> <k_hi> <class> <lanes> <seg> <tile>
+ *     <rpl> <ms> <timed>", where class = floor(log2(constraints of the instance
+ *     in the range)) (a range of a few constraints and one of thousands are
+ *     tuned apart); results found in either are reused, and cache_out is
  *     rewritten with them plus the new ones, keeping only the current kernel
  *     revision.
  *   k_lo, k_hi, lanes, seg: host int32 [max_ranges] (lanes 1 and seg k for a

@@ -11,11 +11,11 @@
 // fastest shape (long) or restarts per lane (short) at the default tile, then the
 // tile sizes for it; a tile other than the default must win by 2% (the medians of
 // neighbouring tiles are often within noise).  Results are cached in a text file
-// keyed by (GPU architecture, FE kernel source revision, restarts, range), one
-// line per entry:
-//     <arch> <revision> <B> <k_lo> <k_hi> <J> <S> <tile> <rpl> <median ms> <constraints timed>
-// so that other instances with constraints in the same ranges reuse them and a
-// change to the kernels invalidates them.
+// keyed by (GPU architecture, FE kernel source revision, restarts, range, size
+// class of the range's constraint count), one line per entry:
+//     <arch> <revision> <B> <k_lo> <k_hi> <class> <J> <S> <tile> <rpl> <median ms> <constraints timed>
+// so that other instances with about as many constraints in the same ranges reuse
+// them and a change to the kernels invalidates them.
 
 #include "afsat.h"
 
@@ -69,12 +69,26 @@ std::vector<std::pair<int, int>> length_ranges()
     return out;
 }
 
+// The size class of a range: floor(log2(constraints of the instance in it)).  The
+// best configuration depends on how many waves a launch has (a range of a few
+// constraints runs in the latency regime, one of thousands fills the device), so
+// instances whose ranges differ in size class are tuned apart.
+int size_class(size_t count)
+{
+    int c = 0;
+    while (count >= 2) {
+        count >>= 1;
+        ++c;
+    }
+    return c;
+}
+
 struct Key {
     std::string arch, rev;
-    int B, lo, hi;
+    int B, lo, hi, cls;
     bool operator<(const Key &o) const
     {
-        return std::tie(arch, rev, B, lo, hi) < std::tie(o.arch, o.rev, o.B, o.lo, o.hi);
+        return std::tie(arch, rev, B, lo, hi, cls) < std::tie(o.arch, o.rev, o.B, o.lo, o.hi, o.cls);
     }
 };
 
@@ -94,7 +108,7 @@ void read_cache(const char *path, std::map<Key, Choice> &cache)
         std::istringstream in(line);
         Key k;
         Choice c;
-        if (in >> k.arch >> k.rev >> k.B >> k.lo >> k.hi >> c.J >> c.S >> c.tile >> c.rpl >> c.ms >> c.timed)
+        if (in >> k.arch >> k.rev >> k.B >> k.lo >> k.hi >> k.cls >> c.J >> c.S >> c.tile >> c.rpl >> c.ms >> c.timed)
             cache[k] = c;
     }
 }
@@ -109,12 +123,12 @@ bool write_cache(const char *path, const std::map<Key, Choice> &cache, const std
     {
         std::ofstream f(tmp);
         if (!f) return false;
-        f << "# arch revision B k_lo k_hi lanes seg tile rpl median_ms constraints_timed\n";
+        f << "# arch revision B k_lo k_hi size_class lanes seg tile rpl median_ms constraints_timed\n";
         for (const auto &kv : cache) {
             if (kv.first.rev != rev) continue;                  // stale kernel revisions are dropped
             char buf[256];
-            std::snprintf(buf, sizeof buf, "%s %s %d %d %d %d %d %d %d %.6f %d\n", kv.first.arch.c_str(),
-                          kv.first.rev.c_str(), kv.first.B, kv.first.lo, kv.first.hi, kv.second.J,
+            std::snprintf(buf, sizeof buf, "%s %s %d %d %d %d %d %d %d %d %.6f %d\n", kv.first.arch.c_str(),
+                          kv.first.rev.c_str(), kv.first.B, kv.first.lo, kv.first.hi, kv.first.cls, kv.second.J,
                           kv.second.S, kv.second.tile, kv.second.rpl, kv.second.ms, kv.second.timed);
             f << buf;
         }
@@ -254,7 +268,7 @@ afs_status afs_autotune(const afs_instance *inst, int32_t device, int32_t B, int
     for (size_t r = 0; r < ranges.size() && st == AFS_OK; ++r) {
         if (members[r].empty()) continue;
         const int lo = ranges[r].first, hi = ranges[r].second;
-        const Key key{arch, rev, B, lo, hi};
+        const Key key{arch, rev, B, lo, hi, size_class(members[r].size())};
         Choice best;
         float reported = -1.0f;                                 // cached: not timed now
         auto it = cache.find(key);

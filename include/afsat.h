@@ -132,7 +132,7 @@ afs_status afs_instance_create(int32_t n_vars, int32_t n_cons, const int64_t *co
  *       constraints longer than 16: a constraint of length k uses the first entry
  *       with k <= shape_k_hi[e] (ascending), evaluated by shape_lanes[e] lanes per
  *       restart (2, 4, 8, 16, 32 or 64) holding shape_seg[e] literals each (even,
- *       8 to 32), with lanes * seg >= shape_k_hi[e].  Lengths past the last entry
+ *       4 to 32), with lanes * seg >= shape_k_hi[e].  Lengths past the last entry
  *       use the default shape model.  (These are what the autotuner picks.)
  *   tile_short / tile_long: constraints per work tile (one wave's share of a
  *       bucket, 0 to 4096, 0: default) for lengths <= 16 / > 16.
@@ -417,7 +417,7 @@ afs_status afs_pgd(afs_instance *inst, int32_t B, float *x, const afs_pgd_params
  * for it; here the kernel that evaluates each length is tuned on the device
  * instead (the results are what afs_options' shape, tile and short arrays take).
  * Ranges: each length 1..16 alone (the one-lane kernel), then the ranges between
- * consecutive candidate capacities J*S (J in {2, ..., 64}, S even in 8..32).  For
+ * consecutive candidate capacities J*S (J in {2, ..., 64}, S even in 4..32).  For
  * every range that holds constraints of inst (a plain instance or a batch, device
  * or host-only), the constraints in that range -- an evenly spaced sample of at
  * most max_cons (<= 0: all; one-lane lengths: at least 65,536) -- are packed alone

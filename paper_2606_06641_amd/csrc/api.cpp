@@ -147,8 +147,10 @@ void release(afs_instance *I)
         if (I->fork) (void)hipEventDestroy(I->fork);
         if (I->join) (void)hipEventDestroy(I->join);
         if (I->side) (void)hipStreamDestroy(I->side);
-        if (I->join2) (void)hipEventDestroy(I->join2);
-        if (I->side2) (void)hipStreamDestroy(I->side2);
+        for (int t = 0; t < afs_instance::kLongSides; ++t) {
+            if (I->join_long[t]) (void)hipEventDestroy(I->join_long[t]);
+            if (I->side_long[t]) (void)hipStreamDestroy(I->side_long[t]);
+        }
         if (I->drive_in) (void)hipEventDestroy(I->drive_in);
         if (I->drive_out) (void)hipEventDestroy(I->drive_out);
         if (I->drive) (void)hipStreamDestroy(I->drive);
@@ -201,13 +203,15 @@ afs_status fe_grad_set(afs_instance *I, int B, const float *x, void *ws, const W
     // Short buckets (one lane per restart, bound by memory traffic) go to the side
     // stream when long buckets (bound by arithmetic) share the range, so the two
     // kinds overlap.  Long buckets hold few constraints each and rarely fill the
-    // device alone, so they are dealt to two streams (the caller's and side2),
-    // largest first to whichever has less estimated work (flops ~ literals x
-    // length).  Every bucket writes its own adjoint rows and objective tiles.
+    // device alone, so they are dealt to up to 1 + kLongSides streams (the
+    // caller's and side_long[]), largest first to whichever has the least
+    // estimated work (flops ~ literals x length).  Every bucket writes its own
+    // adjoint rows and objective tiles.
+    constexpr int NS = 1 + afs_instance::kLongSides;
     std::vector<int> shorts, longs;
     for (int bi : set) (I->H.buckets[bi].J == 1 ? shorts : longs).push_back(bi);
     const bool split_short = !shorts.empty() && !longs.empty() && I->side;
-    const bool split_long = longs.size() >= 2 && I->side2;
+    const int nlong = std::min<int>(NS, (int)longs.size());   // streams the long buckets use
     std::vector<hipStream_t> stream_of(I->H.buckets.size(), s);
     if (split_short)
         for (int bi : shorts) stream_of[bi] = I->side;
@@ -216,20 +220,22 @@ afs_status fe_grad_set(afs_instance *I, int B, const float *x, void *ws, const W
         return (double)b.nslots * (double)(b.k_lo + b.k_hi);
     };
     std::sort(longs.begin(), longs.end(), [&](int a, int b) { return cost(a) > cost(b); });
-    if (split_long) {
-        double load[2] = {0.0, 0.0};
+    if (nlong > 1) {
+        double load[NS] = {};
         for (int bi : longs) {
-            const int t = load[1] < load[0] ? 1 : 0;
+            int t = 0;
+            for (int u = 1; u < nlong; ++u)
+                if (load[u] < load[t]) t = u;
             load[t] += cost(bi);
-            stream_of[bi] = t ? I->side2 : s;
+            stream_of[bi] = t ? I->side_long[t - 1] : s;
         }
     }
     std::unique_lock<std::mutex> lock(I->side_mu, std::defer_lock);
-    if (split_short || split_long) {
+    if (split_short || nlong > 1) {
         lock.lock();
         hipError_t e = hipEventRecord(I->fork, s);
         if (e == hipSuccess && split_short) e = hipStreamWaitEvent(I->side, I->fork, 0);
-        if (e == hipSuccess && split_long) e = hipStreamWaitEvent(I->side2, I->fork, 0);
+        for (int t = 1; t < nlong && e == hipSuccess; ++t) e = hipStreamWaitEvent(I->side_long[t - 1], I->fork, 0);
         if (e != hipSuccess) return dev_fail(e, "fork to the side streams");
     }
     // long buckets largest first, then the short ones (on their own stream)
@@ -248,10 +254,10 @@ afs_status fe_grad_set(afs_instance *I, int B, const float *x, void *ws, const W
         if (e == hipSuccess) e = hipStreamWaitEvent(s, I->join, 0);
         if (e != hipSuccess) return dev_fail(e, "join from the side stream");
     }
-    if (split_long) {
-        hipError_t e = hipEventRecord(I->join2, I->side2);
-        if (e == hipSuccess) e = hipStreamWaitEvent(s, I->join2, 0);
-        if (e != hipSuccess) return dev_fail(e, "join from the second stream");
+    for (int t = 1; t < nlong; ++t) {
+        hipError_t e = hipEventRecord(I->join_long[t - 1], I->side_long[t - 1]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s, I->join_long[t - 1], 0);
+        if (e != hipSuccess) return dev_fail(e, "join from a long-bucket stream");
     }
     return AFS_OK;
 }
@@ -333,8 +339,10 @@ afs_status finish_create(afs_instance *I, int32_t device, afs_instance **out)
         hipError_t e = hipStreamCreateWithFlags(&I->side, hipStreamNonBlocking);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&I->fork, hipEventDisableTiming);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&I->join, hipEventDisableTiming);
-        if (e == hipSuccess) e = hipStreamCreateWithFlags(&I->side2, hipStreamNonBlocking);
-        if (e == hipSuccess) e = hipEventCreateWithFlags(&I->join2, hipEventDisableTiming);
+        for (int t = 0; t < afs_instance::kLongSides && e == hipSuccess; ++t) {
+            e = hipStreamCreateWithFlags(&I->side_long[t], hipStreamNonBlocking);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&I->join_long[t], hipEventDisableTiming);
+        }
         if (e != hipSuccess) st = dev_fail(e, "side streams");
     }
     if (st != AFS_OK) {

@@ -48,7 +48,7 @@ std::vector<int> capacities()
 {
     std::set<int> caps;
     for (int J : kLanes)
-        for (int S = 8; S <= afs::kMaxSeg; S += 2)
+        for (int S = afs::kMinSeg; S <= afs::kMaxSeg; S += 2)
             if (J * S > afs::kShortMax && J * S <= afs::kMaxLen) caps.insert(J * S);
     return std::vector<int>(caps.begin(), caps.end());
 }
@@ -301,7 +301,7 @@ afs_status afs_autotune(const afs_instance *inst, int32_t device, int32_t B, int
                 }
             } else {                                            // segments: lanes x literals
                 for (int J : kLanes) {
-                    for (int S = 8; S <= afs::kMaxSeg && st == AFS_OK; S += 2) {
+                    for (int S = afs::kMinSeg; S <= afs::kMaxSeg && st == AFS_OK; S += 2) {
                         if (J * S < hi || J * S >= 2 * hi + 64) continue;   // too small, or mostly padding
                         Choice c;
                         c.J = J; c.S = S; c.tile = default_tile(J);

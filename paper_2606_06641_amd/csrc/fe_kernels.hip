@@ -349,7 +349,7 @@ __device__ __forceinline__ void butterfly_real(float &g, float &x)
 
 // ---------------------------------------------------------------------------
 // Long constraints: J lanes per restart (64/J restarts per wave), lane j holding
-// literals [j*S, j*S + S), S even in [8, 32].  Per root, each lane
+// literals [j*S, j*S + S), S even in [4, 32].  Per root, each lane
 // runs its local prefix chain (storing the prefixes) and forms its segment's
 // product; the butterfly gives every lane the total and the product of the other
 // lanes' segments, which seeds the lane's suffix chain; that chain accumulates
@@ -381,7 +381,7 @@ __device__ __forceinline__ void fetch_points(const FeArgs &A, int c, int base, i
 template <int J, int S, bool GRAD>
 __global__ __launch_bounds__(kBlock) void fe_grad_seg(FeArgs A, const float4 *__restrict__ T)
 {
-    static_assert(S % 2 == 0 && S >= 8 && S <= 32, "segment length must be even, 8 to 32");
+    static_assert(S % 2 == 0 && S >= 4 && S <= 32, "segment length must be even, 4 to 32");
     constexpr int R = kWave / J;
     constexpr int RP = J * S <= 256 ? 16 : 8;     // rescale period (see the table rows)
     const uint32_t item = (uint32_t)A.item0 + xcd_block() * kWavesPerBlock + wave_id();
@@ -571,6 +571,8 @@ template <int J, bool GRAD>
 hipError_t dispatch_seg_s(int S, dim3 g, hipStream_t s, const FeArgs &a)
 {
     switch (S) {
+    case 4: hipLaunchKernelGGL((fe_grad_seg<J, 4, GRAD>), g, dim3(kBlock), 0, s, a, a.tab); break;
+    case 6: hipLaunchKernelGGL((fe_grad_seg<J, 6, GRAD>), g, dim3(kBlock), 0, s, a, a.tab); break;
     case 8: hipLaunchKernelGGL((fe_grad_seg<J, 8, GRAD>), g, dim3(kBlock), 0, s, a, a.tab); break;
     case 10: hipLaunchKernelGGL((fe_grad_seg<J, 10, GRAD>), g, dim3(kBlock), 0, s, a, a.tab); break;
     case 12: hipLaunchKernelGGL((fe_grad_seg<J, 12, GRAD>), g, dim3(kBlock), 0, s, a, a.tab); break;

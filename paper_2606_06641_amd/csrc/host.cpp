@@ -278,7 +278,7 @@ std::string check_options(const PackOptions &o)
         if (kh <= prev) return "shape_k_hi must be ascending and > 16";
         if (kh > kMaxLen) return "shape_k_hi exceeds the maximum length";
         if (J < 2 || J > 64 || (J & (J - 1))) return "shape_lanes must be 2, 4, 8, 16, 32 or 64";
-        if (S < 8 || S > kMaxSeg || S % 2) return "shape_seg must be even, 8 to 32";
+        if (S < kMinSeg || S > kMaxSeg || S % 2) return "shape_seg must be even, 4 to 32";
         if (J * S < kh) return "shape_lanes * shape_seg is smaller than shape_k_hi";
         prev = kh;
     }

@@ -18,7 +18,8 @@ namespace afs {
 constexpr int kMaxLen = AFS_MAX_LEN;
 // Lengths up to this use one lane per restart with the whole constraint in registers.
 constexpr int kShortMax = 16;
-// Largest number of literals one lane holds in the segment kernels.
+// Fewest and most literals one lane holds in the segment kernels (even counts).
+constexpr int kMinSeg = 4;
 constexpr int kMaxSeg = 32;
 // Largest number of constraints per work tile.
 constexpr int kMaxTile = 4096;

@@ -55,10 +55,15 @@ struct afs_instance {
     hipStream_t side = nullptr;
     hipEvent_t fork = nullptr, join = nullptr;
     // Long buckets are few constraints each, so one of them rarely fills the
-    // device; they are split between the caller's stream and `side2` (joined
-    // back through `join2`) so that two run at a time.
-    hipStream_t side2 = nullptr;
-    hipEvent_t join2 = nullptr;
+    // device; they are split between the caller's stream and the `side_long`
+    // streams (each joined back through its `join_long` event) so that
+    // 1 + kLongSides run at a time.  Three at a time measured within 1 % of two
+    // on the bench workloads (better on the small ones, worse on the long-CARD
+    // one), and the driver's verification stream makes a fifth on a device with
+    // four hardware queues, so two it is.
+    static constexpr int kLongSides = 1;
+    hipStream_t side_long[kLongSides] = {};
+    hipEvent_t join_long[kLongSides] = {};
     std::mutex side_mu;
     // Private stream of the Algorithm 1 driver (afs_pgd), which captures its
     // iterations in a graph there; events order it against the caller's stream.

@@ -83,7 +83,7 @@ def test_every_segment_kernel_shape(J):
     option, on lengths that fill it exactly, leave one lane short, and leave most
     lanes padding."""
     rng = np.random.default_rng(100 + J)
-    for S in range(8, 33, 2):
+    for S in range(4, 33, 2):
         cap = J * S
         if cap > 1024 or cap <= 16:
             continue

@@ -118,6 +118,21 @@ def test_autotuner_shapes_are_valid_and_exact(tmp_path):
     assert not any(r["cached"] for r in report)
     shapes2, report2 = autotune.tune(inst, 64, reps=2, cache_path=cache)
     assert shapes2 == shapes and all(r["cached"] for r in report2)
+    # an instance with more constraints in the same ranges: a range is taken from
+    # the cache exactly when its constraint count has the same floor(log2) (size
+    # class) as in the first instance, else tuned anew
+    big = concat([W.random_instance(np.random.default_rng(22), n=800, count=24, k_lo=20, k_hi=150),
+                  W.random_instance(np.random.default_rng(23), n=800, count=200, k_lo=2, k_hi=8)], n=800)
+    _, report3 = autotune.tune(big, 64, reps=2, cache_path=cache)
+    la, lb = np.diff(inst.con_off), np.diff(big.con_off)
+    fresh = 0
+    for r in report3:
+        lo, hi = r["range"]
+        ca, cb = int(((la >= lo) & (la <= hi)).sum()), int(((lb >= lo) & (lb <= hi)).sum())
+        same = ca > 0 and int(np.log2(ca)) == int(np.log2(cb))
+        assert r["cached"] == same, (r, ca, cb)
+        fresh += not same
+    assert fresh > 0
     x = rng.uniform(-1, 1, size=(inst.n, 64)).astype(np.float32)
     d = afsat.Instance.from_arrays(inst, shapes=shapes)
     conf = {kh: (tile, rpl) for kh, J, _, tile, rpl in shapes if J == 1}

@@ -407,18 +407,23 @@ __global__ __launch_bounds__(kCountWaves * kWave) void count_kernel(CountArgs A)
         }
         return;
     }
-    if (cbeg >= cend) return;
-    int cnt = 0, inst = A.con_inst[cbeg];
-    for (int c = cbeg; c < cend; ++c) {
-        const int ci = A.con_inst[c];
-        if (ci != inst) {                        // constraints of one sub-instance are contiguous
-            add_unsat(A, inst, b, valid, cnt);
-            cnt = 0;
-            inst = ci;
+    // The tile spans sub-instances: the constraints of one sub-instance are
+    // contiguous (con_inst is non-decreasing), so each run's end is found by a
+    // binary search and the run counted like a whole tile.
+    for (int c = cbeg; c < cend;) {
+        const int inst = A.con_inst[c];
+        int lo = c + 1, hi = cend;               // first index in (c, cend] of another sub-instance
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (A.con_inst[mid] == inst) lo = mid + 1;
+            else hi = mid;
         }
-        cnt += (int)((row[c] >> sh) & 1u);
+        int cnt = 0, h = c;
+        for (; h < lo && (h & 3); ++h) cnt += (int)((row[h] >> sh) & 1u);   // up to a 16-byte boundary
+        if (h < lo) cnt += count_tile(row, h, lo, sh);
+        add_unsat(A, inst, b, valid, cnt);
+        c = lo;
     }
-    add_unsat(A, inst, b, valid, cnt);
 }
 
 // One block: done / first_sat bookkeeping and the {t, number done} counter.

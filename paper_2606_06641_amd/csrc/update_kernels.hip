@@ -226,13 +226,15 @@ __global__ __launch_bounds__(kBlock) void round_kernel(EltArgs A)
 // all (t == k), two (t >= 2) and the parity of t, which decide OR, XOR, NAE,
 // AMO and EO.
 //
-// violation_count_kernel (CARD >= K, CARD < K, EK): one constraint and 256
-// restarts per wave, four restarts per lane, the counts t summed in integers;
-// the predicates' nibbles of eight lanes form one word of the mask.
+// violation_count_kernel (CARD >= K, CARD < K, EK): the same lane mapping over
+// the list of counted constraints.  A lane counts the true literals of its 32
+// restarts bit-sliced: plane j holds bit j of the 32 counts, and each literal's
+// word is added with a carry through the planes (k <= 1024, so 11 planes); the
+// counts are then compared with K plane by plane from the top.
 //
-// Both read the literals of a constraint in batches (16, and kLitPad for the
-// counted kernel) so that every load of a batch is in flight at once; the
-// literal array carries kLitPad trailing zeros, so a batch never reads past it.
+// Both read the literals of a constraint in batches of 16 so that every load of
+// a batch is in flight at once; the literal array carries kLitPad trailing
+// zeros, so a batch never reads past it.
 //
 // count_kernel: one lane per restart and a tile of constraints; sums the
 // restart's violation bits and adds them to unsat of the constraint's
@@ -249,7 +251,7 @@ struct ViolArgs {
     const uint32_t *bits;
     uint32_t *viol;
     const int32_t *con_off, *lits, *types, *params, *counted;
-    int B, W, C, Cp, wpw, cpw, wchunks, nchunks;
+    int B, W, C, Cp, wpw, cpw, wchunks, n_counted;
     int64_t items, item0;        // all items; first item of this launch
 };
 
@@ -297,47 +299,74 @@ __global__ __launch_bounds__(kBlock) void violation_kernel(ViolArgs A)
     A.viol[(int64_t)w * A.Cp + c] = viol;
 }
 
+constexpr int kPlanes = 11;                          // counts up to 2047 >= AFS_MAX_LEN
+static_assert((1 << kPlanes) > AFS_MAX_LEN, "bit planes too few for the longest constraint");
+
 __global__ __launch_bounds__(kBlock) void violation_count_kernel(ViolArgs A)
 {
     const int64_t item = A.item0 + (int64_t)blockIdx.x * kWavesPerBlock + wave_id();
     if (item >= A.items) return;
-    const int c = A.counted[item / A.nchunks];
-    const int chunk = (int)(item % A.nchunks);
     const int lane = threadIdx.x & 63;
-    const int b0 = chunk * kScatterChunk + lane * kRestartsPerLane;   // four restarts per lane
-    const int wi = (b0 < A.B ? b0 : A.B - 1) >> 5;
-    const int sh = b0 & 31;
+    const int cl = lane / A.wpw, wl = lane % A.wpw;
+    const int64_t ci = (item / A.wchunks) * A.cpw + cl;       // index into the counted list
+    const int w = (int)(item % A.wchunks) * kWave + wl;
+    if (cl >= A.cpw || ci >= A.n_counted || w >= A.W) return;
+    const int c = A.counted[ci];
     const int o0 = A.con_off[c], o1 = A.con_off[c + 1];
-    int t[kRestartsPerLane] = {0, 0, 0, 0};
-    for (int o = o0; o < o1; o += kLitPad) {
-        int l[kLitPad];
-        uint32_t tv[kLitPad];
+    uint32_t plane[kPlanes];
 #pragma unroll
-        for (int i = 0; i < kLitPad; ++i) l[i] = A.lits[o + i];       // padded: past o1 stays in bounds
+    for (int j = 0; j < kPlanes; ++j) plane[j] = 0u;
+    for (int o = o0; o < o1; o += kLitBatch) {
+        int l[kLitBatch];
+        uint32_t tv[kLitBatch];
 #pragma unroll
-        for (int i = 0; i < kLitPad; ++i) {
+        for (int i = 0; i < kLitBatch; ++i) l[i] = A.lits[o + i];     // padded: past o1 stays in bounds
+#pragma unroll
+        for (int i = 0; i < kLitBatch; ++i) {
             const int v = (l[i] > 0 ? l[i] : -l[i]) - 1;
-            tv[i] = A.bits[(int64_t)(v > 0 ? v : 0) * A.W + wi];
+            tv[i] = A.bits[(int64_t)(v > 0 ? v : 0) * A.W + w];             // 1: variable True
         }
 #pragma unroll
-        for (int i = 0; i < kLitPad; ++i) {
-            if (o + i < o1) {
-                const uint32_t nib = ((tv[i] >> sh) ^ (l[i] < 0 ? 0xFu : 0u)) & 0xFu;   // 1: literal True
+        for (int i = 0; i < kLitBatch; ++i) {
+            uint32_t carry = o + i < o1 ? (l[i] > 0 ? tv[i] : ~tv[i]) : 0u;  // 1: literal True
 #pragma unroll
-                for (int e = 0; e < kRestartsPerLane; ++e) t[e] += (int)((nib >> e) & 1u);
+            for (int j = 0; j < kPlanes; ++j) {
+                const uint32_t t = plane[j] & carry;
+                plane[j] ^= carry;
+                carry = t;
             }
         }
     }
-    const int type = A.types[c], K = A.params[c];
-    uint32_t nib = 0;
+    const int type = A.types[c], K = A.params[c], k = o1 - o0;
+    uint32_t viol;
+    if (K <= 0 || K > k) {
+        // constant predicates: t >= K holds for every t when K <= 0 and for none when
+        // K > k; t == K for none unless K == 0
+        const bool ge_all = K <= 0;
+        if (type == AFS_EK && K == 0) {
+            uint32_t any = 0u;
 #pragma unroll
-    for (int e = 0; e < kRestartsPerLane; ++e) {
-        const bool sat = type == AFS_CARD_GE ? t[e] >= K : type == AFS_CARD_LT ? t[e] < K : t[e] == K;
-        nib |= (b0 + e < A.B && !sat ? 1u : 0u) << e;
+            for (int j = 0; j < kPlanes; ++j) any |= plane[j];
+            viol = any;                                  // violated where t != 0
+        } else if (type == AFS_EK) {
+            viol = ~0u;
+        } else {
+            const bool sat = type == AFS_CARD_GE ? ge_all : !ge_all;
+            viol = sat ? 0u : ~0u;
+        }
+    } else {
+        // 1 <= K <= k < 2^kPlanes: compare the counts with K from the top plane down
+        uint32_t eq = ~0u, gt = 0u;
+#pragma unroll
+        for (int j = kPlanes - 1; j >= 0; --j) {
+            const uint32_t kb = ((K >> j) & 1) ? ~0u : 0u;
+            gt |= eq & plane[j] & ~kb;
+            eq &= ~(plane[j] ^ kb);
+        }
+        const uint32_t ge = gt | eq;
+        viol = type == AFS_CARD_GE ? ~ge : type == AFS_CARD_LT ? ge : ~eq;
     }
-    const uint32_t word = gather_nibbles(nib);
-    const int w = chunk * (kScatterChunk / 32) + (lane >> 3);
-    if ((lane & 7) == 0 && w < A.W) A.viol[(int64_t)w * A.Cp + c] = word;
+    A.viol[(int64_t)w * A.Cp + c] = viol;
 }
 
 struct CountArgs {
@@ -645,8 +674,8 @@ hipError_t launch_verify(const DevInstance &I, int B, const uint32_t *bits, uint
     });
     if (e != hipSuccess) return e;
     if (I.n_counted > 0) {
-        v.nchunks = (B + kScatterChunk - 1) / kScatterChunk;
-        v.items = (int64_t)I.n_counted * v.nchunks;
+        v.n_counted = I.n_counted;
+        v.items = (int64_t)((I.n_counted + v.cpw - 1) / v.cpw) * v.wchunks;
         e = for_launch_chunks(v.items, [&](int64_t first, int64_t count) {
             v.item0 = first;
             hipLaunchKernelGGL(violation_count_kernel, grid_for_waves(count), dim3(kBlock), 0, s, v);

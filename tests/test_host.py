@@ -161,7 +161,11 @@ def test_shape_overrides_and_tiles():
     assert shape_of(150) == (16, 16)
     J, S = shape_of(700)
     assert J * S >= 700                               # past the last override: default model
-    for bad in ([(10, 2, 8)], [(64, 3, 32)], [(64, 4, 13)], [(100, 2, 32)], [(64, 4, 16), (64, 8, 8)]):
+    # segments of 4 and 6 literals are accepted, 2 is not
+    H4 = afsat.Instance(3000, con_off, lits, types, params, device=-1, shapes=[(32, 8, 4), (48, 8, 6)])
+    assert {(b.lanes_per_restart, b.lits_per_lane) for b in H4.buckets() if b.k_lo == 20} == {(8, 4)}
+    for bad in ([(10, 2, 8)], [(64, 3, 32)], [(64, 4, 13)], [(100, 2, 32)], [(64, 4, 16), (64, 8, 8)],
+                [(32, 16, 2)]):
         with pytest.raises(afsat.AfsError) as e:
             afsat.Instance(3000, con_off, lits, types, params, device=-1, shapes=bad)
         assert e.value.status == afsat.AFS_EINVAL

@@ -296,11 +296,12 @@ def test_verify_bit_exact():
     assert np.array_equal(bits.cpu().numpy().view(np.uint32), want_bits)
 
 
-@pytest.mark.parametrize("B", [1, 33, 2100])
+@pytest.mark.parametrize("B", [1, 33, 256, 2100])
 def test_verify_word_layouts_and_parameters(B):
     """Restart counts that leave a partial 32-restart word, one word per lane group
-    (B = 33) and more than 64 words (B = 2100); lengths up to the maximum 1024;
-    parameters outside 0..k (negative, k+1, huge) as well as inside."""
+    (B = 33), eight words (B = 256: eight constraints per wave) and more than 64
+    words (B = 2100); lengths up to the maximum 1024; parameters outside 0..k
+    (negative, k+1, huge) as well as inside."""
     rng = np.random.default_rng(B)
     n = 1100
     parts = [W.random_instance(rng, n=n, count=60, k_lo=1, k_hi=12),

@@ -32,6 +32,8 @@ static bool check_packed(int it, const afs::HostInstance &H)
         CHECK(b.c0 == c_next && b.slot0 == s_next, "buckets are not contiguous");
         CHECK(b.J == 1 ? (b.S == b.k_lo && b.k_lo == b.k_hi) : (int64_t)b.J * b.S >= b.k_hi, "bucket shape");
         CHECK(b.tile >= 1 && (int64_t)b.ntiles * b.tile >= b.nc, "bucket tiles");
+        CHECK(b.rpl == 0 || b.rpl == 1 || b.rpl == 2 || (b.rpl == 4 && b.J == 1 && b.S <= 8), "bucket restarts per lane");
+        CHECK(b.J == 1 || b.rpl == 0, "restarts per lane on a segment bucket");
         for (int32_t c = b.c0; c < b.c0 + b.nc; ++c) {
             const int32_t o = H.bc_orig[c];
             CHECK(o >= 0 && o < H.C, "constraint index");
@@ -109,19 +111,27 @@ int main(int argc, char **argv)
         if (rng() % 3 == 0) {
             int kh = afs::kShortMax;
             const int nb = 1 + (int)(rng() % 4);
+            const bool tiles = rng() % 2;
             for (int b = 0; b < nb; ++b) {
                 const int J = 1 << (1 + (int)(rng() % 6));
-                const int S = 8 + 2 * (int)(rng() % 13);
+                const int S = afs::kMinSeg + 2 * (int)(rng() % ((afs::kMaxSeg - afs::kMinSeg) / 2 + 1));
                 const int next = std::min(J * S, kh + 1 + (int)(rng() % 300));
                 if (next <= kh) break;
                 kh = next;
                 o.k_hi.push_back(kh);
                 o.lanes.push_back(J);
                 o.seg.push_back(S);
+                if (tiles) o.tile.push_back((int)(rng() % 17));
             }
         }
         if (rng() % 4 == 0) o.tile_short = 1 + (int)(rng() % 64);
         if (rng() % 4 == 0) o.tile_long = 1 + (int)(rng() % 64);
+        if (rng() % 3 == 0)
+            for (int k = 1; k <= afs::kShortMax; ++k) {
+                o.short_tile[k] = (int)(rng() % 20);
+                const int r = (int)(rng() % 4);
+                o.short_rpl[k] = r == 3 ? (k <= 8 ? 4 : 2) : r;      // 0, 1, 2, or 4 where allowed
+            }
         if (!afs::check_options(o).empty()) {
             ++rejected;
             continue;

@@ -378,8 +378,23 @@ __device__ __forceinline__ void fetch_points(const FeArgs &A, int c, int base, i
     }
 }
 
+// Minimum resident waves per SIMD asked of the compiler for a segment length.
+// Left to itself it gives segments of 22 literals 155 VGPRs (three waves) and
+// of 26 to 32 literals 177 to 215 (two waves).  Asked for one wave more, it
+// fits 22 in 128 VGPRs and 26 to 32 in 168, spilling 28 bytes per lane for 22,
+// none for 26 and 28, 32 for 30 and 264 for 32, and the kernels still run
+// faster: the segment of 32 by about a tenth.  The same request for 24 (four
+// waves) or for 16 to 20 (five) loses.  J = 64 is left alone.
+constexpr int seg_min_waves(int J, int S)
+{
+    if (J > 32) return 1;
+    if (S == 22) return 4;
+    if (S >= 26) return 3;
+    return 1;
+}
+
 template <int J, int S, bool GRAD>
-__global__ __launch_bounds__(kBlock) void fe_grad_seg(FeArgs A, const float4 *__restrict__ T)
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(seg_min_waves(J, S)))) void fe_grad_seg(FeArgs A, const float4 *__restrict__ T)
 {
     static_assert(S % 2 == 0 && S >= 4 && S <= 32, "segment length must be even, 4 to 32");
     constexpr int R = kWave / J;

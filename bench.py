@@ -259,6 +259,8 @@ def main():
                     help="use the default kernel shapes instead of the tuned ones")
     ap.add_argument("--shapes-cache", default=None,
                     help="tuned-shape cache to read (default: the package's tuned_shapes.txt)")
+    ap.add_argument("--tune-tiles", action="store_true",
+                    help="also tune work tiles and one-lane restarts per lane (slower iterations on mixed lengths)")
     ap.add_argument("--tune-max-cons", type=int, default=400,
                     help="constraints of a length range timed by the tuner when a range is not cached (0: all)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -334,7 +336,8 @@ def throughput(args, name, W, probes):
         out = args.tune_out or os.path.join(tempfile.gettempdir(), "afsat_tuned_shapes.txt")
         os.makedirs(os.path.dirname(os.path.abspath(out)), exist_ok=True)
         shapes, _ = autotune.tune(inst, B, cache_path=args.shapes_cache or autotune.DEFAULT_CACHE, out_path=out,
-                                  log=lambda m: print(m, file=sys.stderr, flush=True), max_cons=args.tune_max_cons)
+                                  log=lambda m: print(m, file=sys.stderr, flush=True), max_cons=args.tune_max_cons,
+                                  tiles=args.tune_tiles)
     if parts is not None:
         d = afsat.Instance.batch(parts, device=0, shapes=shapes)
     else:

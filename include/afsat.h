@@ -423,26 +423,33 @@ afs_status afs_pgd(afs_instance *inst, int32_t B, float *x, const afs_pgd_params
  * most max_cons (<= 0: all; one-lane lengths: at least 65,536) -- are packed alone
  * once per candidate and their FE+gradient pass at B restarts is timed on
  * `device` (median of reps launches after one warm-up, HIP events on a private
- * stream).  First the fastest shape with J*S >= the range's upper length (long) or
- * restarts per lane in {4 (k <= 8), 2, 1} dividing B (short) at the default tile
- * wins; then tiles of 1, 2, 4, 8 and 16 constraints are timed for it, and one
- * other than the default must be 2% faster to replace it.
+ * stream).  The fastest shape with J*S >= the range's upper length at the default
+ * tile wins.  With tiles != 0 a second stage follows: for one-lane lengths the
+ * restarts per lane in {4 (k <= 8), 2, 1} dividing B are timed, then tiles of 1,
+ * 2, 4, 8 and 16 constraints for the configuration, and one other than the
+ * default must be 2% faster to replace it.  With tiles == 0 (the recommended
+ * setting for iterations of mixed lengths, where the short buckets run beside the
+ * long ones and configurations chosen by their time alone made iterations
+ * slower) one-lane lengths are not timed and get the defaults, and every range
+ * reports tile 0 and rpl 0 (the defaults).
  *   cache_in, cache_out: text files (either may be NULL) with one line per
  *     result, "<arch> <revision> <B> <k_lo> <k_hi> <class> <lanes> <seg> <tile>
  *     <rpl> <ms> <timed>", where class = floor(log2(constraints of the instance
  *     in the range)) (a range of a few constraints and one of thousands are
- *     tuned apart); results found in either are reused, and cache_out is
- *     rewritten with them plus the new ones, keeping only the current kernel
- *     revision.
+ *     tuned apart) and tile 0 marks a shape-only result; results found in either
+ *     are reused (cache_in's where both hold one for the same key; with tiles !=
+ *     0 only results with a tile), and cache_out is rewritten with them plus the
+ *     new ones, keeping only the current kernel revision.
  *   k_lo, k_hi, lanes, seg: host int32 [max_ranges] (lanes 1 and seg k for a
- *     one-lane length); tile, rpl: host int32 [max_ranges] or NULL (rpl 0 for
- *     segment shapes); ms: host float [max_ranges] or NULL (the winner's median,
- *     -1 when it came from a cache); *n_ranges: the number of ranges the instance
- *     has (entries past max_ranges are not written).
+ *     one-lane length); tile, rpl: host int32 [max_ranges] or NULL (0: the
+ *     default; rpl 0 for segment shapes); ms: host float [max_ranges] or NULL (the
+ *     winner's median, -1 when it came from a cache, 0 for a one-lane length left
+ *     at its defaults); *n_ranges: the number of ranges the instance has (entries
+ *     past max_ranges are not written).
  * Allocates device memory, synchronises `device`, and restores the caller's
  * current device. */
 afs_status afs_autotune(const afs_instance *inst, int32_t device, int32_t B, int32_t reps, int32_t max_cons,
-                        const char *cache_in, const char *cache_out, int32_t max_ranges, int32_t *k_lo,
+                        int32_t tiles, const char *cache_in, const char *cache_out, int32_t max_ranges, int32_t *k_lo,
                         int32_t *k_hi, int32_t *lanes, int32_t *seg, int32_t *tile, int32_t *rpl, float *ms,
                         int32_t *n_ranges);
 

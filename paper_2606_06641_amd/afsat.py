@@ -109,7 +109,7 @@ SIGNATURES = [
                                       ctypes.POINTER(_PgdState), _vp]),
     ("afs_pgd", ctypes.c_int, [_vp, _i32, _vp, ctypes.POINTER(_PgdParams), _vp, ctypes.c_size_t,
                                ctypes.POINTER(_PgdState), _vp, ctypes.POINTER(_i32), _vp]),
-    ("afs_autotune", ctypes.c_int, [_vp, _i32, _i32, _i32, _i32, ctypes.c_char_p, ctypes.c_char_p, _i32,
+    ("afs_autotune", ctypes.c_int, [_vp, _i32, _i32, _i32, _i32, _i32, ctypes.c_char_p, ctypes.c_char_p, _i32,
                                     _i32p, _i32p, _i32p, _i32p, _i32p, _i32p, ctypes.POINTER(ctypes.c_float),
                                     ctypes.POINTER(_i32)]),
     ("afs_parse_text", ctypes.c_int, [ctypes.c_char_p, ctypes.c_size_t, ctypes.POINTER(_vp)]),

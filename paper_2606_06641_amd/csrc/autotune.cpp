@@ -1,21 +1,28 @@
 // autotune.cpp -- on-device choice of the FE kernel configuration for each
 // length range of an instance: the segment-kernel shape (J lanes per restart x S
-// literals per lane) and work-tile size for lengths above 16, and the restarts per
-// lane and work-tile size of the one-lane kernel for each length up to 16.
+// literals per lane) for lengths above 16 and, on request, the work-tile size of
+// every range and the restarts per lane of the one-lane kernel for each length
+// up to 16.
 //
 // For each range (every length <= 16 alone; above, the ranges between
 // consecutive candidate capacities J*S) the constraints of the instance in that
 // range (an evenly spaced sample of at most max_cons) are packed alone once per
 // candidate, and the FE+gradient pass of that bucket is timed on the device
-// (median of `reps` launches, HIP events on a private stream).  Two stages: the
-// fastest shape (long) or restarts per lane (short) at the default tile, then the
-// tile sizes for it; a tile other than the default must win by 2% (the medians of
-// neighbouring tiles are often within noise).  Results are cached in a text file
-// keyed by (GPU architecture, FE kernel source revision, restarts, range, size
-// class of the range's constraint count), one line per entry:
+// (median of `reps` launches, HIP events on a private stream).  The shape stage
+// takes the fastest shape at the default tile.  The optional second stage times
+// the one-lane kernel's restarts per lane and then the tile sizes of the chosen
+// configuration; a tile other than the default must win by 2% (the medians of
+// neighbouring tiles are often within noise).  That stage is off by default:
+// it ranks configurations by their time alone, and in an iteration the one-lane
+// and the short segment buckets run beside the long ones, where its choices
+// (more waves for the same work) made whole iterations slower.  Results are
+// cached in a text file keyed by (GPU architecture, FE kernel source revision,
+// restarts, range, size class of the range's constraint count), one line per
+// entry:
 //     <arch> <revision> <B> <k_lo> <k_hi> <class> <J> <S> <tile> <rpl> <median ms> <constraints timed>
-// so that other instances with about as many constraints in the same ranges reuse
-// them and a change to the kernels invalidates them.
+// (tile and rpl 0: the defaults, from a shape-only tuning), so that other
+// instances with about as many constraints in the same ranges reuse them and a
+// change to the kernels invalidates them.
 
 #include "afsat.h"
 
@@ -203,7 +210,7 @@ afs_status time_shape(const afs::HostInstance &H, const std::vector<int32_t> &co
 extern "C" {
 
 afs_status afs_autotune(const afs_instance *inst, int32_t device, int32_t B, int32_t reps, int32_t max_cons,
-                        const char *cache_in, const char *cache_out, int32_t max_ranges, int32_t *k_lo,
+                        int32_t tiles, const char *cache_in, const char *cache_out, int32_t max_ranges, int32_t *k_lo,
                         int32_t *k_hi, int32_t *lanes, int32_t *seg, int32_t *tile, int32_t *rpl, float *ms,
                         int32_t *n_ranges)
 {
@@ -225,9 +232,11 @@ afs_status afs_autotune(const afs_instance *inst, int32_t device, int32_t B, int
     arch = arch.substr(0, arch.find(':'));
     const std::string rev = AFS_FE_REV;
 
+    // cache_out first: where both files hold a result for one key, cache_in's,
+    // the one the caller names for reading, is the one used
     std::map<Key, Choice> cache;
-    read_cache(cache_in, cache);
     read_cache(cache_out, cache);
+    read_cache(cache_in, cache);
 
     // constraints per range
     std::vector<std::pair<int, int>> ranges = length_ranges();
@@ -272,8 +281,15 @@ afs_status afs_autotune(const afs_instance *inst, int32_t device, int32_t B, int
         Choice best;
         float reported = -1.0f;                                 // cached: not timed now
         auto it = cache.find(key);
-        if (it != cache.end()) {
+        // a shape-only entry (tile 0) does not answer a request for tiles
+        const bool hit = it != cache.end() && (!tiles || it->second.tile > 0);
+        if (!tiles && hi <= afs::kShortMax) {                   // one lane, defaults: nothing to time
+            best.J = 1;
+            best.S = hi;
+            reported = 0.0f;
+        } else if (hit) {
             best = it->second;
+            if (!tiles) best.tile = best.rpl = 0;
         } else {
             if ((st = prepare()) != AFS_OK) break;
             std::vector<int32_t> cons = members[r];
@@ -314,7 +330,7 @@ afs_status afs_autotune(const afs_instance *inst, int32_t device, int32_t B, int
             // then the tile for that configuration
             const Choice base = best;
             for (int tile : {1, 2, 4, 8, 16}) {
-                if (st != AFS_OK || tile == base.tile) continue;
+                if (!tiles || st != AFS_OK || tile == base.tile) continue;
                 Choice c = base;
                 c.tile = tile;
                 double t = 0.0;
@@ -322,6 +338,7 @@ afs_status afs_autotune(const afs_instance *inst, int32_t device, int32_t B, int
                 if (st == AFS_OK && t < 0.98 * best.ms) { best = c; best.ms = t; }
             }
             if (st != AFS_OK) break;
+            if (!tiles) best.tile = 0;                          // the default, whatever it is
             best.timed = (int)cons.size();
             cache[key] = best;
             reported = (float)best.ms;

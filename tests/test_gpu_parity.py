@@ -102,28 +102,36 @@ def test_every_segment_kernel_shape(J):
 
 def test_autotuner_shapes_are_valid_and_exact(tmp_path):
     """The tuned shapes cover their ranges, give results within the parity bar,
-    and the cache file round-trips: a second call finds every range cached."""
+    and the cache file round-trips: a second call finds every range cached.
+    With tiles the one-lane restarts per lane and every tile are tuned; without,
+    they stay at the defaults (0) and one-lane lengths are not timed."""
     from paper_2606_06641_amd import autotune
     rng = np.random.default_rng(21)
     inst = concat([W.random_instance(rng, n=800, count=6, k_lo=20, k_hi=150),
                    W.random_instance(rng, n=800, count=50, k_lo=2, k_hi=8)], n=800)
     cache = str(tmp_path / "shapes.txt")
-    shapes, report = autotune.tune(inst, 64, reps=2, log=log, out_path=cache)
+    shapes, report = autotune.tune(inst, 64, reps=2, log=log, out_path=cache, tiles=True)
     assert shapes and all((S == kh if J == 1 else J * S >= kh) for kh, J, S, _, _ in shapes)
     assert all(tile in (1, 2, 4, 8, 16) for _, _, _, tile, _ in shapes)
     assert all((rpl in (1, 2, 4) and 64 % rpl == 0) if J == 1 else rpl == 0 for _, J, _, _, rpl in shapes)
     assert [s[0] for s in shapes] == sorted(s[0] for s in shapes)
     lens = np.diff(inst.con_off)
     assert {kh for kh, J, _, _, _ in shapes if J == 1} == {int(k) for k in lens if k <= 16}
-    assert not any(r["cached"] for r in report)
-    shapes2, report2 = autotune.tune(inst, 64, reps=2, cache_path=cache)
+    assert not any(r["cached"] for r in report) and all(r["timed"] for r in report)
+    shapes2, report2 = autotune.tune(inst, 64, reps=2, cache_path=cache, tiles=True)
     assert shapes2 == shapes and all(r["cached"] for r in report2)
+    # shape only: the cached segment shapes at default tiles, one-lane lengths at
+    # their defaults and not timed
+    plain, report_p = autotune.tune(inst, 64, reps=2, cache_path=cache)
+    assert plain == [(kh, J, S, 0, 0) for kh, J, S, _, _ in shapes]
+    assert all(r["cached"] for r in report_p if r["shape"][0] != 1)
+    assert not any(r["cached"] or r["timed"] for r in report_p if r["shape"][0] == 1)
     # an instance with more constraints in the same ranges: a range is taken from
     # the cache exactly when its constraint count has the same floor(log2) (size
     # class) as in the first instance, else tuned anew
     big = concat([W.random_instance(np.random.default_rng(22), n=800, count=24, k_lo=20, k_hi=150),
                   W.random_instance(np.random.default_rng(23), n=800, count=200, k_lo=2, k_hi=8)], n=800)
-    _, report3 = autotune.tune(big, 64, reps=2, cache_path=cache)
+    _, report3 = autotune.tune(big, 64, reps=2, cache_path=cache, tiles=True)
     la, lb = np.diff(inst.con_off), np.diff(big.con_off)
     fresh = 0
     for r in report3:
@@ -133,13 +141,43 @@ def test_autotuner_shapes_are_valid_and_exact(tmp_path):
         assert r["cached"] == same, (r, ca, cb)
         fresh += not same
     assert fresh > 0
+    # a shape-only tuning writes tile 0 for its segment ranges and nothing for
+    # one-lane lengths; a later request for tiles tunes those ranges anew
+    cache_p = str(tmp_path / "plain.txt")
+    p1, r1 = autotune.tune(inst, 64, reps=2, out_path=cache_p)
+    assert all(t == 0 and rp == 0 for _, _, _, t, rp in p1)
+    assert all(r["timed"] for r in r1 if r["shape"][0] != 1)
+    rows = [l.split() for l in open(cache_p) if not l.startswith("#")]
+    assert rows and all(f[6] != "1" and f[8] == "0" and f[9] == "0" for f in rows)
+    _, r2 = autotune.tune(inst, 64, reps=2, cache_path=cache_p, tiles=True)
+    assert not any(r["cached"] for r in r2)
+    # where the file read and the file written both hold a range, the file read
+    # wins: a copy of the cache with every segment shape replaced by J = 64
+    def wide(k_hi):
+        S = max(4, -(-k_hi // 64))
+        return 64, S + S % 2
+    rows = [l.split() for l in open(cache) if not l.startswith("#")]
+    other = str(tmp_path / "other.txt")
+    with open(other, "w") as fh:
+        for f in rows:
+            if f[6] != "1":
+                f[6], f[7] = (str(v) for v in wide(int(f[4])))
+            fh.write(" ".join(f) + "\n")
+    want = {kh: wide(kh) for kh, J, _, _, _ in shapes if J != 1}
+    assert want and want != {kh: (J, S) for kh, J, S, _, _ in shapes if J != 1}
+    got, report4 = autotune.tune(inst, 64, reps=2, cache_path=other, out_path=cache)
+    assert all(r["cached"] for r in report4 if r["shape"][0] != 1)
+    assert {kh: (J, S) for kh, J, S, _, _ in got if J != 1} == want
     x = rng.uniform(-1, 1, size=(inst.n, 64)).astype(np.float32)
     d = afsat.Instance.from_arrays(inst, shapes=shapes)
     conf = {kh: (tile, rpl) for kh, J, _, tile, rpl in shapes if J == 1}
     for b in d.buckets():
         if b.lanes_per_restart == 1:
             assert (b.tile, b.rpl) == conf[b.k_lo]
-    parity.compare(inst, d, parity.gpu_eval(d, x), oracle.eval(inst, x, fe=True, adj=True, grad=True), "tuned")
+    orc = oracle.eval(inst, x, fe=True, adj=True, grad=True)
+    parity.compare(inst, d, parity.gpu_eval(d, x), orc, "tuned")
+    d = afsat.Instance.from_arrays(inst, shapes=got)
+    parity.compare(inst, d, parity.gpu_eval(d, x), orc, "J = 64 shapes from the file read")
 
 
 @pytest.mark.parametrize("rpl", [1, 2, 4])

@@ -100,6 +100,23 @@ def test_every_segment_kernel_shape(J):
         parity.compare(inst, d, gpu, orc, "J=%d S=%d" % (J, S))
 
 
+@pytest.mark.parametrize("J,S,tile", [(2, 12, 5), (4, 22, 4), (8, 26, 4), (8, 32, 2), (16, 14, 4), (32, 30, 2)])
+def test_segment_kernel_uneven_tiles(J, S, tile):
+    """Segment kernels with several constraints per work tile, the last tile
+    ragged (7 constraints of each of three lengths), through the shape option's
+    tile; B = 70 leaves a ragged last restart group."""
+    rng = np.random.default_rng(300 + J + S)
+    cap = J * S
+    ks = sorted({cap, cap - 3, max(17, cap // 2 + 1)})
+    inst = concat([W.random_instance(rng, n=1500, count=7, k_lo=k, k_hi=k) for k in ks], n=1500)
+    x = rng.uniform(-1, 1, size=(inst.n, 70)).astype(np.float32)
+    d = afsat.Instance.from_arrays(inst, shapes=[(cap, J, S, tile)])
+    assert all((b.lanes_per_restart, b.lits_per_lane, b.tile) == (J, S, tile) for b in d.buckets())
+    log("case: J=%d S=%d tile %d lengths %s" % (J, S, tile, ks))
+    parity.compare(inst, d, parity.gpu_eval(d, x), oracle.eval(inst, x, fe=True, adj=True, grad=True),
+                   "J=%d S=%d tile %d" % (J, S, tile))
+
+
 def test_autotuner_shapes_are_valid_and_exact(tmp_path):
     """The tuned shapes cover their ranges, give results within the parity bar,
     and the cache file round-trips: a second call finds every range cached.

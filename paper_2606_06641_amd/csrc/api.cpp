@@ -157,6 +157,7 @@ void release(afs_instance *I)
         if (I->stepped) (void)hipEventDestroy(I->stepped);
         if (I->verified) (void)hipEventDestroy(I->verified);
         if (I->verify) (void)hipStreamDestroy(I->verify);
+        if (I->counter_host) (void)hipHostFree(I->counter_host);
     }
     delete I;
 }
@@ -914,16 +915,20 @@ afs_status afs_pgd(afs_instance *I, int32_t B, float *x, const afs_pgd_params *p
     if (!I->drive) {
         hipStream_t dr = nullptr, vf = nullptr;
         hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+        void *pinned = nullptr;
         e = hipStreamCreateWithFlags(&dr, hipStreamNonBlocking);
         if (e == hipSuccess) e = hipStreamCreateWithFlags(&vf, hipStreamNonBlocking);
         for (int i = 0; i < 4 && e == hipSuccess; ++i) e = hipEventCreateWithFlags(&ev[i], hipEventDisableTiming);
+        if (e == hipSuccess) e = hipHostMalloc(&pinned, 4 * sizeof(int32_t), hipHostMallocDefault);
         if (e != hipSuccess) {
+            if (pinned) (void)hipHostFree(pinned);
             for (hipEvent_t x : ev)
                 if (x) (void)hipEventDestroy(x);
             if (vf) (void)hipStreamDestroy(vf);
             if (dr) (void)hipStreamDestroy(dr);
             return dev_fail(e, "driver streams");
         }
+        I->counter_host = static_cast<int32_t *>(pinned);
         I->drive_in = ev[0];
         I->drive_out = ev[1];
         I->stepped = ev[2];
@@ -952,9 +957,13 @@ afs_status afs_pgd(afs_instance *I, int32_t B, float *x, const afs_pgd_params *p
         if (result == AFS_OK && e2 != hipSuccess) return dev_fail(e2, "ordering the caller's stream");
         return result;
     };
+    // the counter comes back through the instance's pinned buffer, so the copy
+    // never writes into pageable memory (here: this call's stack)
     auto read_counter = [&](int32_t *host) {
-        hipError_t e2 = hipMemcpyAsync(host, P->counter, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, s);
+        hipError_t e2 = hipMemcpyAsync(I->counter_host, P->counter, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, s);
         if (e2 == hipSuccess) e2 = hipStreamSynchronize(s);
+        if (e2 == hipSuccess)
+            for (int i = 0; i < 4; ++i) host[i] = I->counter_host[i];
         return e2;
     };
     // one iteration: constant step (its verification overlapping the next

@@ -75,4 +75,6 @@ struct afs_instance {
     // the verification after the step, `verified` the next step after it.
     hipStream_t verify = nullptr;
     hipEvent_t stepped = nullptr, verified = nullptr;
+    // Pinned host copy of the driver's counter (four int32), read between blocks.
+    int32_t *counter_host = nullptr;
 };

@@ -143,9 +143,10 @@ afs_status afs_instance_create(int32_t n_vars, int32_t n_cons, const int64_t *co
  *       held per lane by the one-lane kernel (0: the default, 4 for k <= 8 and 1
  *       above; else 1, 2, or 4 for k <= 8).  A launch whose B or x (or adjoint
  *       seed) alignment does not allow the asked count uses 1.
- * Tiles and restarts per lane change only the time; a segment shape also
- * changes the order of the FP32 products, so results differ by rounding (within
- * the same error bounds). */
+ * Restarts per lane change only the time; tiles also change how the objective
+ * is split into partial sums, and a segment shape the order of the FP32
+ * products, so those results differ by rounding (within the same error
+ * bounds). */
 typedef struct {
     int32_t n_shapes;
     const int32_t *shape_k_hi;

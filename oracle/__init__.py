@@ -18,6 +18,9 @@ Functions follow the paper:
                   sufficient-decrease test along the projection arc, FP64.
   * ``fixed_columns`` -- the partial-assignment slices of Sec. 3.4 (the restarts
                   divided evenly among the rows of a fixed mask).
+  * ``pgd_momentum`` -- one of the other search algorithms Sec. 3.2 says can take
+                  PGD's place: projected gradient descent with heavy-ball
+                  momentum, FP64.
 """
 import ctypes
 import os
@@ -254,6 +257,40 @@ def _pgd_steps(inst, x0, lr, steps, fixed, delta, epsilon, nthreads):
         done[(done == 0) & (move < epsilon)] = 2
     obj = eval(inst, x, grad=False, nthreads=nthreads)["obj"]
     return {"x": x, "unsat": unsat, "first_sat": first, "obj": obj, "done": done}
+
+
+def pgd_momentum(inst, x0, lr, mu, steps, fixed=None, v0=None, nthreads=None):
+    """Projected gradient descent with heavy-ball momentum, FP64: per restart,
+    v_t = mu v_(t-1) + grad F(x_(t-1)) and x_t = clip(x_(t-1) - lr v_t, -1, 1),
+    with v_0 = ``v0`` (zero by default).  As in Algorithm 1 the point is rounded
+    and counted after every step, and a restart that verifies stops there (its x
+    and v no longer change); fixed variables (Sec. 3.4) keep x and v.  With
+    mu = 0 this is Algorithm 1 with constant step length.
+
+    Returns x, v, unsat, first_sat (-1: never verified; 0: the start point does),
+    done (1 verified) and the objective at the final point."""
+    x = np.array(x0, dtype=np.float64, copy=True)
+    n, B = x.shape
+    v = np.zeros((n, B)) if v0 is None else np.array(v0, dtype=np.float64, copy=True)
+    held_fixed = fixed_columns(fixed, n, B)
+    unsat = unsat_count(inst, x)
+    done = (unsat == 0).astype(np.uint8)
+    first = np.where(unsat == 0, 0, -1).astype(np.int32)
+    for t in range(1, steps + 1):
+        if done.all():
+            break
+        g = eval(inst, x, grad=True, nthreads=nthreads)["grad"]
+        hold = held_fixed | done.astype(bool)[None, :]
+        vn = mu * v + g
+        xn = np.clip(x - lr * vn, -1.0, 1.0)
+        v = np.where(hold, v, vn)
+        x = np.where(hold, x, xn)
+        unsat = unsat_count(inst, x)
+        newly = (done == 0) & (unsat == 0)
+        first[newly] = t
+        done[newly] = 1
+    obj = eval(inst, x, grad=False, nthreads=nthreads)["obj"]
+    return {"x": x, "v": v, "unsat": unsat, "first_sat": first, "done": done, "obj": obj}
 
 
 def unsat_count(inst, x):

@@ -243,3 +243,60 @@ def test_constant_step_first_sat_by_hand(steps):
     x2 = [min(1.0, 0.5 + 0.25 * min(steps, 4)), 1.0, -0.5 + 0.25 * min(steps, 2)]
     np.testing.assert_array_equal(r["x"], np.array([x1, x2]))
     np.testing.assert_array_equal(r["unsat"], [0 if f >= 0 else 1 for f in want_first])
+
+
+@pytest.mark.parametrize("steps", [0, 1, 2, 3, 6])
+def test_momentum_by_hand(steps):
+    """Heavy-ball momentum with lr = 1/4, mu = 1/2 on the clauses (x1), (not x2)
+    (gradient (1, -1) everywhere), in exact dyadic arithmetic.  Restart 0 from
+    (3/4, 1/2): v = (1, -1), (3/2, -3/2), (7/4, -7/4) and x1 = 1/2, 1/8, -5/16,
+    so it verifies at iteration 3; x2 reaches the bound 1 at iteration 2 and stays
+    there while its velocity keeps growing.  Restart 1 starts satisfied.
+    Restart 2 from (1/4, 1): x1 = 0 (False, the rounding tie) after one step and
+    -3/8 after two."""
+    x0 = np.array([[0.75, -1.0, 0.25],
+                   [0.5, 1.0, 1.0]])
+    r = oracle.pgd_momentum(UNITS2, x0, 0.25, 0.5, steps)
+    want_first = [3 if steps >= 3 else -1, 0, 2 if steps >= 2 else -1]
+    np.testing.assert_array_equal(r["first_sat"], want_first)
+    v0_traj = [0.0, 1.0, 1.5, 1.75]
+    x0_traj = [0.75, 0.5, 0.125, -0.3125]
+    x20_traj = [0.5, 0.75, 1.0, 1.0]
+    v2_traj = [0.0, 1.0, 1.5]
+    x2_traj = [0.25, 0.0, -0.375]
+    t0, t2 = min(steps, 3), min(steps, 2)
+    np.testing.assert_array_equal(r["x"], [[x0_traj[t0], -1.0, x2_traj[t2]],
+                                           [x20_traj[t0], 1.0, 1.0]])
+    np.testing.assert_array_equal(r["v"], [[v0_traj[t0], 0.0, v2_traj[t2]],
+                                           [-v0_traj[t0], 0.0, -v2_traj[t2]]])
+    np.testing.assert_array_equal(r["done"], [1 if f >= 0 else 0 for f in want_first])
+
+
+def test_momentum_holds_fixed_variables():
+    """A fixed variable keeps both its value and its velocity; the others move as
+    without it (here their gradients do not depend on it)."""
+    x0 = np.array([[0.75], [0.5]])
+    free = oracle.pgd_momentum(UNITS2, x0, 0.25, 0.5, 3)
+    held = oracle.pgd_momentum(UNITS2, x0, 0.25, 0.5, 3, fixed=np.array([0, 1], np.uint8))
+    assert held["x"][1, 0] == 0.5 and held["v"][1, 0] == 0.0
+    assert held["x"][0, 0] == free["x"][0, 0] and held["v"][0, 0] == free["v"][0, 0]
+    assert held["first_sat"][0] == free["first_sat"][0] == 3
+
+
+def test_momentum_zero_is_algorithm_1():
+    """mu = 0 is PGD with a constant step: the same points, counts and first
+    verifications as the C oracle's Algorithm 1 (exact FP64 equality), and the
+    velocity is the last gradient taken."""
+    rng = np.random.default_rng(77)
+    inst = workloads.random_instance(rng, n=60, count=80, k_lo=2, k_hi=9)
+    x0 = rng.uniform(-1, 1, size=(inst.n, 12))
+    for steps in (1, 4, 15):
+        a = oracle.pgd_momentum(inst, x0, 0.1, 0.0, steps)
+        b = oracle.pgd(inst, x0, 0.1, steps)
+        np.testing.assert_array_equal(a["x"], b["x"])
+        np.testing.assert_array_equal(a["unsat"], b["unsat"])
+        np.testing.assert_array_equal(a["first_sat"], b["first_sat"])
+    one = oracle.pgd_momentum(inst, x0, 0.1, 0.9, 1)
+    g = oracle.eval(inst, x0, grad=True)["grad"]
+    running = one["first_sat"] != 0
+    np.testing.assert_array_equal(one["v"][:, running], g[:, running])

@@ -331,6 +331,20 @@ afs_status afs_pgd_update(afs_instance *inst, int32_t B, float *x, float lr, con
                           int32_t n_partial, void *ws, size_t ws_bytes, const afs_pgd_state *st,
                           void *stream);
 
+/* One iteration of another search algorithm in PGD's place (Sec. 3.2 allows
+ * other algorithms with compatible implementations; this one is projected
+ * gradient descent with heavy-ball momentum): with g the gradient at X_(t-1),
+ * v <- mu v + g and X_(t) = clip(X_(t-1) - lr v, -1, 1), then rounding, the exact
+ * unsat count and the state update as afs_pgd_step.  Done restarts and fixed
+ * variables keep both x and v.
+ *   vel: device f32 [n][B], the velocity, caller-owned and updated in place
+ *     (zero it before the first step); mu in [0, 1) (mu = 0 gives afs_pgd_step).
+ * Same launches every call, so it may be captured in a graph like
+ * afs_pgd_step.  AFS_EINVAL for a NULL vel (B > 0) or mu outside [0, 1). */
+afs_status afs_pgd_step_momentum(afs_instance *inst, int32_t B, float *x, float *vel, float lr, float mu,
+                                 const uint8_t *fixed, int32_t n_partial, void *ws, size_t ws_bytes,
+                                 const afs_pgd_state *st, void *stream);
+
 /* Backtracking line search (Algorithm 1's lineSearch with maximum step s;
  * Sec. 3.3: each restart picks its own step length).  Per restart: f0 = F(x) and
  * g = grad F(x); trial j = 0..trials-1 takes eta = max_step * shrink^j and

@@ -107,6 +107,8 @@ SIGNATURES = [
                                     ctypes.POINTER(_PgdState), _vp]),
     ("afs_pgd_update", ctypes.c_int, [_vp, _i32, _vp, ctypes.c_float, _vp, _i32, _vp, ctypes.c_size_t,
                                       ctypes.POINTER(_PgdState), _vp]),
+    ("afs_pgd_step_momentum", ctypes.c_int, [_vp, _i32, _vp, _vp, ctypes.c_float, ctypes.c_float, _vp, _i32, _vp,
+                                             ctypes.c_size_t, ctypes.POINTER(_PgdState), _vp]),
     ("afs_pgd", ctypes.c_int, [_vp, _i32, _vp, ctypes.POINTER(_PgdParams), _vp, ctypes.c_size_t,
                                ctypes.POINTER(_PgdState), _vp, ctypes.POINTER(_i32), _vp]),
     ("afs_autotune", ctypes.c_int, [_vp, _i32, _i32, _i32, _i32, _i32, ctypes.c_char_p, ctypes.c_char_p, _i32,
@@ -525,6 +527,20 @@ class Instance:
         fp, rows = self._fixed(fixed)
         _check(lib().afs_pgd_update(self._h, B, _ptr(x), float(lr), fp, rows, _ptr(ws), ws.numel(),
                                     ctypes.byref(s), _stream(self._dev())))
+
+    def pgd_step_momentum(self, x, vel, st, lr, mu, fixed=None, ws=None):
+        """One iteration of projected gradient descent with heavy-ball momentum
+        (afs_pgd_step_momentum): vel <- mu vel + grad, x <- clip(x - lr vel), then
+        the exact count and the state update.  vel: float32 CUDA (n, B), zero
+        before the first step, updated in place."""
+        B = self._check_x(x)
+        if self._check_x(vel, "vel") != B:
+            raise ValueError("vel must have the shape of x")
+        ws = self.workspace(B) if ws is None else ws
+        s = self._state_struct(st)
+        fp, rows = self._fixed(fixed)
+        _check(lib().afs_pgd_step_momentum(self._h, B, _ptr(x), _ptr(vel), float(lr), float(mu), fp, rows,
+                                           _ptr(ws), ws.numel(), ctypes.byref(s), _stream(self._dev())))
 
     @staticmethod
     def _search(search):

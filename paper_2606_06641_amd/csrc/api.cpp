@@ -724,7 +724,8 @@ afs_status afs_pgd_init(afs_instance *I, int32_t B, const float *x, void *ws, si
 }
 
 static afs_status pgd_call(afs_instance *I, int32_t B, float *x, float lr, const uint8_t *fixed, int32_t n_partial,
-                           float delta, void *ws, size_t ws_bytes, const afs_pgd_state *P, void *stream, bool with_fe)
+                           float delta, void *ws, size_t ws_bytes, const afs_pgd_state *P, void *stream, bool with_fe,
+                           float *vel = nullptr, float mu = 0.0f)
 {
     afs_status st = check_call(I, B);
     if (st != AFS_OK) return st;
@@ -742,7 +743,8 @@ static afs_status pgd_call(afs_instance *I, int32_t B, float *x, float lr, const
     }
     uint32_t *bits = at<uint32_t>(ws, l.bits);
     hipError_t e = afs::launch_scatter_step(I->D, B, l.Bp, at<float>(ws, l.adj), x, lr, fixed,
-                                            partial_rows(n_partial), P->done, bits, P->unsat, s);
+                                            partial_rows(n_partial), P->done, bits, P->unsat, s, nullptr, 0.0f,
+                                            vel, mu);
     if (e == hipSuccess) e = afs::launch_verify(I->D, B, bits, at<uint32_t>(ws, l.viol), P->unsat, s);
     if (e == hipSuccess)
         e = afs::launch_finalize(I->H.n_inst * B, B, P->unsat, P->done, P->first_sat, P->counter, afs::FIN_STEP, s,
@@ -760,6 +762,15 @@ afs_status afs_pgd_update(afs_instance *I, int32_t B, float *x, float lr, const 
                           void *ws, size_t ws_bytes, const afs_pgd_state *P, void *stream)
 {
     return pgd_call(I, B, x, lr, fixed, n_partial, 0.0f, ws, ws_bytes, P, stream, false);
+}
+
+afs_status afs_pgd_step_momentum(afs_instance *I, int32_t B, float *x, float *vel, float lr, float mu,
+                                 const uint8_t *fixed, int32_t n_partial, void *ws, size_t ws_bytes,
+                                 const afs_pgd_state *P, void *stream)
+{
+    if (B > 0 && !vel) return fail(AFS_EINVAL, "vel is NULL");
+    if (!(mu >= 0.0f && mu < 1.0f)) return fail(AFS_EINVAL, "mu must lie in [0, 1)");
+    return pgd_call(I, B, x, lr, fixed, n_partial, 0.0f, ws, ws_bytes, P, stream, true, vel, mu);
 }
 
 static afs_status check_search(const afs_line_search *ls)

@@ -56,10 +56,12 @@ hipError_t launch_scatter(const DevInstance &I, int B, int Bp, const float *adj,
 // Per-(sub-instance, restart) arrays (unsat, done, first_sat) are [n_inst][B].
 // Fused: gradient sum, projected step, rounding into bits [n][W] and unsat = 0.
 // fixed [n_partial][n]: restart b uses row b * n_partial / B (nullptr: none fixed).
+// vel [n][B] (nullptr: plain step): heavy-ball velocity, v = mu v + g, and the
+// step follows v.
 hipError_t launch_scatter_step(const DevInstance &I, int B, int Bp, const float *adj, float *x,
                                float lr, const uint8_t *fixed, int n_partial, const uint8_t *done,
                                uint32_t *bits, int32_t *unsat, hipStream_t s, uint8_t *moved = nullptr,
-                               float eps = 0.0f);
+                               float eps = 0.0f, float *vel = nullptr, float mu = 0.0f);
 
 // obj[b] = sum over tiles of part[t][b] (two fixed-order passes through part2).
 hipError_t launch_obj_reduce(int tiles, int B, int Bp, const float *part, float *part2,

@@ -37,7 +37,8 @@ struct ScatterArgs {
     uint32_t *bits;
     int32_t *unsat;
     uint8_t *moved;              // [n_inst][B]: set where some variable moves by >= eps (NULL: not tracked)
-    float lr, eps;
+    float *vel;                  // [n][B] heavy-ball velocity (NULL: plain step)
+    float lr, eps, mu;
     int B, Bp, W, nchunks;
     int64_t items, item0;        // all items; first item of this launch
 };
@@ -160,7 +161,12 @@ __global__ __launch_bounds__(kBlock) void scatter_step_kernel(ScatterArgs A)
             float xv = A.x[at];
             if (!is_fixed(A.fixed, A.n_partial, A.n, A.B, v, b) && !(done && done[b])) {
                 const float x0 = xv;
-                xv = project_step(xv, elem(g, e), A.lr);
+                float d = elem(g, e);
+                if (A.vel) {                            // v = mu v + g, and the step follows v
+                    d = fmaf(A.mu, A.vel[at], d);
+                    A.vel[at] = d;
+                }
+                xv = project_step(xv, d, A.lr);
                 A.x[at] = xv;
                 // several variables may store 1 into one flag: every store writes the same value
                 if (A.moved && fabsf(xv - x0) >= A.eps) A.moved[(int64_t)A.var_inst[v] * A.B + b] = 1;
@@ -594,12 +600,13 @@ hipError_t launch_scatter(const DevInstance &I, int B, int Bp, const float *adj,
 
 hipError_t launch_scatter_step(const DevInstance &I, int B, int Bp, const float *adj, float *x,
                                float lr, const uint8_t *fixed, int n_partial, const uint8_t *done,
-                               uint32_t *bits, int32_t *unsat, hipStream_t s, uint8_t *moved, float eps)
+                               uint32_t *bits, int32_t *unsat, hipStream_t s, uint8_t *moved, float eps,
+                               float *vel, float mu)
 {
     if (B == 0) return hipSuccess;
     ScatterArgs a = scatter_args(I, B, Bp, adj);
     a.x = x; a.lr = lr; a.fixed = fixed; a.done = done; a.bits = bits; a.unsat = unsat;
-    a.moved = moved; a.eps = eps;
+    a.moved = moved; a.eps = eps; a.vel = vel; a.mu = mu;
     a.n = I.n; a.n_partial = n_partial;
     return for_launch_chunks(a.items, [&](int64_t first, int64_t count) {
         a.item0 = first;

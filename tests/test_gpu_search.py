@@ -444,3 +444,74 @@ def test_epsilon_is_validated():
     for bad in (-1.0, float("nan"), float("inf")):
         with pytest.raises(afsat.AfsError):
             d.pgd(x, 0.1, 3, epsilon=bad)
+
+
+@pytest.mark.parametrize("mu", [0.0, 0.5, 0.9])
+def test_momentum_steps_match_the_oracle(mu):
+    """Heavy-ball momentum steps (afs_pgd_step_momentum) against the FP64 oracle
+    over 4 iterations on a mixed instance, with partial-assignment rows: points
+    and velocities agree within FP32 drift, held entries never move, the state is
+    the exact verification of the GPU's own points, and mu = 0 is afs_pgd_step
+    bit for bit."""
+    inst, _ = mixed(71)
+    d = afsat.Instance.from_arrays(inst)
+    B = 70
+    rng = np.random.default_rng(72)
+    x0 = rng.uniform(-1, 1, size=(inst.n, B)).astype(np.float32)
+    fixed = (rng.random((2, inst.n)) < 0.2).astype(np.uint8)
+    log("case: momentum mu=%g n=%d B=%d" % (mu, inst.n, B))
+    xd, vd = parity.to_dev(x0), torch.zeros(inst.n, B, dtype=torch.float32, device="cuda")
+    st = d.pgd_state(B)
+    d.pgd_init(xd, st)
+    fd = torch.from_numpy(fixed).cuda()
+    for _ in range(4):
+        d.pgd_step_momentum(xd, vd, st, 0.05, mu, fixed=fd)
+    torch.cuda.synchronize()
+    want = oracle.pgd_momentum(inst, x0.astype(np.float64), 0.05, mu, 4, fixed=fixed)
+    xs, vs = xd.cpu().numpy(), vd.cpu().numpy()
+    np.testing.assert_allclose(xs, want["x"], rtol=0, atol=1e-5)
+    np.testing.assert_allclose(vs, want["v"], rtol=0, atol=1e-4 * max(1.0, float(np.abs(want["v"]).max())))
+    held = oracle.fixed_columns(fixed, inst.n, B)
+    assert np.array_equal(xs[held], x0[held]) and not vs[held].any()
+    assert np.array_equal(st["unsat"].cpu().numpy(), oracle.verify(inst, xs))
+    if mu == 0.0:
+        xb = parity.to_dev(x0)
+        sb = d.pgd_state(B)
+        d.pgd_init(xb, sb)
+        for _ in range(4):
+            d.pgd_step(xb, sb, 0.05, fixed=fd)
+        torch.cuda.synchronize()
+        assert torch.equal(xb, xd)
+
+
+def test_momentum_freezes_verified_restarts_and_rejects_bad_arguments():
+    """Restarts that verify stop (x and v unchanged afterwards, first_sat as the
+    oracle's on an easy planted instance), and invalid mu or a missing velocity
+    are refused before any launch."""
+    inst = W.planted_3sat(n=100, m=300, instance=5)
+    d = afsat.Instance.from_arrays(inst)
+    B = 32
+    x0 = W.uniform_x0(inst.n, B, workload=1, instance=5)
+    xd, vd = parity.to_dev(x0), torch.zeros(inst.n, B, dtype=torch.float32, device="cuda")
+    st = d.pgd_state(B)
+    d.pgd_init(xd, st)
+    snaps = []
+    for _ in range(60):
+        d.pgd_step_momentum(xd, vd, st, 0.05, 0.8)
+        snaps.append((xd.clone(), vd.clone(), st["done"].clone()))
+    torch.cuda.synchronize()
+    done = st["done"].cpu().numpy().astype(bool)
+    first = st["first_sat"].cpu().numpy()
+    assert done.any()
+    for t, (xt, vt, dt) in enumerate(snaps):
+        was = dt.cpu().numpy().astype(bool)
+        assert torch.equal(xt[:, torch.from_numpy(was).cuda()], xd[:, torch.from_numpy(was).cuda()])
+        assert torch.equal(vt[:, torch.from_numpy(was).cuda()], vd[:, torch.from_numpy(was).cuda()])
+    assert np.all(oracle.verify(inst, xd.cpu().numpy()[:, done]) == 0)
+    assert np.all((first >= 0) == done)
+    with pytest.raises(afsat.AfsError):
+        d.pgd_step_momentum(xd, vd, st, 0.05, 1.0)
+    with pytest.raises(afsat.AfsError):
+        d.pgd_step_momentum(xd, vd, st, 0.05, -0.1)
+    with pytest.raises(ValueError):
+        d.pgd_step_momentum(xd, vd[:, :5].contiguous(), st, 0.05, 0.5)

@@ -76,6 +76,8 @@ def main(argv=None, out=None):
     ap.add_argument("--shrink", type=float, default=0.5, help="line search: factor between trials")
     ap.add_argument("--armijo", type=float, default=1e-4, help="line search: sufficient-decrease constant")
     ap.add_argument("--trials", type=int, default=8, help="line search: trials per iteration")
+    ap.add_argument("--momentum", type=float, default=0.0, metavar="MU",
+                    help="heavy-ball momentum in [0, 1) instead of plain PGD (steps taken one call at a time)")
     ap.add_argument("--delta", type=float, default=0.0, help="stop a restart once its step length < delta")
     ap.add_argument("--epsilon", type=float, default=0.0,
                     help="stop a restart once no variable of it moves by epsilon or more in an iteration")
@@ -90,6 +92,10 @@ def main(argv=None, out=None):
                     help="when no restart verifies, print the best restart's assignment (best effort, "
                          "with its unsatisfied-constraint count on an 'o' line)")
     a = ap.parse_args(argv)
+    if a.momentum and (a.line_search or a.delta or a.epsilon):
+        raise SystemExit("--momentum takes a constant step (no --line-search, --delta or --epsilon)")
+    if not 0.0 <= a.momentum < 1.0:
+        raise SystemExit("--momentum must lie in [0, 1)")
 
     t0 = time.perf_counter()
     try:
@@ -129,8 +135,11 @@ def main(argv=None, out=None):
     x = inst.init_points(B, a.seed, vd if fixed is not None else None)
     search = afsat.LineSearch(a.max_step, a.shrink, a.armijo, a.trials) if a.line_search else None
     t1 = time.perf_counter()
-    st = inst.pgd(x, a.lr, a.iters, fixed=fixed, poll=a.poll, stop_on_sat=True, graph=not a.no_graph,
-                  search=search, delta=a.delta, epsilon=a.epsilon)
+    if a.momentum:
+        st = momentum_search(inst, x, a.lr, a.momentum, a.iters, fixed, a.poll)
+    else:
+        st = inst.pgd(x, a.lr, a.iters, fixed=fixed, poll=a.poll, stop_on_sat=True, graph=not a.no_graph,
+                      search=search, delta=a.delta, epsilon=a.epsilon)
     torch.cuda.synchronize(dev)
     dt = time.perf_counter() - t1
     unsat = st["unsat"].cpu().numpy()
@@ -163,6 +172,24 @@ def main(argv=None, out=None):
         for line in assignment_lines((x[:p.n, b] < 0).cpu().numpy()):
             print(line, file=out)
     return 0
+
+
+def momentum_search(inst, x, lr, mu, iters, fixed, poll):
+    """Heavy-ball momentum steps (afs_pgd_step_momentum) until a restart verifies
+    (checked every `poll` iterations) or `iters` are done; returns the state as
+    Instance.pgd does."""
+    B = x.shape[1]
+    st = inst.pgd_state(B)
+    inst.pgd_init(x, st)
+    vel = torch.zeros_like(x)
+    t = 0
+    while t < iters and int(st["counter"][1]) == 0:
+        for _ in range(min(poll, iters - t)):
+            inst.pgd_step_momentum(x, vel, st, lr, mu, fixed=fixed)
+        t += min(poll, iters - t)
+    st["x"] = x
+    st["iters"] = int(st["counter"][0])
+    return st
 
 
 def input_unsat(p, xb, device):

@@ -39,6 +39,15 @@ def run(args):
     return rc, buf.getvalue()
 
 
+def test_momentum_options_are_checked_first(tmp_path):
+    f = tmp_path / "u.cnf"
+    f.write_text("p cnf 2 1\n1 2 0\n")
+    for bad in (["--momentum", "0.5", "--line-search"], ["--momentum", "0.5", "--delta", "0.1"],
+                ["--momentum", "1.0"], ["--momentum", "-0.2"]):
+        with pytest.raises(SystemExit):
+            run([str(f)] + bad)
+
+
 def test_read_partials(tmp_path):
     f = tmp_path / "p.txt"
     f.write_text("c two assignments\n1 -3 0\n\n2 0\n")
@@ -65,7 +74,7 @@ def test_units_alone_satisfy_without_a_search(tmp_path):
 
 
 @pytest.mark.gpu
-@pytest.mark.parametrize("extra", [[], ["--line-search", "--trials", "6"], ["--no-graph"]])
+@pytest.mark.parametrize("extra", [[], ["--line-search", "--trials", "6"], ["--no-graph"], ["--momentum", "0.5"]])
 def test_solves_a_planted_instance(tmp_path, extra):
     if not torch.cuda.is_available():
         pytest.skip("no GPU")

@@ -409,12 +409,18 @@ typedef struct {
                                restart that verifies in the same iteration counts as
                                verified.  Uses the flags at the end of the workspace,
                                which afs_pgd_init clears                                    */
+    float momentum;         /* > 0 (below 1): heavy-ball momentum in PGD's place, each
+                               iteration as afs_pgd_step_momentum; 0: plain steps. Not
+                               with the line search                                        */
+    float *velocity;        /* device f32 [n][B], the velocity (required with momentum;
+                               caller-owned, updated in place, zero it first)              */
 } afs_pgd_params;
 
 /* Algorithm 1 on the B columns of x (device f32 [n][B], updated in place to the
  * final point): afs_pgd_init, then up to max_iters iterations of afs_pgd_step
- * (constant step) or afs_pgd_search_step (line search), reading the device
- * counter every `poll` iterations (when stop_on_sat is set or delta or epsilon > 0) and
+ * (constant step), afs_pgd_search_step (line search) or afs_pgd_step_momentum
+ * (momentum > 0), reading the device counter every `poll` iterations (when
+ * stop_on_sat is set or delta or epsilon > 0) and
  * stopping when stop_on_sat is set and some (part, restart) has verified, or
  * when every (part, restart) has verified or converged.
  * On return st holds unsat / done / first_sat / counter as after those calls,

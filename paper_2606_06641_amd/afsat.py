@@ -64,7 +64,8 @@ class _PgdParams(ctypes.Structure):
                 ("stop_on_sat", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("fixed", ctypes.c_void_p),
                 ("n_partial", ctypes.c_int32), ("delta", ctypes.c_float),
                 ("search", ctypes.POINTER(_LineSearch)), ("search_ws", ctypes.c_void_p),
-                ("search_ws_bytes", ctypes.c_size_t), ("epsilon", ctypes.c_float)]
+                ("search_ws_bytes", ctypes.c_size_t), ("epsilon", ctypes.c_float),
+                ("momentum", ctypes.c_float), ("velocity", ctypes.c_void_p)]
 
 
 class _PgdState(ctypes.Structure):
@@ -563,14 +564,17 @@ class Instance:
                                          _stream(self._dev())))
 
     def pgd(self, x, lr, steps, fixed=None, poll=10, stop_on_sat=True, graph=True, obj=False, search=None,
-            delta=0.0, epsilon=0.0):
+            delta=0.0, epsilon=0.0, momentum=0.0, velocity=None):
         """Algorithm 1 on the columns of x (updated in place), run by the
         library's driver (afs_pgd): constant step ``lr``, or with ``search`` (a
         ``LineSearch`` or (max_step, shrink, armijo, trials)) the backtracking
         line search.  ``fixed``: u8/i8 (n,) or (n_partial, n) mask of held
         variables, the restarts divided evenly among its rows; ``delta`` > 0
         stops restarts whose step length falls below it, ``epsilon`` > 0 those
-        whose point moves less than it in every variable.
+        whose point moves less than it in every variable.  ``momentum`` > 0
+        takes heavy-ball momentum steps in PGD's place (afs_pgd_step_momentum);
+        ``velocity`` (float32 CUDA (n, B), zero by default) holds and returns the
+        velocity.
 
         Stops after ``steps`` iterations, or (``stop_on_sat``) once any restart
         verifies, or once every restart has verified or converged; the driver
@@ -585,11 +589,15 @@ class Instance:
         fp, rows = self._fixed(fixed)
         ls = self._search(search) if search is not None else None
         sws = self.search_workspace(B) if search is not None else None
+        if momentum and velocity is None:
+            velocity = torch.zeros_like(x)
+        if velocity is not None and self._check_x(velocity, "velocity") != B:
+            raise ValueError("velocity must have the shape of x")
         prm = _PgdParams(float(lr), int(steps), int(poll), int(bool(stop_on_sat)), int(bool(graph)),
                          None if fp is None else fp.value, int(rows), float(delta),
                          ctypes.pointer(ls) if ls is not None else None,
                          None if sws is None else sws.data_ptr(), 0 if sws is None else sws.numel(),
-                         float(epsilon))
+                         float(epsilon), float(momentum), None if velocity is None else velocity.data_ptr())
         s = self._state_struct(st)
         o = torch.empty(B, dtype=torch.float32, device=self._dev()) if obj else None
         iters = _i32(0)
@@ -597,6 +605,8 @@ class Instance:
                              _ptr(o), ctypes.byref(iters), _stream(self._dev())))
         st["x"] = x
         st["iters"] = int(iters.value)
+        if velocity is not None:
+            st["velocity"] = velocity
         if obj:
             st["obj"] = o
         return st

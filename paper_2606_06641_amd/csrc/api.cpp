@@ -888,9 +888,11 @@ static afs_status overlapped_step(afs_instance *I, int32_t B, float *x, const af
     hipError_t e = wait_prev ? hipStreamWaitEvent(s, I->verified, 0) : hipSuccess;
     uint32_t *bits = at<uint32_t>(ws, l.bits);
     uint8_t *moved = prm->epsilon > 0.0f ? at<uint8_t>(ws, l.moved) : nullptr;
+    float *vel = prm->momentum > 0.0f ? prm->velocity : nullptr;
     if (e == hipSuccess)
         e = afs::launch_scatter_step(I->D, B, l.Bp, at<float>(ws, l.adj), x, prm->lr, prm->fixed,
-                                     partial_rows(prm->n_partial), P->done, bits, P->unsat, s, moved, prm->epsilon);
+                                     partial_rows(prm->n_partial), P->done, bits, P->unsat, s, moved, prm->epsilon,
+                                     vel, prm->momentum);
     if (e == hipSuccess) e = hipEventRecord(I->stepped, s);
     if (e == hipSuccess) e = hipStreamWaitEvent(I->verify, I->stepped, 0);
     if (e == hipSuccess) e = afs::launch_verify(I->D, B, bits, at<uint32_t>(ws, l.viol), P->unsat, I->verify);
@@ -912,6 +914,9 @@ afs_status afs_pgd(afs_instance *I, int32_t B, float *x, const afs_pgd_params *p
         return fail(AFS_EINVAL, "delta and epsilon must be >= 0 (epsilon finite)");
     if (prm->search && (st = check_search(prm->search)) != AFS_OK) return st;
     if (prm->search && I->H.n_inst != 1) return fail(AFS_EINVAL, "the line search takes a plain instance, not a batch");
+    if (!(prm->momentum >= 0.0f && prm->momentum < 1.0f)) return fail(AFS_EINVAL, "momentum must lie in [0, 1)");
+    if (prm->momentum > 0.0f && prm->search) return fail(AFS_EINVAL, "momentum does not combine with the line search");
+    if (prm->momentum > 0.0f && B > 0 && !prm->velocity) return fail(AFS_EINVAL, "momentum needs a velocity array");
     if ((st = check_partial(B, prm->fixed, prm->n_partial)) != AFS_OK) return st;
     WsLayout l;
     if ((st = check_ws(I, B, ws, ws_bytes, l)) != AFS_OK) return st;

@@ -77,7 +77,7 @@ def main(argv=None, out=None):
     ap.add_argument("--armijo", type=float, default=1e-4, help="line search: sufficient-decrease constant")
     ap.add_argument("--trials", type=int, default=8, help="line search: trials per iteration")
     ap.add_argument("--momentum", type=float, default=0.0, metavar="MU",
-                    help="heavy-ball momentum in [0, 1) instead of plain PGD (steps taken one call at a time)")
+                    help="heavy-ball momentum in [0, 1) in place of plain PGD steps")
     ap.add_argument("--delta", type=float, default=0.0, help="stop a restart once its step length < delta")
     ap.add_argument("--epsilon", type=float, default=0.0,
                     help="stop a restart once no variable of it moves by epsilon or more in an iteration")
@@ -135,11 +135,8 @@ def main(argv=None, out=None):
     x = inst.init_points(B, a.seed, vd if fixed is not None else None)
     search = afsat.LineSearch(a.max_step, a.shrink, a.armijo, a.trials) if a.line_search else None
     t1 = time.perf_counter()
-    if a.momentum:
-        st = momentum_search(inst, x, a.lr, a.momentum, a.iters, fixed, a.poll)
-    else:
-        st = inst.pgd(x, a.lr, a.iters, fixed=fixed, poll=a.poll, stop_on_sat=True, graph=not a.no_graph,
-                      search=search, delta=a.delta, epsilon=a.epsilon)
+    st = inst.pgd(x, a.lr, a.iters, fixed=fixed, poll=a.poll, stop_on_sat=True, graph=not a.no_graph,
+                  search=search, delta=a.delta, epsilon=a.epsilon, momentum=a.momentum)
     torch.cuda.synchronize(dev)
     dt = time.perf_counter() - t1
     unsat = st["unsat"].cpu().numpy()
@@ -172,24 +169,6 @@ def main(argv=None, out=None):
         for line in assignment_lines((x[:p.n, b] < 0).cpu().numpy()):
             print(line, file=out)
     return 0
-
-
-def momentum_search(inst, x, lr, mu, iters, fixed, poll):
-    """Heavy-ball momentum steps (afs_pgd_step_momentum) until a restart verifies
-    (checked every `poll` iterations) or `iters` are done; returns the state as
-    Instance.pgd does."""
-    B = x.shape[1]
-    st = inst.pgd_state(B)
-    inst.pgd_init(x, st)
-    vel = torch.zeros_like(x)
-    t = 0
-    while t < iters and int(st["counter"][1]) == 0:
-        for _ in range(min(poll, iters - t)):
-            inst.pgd_step_momentum(x, vel, st, lr, mu, fixed=fixed)
-        t += min(poll, iters - t)
-    st["x"] = x
-    st["iters"] = int(st["counter"][0])
-    return st
 
 
 def input_unsat(p, xb, device):

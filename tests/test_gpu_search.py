@@ -515,3 +515,32 @@ def test_momentum_freezes_verified_restarts_and_rejects_bad_arguments():
         d.pgd_step_momentum(xd, vd, st, 0.05, -0.1)
     with pytest.raises(ValueError):
         d.pgd_step_momentum(xd, vd[:, :5].contiguous(), st, 0.05, 0.5)
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_momentum_driver_equals_its_steps(graph):
+    """The driver with momentum (afs_pgd, verification overlapping the next
+    iteration, eager or replayed from its graph) gives the same points, velocity
+    and state bits as 30 afs_pgd_step_momentum calls on one stream; and the
+    driver refuses momentum with the line search and out-of-range momentum."""
+    inst, _ = mixed(81)
+    d = afsat.Instance.from_arrays(inst)
+    B = 48
+    x0 = W.uniform_x0(inst.n, B, workload=1, instance=81)
+    log("case: momentum driver graph=%s" % graph)
+    xa = parity.to_dev(x0)
+    ra = d.pgd(xa, 0.05, 30, poll=10, stop_on_sat=False, graph=graph, momentum=0.7)
+    xb, vb = parity.to_dev(x0), torch.zeros(inst.n, B, dtype=torch.float32, device="cuda")
+    sb = d.pgd_state(B)
+    d.pgd_init(xb, sb)
+    for _ in range(30):
+        d.pgd_step_momentum(xb, vb, sb, 0.05, 0.7)
+    torch.cuda.synchronize()
+    assert ra["iters"] == 30
+    assert torch.equal(xa, xb) and torch.equal(ra["velocity"], vb)
+    for k in ("unsat", "done", "first_sat", "counter"):
+        assert torch.equal(ra[k], sb[k]), k
+    xc = parity.to_dev(x0)
+    for bad in (dict(momentum=1.0), dict(momentum=-0.5), dict(momentum=0.5, search=(1.0, 0.5, 1e-4, 4))):
+        with pytest.raises(afsat.AfsError):
+            d.pgd(xc, 0.05, 5, **bad)
